@@ -1,0 +1,26 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line(
+        "markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line(
+        "markers", "slow: CPU test taking more than a few seconds")
+
+
+def pytest_collection_modifyitems(config, items):
+    # GPU tests run in file order; nothing to reorder here, the hook only
+    # keeps the marker registration in one place.
+    return None
+
+
+@pytest.fixture(scope="session")
+def repo_root():
+    return ROOT

@@ -1,0 +1,214 @@
+"""Seeded synthetic workloads.
+
+Every workload is a plain description: arcs (curve objects plus node counts),
+wavenumber lists, incident-field parameters, observation points and time
+samples.  Speed of propagation is 1 throughout, so wavenumber k equals angular
+frequency omega.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .curves import (Curve, Segment, CircularArc, KiteArc, EllipseArc,
+                     SineArc, kite_point)
+
+
+@dataclass
+class IncidentSpec:
+    """Incident field parameters (Section 5, the incident fields list).
+
+    kind = "plane"   : exp(i k x.d), d = (cos theta, sin theta)
+    kind = "gplane"  : Gaussian-modulated plane wave (u2)
+    kind = "point"   : Gaussian-modulated point source (u1), amplitude 5i/2
+    """
+    kind: str
+    theta: float = 0.0
+    z0: tuple = (0.0, 0.0)
+    omega0: float = 0.0
+    sigma: float = 1.0
+    tau0: float = 0.0
+
+
+@dataclass
+class ArcSpec:
+    curve: Curve
+    n: int
+
+
+@dataclass
+class MSProblem:
+    """Closed curve split into overlapping arcs, cyclically ordered: arc j
+    overlaps arcs j-1 and j+1 only (indices modulo the arc count)."""
+    arcs: list
+    incident: IncidentSpec
+    omegas: np.ndarray
+    M: int
+    obs: np.ndarray
+    times: np.ndarray
+    c0: float = 1.0 / 3.0
+    c1: float = 2.0 / 3.0
+    period: float = 2.0 * math.pi
+    name: str = ""
+
+
+def _circle_points(n, radius, center=(0.0, 0.0)):
+    p = 2.0 * np.pi * np.arange(n) / n
+    return np.stack([center[0] + radius * np.cos(p),
+                     center[1] + radius * np.sin(p)], axis=-1)
+
+
+def plain_segment_case(n=128, nk=64):
+    """One straight arc (-1,0)-(1,0), plane wave at 30 degrees, k uniform in
+    [0.5, 32], fields on 256 points of the radius-3 circle."""
+    k = 0.5 + 31.5 * np.arange(nk) / (nk - 1)
+    return dict(curve=Segment((-1.0, 0.0), (1.0, 0.0)), n=n, k=k,
+                incident=IncidentSpec("plane", theta=math.pi / 6.0),
+                obs=_circle_points(256, 3.0), name="segment_n%d_k%d" % (n, nk))
+
+
+def fixed512_case(nk=4096, n=512):
+    """Circular arc R = 1 spanning 2.5 rad, N = 512, k uniform in [1, 120],
+    plane wave at 30 degrees, fields on the 256 radius-3 circle points."""
+    k = 1.0 + 119.0 * np.arange(nk) / max(nk - 1, 1)
+    return dict(curve=CircularArc(1.0, -1.25, 1.25), n=n, k=k,
+                incident=IncidentSpec("plane", theta=math.pi / 6.0),
+                obs=_circle_points(256, 3.0), name="arc512_k%d" % nk)
+
+
+def _kite_arcs(n, scale=1.0, center=(0.0, 0.0), rot=0.0):
+    d = math.pi / 180.0
+    arcs = []
+    for j in range(4):
+        a = (90.0 * j - 15.0) * d
+        b = (90.0 * (j + 1) + 15.0) * d
+        arcs.append(ArcSpec(KiteArc(a, b, scale, center, rot), n))
+    return arcs
+
+
+def _inside_polygon(pts, poly):
+    """Even-odd ray casting (input helper for sampling interior points)."""
+    x, y = pts[:, 0][:, None], pts[:, 1][:, None]
+    x0, y0 = poly[:, 0][None, :], poly[:, 1][None, :]
+    x1, y1 = np.roll(poly[:, 0], -1)[None, :], np.roll(poly[:, 1], -1)[None, :]
+    cond = (y0 > y) != (y1 > y)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        xint = x0 + (y - y0) * (x1 - x0) / (y1 - y0)
+    cross = cond & (x < xint)
+    return (np.count_nonzero(cross, axis=1) % 2) == 1
+
+
+def kite_interior_points(count, seed, min_dist=0.2):
+    poly = kite_point(np.linspace(0.0, 2.0 * np.pi, 4000, endpoint=False))
+    lo, hi = poly.min(axis=0), poly.max(axis=0)
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        p = lo + (hi - lo) * rng.random((256, 2))
+        ok = _inside_polygon(p, poly)
+        d = np.min(np.hypot(p[:, None, 0] - poly[None, :, 0],
+                            p[:, None, 1] - poly[None, :, 1]), axis=1)
+        for q in p[ok & (d >= min_dist)]:
+            if len(out) < count:
+                out.append(q)
+    return np.array(out)
+
+
+def kite_cavity_case(n=256, nfreq=512, M=6, nobs=64, nt=2001, dt=0.01):
+    """Kite split into 4 arcs of 120 degrees of parameter (30 degree
+    overlaps), point source at (0.1, 0.2) with omega0 = 20, sigma = 4,
+    tau0 = 4; omega_l = 80 l / 512; time traces at 64 interior points."""
+    omegas = 80.0 * np.arange(1, nfreq + 1) / nfreq
+    return MSProblem(arcs=_kite_arcs(n),
+                     incident=IncidentSpec("point", z0=(0.1, 0.2), omega0=20.0,
+                                           sigma=4.0, tau0=4.0),
+                     omegas=omegas, M=M,
+                     obs=kite_interior_points(nobs, seed=2),
+                     times=dt * np.arange(nt), name="kite4_n%d" % n)
+
+
+def small_kite_case(n=40, omegas=(3.0, 7.5, 12.25), M=3, nobs=8, nt=64,
+                    dt=0.05):
+    """Reduced kite problem the oracle finishes in seconds."""
+    return MSProblem(arcs=_kite_arcs(n),
+                     incident=IncidentSpec("point", z0=(0.1, 0.2), omega0=8.0,
+                                           sigma=3.0, tau0=4.0),
+                     omegas=np.asarray(omegas), M=M,
+                     obs=kite_interior_points(nobs, seed=2),
+                     times=dt * np.arange(nt), name="kite4_small_n%d" % n)
+
+
+def disc_interior_case(n=48, R=1.0, omegas=(6.0,), M=8, nobs=6,
+                       incident=None):
+    """Disc of radius R covered by three arcs of 180 degrees with 60 degree
+    overlaps; the first arc is the polar interval (-pi/6, 5pi/6) (the layout
+    of Geometry 1 and the density illustration of Section 4.3)."""
+    arcs = []
+    for j in range(3):
+        a = -math.pi / 6.0 + j * 2.0 * math.pi / 3.0
+        arcs.append(ArcSpec(CircularArc(R, a, a + math.pi), n))
+    rng = np.random.default_rng(11)
+    rr = 0.6 * R * np.sqrt(rng.random(nobs))
+    pp = 2.0 * np.pi * rng.random(nobs)
+    obs = np.stack([rr * np.cos(pp), rr * np.sin(pp)], axis=-1)
+    if incident is None:
+        incident = IncidentSpec("point", z0=(1.6 * R, 0.3 * R), omega0=0.0,
+                                sigma=0.0, tau0=0.0)
+    return MSProblem(arcs=arcs, incident=incident,
+                     omegas=np.asarray(omegas, dtype=complex), M=M, obs=obs,
+                     times=np.zeros(0), name="disc3_n%d" % n)
+
+
+def _sine_length(ell, amp_ratio, nu):
+    c = SineArc((0.0, 0.0), ell, amp_ratio * ell, nu, 0.0)
+    return c.length(400)
+
+
+def uneven_batch_case(seed=3, narcs=8, nk=2048, kmin=1.0, kmax=120.0,
+                      nmax=1024, nmin=64, ppw=10.0):
+    """Eight arcs of three kinds with lengths U[0.5, 4]; N per (arc, k) from
+    ppw points per wavelength, clamped to [nmin, nmax]."""
+    rng = np.random.default_rng(seed)
+    arcs = []
+    for i in range(narcs):
+        L = rng.uniform(0.5, 4.0)
+        kind = i % 3
+        if kind == 0:
+            R = rng.uniform(0.5, 2.0)
+            span = L / R
+            if span > 1.5 * math.pi:
+                R = L / (1.5 * math.pi)
+                span = 1.5 * math.pi
+            a = rng.uniform(0.0, 2.0 * math.pi)
+            c = CircularArc(R, a, a + span,
+                            center=tuple(rng.uniform(-3.0, 3.0, 2)))
+        elif kind == 1:
+            ea = rng.uniform(0.5, 2.0)
+            eb = ea * rng.uniform(0.3, 1.0)
+            sc = rng.uniform(0.0, 2.0 * math.pi)
+            lo, hi = 1e-6, 0.75 * math.pi
+            for _ in range(80):
+                mid = 0.5 * (lo + hi)
+                if EllipseArc(ea, eb, sc - mid, sc + mid).length() < L:
+                    lo = mid
+                else:
+                    hi = mid
+            h = 0.5 * (lo + hi)
+            c = EllipseArc(ea, eb, sc - h, sc + h,
+                           center=tuple(rng.uniform(-3.0, 3.0, 2)),
+                           rot=rng.uniform(0.0, math.pi))
+        else:
+            ratio = rng.uniform(0.05, 0.2)
+            nu = int(rng.integers(1, 4))
+            ell = L / _sine_length(1.0, ratio, nu)
+            c = SineArc(tuple(rng.uniform(-3.0, 3.0, 2)), ell, ratio * ell, nu,
+                        rng.uniform(0.0, 2.0 * math.pi))
+        theta = rng.uniform(0.0, 2.0 * math.pi)
+        arcs.append(dict(curve=c, length=c.length(), theta=theta))
+    k = kmin + (kmax - kmin) * np.arange(nk) / max(nk - 1, 1)
+    for a in arcs:
+        n = np.ceil(ppw * k * a["length"] / (2.0 * math.pi)).astype(int)
+        a["n"] = np.minimum(nmax, np.maximum(nmin, n))
+    return dict(arcs=arcs, k=k, name="uneven%d_k%d" % (narcs, nk))
