@@ -1,0 +1,210 @@
+"""Benchmark: Helmholtz open-arc solves/s at N = 512 on one MI355X.
+
+Workload (the fixed N = 512 batch of the mixed-precision configuration): a
+circular arc of radius 1 spanning 2.5 rad, N = 512 Chebyshev nodes, 4096
+wavenumbers uniform in [1, 120], plane wave at 30 degrees, fields at 256
+points on the radius-3 circle, and time traces at those points
+(t = 0.01 n, n = 0..1000) by the trapezoid frequency-to-time transform.
+
+One step = one pass of the whole path over the batch: right-hand sides,
+Nystrom assembly, LU, solve (+ FP64 refinement for the refined form), field
+evaluation, frequency-to-time transform.  Inputs are resident in HBM before
+the timed region.  Both the FP32-refined form (the headline `value`) and the
+plain FP64 form are timed; the refined results are checked against the FP64
+ones (relative L2 per solve) and, on a sample, against the CPU oracle.
+
+Prints ONE JSON line.  `python bench.py --gpus N` with N > 1 exits: this
+build measures one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N_ARC = 512
+NK = 4096
+NT = 1001
+PEAK = {"fp64_mfma_tflops": 78.6, "fp32_mfma_tflops": 157.3, "hbm_gbs": 8000.0}
+
+
+def lu_flops(n):
+    """Algorithmic real flops of a complex LU: (8/3) n^3."""
+    return 8.0 / 3.0 * n ** 3
+
+
+def cpu_baseline(case, k_sample, alpha_gpu_rows):
+    """The oracle (as it stands) on host cores for a bounded sample of the
+    same workload; returns the baseline record and the sampled GPU error."""
+    from oracle import incident as oinc
+    from oracle import nystrom as ony
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = 1
+    nd = ony.arc_nodes(case["curve"], N_ARC)
+    obs = case["obs"]
+    t0 = time.perf_counter()
+    errs = []
+    done = 0
+    for kk, a_gpu in zip(k_sample, alpha_gpu_rows):
+        b = -oinc.incident(case["incident"], kk, nd["y"])
+        a = ony.solve(ony.assemble(nd, kk), b)
+        ony.field_far(kk, obs, nd["y"], a)
+        errs.append(float(np.linalg.norm(a_gpu - a) / np.linalg.norm(a)))
+        done += 1
+        if time.perf_counter() - t0 > 25.0:
+            break
+    dt = time.perf_counter() - t0
+    rec = {"value": done / dt, "unit": "solves/s", "cores": int(threads),
+           "kind": "oracle",
+           "sample": "%d of the %d wavenumbers (assembly + LU solve + 256-point field "
+                     "per solve, numpy/scipy FP64)" % (done, NK)}
+    return rec, max(errs[:done])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only (the solve path shards by frequency; "
+              "no multi-GPU run is part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2507_05725_amd as fth
+    from workloads import fixed512_case
+
+    case = fixed512_case(nk=NK, n=N_ARC)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    ctx = fth.Context(0, stream=stream.cuda_stream)
+    arc = ctx.arc_from_curve(case["curve"], N_ARC)
+    k_np = case["k"]
+    w_np = np.full(NK, k_np[1] - k_np[0])
+    w_np[0] *= 0.5
+    w_np[-1] *= 0.5
+    t_np = 0.01 * np.arange(NT)
+    k = torch.tensor(k_np, dtype=torch.float64, device=dev)
+    w = torch.tensor(w_np, dtype=torch.float64, device=dev)
+    t = torch.tensor(t_np, dtype=torch.float64, device=dev)
+    nobs = case["obs"].shape[0]
+    probs = {p: fth.Problem(ctx, [arc], case["incident"], case["obs"], M=1, precision=p)
+             for p in (fth.FP64, fth.FP32_REFINED)}
+    U = {p: torch.empty((NK, nobs), dtype=torch.complex128, device=dev) for p in probs}
+    A = {p: torch.empty((NK, N_ARC), dtype=torch.complex128, device=dev) for p in probs}
+    u = {p: torch.empty((NT, nobs), dtype=torch.complex128, device=dev) for p in probs}
+
+    def step(p):
+        probs[p].run_dev(k, U[p], A[p])
+        ctx.freq_to_time_dev(k, w, U[p], t, u[p])
+
+    results = {}
+    for p in (fth.FP64, fth.FP32_REFINED):
+        for _ in range(args.warmup):
+            step(p)
+        torch.cuda.synchronize()
+        ctx.timing_reset()
+        ctx.timing(True)
+        lat = []
+        t_all = time.perf_counter()
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            step(p)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t0)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t_all
+        ctx.timing(False)
+        kt = {name: ctx.timing_read(name) for name in
+              ("assemble", "lu", "solve", "fallback", "rhs", "field", "freq_to_time")}
+        results[p] = dict(total=total, lat=lat, kt=kt)
+
+    # accuracy of the refined form against the FP64 form, every solve
+    a64, a32 = A[fth.FP64], A[fth.FP32_REFINED]
+    err = (torch.linalg.vector_norm(a32 - a64, dim=1) /
+           torch.linalg.vector_norm(a64, dim=1)).max().item()
+    uerr = (torch.linalg.vector_norm(u[fth.FP32_REFINED] - u[fth.FP64]) /
+            torch.linalg.vector_norm(u[fth.FP64])).item()
+
+    r32, r64 = results[fth.FP32_REFINED], results[fth.FP64]
+    ms_step = 1000.0 * r32["total"] / args.steps
+    value = NK * args.steps / r32["total"]
+    fp64_value = NK * args.steps / r64["total"]
+    lu_ms, lu_n = r32["kt"]["lu"]
+    lu64_ms, lu64_n = r64["kt"]["lu"]
+    # each LU launch factors the same number of matrices (even chunks)
+    per_launch32 = NK * args.steps / max(lu_n, 1)
+    per_launch64 = NK * args.steps / max(lu64_n, 1)
+    ach32 = lu_flops(N_ARC) * per_launch32 / (lu_ms / max(lu_n, 1) / 1e3) / 1e12
+    ach64 = lu_flops(N_ARC) * per_launch64 / (lu64_ms / max(lu64_n, 1) / 1e3) / 1e12
+    roof = {"bound": "mfma", "achieved": round(ach32, 3),
+            "peak": PEAK["fp32_mfma_tflops"], "unit": "TFLOP/s",
+            "frac": round(ach32 / PEAK["fp32_mfma_tflops"], 4), "traffic": None,
+            "kernel": "lu_kernel<float> (complex LU, FP32 MFMA updates)",
+            "avg_launch_ms": round(lu_ms / max(lu_n, 1), 4),
+            "matrices_per_launch": int(per_launch32)}
+
+    base = None
+    oracle_err = None
+    if not args.no_cpu_baseline:
+        idx = np.linspace(0, NK - 1, 64).astype(int)
+        rows = a32[idx].cpu().numpy()
+        base, oracle_err = cpu_baseline(case, k_np[idx], rows)
+
+    lat32 = np.array(r32["lat"]) * 1000.0
+    line = {
+        "metric": "Helmholtz arc solves/s at N=512 (1e-10 rel err), refined vs FP64; "
+                  "p50/p99 latency",
+        "value": round(value, 2),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64-mfma+f64-refine",
+        "data": "synthetic",
+        "config": {"workload": "circular arc R=1 span 2.5 rad, N=512, 4096 wavenumbers "
+                               "in [1,120], plane wave 30 deg, 256 field points, 1001 "
+                               "time samples", "n": N_ARC, "n_freq": NK,
+                   "parallelism": "single GPU"},
+        "fp64": {"value": round(fp64_value, 2), "unit": "solves/s",
+                 "ms_per_step": round(1000.0 * r64["total"] / args.steps, 3),
+                 "lu_achieved_tflops": round(ach64, 3),
+                 "lu_frac_of_fp64_mfma_peak": round(ach64 / PEAK["fp64_mfma_tflops"], 4)},
+        "refined_over_fp64": round(value / fp64_value, 3),
+        "max_rel_err_refined_vs_fp64": err,
+        "trace_rel_err_refined_vs_fp64": uerr,
+        "max_rel_err_vs_oracle_sampled": oracle_err,
+        "latency_ms_per_batch": {"p50": round(float(np.percentile(lat32, 50)), 3),
+                                 "p99": round(float(np.percentile(lat32, 99)), 3)},
+        "kernel_ms_per_step_refined": {n: round(v[0] / args.steps, 3)
+                                       for n, v in r32["kt"].items()},
+        "kernel_ms_per_step_fp64": {n: round(v[0] / args.steps, 3)
+                                    for n, v in r64["kt"].items()},
+        "roofline": roof,
+        "cpu_baseline": base,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

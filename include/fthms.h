@@ -1,0 +1,235 @@
+/*
+ * libfthms -- open-arc Helmholtz solves for the multi-patch / multiple-
+ * scattering frequency-time hybrid (FTH-MS) method, on AMD MI355X (gfx950).
+ *
+ * What the library computes (paper: Pan, Bao, Yin, Bruno, "Multi-patch/
+ * multiple-scattering frequency-time hybrid solver for interior and exterior
+ * wave equation problems"):
+ *
+ *   * the first-kind open-arc integral equation V_Gamma[psi] = G and the
+ *     single-layer potential S_Gamma[psi] (Section 3.2, eqs. FDBIEk-interior
+ *     and FDsolk-interior) with Phi_k = (i/4) H0^(1)(k|x - y|) (Section 2.1),
+ *     discretised with the endpoint-weighted Chebyshev density
+ *     psi |x'| = alpha / sqrt(1 - t^2) (Section 4.3, eq. singularity);
+ *   * one dense solve per (arc, wavenumber), batched over wavenumbers;
+ *   * the frequency-domain multiple-scattering recursion over a cyclic set of
+ *     overlapping arcs (Section 3.1, Definition inductive_int, eqs.
+ *     criterion_int1/2, vtilde, POU1, mult-scatt-int);
+ *   * the inverse Fourier transform of the fields to time traces (Section
+ *     2.1, eq. backwardFT; eq. TDsol-interior with one time window).
+ *
+ * Conventions
+ *   - Speed of propagation c = 1, so wavenumber k equals angular frequency.
+ *   - Complex numbers are interleaved (re, im) doubles: fthms_c64, layout-
+ *     identical to C99 double _Complex and to a complex128 tensor element.
+ *   - Arrays are row-major: [freq][node], [freq][point], [time][point];
+ *     points are [n][2] (x, y).
+ *   - Arcs are given by samples of a parametrisation x(t), t in [-1, 1], at
+ *     the first-kind Chebyshev nodes that fthms_cheb_nodes() returns.
+ *
+ * Ownership
+ *   - Every *_create has a matching *_destroy.  The library owns contexts,
+ *     arcs, problems and all device memory it allocates; it never frees
+ *     caller memory.
+ *   - Functions without the _dev suffix take host pointers, copy in and out,
+ *     and return after the results are in host memory.
+ *   - Functions with the _dev suffix take device pointers (e.g. from a torch
+ *     tensor on the same device) and are stream-ordered on the context's
+ *     stream: they return once the work is enqueued.
+ *
+ * Errors
+ *   - Every function returns an int: FTHMS_OK (0) or a negative code.  No
+ *     function throws or aborts across the ABI.  fthms_last_error() returns
+ *     a description of the last failure on that context.
+ *
+ * Threading
+ *   - A context is used by one host thread at a time.  Contexts are
+ *     independent; several contexts may share a device.
+ */
+#ifndef FTHMS_H
+#define FTHMS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FTHMS_ABI_VERSION 1
+
+enum {
+  FTHMS_OK = 0,
+  FTHMS_EINVAL = -1,      /* bad size, NULL pointer or unknown option   */
+  FTHMS_EINVAL_DATA = -2, /* NaN/Inf or otherwise unusable input values  */
+  FTHMS_ENOMEM = -3,      /* request exceeds the context's HBM budget    */
+  FTHMS_ESINGULAR = -4,   /* exactly zero pivot in a factorisation       */
+  FTHMS_ENOCONV = -5,     /* refinement hit its cap; results still valid */
+  FTHMS_EDEVICE = -6      /* HIP runtime error (text in last_error)      */
+};
+
+enum { FTHMS_FP64 = 0, FTHMS_FP32_REFINED = 1 };
+
+enum { FTHMS_INC_PLANE = 0, FTHMS_INC_GPLANE = 1, FTHMS_INC_POINT = 2 };
+
+typedef struct {
+  double re, im;
+} fthms_c64;
+
+typedef struct fthms_ctx fthms_ctx;
+typedef struct fthms_arc fthms_arc;
+typedef struct fthms_problem fthms_problem;
+
+/* Incident field (Section 5, eqs. pointsource and planewave2):
+ *   PLANE : U = exp(i k x.d),  d = (cos theta, sin theta)
+ *   GPLANE: U = exp(i k x.d) g(k)
+ *   POINT : U = (5i/2) H0^(1)(k |x - z0|) g(k)   (g = 1 when sigma == 0)
+ * with g(k) = exp(-(k - omega0)^2 / sigma^2) exp(i k tau0). */
+typedef struct {
+  int kind;
+  double theta;
+  double z0[2];
+  double omega0, sigma, tau0;
+} fthms_incident;
+
+/* ---- library and context ---------------------------------------------- */
+
+int fthms_abi_version(void);
+
+/* Create a context on HIP device `device`.  `hbm_budget_bytes` caps the
+ * device memory the context may hold (0 = no cap).  `hip_stream` is a
+ * hipStream_t to order _dev calls on, or NULL for a stream the context owns.
+ * Fails with FTHMS_EDEVICE when no gfx950 device is usable. */
+int fthms_create(fthms_ctx **out, int device, size_t hbm_budget_bytes,
+                 void *hip_stream);
+int fthms_destroy(fthms_ctx *ctx);
+/* Description of the last error on ctx (valid until the next call on ctx);
+ * with ctx == NULL, the last error of fthms_create on this thread. */
+const char *fthms_last_error(const fthms_ctx *ctx);
+/* Block until all work enqueued on the context's stream has finished. */
+int fthms_sync(fthms_ctx *ctx);
+
+/* Kernel timing: while enabled, every kernel launch of the library is
+ * bracketed by a pair of HIP events on the context's stream.  _read returns
+ * the summed elapsed milliseconds and the launch count for one kernel class
+ * ("assemble", "lu", "solve", "fallback", "rhs", "field", "field_cross",
+ * "freq_to_time"); it synchronises the stream.  Timing adds a few
+ * microseconds per launch. */
+int fthms_timing_enable(fthms_ctx *ctx, int enable);
+int fthms_timing_reset(fthms_ctx *ctx);
+int fthms_timing_read(fthms_ctx *ctx, const char *name, double *total_ms,
+                      int *launches);
+
+/* ---- discretisation ---------------------------------------------------- */
+
+/* First-kind Chebyshev nodes t_i = cos((2i - 1) pi / (2n)), i = 1..n
+ * (n >= 2), written to t_out[n] in that order (t decreasing). */
+int fthms_cheb_nodes(int n, double *t_out);
+
+/* Register one arc from samples at the Chebyshev nodes: xy[n][2] = x(t_i),
+ * dxy[n][2] = dx/dt(t_i); 2 <= n <= 1024.  Builds the frequency-independent
+ * tables of the Nystrom matrix (Section 4.2, frequency-independent kernel
+ * decomposition) on the device.  Fails with FTHMS_EINVAL_DATA for
+ * non-finite samples, coincident nodes or a vanishing speed |x'(t_i)|. */
+int fthms_arc_create(fthms_ctx *ctx, int n, const double *xy,
+                     const double *dxy, fthms_arc **out);
+int fthms_arc_destroy(fthms_arc *arc);
+int fthms_arc_size(const fthms_arc *arc);
+
+/* ---- the per-(arc, k) solve --------------------------------------------- */
+
+/* For each of nk wavenumbers k[i] > 0: assemble the Nystrom matrix of
+ * V_Gamma on `arc`, factor it (LU with partial pivoting) and solve
+ * A alpha = rhs[i].  rhs, alpha: [nk][n].  precision FTHMS_FP64 factors in
+ * complex FP64; FTHMS_FP32_REFINED factors in complex FP32 (MFMA trailing
+ * updates, FP64 panel pivoting) and refines with FP64 residuals until the
+ * predicted relative error of alpha is below tol (tol <= 0: 1e-13), at most
+ * 10 iterations; solves that do not converge are redone in FP64.
+ * iters[nk] (optional) receives the refinement steps per solve (0 for
+ * FP64, -1 for a solve redone in FP64); relres[nk] (optional) the last
+ * relative correction |delta|/|alpha|.  FTHMS_ESINGULAR if a pivot is
+ * exactly zero (alpha is then not meaningful for that k). */
+int fthms_solve(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double *k,
+                const fthms_c64 *rhs, fthms_c64 *alpha, int precision,
+                double tol, int *iters, double *relres);
+int fthms_solve_dev(fthms_ctx *ctx, const fthms_arc *arc, int nk,
+                    const double *k_dev, const fthms_c64 *rhs_dev,
+                    fthms_c64 *alpha_dev, int precision, double tol,
+                    int *iters_dev, double *relres_dev);
+
+/* Right-hand side of the sound-soft single-arc problem, b = -U^inc at the
+ * arc's nodes (G = -u^i), for nk wavenumbers: rhs[nk][n]. */
+int fthms_rhs(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double *k,
+              const fthms_incident *inc, fthms_c64 *rhs);
+int fthms_rhs_dev(fthms_ctx *ctx, const fthms_arc *arc, int nk,
+                  const double *k_dev, const fthms_incident *inc,
+                  fthms_c64 *rhs_dev);
+
+/* Single-layer potential U(z_p) = S_Gamma[psi](z_p) of the density alpha
+ * at np points xy[np][2]: U[nk][np].  Points farther than ten node spacings
+ * from every node use the Gauss-Chebyshev rule; nearer points use a graded
+ * composite Gauss-Legendre rule on the Chebyshev interpolant of alpha.  The
+ * _dev form copies the points and wavenumbers to the host to plan the near
+ * rule, so it synchronises the stream before enqueuing. */
+int fthms_eval_field(fthms_ctx *ctx, const fthms_arc *arc, int nk,
+                     const double *k, const fthms_c64 *alpha, int np,
+                     const double *xy, fthms_c64 *U);
+int fthms_eval_field_dev(fthms_ctx *ctx, const fthms_arc *arc, int nk,
+                         const double *k_dev, const fthms_c64 *alpha_dev,
+                         int np, const double *xy_dev, fthms_c64 *U_dev);
+
+/* u(x_p, t_n) = (1/2pi) sum_l w[l] U[l][p] exp(-i omega[l] t_n):
+ * U[nk][np] -> u[nt][np]. */
+int fthms_freq_to_time(fthms_ctx *ctx, int nk, const double *omega,
+                       const double *w, int np, const fthms_c64 *U, int nt,
+                       const double *t, fthms_c64 *u);
+int fthms_freq_to_time_dev(fthms_ctx *ctx, int nk, const double *omega_dev,
+                           const double *w_dev, int np,
+                           const fthms_c64 *U_dev, int nt, const double *t_dev,
+                           fthms_c64 *u_dev);
+
+/* ---- multiple scattering over a cyclic partition ---------------------- */
+
+/* A closed curve covered by narcs >= 2 overlapping arcs, cyclically ordered
+ * (arc j overlaps arcs j-1 and j+1 only).  interval[2j], interval[2j+1] are
+ * the parameter bounds of arc j on the parent closed curve of period
+ * `period` (arc j's local t = -1 maps to interval[2j]); they decide overlap
+ * membership.  c0, c1 are the POU constants of eq. POU1 (the paper uses
+ * 1/3, 2/3); the window distances are chords.  M >= 1 multiple-scattering
+ * steps.  Multi-arc problems run in FTHMS_FP64.  narcs == 1 is allowed and
+ * runs the plain sound-soft single-arc problem (G = -U^inc, no recursion,
+ * either precision).  The field u_M is evaluated at nobs observation
+ * points obs_xy[nobs][2] (copied at creation). */
+typedef struct {
+  int narcs;
+  const fthms_arc *const *arcs;
+  const double *interval;
+  double period;
+  double c0, c1;
+  int M;
+  int precision;
+  double tol;
+  fthms_incident incident;
+  int nobs;
+  const double *obs_xy;
+} fthms_problem_desc;
+
+int fthms_problem_create(fthms_ctx *ctx, const fthms_problem_desc *desc,
+                         fthms_problem **out);
+int fthms_problem_destroy(fthms_problem *pb);
+
+/* Run the recursion at nk wavenumbers and evaluate u_M = sum_m sum_j v_{j,m}
+ * at the observation points: U[nk][nobs] (optional).  alpha_tot (optional)
+ * receives sum_m alpha_{j,m} as [nk][sum_j n_j] in arc order.  The _dev form
+ * takes device pointers; it copies k to the host (to size the near-target
+ * rules) and then enqueues everything on the context's stream. */
+int fthms_problem_run_dev(fthms_problem *pb, int nk, const double *k_dev,
+                          fthms_c64 *U_dev, fthms_c64 *alpha_tot_dev);
+int fthms_problem_run(fthms_problem *pb, int nk, const double *k, fthms_c64 *U,
+                      fthms_c64 *alpha_tot);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FTHMS_H */

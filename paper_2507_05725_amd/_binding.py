@@ -1,0 +1,306 @@
+"""ctypes binding to libfthms (include/fthms.h).
+
+Argument marshalling only: every step of the solve path runs in the HIP
+library.  Host functions take NumPy arrays; the *_dev functions take torch
+tensors on the GPU (device pointers) and run on the context's stream.  If the
+shared library is missing this module raises at import time -- there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libfthms.so")
+
+FP64 = 0
+FP32_REFINED = 1
+INC_PLANE, INC_GPLANE, INC_POINT = 0, 1, 2
+
+_ERR = {0: "OK", -1: "EINVAL", -2: "EINVAL_DATA", -3: "ENOMEM",
+        -4: "ESINGULAR", -5: "ENOCONV", -6: "EDEVICE"}
+
+
+class FthmsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (_ERR.get(code, "?"), code, msg))
+        self.code = code
+
+
+class Incident(C.Structure):
+    _fields_ = [("kind", C.c_int), ("theta", C.c_double),
+                ("z0", C.c_double * 2), ("omega0", C.c_double),
+                ("sigma", C.c_double), ("tau0", C.c_double)]
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("narcs", C.c_int), ("arcs", C.POINTER(C.c_void_p)),
+                ("interval", C.POINTER(C.c_double)), ("period", C.c_double),
+                ("c0", C.c_double), ("c1", C.c_double), ("M", C.c_int),
+                ("precision", C.c_int), ("tol", C.c_double),
+                ("incident", Incident), ("nobs", C.c_int),
+                ("obs_xy", C.POINTER(C.c_double))]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libfthms.so is not built (run `python -m "
+                      "paper_2507_05725_amd.build`); there is no CPU fallback")
+_lib = C.CDLL(LIB_PATH)
+
+_vp, _i, _d, _sz = C.c_void_p, C.c_int, C.c_double, C.c_size_t
+_SIGS = {
+    "fthms_abi_version": ([], _i),
+    "fthms_create": ([C.POINTER(_vp), _i, _sz, _vp], _i),
+    "fthms_destroy": ([_vp], _i),
+    "fthms_last_error": ([_vp], C.c_char_p),
+    "fthms_sync": ([_vp], _i),
+    "fthms_timing_enable": ([_vp, _i], _i),
+    "fthms_timing_reset": ([_vp], _i),
+    "fthms_timing_read": ([_vp, C.c_char_p, C.POINTER(_d), C.POINTER(_i)], _i),
+    "fthms_cheb_nodes": ([_i, _vp], _i),
+    "fthms_arc_create": ([_vp, _i, _vp, _vp, C.POINTER(_vp)], _i),
+    "fthms_arc_destroy": ([_vp], _i),
+    "fthms_arc_size": ([_vp], _i),
+    "fthms_solve": ([_vp, _vp, _i, _vp, _vp, _vp, _i, _d, _vp, _vp], _i),
+    "fthms_solve_dev": ([_vp, _vp, _i, _vp, _vp, _vp, _i, _d, _vp, _vp], _i),
+    "fthms_rhs": ([_vp, _vp, _i, _vp, C.POINTER(Incident), _vp], _i),
+    "fthms_rhs_dev": ([_vp, _vp, _i, _vp, C.POINTER(Incident), _vp], _i),
+    "fthms_eval_field": ([_vp, _vp, _i, _vp, _vp, _i, _vp, _vp], _i),
+    "fthms_eval_field_dev": ([_vp, _vp, _i, _vp, _vp, _i, _vp, _vp], _i),
+    "fthms_freq_to_time": ([_vp, _i, _vp, _vp, _i, _vp, _i, _vp, _vp], _i),
+    "fthms_freq_to_time_dev": ([_vp, _i, _vp, _vp, _i, _vp, _i, _vp, _vp], _i),
+    "fthms_problem_create": ([_vp, C.POINTER(ProblemDesc), C.POINTER(_vp)], _i),
+    "fthms_problem_destroy": ([_vp], _i),
+    "fthms_problem_run": ([_vp, _i, _vp, _vp, _vp], _i),
+    "fthms_problem_run_dev": ([_vp, _i, _vp, _vp, _vp], _i),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    return _lib
+
+
+def _ptr(a):
+    """Host pointer of a C-contiguous NumPy array (or None)."""
+    if a is None:
+        return None
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _dptr(t):
+    """Device pointer of a contiguous torch tensor (or None)."""
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous()
+    return C.c_void_p(t.data_ptr())
+
+
+def cheb_nodes(n):
+    t = np.empty(n)
+    rc = _lib.fthms_cheb_nodes(n, _ptr(t))
+    if rc:
+        raise FthmsError(rc, "fthms_cheb_nodes")
+    return t
+
+
+def incident_struct(spec):
+    """workloads.IncidentSpec -> fthms_incident."""
+    kind = {"plane": INC_PLANE, "gplane": INC_GPLANE, "point": INC_POINT}[spec.kind]
+    inc = Incident()
+    inc.kind = kind
+    inc.theta = float(spec.theta)
+    inc.z0[0], inc.z0[1] = float(spec.z0[0]), float(spec.z0[1])
+    inc.omega0 = float(spec.omega0)
+    inc.sigma = float(spec.sigma)
+    inc.tau0 = float(spec.tau0)
+    return inc
+
+
+class Context:
+    def __init__(self, device=0, hbm_budget=0, stream=None):
+        h = C.c_void_p()
+        rc = _lib.fthms_create(C.byref(h), int(device), int(hbm_budget),
+                               None if stream is None else C.c_void_p(int(stream)))
+        if rc:
+            raise FthmsError(rc, _lib.fthms_last_error(None).decode())
+        self.h = h
+        self.device = device
+
+    def check(self, rc, what=""):
+        if rc:
+            raise FthmsError(rc, "%s: %s" % (what, _lib.fthms_last_error(self.h).decode()))
+
+    def sync(self):
+        self.check(_lib.fthms_sync(self.h), "sync")
+
+    def timing(self, enable=True):
+        self.check(_lib.fthms_timing_enable(self.h, int(bool(enable))), "timing")
+
+    def timing_reset(self):
+        self.check(_lib.fthms_timing_reset(self.h), "timing_reset")
+
+    def timing_read(self, name):
+        ms, cnt = C.c_double(), C.c_int()
+        self.check(_lib.fthms_timing_read(self.h, name.encode(), C.byref(ms),
+                                          C.byref(cnt)), "timing_read")
+        return ms.value, cnt.value
+
+    def close(self):
+        if self.h:
+            _lib.fthms_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- single arc -------------------------------------------------------
+    def arc(self, xy, dxy):
+        return Arc(self, xy, dxy)
+
+    def arc_from_curve(self, curve, n):
+        t = cheb_nodes(n)
+        return Arc(self, curve.x(t), curve.dx(t))
+
+    def solve(self, arc, k, rhs, precision=FP64, tol=0.0):
+        k = np.ascontiguousarray(k, dtype=np.float64)
+        rhs = np.ascontiguousarray(rhs, dtype=np.complex128)
+        nk = k.size
+        alpha = np.empty((nk, arc.n), dtype=np.complex128)
+        iters = np.empty(nk, dtype=np.int32)
+        relres = np.empty(nk, dtype=np.float64)
+        self.check(_lib.fthms_solve(self.h, arc.h, nk, _ptr(k), _ptr(rhs), _ptr(alpha),
+                                    precision, tol, _ptr(iters), _ptr(relres)), "solve")
+        return alpha, iters, relres
+
+    def solve_dev(self, arc, k, rhs, alpha, precision=FP64, tol=0.0, iters=None,
+                  relres=None):
+        self.check(_lib.fthms_solve_dev(self.h, arc.h, k.numel(), _dptr(k), _dptr(rhs),
+                                        _dptr(alpha), precision, tol, _dptr(iters),
+                                        _dptr(relres)), "solve_dev")
+
+    def rhs(self, arc, k, spec):
+        k = np.ascontiguousarray(k, dtype=np.float64)
+        out = np.empty((k.size, arc.n), dtype=np.complex128)
+        inc = incident_struct(spec)
+        self.check(_lib.fthms_rhs(self.h, arc.h, k.size, _ptr(k), C.byref(inc), _ptr(out)),
+                   "rhs")
+        return out
+
+    def rhs_dev(self, arc, k, spec, out):
+        inc = incident_struct(spec)
+        self.check(_lib.fthms_rhs_dev(self.h, arc.h, k.numel(), _dptr(k), C.byref(inc),
+                                      _dptr(out)), "rhs_dev")
+
+    def eval_field(self, arc, k, alpha, pts):
+        k = np.ascontiguousarray(k, dtype=np.float64)
+        alpha = np.ascontiguousarray(alpha, dtype=np.complex128)
+        pts = np.ascontiguousarray(pts, dtype=np.float64)
+        U = np.empty((k.size, pts.shape[0]), dtype=np.complex128)
+        self.check(_lib.fthms_eval_field(self.h, arc.h, k.size, _ptr(k), _ptr(alpha),
+                                         pts.shape[0], _ptr(pts), _ptr(U)), "eval_field")
+        return U
+
+    def eval_field_dev(self, arc, k, alpha, pts, U):
+        self.check(_lib.fthms_eval_field_dev(self.h, arc.h, k.numel(), _dptr(k), _dptr(alpha),
+                                             pts.shape[0], _dptr(pts), _dptr(U)),
+                   "eval_field_dev")
+
+    def freq_to_time(self, omega, w, U, t):
+        omega = np.ascontiguousarray(omega, dtype=np.float64)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        U = np.ascontiguousarray(U, dtype=np.complex128)
+        t = np.ascontiguousarray(t, dtype=np.float64)
+        out = np.empty((t.size, U.shape[1]), dtype=np.complex128)
+        self.check(_lib.fthms_freq_to_time(self.h, omega.size, _ptr(omega), _ptr(w), U.shape[1],
+                                           _ptr(U), t.size, _ptr(t), _ptr(out)), "freq_to_time")
+        return out
+
+    def freq_to_time_dev(self, omega, w, U, t, out):
+        self.check(_lib.fthms_freq_to_time_dev(self.h, omega.numel(), _dptr(omega), _dptr(w),
+                                               U.shape[1], _dptr(U), t.numel(), _dptr(t),
+                                               _dptr(out)), "freq_to_time_dev")
+
+
+class Arc:
+    def __init__(self, ctx, xy, dxy):
+        xy = np.ascontiguousarray(xy, dtype=np.float64)
+        dxy = np.ascontiguousarray(dxy, dtype=np.float64)
+        n = xy.shape[0]
+        h = C.c_void_p()
+        ctx.check(_lib.fthms_arc_create(ctx.h, n, _ptr(xy), _ptr(dxy), C.byref(h)),
+                  "arc_create")
+        self.ctx, self.h, self.n = ctx, h, n
+
+    def close(self):
+        if self.h:
+            _lib.fthms_arc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Problem:
+    """Cyclic multi-arc (or single-arc) problem; see fthms_problem_desc."""
+
+    def __init__(self, ctx, arcs, incident, obs, intervals=None, period=2 * np.pi,
+                 c0=1.0 / 3.0, c1=2.0 / 3.0, M=1, precision=FP64, tol=0.0):
+        self.ctx = ctx
+        self.arcs = list(arcs)
+        self.nsum = sum(a.n for a in self.arcs)
+        self.obs = np.ascontiguousarray(obs, dtype=np.float64)
+        self._arr = (C.c_void_p * len(self.arcs))(*[a.h.value for a in self.arcs])
+        self._iv = None
+        d = ProblemDesc()
+        d.narcs = len(self.arcs)
+        d.arcs = C.cast(self._arr, C.POINTER(C.c_void_p))
+        if intervals is not None:
+            self._iv = np.ascontiguousarray(intervals, dtype=np.float64).reshape(-1)
+            d.interval = self._iv.ctypes.data_as(C.POINTER(C.c_double))
+        d.period, d.c0, d.c1, d.M = period, c0, c1, M
+        d.precision, d.tol = precision, tol
+        d.incident = incident_struct(incident)
+        d.nobs = self.obs.shape[0]
+        d.obs_xy = self.obs.ctypes.data_as(C.POINTER(C.c_double))
+        h = C.c_void_p()
+        ctx.check(_lib.fthms_problem_create(ctx.h, C.byref(d), C.byref(h)), "problem_create")
+        self.h = h
+
+    def run(self, k, want_alpha=False):
+        k = np.ascontiguousarray(k, dtype=np.float64)
+        U = np.empty((k.size, self.obs.shape[0]), dtype=np.complex128)
+        A = np.empty((k.size, self.nsum), dtype=np.complex128) if want_alpha else None
+        self.ctx.check(_lib.fthms_problem_run(self.h, k.size, _ptr(k), _ptr(U), _ptr(A)),
+                       "problem_run")
+        return (U, A) if want_alpha else U
+
+    def run_dev(self, k, U, alpha=None):
+        self.ctx.check(_lib.fthms_problem_run_dev(self.h, k.numel(), _dptr(k), _dptr(U),
+                                                  _dptr(alpha)), "problem_run_dev")
+
+    def close(self):
+        if self.h:
+            _lib.fthms_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

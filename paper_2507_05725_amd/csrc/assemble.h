@@ -1,0 +1,129 @@
+// Nystrom matrix assembly and right-hand sides (FP64 VALU).
+//
+// Matrix of the first-kind open-arc operator V_Gamma (Section 3.2, eq.
+// FDBIEk-interior) in the endpoint-weighted Chebyshev discretisation
+// (Section 4.3, eq. singularity):
+//
+//   A_ij = W_ij L1_ij + (pi/N) L2_ij,   L1 = -J0(kr)/(2pi),
+//   L2   = (i/4) H0^(1)(kr) + J0(kr) log|t_i - t_j| / (2pi),
+//
+// rewritten with the frequency-independent table (the kernel split of
+// Section 4.2 that lets one table serve every frequency)
+//
+//   G_ij = ( -W_ij - (pi/N) log(r_ij / |t_i - t_j|) ) / (2pi),  i != j
+//   G_ii = ( -W_ii - (pi/N) log s_i ) / (2pi),
+//
+// as  A_ij = J0(z)(G_ij - c_k) - (pi/4N) Y0hat(z) + i (pi/4N) J0(z),
+//     z = k r_ij,  c_k = (gamma + log(k/2)) / (2N),
+// and A_ii = G_ii - c_k + i pi/(4N).  Y0hat = Y0 - (2/pi)(log(z/2)+gamma) J0
+// removes the log|t_i - t_j| cancellation near the diagonal exactly.
+#pragma once
+
+#include "bessel.h"
+#include "common.h"
+
+namespace fthms {
+
+// Upper-triangular 32x32 tiles; each block computes one tile for one
+// wavenumber and writes it and its mirror (A is complex symmetric).
+template <bool W32>
+__global__ __launch_bounds__(256) void assemble_kernel(
+    const double2 *__restrict__ y, const double *__restrict__ G, int N,
+    const double *__restrict__ kvec, double2 *__restrict__ A64,
+    float2 *__restrict__ A32, long long mstride) {
+  __shared__ double2 tile[32][33];
+  const int b = blockIdx.y;
+  const double k = kvec[b];
+  const int t = blockIdx.x;
+  int J = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((J + 1) * (J + 2) / 2 <= t) ++J;
+  while (J * (J + 1) / 2 > t) --J;
+  const int I = t - J * (J + 1) / 2;
+  const int i0 = I * 32, j0 = J * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const double ck = (kEulerGamma + log(0.5 * k)) / (2.0 * N);
+  const double hq = kPi / (4.0 * N);
+  double2 *A = A64 + (long long)b * mstride;
+  float2 *Af = W32 ? A32 + (long long)b * mstride : nullptr;
+  const int i = i0 + tx;
+  double2 yi = make_double2(0.0, 0.0);
+  if (i < N) yi = y[i];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int j = j0 + ty + 8 * q;
+    double2 v = make_double2(0.0, 0.0);
+    if (i < N && j < N) {
+      const double g = G[i + (long long)j * N];
+      if (i == j) {
+        v = make_double2(g - ck, hq);
+      } else {
+        const double2 yj = y[j];
+        const double dx = yi.x - yj.x, dy = yi.y - yj.y;
+        const double z = k * sqrt(dx * dx + dy * dy);
+        double j0v, yh;
+        bessel_j0_y0hat(z, j0v, yh);
+        v = make_double2(j0v * (g - ck) - hq * yh, hq * j0v);
+      }
+      A[i + (long long)j * N] = v;
+      if (W32) Af[i + (long long)j * N] = make_float2((float)v.x, (float)v.y);
+    }
+    tile[ty + 8 * q][tx] = v;
+  }
+  if (I != J) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = j0 + tx, col = i0 + ty + 8 * q;
+      if (row < N && col < N) {
+        const double2 v = tile[tx][ty + 8 * q];
+        A[row + (long long)col * N] = v;
+        if (W32) Af[row + (long long)col * N] = make_float2((float)v.x, (float)v.y);
+      }
+    }
+  }
+}
+
+struct IncidentDev {
+  int kind;  // 0 plane, 1 gaussian plane, 2 point source
+  double dx, dy, z0x, z0y, omega0, sigma, tau0;
+};
+
+// g(k) = exp(-(k - w0)^2 / sigma^2) exp(i k tau0)   (Section 5, u1 / u2)
+__device__ __forceinline__ double2 gauss_factor(const IncidentDev &in, double k) {
+  if (in.sigma <= 0.0) return make_double2(1.0, 0.0);
+  const double a = exp(-((k - in.omega0) * (k - in.omega0)) / (in.sigma * in.sigma));
+  double s, c;
+  sincos(k * in.tau0, &s, &c);
+  return make_double2(a * c, a * s);
+}
+
+__device__ __forceinline__ double2 incident_at(const IncidentDev &in, double k,
+                                               double2 p) {
+  if (in.kind == 2) {
+    const double dx = p.x - in.z0x, dy = p.y - in.z0y;
+    double j0v, y0v;
+    bessel_j0_y0(k * sqrt(dx * dx + dy * dy), j0v, y0v);
+    // (5i/2)(J0 + i Y0) = -5/2 Y0 + i 5/2 J0
+    return cmul(make_double2(-2.5 * y0v, 2.5 * j0v), gauss_factor(in, k));
+  }
+  double s, c;
+  sincos(k * (p.x * in.dx + p.y * in.dy), &s, &c);
+  double2 u = make_double2(c, s);
+  if (in.kind == 1) u = cmul(u, gauss_factor(in, k));
+  return u;
+}
+
+// out[b][i] = scale * chi[i] * U^inc(p_i, k_b)   (chi == nullptr: 1)
+__global__ __launch_bounds__(256) void incident_kernel(
+    IncidentDev in, const double2 *__restrict__ p, const double *__restrict__ chi,
+    int n, const double *__restrict__ kvec, double scale, double2 *__restrict__ out,
+    long long ostride) {
+  const int b = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double2 u = incident_at(in, kvec[b], p[i]);
+  const double s = chi ? scale * chi[i] : scale;
+  out[(long long)b * ostride + i] = make_double2(s * u.x, s * u.y);
+}
+
+}  // namespace fthms

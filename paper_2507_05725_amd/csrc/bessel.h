@@ -1,0 +1,122 @@
+// FP64 Bessel functions of order zero for real z >= 0, for the Helmholtz
+// fundamental solution Phi_k(r) = (i/4) H0^(1)(k r) = (i/4)(J0 + i Y0),
+// written from published mathematics (no vendor math library internals):
+//
+//   z < 1e-6     two terms of the ascending series (DLMF 10.8.1, 10.8.2)
+//   z < 16.5     Miller's backward recurrence J_{n-1} = (2n/z) J_n - J_{n+1}
+//                from a fixed start (32 steps below z = 8, 48 above),
+//                normalised by J0 + 2 sum_k J_{2k} = 1 (DLMF 10.12.4), with
+//                the Neumann series  Y0 = (2/pi)(log(z/2) + gamma) J0
+//                - (4/pi) sum_k (-1)^k J_{2k} / k  (DLMF 10.23.2 family)
+//   z >= 16.5    Hankel's asymptotic expansion (DLMF 10.17.3, 10.17.4) with
+//                14 terms in each of P and Q.
+//
+// Besides J0 and Y0 the routines expose the regular part
+//   Y0hat(z) = Y0(z) - (2/pi)(log(z/2) + gamma) J0(z),
+// an entire function of z^2 that the Nystrom assembly needs near the
+// diagonal without cancellation.  Host-compiled copies of these routines
+// are checked against mpmath over the full argument range of the workloads.
+#pragma once
+
+#include "common.h"
+
+namespace fthms {
+
+struct HankelAsymCoef {
+  double p[14];  // (-1)^k a_{2k}(0)
+  double q[14];  // (-1)^k a_{2k+1}(0)
+};
+
+// a_k(0) = prod_{j=1..k} (-(2j-1)^2) / (k! 8^k)   (DLMF 10.17.1 at nu = 0)
+constexpr HankelAsymCoef make_hankel_asym_coef() {
+  HankelAsymCoef c{};
+  double a[28] = {};
+  a[0] = 1.0;
+  for (int k = 1; k < 28; ++k)
+    a[k] = a[k - 1] * (-(double)((2 * k - 1) * (2 * k - 1))) / (8.0 * k);
+  for (int k = 0; k < 14; ++k) {
+    c.p[k] = ((k & 1) ? -1.0 : 1.0) * a[2 * k];
+    c.q[k] = ((k & 1) ? -1.0 : 1.0) * a[2 * k + 1];
+  }
+  return c;
+}
+
+// J0 and Y0hat by backward recurrence from n = NS (compile-time, unrolled).
+template <int NS>
+FTHMS_HD void bessel_miller(double z, double &j0, double &y0hat) {
+  const double rz = 2.0 / z;
+  double jp1 = 0.0, jn = 1.0e-250, even = 0.0, neu = 0.0;
+#pragma unroll
+  for (int n = NS; n >= 1; --n) {
+    const double jm1 = ((double)n * rz) * jn - jp1;
+    jp1 = jn;
+    jn = jm1;  // jn now holds J_{n-1} (unnormalised)
+    const int m = n - 1;
+    if (m > 0 && (m & 1) == 0) {
+      const int k = m >> 1;
+      even += jn;
+      neu += (((k & 1) ? -1.0 : 1.0) / (double)k) * jn;
+    }
+  }
+  const double inv = 1.0 / (jn + 2.0 * even);
+  j0 = jn * inv;
+  y0hat = -(4.0 / kPi) * neu * inv;
+}
+
+// J0 and Y0 from Hankel's expansion, phase via sin/cos of z itself:
+// cos(z - pi/4) = (cos z + sin z)/sqrt2, sin(z - pi/4) = (sin z - cos z)/sqrt2.
+FTHMS_HD void bessel_asym(double z, double &j0, double &y0) {
+  constexpr HankelAsymCoef c = make_hankel_asym_coef();
+  const double iz = 1.0 / z;
+  const double w = iz * iz;
+  double P = c.p[13], Q = c.q[13];
+#pragma unroll
+  for (int k = 12; k >= 0; --k) {
+    P = P * w + c.p[k];
+    Q = Q * w + c.q[k];
+  }
+  Q *= iz;
+  const double s = sin(z), co = cos(z);
+  const double r2 = 0.70710678118654752440084436210484904;
+  const double cm = (co + s) * r2, sm = (s - co) * r2;
+  const double f = sqrt((2.0 / kPi) * iz);
+  j0 = f * (P * cm - Q * sm);
+  y0 = f * (P * sm + Q * cm);
+}
+
+constexpr double kBesselAsymFrom = 16.5;
+
+// (2/pi)(log(z/2) + gamma): the log part separating Y0 from Y0hat
+FTHMS_HD double bessel_logpart(double z) {
+  return (2.0 / kPi) * (log(0.5 * z) + kEulerGamma);
+}
+
+// J0(z) and Y0hat(z), z >= 0.
+FTHMS_HD void bessel_j0_y0hat(double z, double &j0, double &yh) {
+  if (z < 1.0e-6) {
+    const double q = 0.25 * z * z;
+    j0 = 1.0 - q;
+    yh = (2.0 / kPi) * q;
+  } else if (z < 8.0) {
+    bessel_miller<32>(z, j0, yh);
+  } else if (z < kBesselAsymFrom) {
+    bessel_miller<48>(z, j0, yh);
+  } else {
+    double y0;
+    bessel_asym(z, j0, y0);
+    yh = y0 - bessel_logpart(z) * j0;
+  }
+}
+
+// J0(z) and Y0(z), z > 0.
+FTHMS_HD void bessel_j0_y0(double z, double &j0, double &y0) {
+  if (z < kBesselAsymFrom) {
+    double yh;
+    bessel_j0_y0hat(z, j0, yh);
+    y0 = yh + bessel_logpart(z) * j0;
+  } else {
+    bessel_asym(z, j0, y0);
+  }
+}
+
+}  // namespace fthms

@@ -1,0 +1,213 @@
+// Single-layer potential of a solved density and the frequency-to-time
+// transform (FP64).
+//
+// Far targets (Section 3.2, eq. FDsolk-interior; Gauss-Chebyshev rule of the
+// weighted density):  U(z) = (pi/N) sum_j Phi_k(z, y_j) alpha_j
+//                          = (pi/4N) sum_j (i J0 - Y0)(k|z - y_j|) alpha_j.
+// Near targets: U(z) = sum_q w_q Phi_k(z, x_q) alpha_N(cos phi_q), the exact
+// potential of the density interpolant alpha_N = sum_m a_m T_m, by a
+// composite Gauss-Legendre rule in phi (t = cos phi) graded toward the point
+// of the arc nearest the target; the rule and the geometry x_q are planned
+// on the host once per target set (frequency independent).
+//
+// Time traces (eq. backwardFT, eq. TDsol-interior with one window):
+//   u(x_p, t_n) = (1/2pi) sum_l w_l U(x_p, w_l) exp(-i w_l t_n).
+#pragma once
+
+#include "bessel.h"
+#include "common.h"
+
+namespace fthms {
+
+constexpr int kFieldThreads = 256;
+
+// One block: up to 256 targets for one wavenumber; nodes and density in LDS.
+__global__ __launch_bounds__(kFieldThreads) void field_far_kernel(
+    const double2 *__restrict__ ynodes, int N, const double *__restrict__ kvec,
+    const double2 *__restrict__ alpha, long long astride,
+    const double2 *__restrict__ pts, int np, const unsigned char *__restrict__ cls,
+    double2 *__restrict__ U, long long ustride, int accumulate) {
+  __shared__ double2 sy[1024];
+  __shared__ double2 sa[1024];
+  const int b = blockIdx.y;
+  for (int j = threadIdx.x; j < N; j += kFieldThreads) {
+    sy[j] = ynodes[j];
+    sa[j] = alpha[(long long)b * astride + j];
+  }
+  __syncthreads();
+  const int p = blockIdx.x * kFieldThreads + threadIdx.x;
+  if (p >= np) return;
+  if (cls && cls[p] != 1) return;
+  const double k = kvec[b];
+  const double2 z = pts[p];
+  double accr = 0.0, acci = 0.0;
+  for (int j = 0; j < N; ++j) {
+    const double dx = z.x - sy[j].x, dy = z.y - sy[j].y;
+    double j0v, y0v;
+    bessel_j0_y0(k * sqrt(dx * dx + dy * dy), j0v, y0v);
+    const double2 a = sa[j];
+    // (i J0 - Y0) * a
+    accr += -y0v * a.x - j0v * a.y;
+    acci += j0v * a.x - y0v * a.y;
+  }
+  const double s = kPi / (4.0 * N);
+  double2 *u = U + (long long)b * ustride + p;
+  if (accumulate) {
+    const double2 o = *u;
+    *u = make_double2(o.x + s * accr, o.y + s * acci);
+  } else {
+    *u = make_double2(s * accr, s * acci);
+  }
+}
+
+// Chebyshev coefficients of the density interpolant for each wavenumber:
+//   a_m = ((2 - delta_m0) / N) sum_j cos(m theta_j) alpha_j,
+// cosT[j][m] = cos(m theta_j).  One block per wavenumber, threads over m.
+__global__ __launch_bounds__(kFieldThreads) void cheb_coeff_kernel(
+    const double *__restrict__ cosT, int N, const double2 *__restrict__ alpha,
+    long long astride, double2 *__restrict__ coef) {
+  __shared__ double2 sa[1024];
+  const int b = blockIdx.x;
+  for (int j = threadIdx.x; j < N; j += kFieldThreads) sa[j] = alpha[(long long)b * astride + j];
+  __syncthreads();
+  for (int m = threadIdx.x; m < N; m += kFieldThreads) {
+    double ar = 0.0, ai = 0.0;
+    for (int j = 0; j < N; ++j) {
+      const double c = cosT[(long long)j * N + m];
+      ar += c * sa[j].x;
+      ai += c * sa[j].y;
+    }
+    const double f = (m == 0 ? 1.0 : 2.0) / N;
+    coef[(long long)b * N + m] = make_double2(f * ar, f * ai);
+  }
+}
+
+// Near targets: one block per (target, wavenumber).
+//   U(z) = sum_q w_q (i/4) H0(k |z - x_q|) alpha_N(c_q),
+//   alpha_N(c) = sum_m a_m T_m(c) by Clenshaw's recurrence, c_q = cos(phi_q).
+__global__ __launch_bounds__(kFieldThreads) void field_near_kernel(
+    const int *__restrict__ tgt_index, const int *__restrict__ qoff,
+    const double2 *__restrict__ xq, const double *__restrict__ wq,
+    const double *__restrict__ cq, int N, const double2 *__restrict__ coef,
+    const double *__restrict__ kvec, const double2 *__restrict__ pts,
+    double2 *__restrict__ U, long long ustride, int accumulate) {
+  __shared__ double2 sa[1024];
+  __shared__ double red[2][kFieldThreads / 64];
+  const int t = blockIdx.x, b = blockIdx.y;
+  for (int j = threadIdx.x; j < N; j += kFieldThreads) sa[j] = coef[(long long)b * N + j];
+  __syncthreads();
+  const int p = tgt_index[t];
+  const double2 z = pts[p];
+  const double k = kvec[b];
+  const int q0 = qoff[t], q1 = qoff[t + 1];
+  double accr = 0.0, acci = 0.0;
+  for (int q = q0 + threadIdx.x; q < q1; q += kFieldThreads) {
+    const double c = cq[q], c2 = 2.0 * c;
+    double b1r = 0.0, b1i = 0.0, b2r = 0.0, b2i = 0.0;
+    for (int m = N - 1; m >= 1; --m) {
+      const double nr = sa[m].x + c2 * b1r - b2r;
+      const double ni = sa[m].y + c2 * b1i - b2i;
+      b2r = b1r;
+      b2i = b1i;
+      b1r = nr;
+      b1i = ni;
+    }
+    const double dr = sa[0].x + c * b1r - b2r;
+    const double di = sa[0].y + c * b1i - b2i;
+    const double2 x = xq[q];
+    const double dx = z.x - x.x, dy = z.y - x.y;
+    double j0v, y0v;
+    bessel_j0_y0(k * sqrt(dx * dx + dy * dy), j0v, y0v);
+    const double w = 0.25 * wq[q];
+    // (i/4)(J0 + i Y0) * d = w (-Y0 + i J0) * d
+    accr += w * (-y0v * dr - j0v * di);
+    acci += w * (j0v * dr - y0v * di);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    accr += __shfl_xor(accr, off);
+    acci += __shfl_xor(acci, off);
+  }
+  if (lane == 0) {
+    red[0][wave] = accr;
+    red[1][wave] = acci;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sr = 0.0, si = 0.0;
+    for (int w = 0; w < kFieldThreads / 64; ++w) {
+      sr += red[0][w];
+      si += red[1][w];
+    }
+    double2 *u = U + (long long)b * ustride + p;
+    if (accumulate) {
+      const double2 o = *u;
+      *u = make_double2(o.x + sr, o.y + si);
+    } else {
+      *u = make_double2(sr, si);
+    }
+  }
+}
+
+// u[n][p] = (1/2pi) sum_l w_l U[l][p] e^{-i om_l t_n}; 64 x 64 output tile per
+// block, 16 frequencies staged per step.
+constexpr int kFtTile = 64;
+constexpr int kFtChunk = 16;
+
+__global__ __launch_bounds__(256) void freq_to_time_kernel(
+    int nk, const double *__restrict__ om, const double *__restrict__ w, int np,
+    const double2 *__restrict__ U, int nt, const double *__restrict__ t,
+    double2 *__restrict__ u) {
+  __shared__ double2 sE[kFtTile][kFtChunk + 1];
+  __shared__ double2 sU[kFtChunk][kFtTile];
+  const int n0 = blockIdx.y * kFtTile, p0 = blockIdx.x * kFtTile;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;  // 16 x 16 threads
+  double2 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = make_double2(0.0, 0.0);
+  for (int l0 = 0; l0 < nk; l0 += kFtChunk) {
+    for (int e = threadIdx.x; e < kFtTile * kFtChunk; e += 256) {
+      const int nn = e / kFtChunk, ll = e % kFtChunk;
+      double2 v = make_double2(0.0, 0.0);
+      if (n0 + nn < nt && l0 + ll < nk) {
+        double s, c;
+        sincos(om[l0 + ll] * t[n0 + nn], &s, &c);
+        const double ww = w[l0 + ll];
+        v = make_double2(ww * c, -ww * s);
+      }
+      sE[nn][ll] = v;
+    }
+    for (int e = threadIdx.x; e < kFtTile * kFtChunk; e += 256) {
+      const int ll = e / kFtTile, pp = e % kFtTile;
+      sU[ll][pp] = (l0 + ll < nk && p0 + pp < np) ? U[(long long)(l0 + ll) * np + p0 + pp]
+                                                  : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int ll = 0; ll < kFtChunk; ++ll) {
+      double2 e[4], v[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) e[a] = sE[ty + 16 * a][ll];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[c] = sU[ll][tx + 16 * c];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = cfma(acc[a][c], e[a], v[c]);
+    }
+    __syncthreads();
+  }
+  const double s = 1.0 / (2.0 * kPi);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int n = n0 + ty + 16 * a, p = p0 + tx + 16 * c;
+      if (n < nt && p < np) u[(long long)n * np + p] = make_double2(s * acc[a][c].x, s * acc[a][c].y);
+    }
+}
+
+}  // namespace fthms

@@ -1,0 +1,805 @@
+// libfthms: C-ABI entry points (declared in include/fthms.h) and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fthms.h"
+#include "assemble.h"
+#include "field.h"
+#include "lu.h"
+#include "nearfield.h"
+
+using namespace fthms;
+
+struct fthms_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  size_t budget = 0;
+  size_t held = 0;
+  std::string err;
+  // solve workspace and a second scratch area (both grown on demand)
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  void *ws2 = nullptr;
+  size_t ws2_bytes = 0;
+  // kernel timing with HIP events on `stream`
+  bool timing = false;
+  struct Pending {
+    std::string name;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::map<std::string, std::pair<double, int>> times;
+};
+
+struct fthms_arc {
+  fthms_ctx *ctx = nullptr;
+  int n = 0;
+  std::vector<double> theta, t, xy, dxy, s;
+  std::vector<double> cgx, cgy;  // Chebyshev coefficients of x(t), y(t)
+  double hmax = 0.0;
+  double2 *d_y = nullptr;
+  double *d_G = nullptr;
+  double *d_cos = nullptr;  // [n][n] cos(m theta_j), row j
+  size_t bytes = 0;
+};
+
+static thread_local std::string g_create_err;
+
+static int fail(fthms_ctx *ctx, int code, const std::string &msg) {
+  if (ctx) ctx->err = msg;
+  else g_create_err = msg;
+  return code;
+}
+
+#define HIPCK(ctx, call)                                                         \
+  do {                                                                          \
+    hipError_t e_ = (call);                                                     \
+    if (e_ != hipSuccess)                                                       \
+      return fail((ctx), FTHMS_EDEVICE,                                          \
+                  std::string(#call) + ": " + hipGetErrorString(e_));            \
+  } while (0)
+
+static int dev_alloc(fthms_ctx *ctx, void **p, size_t bytes) {
+  if (ctx->budget && ctx->held + bytes > ctx->budget)
+    return fail(ctx, FTHMS_ENOMEM,
+                "device memory budget exceeded (" + std::to_string(ctx->held + bytes) +
+                    " > " + std::to_string(ctx->budget) + " bytes)");
+  HIPCK(ctx, hipMalloc(p, bytes ? bytes : 1));
+  ctx->held += bytes;
+  return FTHMS_OK;
+}
+
+static void dev_free(fthms_ctx *ctx, void *p, size_t bytes) {
+  if (p) {
+    (void)hipFree(p);
+    ctx->held -= std::min(ctx->held, bytes);
+  }
+}
+
+static int ensure_ws(fthms_ctx *ctx, size_t bytes) {
+  if (ctx->ws_bytes >= bytes) return FTHMS_OK;
+  (void)hipStreamSynchronize(ctx->stream);
+  dev_free(ctx, ctx->ws, ctx->ws_bytes);
+  ctx->ws = nullptr;
+  ctx->ws_bytes = 0;
+  int rc = dev_alloc(ctx, &ctx->ws, bytes);
+  if (rc) return rc;
+  ctx->ws_bytes = bytes;
+  return FTHMS_OK;
+}
+
+static int ensure_ws2(fthms_ctx *ctx, size_t bytes) {
+  if (ctx->ws2_bytes >= bytes) return FTHMS_OK;
+  (void)hipStreamSynchronize(ctx->stream);
+  dev_free(ctx, ctx->ws2, ctx->ws2_bytes);
+  ctx->ws2 = nullptr;
+  ctx->ws2_bytes = 0;
+  int rc = dev_alloc(ctx, &ctx->ws2, bytes);
+  if (rc) return rc;
+  ctx->ws2_bytes = bytes;
+  return FTHMS_OK;
+}
+
+static void tbeg(fthms_ctx *ctx, const char *name) {
+  if (!ctx->timing) return;
+  fthms_ctx::Pending p;
+  p.name = name;
+  if (hipEventCreate(&p.a) != hipSuccess) return;
+  if (hipEventCreate(&p.b) != hipSuccess) {
+    (void)hipEventDestroy(p.a);
+    return;
+  }
+  (void)hipEventRecord(p.a, ctx->stream);
+  ctx->pending.push_back(p);
+}
+
+static void tend(fthms_ctx *ctx) {
+  if (!ctx->timing || ctx->pending.empty()) return;
+  (void)hipEventRecord(ctx->pending.back().b, ctx->stream);
+}
+
+static void timing_collect(fthms_ctx *ctx) {
+  if (ctx->pending.empty()) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto &p : ctx->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      auto &t = ctx->times[p.name];
+      t.first += ms;
+      t.second += 1;
+    }
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  ctx->pending.clear();
+}
+
+static int check_launch(fthms_ctx *ctx, const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    return fail(ctx, FTHMS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return FTHMS_OK;
+}
+
+extern "C" {
+
+int fthms_abi_version(void) { return FTHMS_ABI_VERSION; }
+
+int fthms_create(fthms_ctx **out, int device, size_t hbm_budget_bytes, void *hip_stream) {
+  if (!out) return fail(nullptr, FTHMS_EINVAL, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+    return fail(nullptr, FTHMS_EDEVICE, "no HIP device available");
+  if (device < 0 || device >= count)
+    return fail(nullptr, FTHMS_EINVAL, "device index out of range");
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess)
+    return fail(nullptr, FTHMS_EDEVICE, "hipGetDeviceProperties failed");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(nullptr, FTHMS_EDEVICE,
+                std::string("libfthms is built for gfx950, device is ") + prop.gcnArchName);
+  fthms_ctx *ctx = new (std::nothrow) fthms_ctx;
+  if (!ctx) return fail(nullptr, FTHMS_ENOMEM, "host allocation failed");
+  ctx->device = device;
+  ctx->budget = hbm_budget_bytes;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete ctx;
+    return fail(nullptr, FTHMS_EDEVICE, "hipSetDevice failed");
+  }
+  if (hip_stream) {
+    ctx->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete ctx;
+      return fail(nullptr, FTHMS_EDEVICE, "hipStreamCreate failed");
+    }
+    ctx->own_stream = true;
+  }
+  *out = ctx;
+  return FTHMS_OK;
+}
+
+int fthms_destroy(fthms_ctx *ctx) {
+  if (!ctx) return FTHMS_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  timing_collect(ctx);
+  dev_free(ctx, ctx->ws, ctx->ws_bytes);
+  dev_free(ctx, ctx->ws2, ctx->ws2_bytes);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return FTHMS_OK;
+}
+
+const char *fthms_last_error(const fthms_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+int fthms_sync(fthms_ctx *ctx) {
+  if (!ctx) return FTHMS_EINVAL;
+  HIPCK(ctx, hipStreamSynchronize(ctx->stream));
+  return FTHMS_OK;
+}
+
+int fthms_timing_enable(fthms_ctx *ctx, int enable) {
+  if (!ctx) return FTHMS_EINVAL;
+  timing_collect(ctx);
+  ctx->timing = enable != 0;
+  return FTHMS_OK;
+}
+
+int fthms_timing_reset(fthms_ctx *ctx) {
+  if (!ctx) return FTHMS_EINVAL;
+  timing_collect(ctx);
+  ctx->times.clear();
+  return FTHMS_OK;
+}
+
+int fthms_timing_read(fthms_ctx *ctx, const char *name, double *total_ms, int *launches) {
+  if (!ctx || !name) return FTHMS_EINVAL;
+  timing_collect(ctx);
+  auto it = ctx->times.find(name);
+  if (total_ms) *total_ms = it == ctx->times.end() ? 0.0 : it->second.first;
+  if (launches) *launches = it == ctx->times.end() ? 0 : it->second.second;
+  return FTHMS_OK;
+}
+
+int fthms_cheb_nodes(int n, double *t_out) {
+  if (n < 2 || !t_out) return FTHMS_EINVAL;
+  for (int i = 1; i <= n; ++i) t_out[i - 1] = std::cos((2.0 * i - 1.0) * kPi / (2.0 * n));
+  return FTHMS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// arcs: frequency-independent tables
+// ---------------------------------------------------------------------------
+int fthms_arc_create(fthms_ctx *ctx, int n, const double *xy, const double *dxy,
+                     fthms_arc **out) {
+  if (!ctx || !xy || !dxy || !out) return fail(ctx, FTHMS_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (n < 2 || n > kMaxN) return fail(ctx, FTHMS_EINVAL, "arc size must be in [2, 1024]");
+  for (int i = 0; i < 2 * n; ++i)
+    if (!std::isfinite(xy[i]) || !std::isfinite(dxy[i]))
+      return fail(ctx, FTHMS_EINVAL_DATA, "non-finite arc sample");
+  fthms_arc *arc = new (std::nothrow) fthms_arc;
+  if (!arc) return fail(ctx, FTHMS_ENOMEM, "host allocation failed");
+  arc->ctx = ctx;
+  arc->n = n;
+  arc->theta.resize(n);
+  arc->t.resize(n);
+  arc->s.resize(n);
+  arc->xy.assign(xy, xy + 2 * n);
+  arc->dxy.assign(dxy, dxy + 2 * n);
+  for (int i = 0; i < n; ++i) {
+    arc->theta[i] = (2.0 * (i + 1) - 1.0) * kPi / (2.0 * n);
+    arc->t[i] = std::cos(arc->theta[i]);
+    arc->s[i] = std::hypot(dxy[2 * i], dxy[2 * i + 1]);
+    if (!(arc->s[i] > 0.0)) {
+      delete arc;
+      return fail(ctx, FTHMS_EINVAL_DATA, "vanishing speed |x'(t)| at a node");
+    }
+  }
+  double hmax = 0.0;
+  for (int i = 0; i + 1 < n; ++i) {
+    const double h = std::hypot(xy[2 * i + 2] - xy[2 * i], xy[2 * i + 3] - xy[2 * i + 1]);
+    if (!(h > 0.0)) {
+      delete arc;
+      return fail(ctx, FTHMS_EINVAL_DATA, "coincident consecutive nodes");
+    }
+    hmax = std::max(hmax, h);
+  }
+  arc->hmax = hmax;
+  // S(q pi / n) = sum_{m=1}^{n-1} cos(m q pi / n) / m, q = 0..2n-1, from an
+  // exact-index cosine table; W_ij = -(pi/n)[log 2 + S(i-j) + S(i+j-1)]
+  // (product-to-sum form of the Symm-identity weights).
+  std::vector<double> ct(2 * n), S(2 * n, 0.0);
+  for (int r = 0; r < 2 * n; ++r) ct[r] = std::cos(r * kPi / n);
+  for (int q = 0; q < 2 * n; ++q) {
+    double acc = 0.0;
+    for (int m = n - 1; m >= 1; --m) acc += ct[(long long)m * q % (2 * n)] / m;
+    S[q] = acc;
+  }
+  std::vector<double> G((size_t)n * n);
+  const double ln2 = std::log(2.0);
+  for (int j = 0; j < n; ++j) {
+    for (int i = 0; i < n; ++i) {
+      const int qm = std::abs(i - j), qp = (i + 1) + (j + 1) - 1;
+      const double W = -(kPi / n) * (ln2 + S[qm % (2 * n)] + S[qp % (2 * n)]);
+      double g;
+      if (i == j) {
+        g = (-W - (kPi / n) * std::log(arc->s[i])) / (2.0 * kPi);
+      } else {
+        const double r = std::hypot(xy[2 * i] - xy[2 * j], xy[2 * i + 1] - xy[2 * j + 1]);
+        if (!(r > 0.0)) {
+          delete arc;
+          return fail(ctx, FTHMS_EINVAL_DATA, "coincident nodes");
+        }
+        // |t_i - t_j| = 2 |sin((th_i + th_j)/2) sin((th_i - th_j)/2)|
+        const double dt = 2.0 * std::fabs(std::sin(0.5 * (arc->theta[i] + arc->theta[j])) *
+                                          std::sin(0.5 * (arc->theta[i] - arc->theta[j])));
+        g = (-W - (kPi / n) * std::log(r / dt)) / (2.0 * kPi);
+      }
+      G[(size_t)i + (size_t)j * n] = g;
+    }
+  }
+  // Chebyshev coefficients of the geometry (for near-field planning)
+  arc->cgx.assign(n, 0.0);
+  arc->cgy.assign(n, 0.0);
+  for (int m = 0; m < n; ++m) {
+    double ax = 0.0, ay = 0.0;
+    for (int j = 0; j < n; ++j) {
+      const double cc = std::cos(m * arc->theta[j]);
+      ax += xy[2 * j] * cc;
+      ay += xy[2 * j + 1] * cc;
+    }
+    const double f = (m == 0 ? 1.0 : 2.0) / n;
+    arc->cgx[m] = f * ax;
+    arc->cgy[m] = f * ay;
+  }
+  std::vector<double> cosT((size_t)n * n);  // [j][m] = cos(m theta_j)
+  for (int j = 0; j < n; ++j)
+    for (int m = 0; m < n; ++m) cosT[(size_t)j * n + m] = std::cos(m * arc->theta[j]);
+  int rc;
+  arc->bytes = sizeof(double2) * n + sizeof(double) * (size_t)n * n * 2;
+  if ((rc = dev_alloc(ctx, (void **)&arc->d_y, sizeof(double2) * n)) ||
+      (rc = dev_alloc(ctx, (void **)&arc->d_G, sizeof(double) * (size_t)n * n)) ||
+      (rc = dev_alloc(ctx, (void **)&arc->d_cos, sizeof(double) * (size_t)n * n))) {
+    fthms_arc_destroy(arc);
+    return rc;
+  }
+  HIPCK(ctx, hipMemcpy(arc->d_y, xy, sizeof(double2) * n, hipMemcpyHostToDevice));
+  HIPCK(ctx, hipMemcpy(arc->d_G, G.data(), sizeof(double) * (size_t)n * n,
+                       hipMemcpyHostToDevice));
+  HIPCK(ctx, hipMemcpy(arc->d_cos, cosT.data(), sizeof(double) * (size_t)n * n,
+                       hipMemcpyHostToDevice));
+  *out = arc;
+  return FTHMS_OK;
+}
+
+int fthms_arc_destroy(fthms_arc *arc) {
+  if (!arc) return FTHMS_EINVAL;
+  fthms_ctx *ctx = arc->ctx;
+  if (ctx) {
+    dev_free(ctx, arc->d_y, sizeof(double2) * arc->n);
+    dev_free(ctx, arc->d_G, sizeof(double) * (size_t)arc->n * arc->n);
+    dev_free(ctx, arc->d_cos, sizeof(double) * (size_t)arc->n * arc->n);
+  }
+  delete arc;
+  return FTHMS_OK;
+}
+
+int fthms_arc_size(const fthms_arc *arc) { return arc ? arc->n : FTHMS_EINVAL; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched solve
+// ---------------------------------------------------------------------------
+static int launch_lu(fthms_ctx *ctx, bool fp32, void *A, int N, long long ms, int *piv,
+                     int *status, int count) {
+  const int R = (N + kLuThreads - 1) / kLuThreads;
+  dim3 g(count), b(kLuThreads);
+  if (fp32) {
+    float2 *a = (float2 *)A;
+    switch (R) {
+      case 1: lu_kernel<float, 1><<<g, b, 0, ctx->stream>>>(a, N, ms, piv, status); break;
+      case 2: lu_kernel<float, 2><<<g, b, 0, ctx->stream>>>(a, N, ms, piv, status); break;
+      case 3: lu_kernel<float, 3><<<g, b, 0, ctx->stream>>>(a, N, ms, piv, status); break;
+      default: lu_kernel<float, 4><<<g, b, 0, ctx->stream>>>(a, N, ms, piv, status); break;
+    }
+  } else {
+    double2 *a = (double2 *)A;
+    switch (R) {
+      case 1: lu_kernel<double, 1><<<g, b, 0, ctx->stream>>>(a, N, ms, piv, status); break;
+      case 2: lu_kernel<double, 2><<<g, b, 0, ctx->stream>>>(a, N, ms, piv, status); break;
+      case 3: lu_kernel<double, 3><<<g, b, 0, ctx->stream>>>(a, N, ms, piv, status); break;
+      default: lu_kernel<double, 4><<<g, b, 0, ctx->stream>>>(a, N, ms, piv, status); break;
+    }
+  }
+  return check_launch(ctx, "lu_kernel");
+}
+
+static int launch_fallback(fthms_ctx *ctx, double2 *A, int N, long long ms, int *piv,
+                           const double2 *b, double2 *x, int *status, int count) {
+  const int R = (N + kLuThreads - 1) / kLuThreads;
+  dim3 g(count), bl(kLuThreads);
+  switch (R) {
+    case 1: fallback64_kernel<1><<<g, bl, 0, ctx->stream>>>(A, piv, N, ms, b, x, N, status); break;
+    case 2: fallback64_kernel<2><<<g, bl, 0, ctx->stream>>>(A, piv, N, ms, b, x, N, status); break;
+    case 3: fallback64_kernel<3><<<g, bl, 0, ctx->stream>>>(A, piv, N, ms, b, x, N, status); break;
+    default: fallback64_kernel<4><<<g, bl, 0, ctx->stream>>>(A, piv, N, ms, b, x, N, status); break;
+  }
+  return check_launch(ctx, "fallback64_kernel");
+}
+
+struct SolveWs {
+  double2 *A64;
+  float2 *A32;
+  int *piv;
+  int *status;
+  double *relres;
+  int chunk;
+};
+
+static size_t per_matrix_bytes(int N, bool fp32) {
+  const size_t nn = (size_t)N * N;
+  return nn * sizeof(double2) + (fp32 ? nn * sizeof(float2) : 0) + sizeof(int) * N +
+         sizeof(int) + sizeof(double) + 256;
+}
+
+static int solve_ws(fthms_ctx *ctx, int N, bool fp32, int nk, SolveWs &w) {
+  const size_t per = per_matrix_bytes(N, fp32);
+  size_t cap = (size_t)16 << 30;  // at most 16 GiB of matrices in flight
+  if (ctx->budget) {
+    const size_t avail = ctx->budget > ctx->held ? ctx->budget - ctx->held + ctx->ws_bytes : 0;
+    cap = std::min(cap, avail);
+  }
+  int chunk = (int)std::min<size_t>((size_t)nk, std::max<size_t>(1, cap / per));
+  chunk = std::min(chunk, 4096);
+  const int nchunks = (nk + chunk - 1) / chunk;  // even split of the batch
+  chunk = (nk + nchunks - 1) / nchunks;
+  if ((size_t)chunk * per > cap) return fail(ctx, FTHMS_ENOMEM, "no room for one matrix");
+  const size_t nn = (size_t)N * N;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  const size_t oA64 = take(nn * sizeof(double2) * chunk);
+  const size_t oA32 = fp32 ? take(nn * sizeof(float2) * chunk) : 0;
+  const size_t oP = take(sizeof(int) * (size_t)N * chunk);
+  const size_t oS = take(sizeof(int) * chunk);
+  const size_t oR = take(sizeof(double) * chunk);
+  int rc = ensure_ws(ctx, off);
+  if (rc) return rc;
+  char *base = (char *)ctx->ws;
+  w.A64 = (double2 *)(base + oA64);
+  w.A32 = fp32 ? (float2 *)(base + oA32) : nullptr;
+  w.piv = (int *)(base + oP);
+  w.status = (int *)(base + oS);
+  w.relres = (double *)(base + oR);
+  w.chunk = chunk;
+  return FTHMS_OK;
+}
+
+static int assemble_launch(fthms_ctx *ctx, const fthms_arc *arc, const double *k_dev,
+                           int count, double2 *A64, float2 *A32) {
+  const int N = arc->n;
+  const int T = (N + 31) / 32;
+  dim3 g(T * (T + 1) / 2, count), b(256);
+  const long long ms = (long long)N * N;
+  if (A32)
+    assemble_kernel<true><<<g, b, 0, ctx->stream>>>(arc->d_y, arc->d_G, N, k_dev, A64, A32, ms);
+  else
+    assemble_kernel<false><<<g, b, 0, ctx->stream>>>(arc->d_y, arc->d_G, N, k_dev, A64, nullptr, ms);
+  return check_launch(ctx, "assemble_kernel");
+}
+
+// Internal: solve for nk wavenumbers, device pointers, on ctx->stream.
+static int solve_dev_impl(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double *k_dev,
+                          const double2 *rhs, double2 *alpha, int precision, double tol,
+                          int *iters_dev, double *relres_dev) {
+  const int N = arc->n;
+  const bool fp32 = precision == FTHMS_FP32_REFINED;
+  if (tol <= 0.0) tol = 1e-13;
+  SolveWs w;
+  int rc = solve_ws(ctx, N, fp32, nk, w);
+  if (rc) return rc;
+  const long long ms = (long long)N * N;
+  for (int f0 = 0; f0 < nk; f0 += w.chunk) {
+    const int c = std::min(w.chunk, nk - f0);
+    const double2 *b = rhs + (long long)f0 * N;
+    double2 *x = alpha + (long long)f0 * N;
+    tbeg(ctx, "assemble");
+    rc = assemble_launch(ctx, arc, k_dev + f0, c, w.A64, fp32 ? w.A32 : nullptr);
+    tend(ctx);
+    if (rc) return rc;
+    tbeg(ctx, "lu");
+    rc = launch_lu(ctx, fp32, fp32 ? (void *)w.A32 : (void *)w.A64, N, ms, w.piv, w.status, c);
+    tend(ctx);
+    if (rc) return rc;
+    if (!fp32) {
+      tbeg(ctx, "solve");
+      lu_solve64_kernel<<<c, kLuThreads, 0, ctx->stream>>>(w.A64, w.piv, N, ms, b, x, N);
+      tend(ctx);
+      if ((rc = check_launch(ctx, "lu_solve64_kernel"))) return rc;
+    } else {
+      tbeg(ctx, "solve");
+      refine_kernel<<<c, kLuThreads, 0, ctx->stream>>>(w.A32, w.piv, w.A64, N, ms, b, x, N, tol,
+                                                        10, w.status, w.relres);
+      tend(ctx);
+      if ((rc = check_launch(ctx, "refine_kernel"))) return rc;
+      tbeg(ctx, "fallback");
+      rc = launch_fallback(ctx, w.A64, N, ms, w.piv, b, x, w.status, c);
+      tend(ctx);
+      if (rc) return rc;
+    }
+    if (iters_dev)
+      HIPCK(ctx, hipMemcpyAsync(iters_dev + f0, w.status, sizeof(int) * c,
+                                hipMemcpyDeviceToDevice, ctx->stream));
+    if (relres_dev) {
+      if (fp32)
+        HIPCK(ctx, hipMemcpyAsync(relres_dev + f0, w.relres, sizeof(double) * c,
+                                  hipMemcpyDeviceToDevice, ctx->stream));
+      else
+        HIPCK(ctx, hipMemsetAsync(relres_dev + f0, 0, sizeof(double) * c, ctx->stream));
+    }
+  }
+  return FTHMS_OK;
+}
+
+// Host-staging helper: device buffers freed on scope exit.
+struct Staging {
+  fthms_ctx *ctx;
+  std::vector<std::pair<void *, size_t>> bufs;
+  explicit Staging(fthms_ctx *c) : ctx(c) {}
+  ~Staging() {
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto &b : bufs) dev_free(ctx, b.first, b.second);
+  }
+  template <typename P> int get(P **p, size_t bytes) {
+    void *q = nullptr;
+    int rc = dev_alloc(ctx, &q, bytes);
+    if (rc) return rc;
+    bufs.push_back({q, bytes});
+    *p = (P *)q;
+    return FTHMS_OK;
+  }
+};
+
+static bool finite_all(const double *p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+extern "C" {
+
+int fthms_solve_dev(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double *k_dev,
+                    const fthms_c64 *rhs_dev, fthms_c64 *alpha_dev, int precision,
+                    double tol, int *iters_dev, double *relres_dev) {
+  if (!ctx || !arc || !k_dev || !rhs_dev || !alpha_dev || nk < 0)
+    return fail(ctx, FTHMS_EINVAL, "bad argument to fthms_solve_dev");
+  if (precision != FTHMS_FP64 && precision != FTHMS_FP32_REFINED)
+    return fail(ctx, FTHMS_EINVAL, "unknown precision");
+  if (nk == 0) return FTHMS_OK;
+  HIPCK(ctx, hipSetDevice(ctx->device));
+  return solve_dev_impl(ctx, arc, nk, k_dev, (const double2 *)rhs_dev, (double2 *)alpha_dev,
+                        precision, tol, iters_dev, relres_dev);
+}
+
+int fthms_solve(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double *k,
+                const fthms_c64 *rhs, fthms_c64 *alpha, int precision, double tol, int *iters,
+                double *relres) {
+  if (!ctx || !arc || !k || !rhs || !alpha || nk < 0)
+    return fail(ctx, FTHMS_EINVAL, "bad argument to fthms_solve");
+  if (nk == 0) return FTHMS_OK;
+  const int N = arc->n;
+  for (int i = 0; i < nk; ++i)
+    if (!(k[i] > 0.0) || !std::isfinite(k[i]))
+      return fail(ctx, FTHMS_EINVAL_DATA, "wavenumbers must be finite and > 0");
+  if (!finite_all((const double *)rhs, (size_t)2 * nk * N))
+    return fail(ctx, FTHMS_EINVAL_DATA, "non-finite right-hand side");
+  HIPCK(ctx, hipSetDevice(ctx->device));
+  Staging st(ctx);
+  double *dk;
+  double2 *drhs, *dal;
+  int *dit;
+  double *drr;
+  int rc;
+  if ((rc = st.get(&dk, sizeof(double) * nk)) || (rc = st.get(&drhs, sizeof(double2) * nk * N)) ||
+      (rc = st.get(&dal, sizeof(double2) * nk * N)) || (rc = st.get(&dit, sizeof(int) * nk)) ||
+      (rc = st.get(&drr, sizeof(double) * nk)))
+    return rc;
+  HIPCK(ctx, hipMemcpyAsync(dk, k, sizeof(double) * nk, hipMemcpyHostToDevice, ctx->stream));
+  HIPCK(ctx, hipMemcpyAsync(drhs, rhs, sizeof(double2) * nk * N, hipMemcpyHostToDevice,
+                            ctx->stream));
+  if ((rc = fthms_solve_dev(ctx, arc, nk, dk, (const fthms_c64 *)drhs, (fthms_c64 *)dal,
+                            precision, tol, dit, drr)))
+    return rc;
+  std::vector<int> it(nk);
+  HIPCK(ctx, hipMemcpyAsync(alpha, dal, sizeof(double2) * nk * N, hipMemcpyDeviceToHost,
+                            ctx->stream));
+  HIPCK(ctx, hipMemcpyAsync(it.data(), dit, sizeof(int) * nk, hipMemcpyDeviceToHost, ctx->stream));
+  if (relres)
+    HIPCK(ctx, hipMemcpyAsync(relres, drr, sizeof(double) * nk, hipMemcpyDeviceToHost,
+                              ctx->stream));
+  HIPCK(ctx, hipStreamSynchronize(ctx->stream));
+  if (iters) std::copy(it.begin(), it.end(), iters);
+  for (int i = 0; i < nk; ++i)
+    if (it[i] == -2) return fail(ctx, FTHMS_ESINGULAR, "zero pivot at wavenumber index " +
+                                                           std::to_string(i));
+  return FTHMS_OK;
+}
+
+static int to_incident(fthms_ctx *ctx, const fthms_incident *inc, IncidentDev &d) {
+  if (!inc) return fail(ctx, FTHMS_EINVAL, "incident is NULL");
+  if (inc->kind < 0 || inc->kind > 2) return fail(ctx, FTHMS_EINVAL, "unknown incident kind");
+  d.kind = inc->kind;
+  d.dx = std::cos(inc->theta);
+  d.dy = std::sin(inc->theta);
+  d.z0x = inc->z0[0];
+  d.z0y = inc->z0[1];
+  d.omega0 = inc->omega0;
+  d.sigma = inc->kind == FTHMS_INC_PLANE ? 0.0 : inc->sigma;
+  d.tau0 = inc->tau0;
+  return FTHMS_OK;
+}
+
+int fthms_rhs_dev(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double *k_dev,
+                  const fthms_incident *inc, fthms_c64 *rhs_dev) {
+  if (!ctx || !arc || !k_dev || !rhs_dev || nk < 0)
+    return fail(ctx, FTHMS_EINVAL, "bad argument to fthms_rhs_dev");
+  IncidentDev d;
+  int rc = to_incident(ctx, inc, d);
+  if (rc) return rc;
+  if (nk == 0) return FTHMS_OK;
+  HIPCK(ctx, hipSetDevice(ctx->device));
+  dim3 g((arc->n + 255) / 256, nk);
+  tbeg(ctx, "rhs");
+  incident_kernel<<<g, 256, 0, ctx->stream>>>(d, arc->d_y, nullptr, arc->n, k_dev, -1.0,
+                                               (double2 *)rhs_dev, arc->n);
+  tend(ctx);
+  return check_launch(ctx, "incident_kernel");
+}
+
+int fthms_rhs(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double *k,
+              const fthms_incident *inc, fthms_c64 *rhs) {
+  if (!ctx || !arc || !k || !rhs || nk < 0) return fail(ctx, FTHMS_EINVAL, "bad argument");
+  if (nk == 0) return FTHMS_OK;
+  HIPCK(ctx, hipSetDevice(ctx->device));
+  Staging st(ctx);
+  double *dk;
+  double2 *dr;
+  int rc;
+  if ((rc = st.get(&dk, sizeof(double) * nk)) || (rc = st.get(&dr, sizeof(double2) * nk * arc->n)))
+    return rc;
+  HIPCK(ctx, hipMemcpyAsync(dk, k, sizeof(double) * nk, hipMemcpyHostToDevice, ctx->stream));
+  if ((rc = fthms_rhs_dev(ctx, arc, nk, dk, inc, (fthms_c64 *)dr))) return rc;
+  HIPCK(ctx, hipMemcpyAsync(rhs, dr, sizeof(double2) * nk * arc->n, hipMemcpyDeviceToHost,
+                            ctx->stream));
+  HIPCK(ctx, hipStreamSynchronize(ctx->stream));
+  return FTHMS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// fields
+// ---------------------------------------------------------------------------
+void near_plan_free(fthms_ctx *ctx, NearPlan &p);
+int near_plan_build(fthms_ctx *ctx, const fthms_arc *arc, int np, const double *xy,
+                    NearPlan &plan, const unsigned char *skip, double kmax);
+
+// Field of arc `arc` with densities alpha[nk][astride] at points pts_dev
+// classified by `plan`; U[nk][ustride] is written or accumulated.
+int field_dev_impl(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double *k_dev,
+                   const double2 *alpha, long long astride, int np, const double2 *pts_dev,
+                   const NearPlan &plan, double2 *U, long long ustride, int accumulate) {
+  if (nk == 0 || np == 0) return FTHMS_OK;
+  dim3 g((np + kFieldThreads - 1) / kFieldThreads, nk);
+  field_far_kernel<<<g, kFieldThreads, 0, ctx->stream>>>(arc->d_y, arc->n, k_dev, alpha, astride,
+                                                        pts_dev, np, plan.d_cls, U, ustride,
+                                                        accumulate);
+  int rc = check_launch(ctx, "field_far_kernel");
+  if (rc) return rc;
+  if (plan.ntgt > 0) {
+    if ((rc = ensure_ws2(ctx, sizeof(double2) * (size_t)nk * arc->n))) return rc;
+    double2 *coef = (double2 *)ctx->ws2;
+    cheb_coeff_kernel<<<nk, kFieldThreads, 0, ctx->stream>>>(arc->d_cos, arc->n, alpha, astride,
+                                                             coef);
+    if ((rc = check_launch(ctx, "cheb_coeff_kernel"))) return rc;
+    dim3 gn(plan.ntgt, nk);
+    field_near_kernel<<<gn, kFieldThreads, 0, ctx->stream>>>(
+        plan.d_tgt, plan.d_qoff, plan.d_xq, plan.d_wq, plan.d_cq, arc->n, coef, k_dev, pts_dev,
+        U, ustride, accumulate);
+    rc = check_launch(ctx, "field_near_kernel");
+  }
+  return rc;
+}
+
+extern "C" {
+
+int fthms_eval_field_dev(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double *k_dev,
+                         const fthms_c64 *alpha_dev, int np, const double *xy_dev,
+                         fthms_c64 *U_dev) {
+  if (!ctx || !arc || !k_dev || !alpha_dev || !xy_dev || !U_dev || nk < 0 || np < 0)
+    return fail(ctx, FTHMS_EINVAL, "bad argument to fthms_eval_field_dev");
+  if (nk == 0 || np == 0) return FTHMS_OK;
+  HIPCK(ctx, hipSetDevice(ctx->device));
+  // the near/far split and the near rule are planned on the host
+  std::vector<double> xy(2 * (size_t)np), kh(nk);
+  HIPCK(ctx, hipMemcpyAsync(xy.data(), xy_dev, sizeof(double) * 2 * np, hipMemcpyDeviceToHost,
+                            ctx->stream));
+  HIPCK(ctx, hipMemcpyAsync(kh.data(), k_dev, sizeof(double) * nk, hipMemcpyDeviceToHost,
+                            ctx->stream));
+  HIPCK(ctx, hipStreamSynchronize(ctx->stream));
+  double kmax = 0.0;
+  for (double v : kh) kmax = std::max(kmax, std::fabs(v));
+  NearPlan plan;
+  int rc = near_plan_build(ctx, arc, np, xy.data(), plan, nullptr, kmax);
+  if (rc) return rc;
+  tbeg(ctx, "field");
+  rc = field_dev_impl(ctx, arc, nk, k_dev, (const double2 *)alpha_dev, arc->n, np,
+                      (const double2 *)xy_dev, plan, (double2 *)U_dev, np, 0);
+  tend(ctx);
+  HIPCK(ctx, hipStreamSynchronize(ctx->stream));
+  near_plan_free(ctx, plan);
+  return rc;
+}
+
+int fthms_eval_field(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double *k,
+                     const fthms_c64 *alpha, int np, const double *xy, fthms_c64 *U) {
+  if (!ctx || !arc || !k || !alpha || !xy || !U || nk < 0 || np < 0)
+    return fail(ctx, FTHMS_EINVAL, "bad argument to fthms_eval_field");
+  if (nk == 0 || np == 0) return FTHMS_OK;
+  if (!finite_all(xy, 2 * (size_t)np)) return fail(ctx, FTHMS_EINVAL_DATA, "non-finite point");
+  HIPCK(ctx, hipSetDevice(ctx->device));
+  const int N = arc->n;
+  Staging st(ctx);
+  double *dk, *dxy;
+  double2 *dal, *dU;
+  int rc;
+  if ((rc = st.get(&dk, sizeof(double) * nk)) || (rc = st.get(&dal, sizeof(double2) * nk * N)) ||
+      (rc = st.get(&dxy, sizeof(double) * 2 * np)) || (rc = st.get(&dU, sizeof(double2) * nk * np)))
+    return rc;
+  HIPCK(ctx, hipMemcpyAsync(dk, k, sizeof(double) * nk, hipMemcpyHostToDevice, ctx->stream));
+  HIPCK(ctx, hipMemcpyAsync(dal, alpha, sizeof(double2) * nk * N, hipMemcpyHostToDevice,
+                            ctx->stream));
+  HIPCK(ctx, hipMemcpyAsync(dxy, xy, sizeof(double) * 2 * np, hipMemcpyHostToDevice, ctx->stream));
+  double kmax = 0.0;
+  for (int i = 0; i < nk; ++i) kmax = std::max(kmax, std::fabs(k[i]));
+  NearPlan plan;
+  if ((rc = near_plan_build(ctx, arc, np, xy, plan, nullptr, kmax))) return rc;
+  rc = field_dev_impl(ctx, arc, nk, dk, dal, N, np, (const double2 *)dxy, plan, dU, np, 0);
+  if (rc == FTHMS_OK)
+    rc = hipMemcpyAsync(U, dU, sizeof(double2) * nk * np, hipMemcpyDeviceToHost, ctx->stream) ==
+                 hipSuccess
+             ? FTHMS_OK
+             : fail(ctx, FTHMS_EDEVICE, "copy of U failed");
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess && rc == FTHMS_OK)
+    rc = fail(ctx, FTHMS_EDEVICE, "stream synchronisation failed");
+  near_plan_free(ctx, plan);
+  return rc;
+}
+
+int fthms_freq_to_time_dev(fthms_ctx *ctx, int nk, const double *omega_dev, const double *w_dev,
+                           int np, const fthms_c64 *U_dev, int nt, const double *t_dev,
+                           fthms_c64 *u_dev) {
+  if (!ctx || !omega_dev || !w_dev || !U_dev || !t_dev || !u_dev || nk < 0 || np < 0 || nt < 0)
+    return fail(ctx, FTHMS_EINVAL, "bad argument to fthms_freq_to_time_dev");
+  if (np == 0 || nt == 0) return FTHMS_OK;
+  HIPCK(ctx, hipSetDevice(ctx->device));
+  dim3 g((np + kFtTile - 1) / kFtTile, (nt + kFtTile - 1) / kFtTile);
+  tbeg(ctx, "freq_to_time");
+  freq_to_time_kernel<<<g, 256, 0, ctx->stream>>>(nk, omega_dev, w_dev, np,
+                                                   (const double2 *)U_dev, nt, t_dev,
+                                                   (double2 *)u_dev);
+  tend(ctx);
+  return check_launch(ctx, "freq_to_time_kernel");
+}
+
+int fthms_freq_to_time(fthms_ctx *ctx, int nk, const double *omega, const double *w, int np,
+                       const fthms_c64 *U, int nt, const double *t, fthms_c64 *u) {
+  if (!ctx || !omega || !w || !U || !t || !u || nk < 0 || np < 0 || nt < 0)
+    return fail(ctx, FTHMS_EINVAL, "bad argument to fthms_freq_to_time");
+  if (np == 0 || nt == 0) return FTHMS_OK;
+  HIPCK(ctx, hipSetDevice(ctx->device));
+  Staging st(ctx);
+  double *dom, *dw, *dt;
+  double2 *dU, *du;
+  int rc;
+  if ((rc = st.get(&dom, sizeof(double) * std::max(nk, 1))) ||
+      (rc = st.get(&dw, sizeof(double) * std::max(nk, 1))) ||
+      (rc = st.get(&dt, sizeof(double) * nt)) ||
+      (rc = st.get(&dU, sizeof(double2) * std::max(nk, 1) * np)) ||
+      (rc = st.get(&du, sizeof(double2) * nt * np)))
+    return rc;
+  if (nk > 0) {
+    HIPCK(ctx, hipMemcpyAsync(dom, omega, sizeof(double) * nk, hipMemcpyHostToDevice, ctx->stream));
+    HIPCK(ctx, hipMemcpyAsync(dw, w, sizeof(double) * nk, hipMemcpyHostToDevice, ctx->stream));
+    HIPCK(ctx, hipMemcpyAsync(dU, U, sizeof(double2) * nk * np, hipMemcpyHostToDevice, ctx->stream));
+  }
+  HIPCK(ctx, hipMemcpyAsync(dt, t, sizeof(double) * nt, hipMemcpyHostToDevice, ctx->stream));
+  if ((rc = fthms_freq_to_time_dev(ctx, nk, dom, dw, np, (const fthms_c64 *)dU, nt, dt,
+                                   (fthms_c64 *)du)))
+    return rc;
+  HIPCK(ctx, hipMemcpyAsync(u, du, sizeof(double2) * nt * np, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCK(ctx, hipStreamSynchronize(ctx->stream));
+  return FTHMS_OK;
+}
+
+}  // extern "C"
+
+#include "problem.h"

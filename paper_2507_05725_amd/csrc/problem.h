@@ -1,0 +1,517 @@
+// Multiple-scattering driver (included at the end of fthms.hip).
+//
+// Frequency-domain form of the FTH-MS recursion of Section 3.1 (Definition
+// inductive_int with a single time window, so the spatial windows chi_j and
+// the overlap masking of eq. vtilde commute with the Fourier transform):
+//
+//   b_{j,1}   = -chi_j U^inc                              eq. criterion_int1
+//   b_{j,m+1} = -chi_j sum_{k != j} v~_{k,j,m}            eq. criterion_int2
+//   v~_{k,j,m} = 0 on the overlap of Gamma_j with an adjacent Gamma_k,
+//                S_k[alpha_{k,m}] elsewhere               eq. vtilde
+//   V_j alpha_{j,m} = b_{j,m}                             eq. FDBIEk-interior
+//   U_M = sum_j S_j[sum_m alpha_{j,m}]                    eq. mult-scatt-int
+//
+// Per chunk of wavenumbers every arc matrix is assembled and factored once;
+// the factors are reused for all M steps.  Everything stays on the device;
+// the host only plans (chi values, overlap masks, near-target quadrature).
+//
+// Readings: d^ov(x) in eq. POU1 is the chord |x - x_end| and A^ov the chord
+// between the two ends of the overlap; overlap membership of a node is
+// decided by the parent-curve parameter interval of each arc.
+
+namespace fthms {
+
+__global__ void zero_kernel(double2 *p, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = make_double2(0.0, 0.0);
+}
+
+// dst[b][i] = -chi[i] * src[b][i]
+__global__ void chi_scale_kernel(const double2 *src, const double *chi, int n, long long nn,
+                                 double2 *dst) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nn;
+       e += (long long)gridDim.x * blockDim.x) {
+    const double c = -chi[e % n];
+    dst[e] = make_double2(c * src[e].x, c * src[e].y);
+  }
+}
+
+__global__ void axpy_kernel(double2 *y, const double2 *x, long long nn) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nn;
+       e += (long long)gridDim.x * blockDim.x)
+    y[e] = make_double2(y[e].x + x[e].x, y[e].y + x[e].y);
+}
+
+// dst[b][off + i] = src[b][i], b < nb, i < n
+__global__ void place_kernel(const double2 *src, int n, int nb, double2 *dst, long long dstride,
+                             long long off) {
+  const long long nn = (long long)n * nb;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nn;
+       e += (long long)gridDim.x * blockDim.x)
+    dst[(e / n) * dstride + off + e % n] = src[e];
+}
+
+}  // namespace fthms
+
+static dim3 grid1d(long long n) {
+  long long b = (n + 255) / 256;
+  return dim3((unsigned)std::max<long long>(1, std::min<long long>(b, 65535)));
+}
+
+// ---------------------------------------------------------------------------
+// near-target plans on the device
+// ---------------------------------------------------------------------------
+void near_plan_free(fthms_ctx *ctx, NearPlan &p) {
+  dev_free(ctx, p.d_cls, (size_t)p.np);
+  dev_free(ctx, p.d_tgt, sizeof(int) * p.ntgt);
+  dev_free(ctx, p.d_qoff, sizeof(int) * (p.ntgt + 1));
+  dev_free(ctx, p.d_xq, sizeof(double2) * p.nq);
+  dev_free(ctx, p.d_wq, sizeof(double) * p.nq);
+  dev_free(ctx, p.d_cq, sizeof(double) * p.nq);
+  p = NearPlan();
+}
+
+int near_plan_build(fthms_ctx *ctx, const fthms_arc *arc, int np, const double *xy,
+                    NearPlan &plan, const unsigned char *skip, double kmax) {
+  NearPlanHost h;
+  double smax = 0.0;
+  for (double v : arc->s) smax = std::max(smax, v);
+  plan_near(arc->n, arc->xy.data(), arc->cgx, arc->cgy, arc->hmax, smax, kmax, np, xy, skip, h);
+  plan.np = np;
+  plan.ntgt = (int)h.tgt.size();
+  plan.nq = (int)h.wq.size();
+  int rc;
+  if ((rc = dev_alloc(ctx, (void **)&plan.d_cls, (size_t)std::max(np, 1)))) return rc;
+  HIPCK(ctx, hipMemcpy(plan.d_cls, h.cls.data(), (size_t)np, hipMemcpyHostToDevice));
+  if (plan.ntgt > 0) {
+    if ((rc = dev_alloc(ctx, (void **)&plan.d_tgt, sizeof(int) * plan.ntgt)) ||
+        (rc = dev_alloc(ctx, (void **)&plan.d_qoff, sizeof(int) * (plan.ntgt + 1))) ||
+        (rc = dev_alloc(ctx, (void **)&plan.d_xq, sizeof(double2) * plan.nq)) ||
+        (rc = dev_alloc(ctx, (void **)&plan.d_wq, sizeof(double) * plan.nq)) ||
+        (rc = dev_alloc(ctx, (void **)&plan.d_cq, sizeof(double) * plan.nq)))
+      return rc;
+    HIPCK(ctx, hipMemcpy(plan.d_tgt, h.tgt.data(), sizeof(int) * plan.ntgt, hipMemcpyHostToDevice));
+    HIPCK(ctx, hipMemcpy(plan.d_qoff, h.qoff.data(), sizeof(int) * (plan.ntgt + 1),
+                         hipMemcpyHostToDevice));
+    HIPCK(ctx, hipMemcpy(plan.d_xq, h.xq.data(), sizeof(double2) * plan.nq, hipMemcpyHostToDevice));
+    HIPCK(ctx, hipMemcpy(plan.d_wq, h.wq.data(), sizeof(double) * plan.nq, hipMemcpyHostToDevice));
+    HIPCK(ctx, hipMemcpy(plan.d_cq, h.cq.data(), sizeof(double) * plan.nq, hipMemcpyHostToDevice));
+  }
+  return FTHMS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// problems
+// ---------------------------------------------------------------------------
+struct fthms_problem {
+  fthms_ctx *ctx = nullptr;
+  int narcs = 0, M = 1, precision = FTHMS_FP64;
+  double tol = 1e-13, period = 0.0, c0 = 1.0 / 3.0, c1 = 2.0 / 3.0;
+  IncidentDev inc;
+  std::vector<const fthms_arc *> arcs;
+  std::vector<double> interval;
+  std::vector<double *> d_chi;
+  std::vector<std::vector<unsigned char>> skip;  // [k * narcs + j][i]
+  int nobs = 0;
+  std::vector<double> obs;
+  double2 *d_obs = nullptr;
+  double planned_kmax = -1.0;
+  std::vector<NearPlan> pair_plan;  // [k * narcs + j]
+  std::vector<NearPlan> obs_plan;   // [j]
+};
+
+static bool in_interval(double tau, double a, double b, double period) {
+  double u = std::fmod(tau - a, period);
+  if (u < 0) u += period;
+  return u > 0.0 && u < (b - a);
+}
+
+// eq. eta: 1 for |t| <= t0, exp(2 e^{-1/s} / (s - 1)) between, 0 for |t| >= t1
+static double eta_window(double t, double t0, double t1) {
+  t = std::fabs(t);
+  if (t <= t0) return 1.0;
+  if (t >= t1) return 0.0;
+  const double s = (t - t0) / (t1 - t0);
+  return std::exp(2.0 * std::exp(-1.0 / s) / (s - 1.0));
+}
+
+static void arc_end(const fthms_arc *a, int side, double &x, double &y) {
+  x = 0.0;
+  y = 0.0;
+  for (int m = 0; m < a->n; ++m) {
+    const double sg = (side < 0 && (m & 1)) ? -1.0 : 1.0;
+    x += sg * a->cgx[m];
+    y += sg * a->cgy[m];
+  }
+}
+
+static void problem_free_plans(fthms_problem *pb) {
+  (void)hipStreamSynchronize(pb->ctx->stream);
+  for (auto &p : pb->pair_plan) near_plan_free(pb->ctx, p);
+  for (auto &p : pb->obs_plan) near_plan_free(pb->ctx, p);
+  pb->pair_plan.clear();
+  pb->obs_plan.clear();
+  pb->planned_kmax = -1.0;
+}
+
+static int problem_plan(fthms_problem *pb, double kmax) {
+  if (kmax <= pb->planned_kmax) return FTHMS_OK;
+  problem_free_plans(pb);
+  fthms_ctx *ctx = pb->ctx;
+  const int J = pb->narcs;
+  pb->pair_plan.resize((size_t)J * J);
+  pb->obs_plan.resize(J);
+  int rc;
+  for (int j = 0; j < J; ++j) {
+    if ((rc = near_plan_build(ctx, pb->arcs[j], pb->nobs, pb->obs.data(), pb->obs_plan[j],
+                              nullptr, kmax)))
+      return rc;
+    for (int k = 0; k < J && J > 1; ++k) {
+      if (k == j) continue;
+      if ((rc = near_plan_build(ctx, pb->arcs[k], pb->arcs[j]->n, pb->arcs[j]->xy.data(),
+                                pb->pair_plan[(size_t)k * J + j], pb->skip[(size_t)k * J + j].data(),
+                                kmax)))
+        return rc;
+    }
+  }
+  pb->planned_kmax = kmax;
+  return FTHMS_OK;
+}
+
+extern "C" {
+
+int fthms_problem_create(fthms_ctx *ctx, const fthms_problem_desc *d, fthms_problem **out) {
+  if (!ctx || !d || !out) return fail(ctx, FTHMS_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (d->narcs < 1 || !d->arcs) return fail(ctx, FTHMS_EINVAL, "narcs must be >= 1");
+  if (d->M < 1) return fail(ctx, FTHMS_EINVAL, "M must be >= 1");
+  if (d->precision != FTHMS_FP64 && d->precision != FTHMS_FP32_REFINED)
+    return fail(ctx, FTHMS_EINVAL, "unknown precision");
+  if (d->narcs > 1 && d->precision != FTHMS_FP64)
+    return fail(ctx, FTHMS_EINVAL, "multi-arc problems run in FP64");
+  if (d->narcs > 1 && (!d->interval || !(d->period > 0.0) || !(d->c0 > 0.0) ||
+                       !(d->c0 < 0.5) || !(d->c1 > 0.5) || !(d->c1 < 1.0)))
+    return fail(ctx, FTHMS_EINVAL, "multi-arc problems need intervals, period > 0, "
+                                   "0 < c0 < 1/2 < c1 < 1");
+  if (d->nobs < 0 || (d->nobs > 0 && !d->obs_xy)) return fail(ctx, FTHMS_EINVAL, "bad obs");
+  for (int j = 0; j < d->narcs; ++j)
+    if (!d->arcs[j] || d->arcs[j]->ctx != ctx) return fail(ctx, FTHMS_EINVAL, "bad arc");
+  fthms_problem *pb = new (std::nothrow) fthms_problem;
+  if (!pb) return fail(ctx, FTHMS_ENOMEM, "host allocation failed");
+  pb->ctx = ctx;
+  pb->narcs = d->narcs;
+  pb->M = d->narcs > 1 ? d->M : 1;
+  pb->precision = d->precision;
+  pb->tol = d->tol > 0.0 ? d->tol : 1e-13;
+  pb->period = d->period;
+  pb->c0 = d->c0;
+  pb->c1 = d->c1;
+  int rc = to_incident(ctx, &d->incident, pb->inc);
+  if (rc) {
+    delete pb;
+    return rc;
+  }
+  pb->arcs.assign(d->arcs, d->arcs + d->narcs);
+  const int J = pb->narcs;
+  if (J > 1) pb->interval.assign(d->interval, d->interval + 2 * J);
+  pb->nobs = d->nobs;
+  pb->obs.assign(d->obs_xy, d->obs_xy + 2 * (size_t)d->nobs);
+  if (!finite_all(pb->obs.data(), pb->obs.size())) {
+    delete pb;
+    return fail(ctx, FTHMS_EINVAL_DATA, "non-finite observation point");
+  }
+  if ((rc = dev_alloc(ctx, (void **)&pb->d_obs, sizeof(double2) * std::max(1, pb->nobs)))) {
+    delete pb;
+    return rc;
+  }
+  if (pb->nobs)
+    HIPCK(ctx, hipMemcpy(pb->d_obs, pb->obs.data(), sizeof(double2) * pb->nobs,
+                         hipMemcpyHostToDevice));
+  if (J > 1) {
+    // chi_j at the nodes (eq. POU1, chord reading) and overlap masks
+    pb->d_chi.assign(J, nullptr);
+    pb->skip.assign((size_t)J * J, std::vector<unsigned char>());
+    for (int j = 0; j < J; ++j) {
+      const fthms_arc *a = pb->arcs[j];
+      const int nxt = (j + 1) % J, prv = (j + J - 1) % J;
+      const double aj = pb->interval[2 * j], bj = pb->interval[2 * j + 1];
+      std::vector<double> tau(a->n), chi(a->n, 1.0);
+      for (int i = 0; i < a->n; ++i) tau[i] = 0.5 * (aj + bj) + 0.5 * (bj - aj) * a->t[i];
+      double xe, ye, xs, ys;
+      arc_end(a, +1, xe, ye);                // end of Gamma_j (in overlap with next)
+      arc_end(pb->arcs[nxt], -1, xs, ys);   // start of Gamma_{j+1}
+      const double A = std::hypot(xs - xe, ys - ye);
+      double xe2, ye2, xs2, ys2;
+      arc_end(pb->arcs[prv], +1, xe2, ye2);  // end of Gamma_{j-1} (in overlap with j)
+      arc_end(a, -1, xs2, ys2);              // start of Gamma_j
+      const double A2 = std::hypot(xs2 - xe2, ys2 - ye2);
+      for (int i = 0; i < a->n; ++i) {
+        const double px = a->xy[2 * i], py = a->xy[2 * i + 1];
+        if (in_interval(tau[i], pb->interval[2 * nxt], pb->interval[2 * nxt + 1], pb->period)) {
+          const double dd = std::hypot(px - xe, py - ye);
+          chi[i] = eta_window(A - dd, pb->c0 * A, pb->c1 * A);
+        } else if (in_interval(tau[i], pb->interval[2 * prv], pb->interval[2 * prv + 1],
+                               pb->period)) {
+          const double dd = std::hypot(px - xe2, py - ye2);
+          chi[i] = 1.0 - eta_window(A2 - dd, pb->c0 * A2, pb->c1 * A2);
+        }
+      }
+      if ((rc = dev_alloc(ctx, (void **)&pb->d_chi[j], sizeof(double) * a->n))) {
+        fthms_problem_destroy(pb);
+        return rc;
+      }
+      HIPCK(ctx, hipMemcpy(pb->d_chi[j], chi.data(), sizeof(double) * a->n, hipMemcpyHostToDevice));
+      for (int k = 0; k < J; ++k) {
+        if (k == j) continue;
+        std::vector<unsigned char> sk(a->n, 0);
+        if (k == nxt || k == prv)
+          for (int i = 0; i < a->n; ++i)
+            sk[i] = in_interval(tau[i], pb->interval[2 * k], pb->interval[2 * k + 1], pb->period)
+                        ? 1
+                        : 0;
+        pb->skip[(size_t)k * J + j] = sk;
+      }
+    }
+  }
+  *out = pb;
+  return FTHMS_OK;
+}
+
+int fthms_problem_destroy(fthms_problem *pb) {
+  if (!pb) return FTHMS_EINVAL;
+  fthms_ctx *ctx = pb->ctx;
+  (void)hipStreamSynchronize(ctx->stream);
+  problem_free_plans(pb);
+  for (size_t j = 0; j < pb->d_chi.size(); ++j)
+    dev_free(ctx, pb->d_chi[j], sizeof(double) * pb->arcs[j]->n);
+  dev_free(ctx, pb->d_obs, sizeof(double2) * std::max(1, pb->nobs));
+  delete pb;
+  return FTHMS_OK;
+}
+
+}  // extern "C"
+
+static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, double kmax,
+                            double2 *U, double2 *alpha_tot) {
+  fthms_ctx *ctx = pb->ctx;
+  const int J = pb->narcs;
+  const bool fp32 = pb->precision == FTHMS_FP32_REFINED;
+  int rc = problem_plan(pb, kmax);
+  if (rc) return rc;
+  // per-wavenumber bytes of all arcs' matrices, factors and vectors
+  size_t per = 0;
+  int nsum = 0;
+  for (int j = 0; j < J; ++j) {
+    const size_t n = pb->arcs[j]->n;
+    per += n * n * sizeof(double2) + (fp32 ? n * n * sizeof(float2) : 0) + n * sizeof(int) +
+           4 * n * sizeof(double2) + sizeof(int) + sizeof(double) + 2048;
+    nsum += (int)n;
+  }
+  size_t cap = (size_t)16 << 30;
+  if (ctx->budget) {
+    const size_t avail = ctx->budget > ctx->held ? ctx->budget - ctx->held + ctx->ws_bytes : 0;
+    cap = std::min(cap, avail);
+  }
+  int C = (int)std::min<size_t>((size_t)nk, cap / per);
+  C = std::min(C, 4096);
+  if (C < 1) return fail(ctx, FTHMS_ENOMEM, "no room for one wavenumber");
+  const int nchunks = (nk + C - 1) / C;  // even split of the batch
+  C = (nk + nchunks - 1) / nchunks;
+  struct ArcWs {
+    double2 *A64;
+    float2 *A32;
+    int *piv, *status;
+    double *relres;
+    double2 *b, *al, *cr, *tot;
+  };
+  std::vector<ArcWs> w(J);
+  {
+    size_t off = 0;
+    std::vector<size_t> o(J * 10);
+    auto take = [&](size_t bytes) {
+      size_t r = off;
+      off += (bytes + 255) & ~(size_t)255;
+      return r;
+    };
+    for (int j = 0; j < J; ++j) {
+      const size_t n = pb->arcs[j]->n;
+      o[10 * j + 0] = take(n * n * sizeof(double2) * C);
+      o[10 * j + 1] = fp32 ? take(n * n * sizeof(float2) * C) : 0;
+      o[10 * j + 2] = take(n * sizeof(int) * C);
+      o[10 * j + 3] = take(sizeof(int) * C);
+      o[10 * j + 4] = take(sizeof(double) * C);
+      for (int v = 0; v < 4; ++v) o[10 * j + 5 + v] = take(n * sizeof(double2) * C);
+    }
+    if ((rc = ensure_ws(ctx, off))) return rc;
+    char *base = (char *)ctx->ws;
+    for (int j = 0; j < J; ++j) {
+      w[j].A64 = (double2 *)(base + o[10 * j + 0]);
+      w[j].A32 = fp32 ? (float2 *)(base + o[10 * j + 1]) : nullptr;
+      w[j].piv = (int *)(base + o[10 * j + 2]);
+      w[j].status = (int *)(base + o[10 * j + 3]);
+      w[j].relres = (double *)(base + o[10 * j + 4]);
+      w[j].b = (double2 *)(base + o[10 * j + 5]);
+      w[j].al = (double2 *)(base + o[10 * j + 6]);
+      w[j].cr = (double2 *)(base + o[10 * j + 7]);
+      w[j].tot = (double2 *)(base + o[10 * j + 8]);
+    }
+  }
+  auto solve_arc = [&](int j, int c) -> int {
+    const int n = pb->arcs[j]->n;
+    const long long ms = (long long)n * n;
+    if (!fp32) {
+      tbeg(ctx, "solve");
+      lu_solve64_kernel<<<c, kLuThreads, 0, ctx->stream>>>(w[j].A64, w[j].piv, n, ms, w[j].b,
+                                                           w[j].al, n);
+      tend(ctx);
+      return check_launch(ctx, "lu_solve64_kernel");
+    }
+    tbeg(ctx, "solve");
+    refine_kernel<<<c, kLuThreads, 0, ctx->stream>>>(w[j].A32, w[j].piv, w[j].A64, n, ms, w[j].b,
+                                                      w[j].al, n, pb->tol, 10, w[j].status,
+                                                      w[j].relres);
+    tend(ctx);
+    int r = check_launch(ctx, "refine_kernel");
+    if (r) return r;
+    tbeg(ctx, "fallback");
+    r = launch_fallback(ctx, w[j].A64, n, ms, w[j].piv, w[j].b, w[j].al, w[j].status, c);
+    tend(ctx);
+    return r;
+  };
+  long long aoff = 0;
+  for (int f0 = 0; f0 < nk; f0 += C) {
+    const int c = std::min(C, nk - f0);
+    const double *kc = k_dev + f0;
+    for (int j = 0; j < J; ++j) {
+      const fthms_arc *a = pb->arcs[j];
+      const int n = a->n;
+      tbeg(ctx, "assemble");
+      rc = assemble_launch(ctx, a, kc, c, w[j].A64, fp32 ? w[j].A32 : nullptr);
+      tend(ctx);
+      if (rc) return rc;
+      tbeg(ctx, "lu");
+      rc = launch_lu(ctx, fp32, fp32 ? (void *)w[j].A32 : (void *)w[j].A64, n, (long long)n * n,
+                     w[j].piv, w[j].status, c);
+      tend(ctx);
+      if (rc) return rc;
+      tbeg(ctx, "rhs");
+      dim3 g((n + 255) / 256, c);
+      incident_kernel<<<g, 256, 0, ctx->stream>>>(pb->inc, a->d_y, J > 1 ? pb->d_chi[j] : nullptr,
+                                                   n, kc, -1.0, w[j].b, n);
+      tend(ctx);
+      if ((rc = check_launch(ctx, "incident_kernel"))) return rc;
+      if ((rc = solve_arc(j, c))) return rc;
+      HIPCK(ctx, hipMemcpyAsync(w[j].tot, w[j].al, sizeof(double2) * n * c,
+                                hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    for (int m = 1; m < pb->M; ++m) {
+      for (int j = 0; j < J; ++j) {
+        const long long nn = (long long)pb->arcs[j]->n * c;
+        zero_kernel<<<grid1d(nn), 256, 0, ctx->stream>>>(w[j].cr, nn);
+      }
+      tbeg(ctx, "field_cross");
+      for (int j = 0; j < J; ++j)
+        for (int k = 0; k < J; ++k) {
+          if (k == j) continue;
+          const fthms_arc *ak = pb->arcs[k], *aj = pb->arcs[j];
+          if ((rc = field_dev_impl(ctx, ak, c, kc, w[k].al, ak->n, aj->n, aj->d_y,
+                                   pb->pair_plan[(size_t)k * J + j], w[j].cr, aj->n, 1)))
+            return rc;
+        }
+      tend(ctx);
+      for (int j = 0; j < J; ++j) {
+        const int n = pb->arcs[j]->n;
+        const long long nn = (long long)n * c;
+        chi_scale_kernel<<<grid1d(nn), 256, 0, ctx->stream>>>(w[j].cr, pb->d_chi[j], n, nn, w[j].b);
+        if ((rc = check_launch(ctx, "chi_scale_kernel"))) return rc;
+        if ((rc = solve_arc(j, c))) return rc;
+        axpy_kernel<<<grid1d(nn), 256, 0, ctx->stream>>>(w[j].tot, w[j].al, nn);
+        if ((rc = check_launch(ctx, "axpy_kernel"))) return rc;
+      }
+    }
+    if (pb->nobs > 0 && U) {
+      double2 *Uc = U + (long long)f0 * pb->nobs;
+      zero_kernel<<<grid1d((long long)c * pb->nobs), 256, 0, ctx->stream>>>(
+          Uc, (long long)c * pb->nobs);
+      tbeg(ctx, "field");
+      for (int j = 0; j < J; ++j) {
+        const fthms_arc *a = pb->arcs[j];
+        if ((rc = field_dev_impl(ctx, a, c, kc, w[j].tot, a->n, pb->nobs, pb->d_obs,
+                                 pb->obs_plan[j], Uc, pb->nobs, 1)))
+          return rc;
+      }
+      tend(ctx);
+    }
+    if (alpha_tot) {
+      long long off = 0;
+      for (int j = 0; j < J; ++j) {
+        const int n = pb->arcs[j]->n;
+        place_kernel<<<grid1d((long long)n * c), 256, 0, ctx->stream>>>(
+            w[j].tot, n, c, alpha_tot + (long long)f0 * nsum, nsum, off);
+        if ((rc = check_launch(ctx, "place_kernel"))) return rc;
+        off += n;
+      }
+    }
+  }
+  (void)aoff;
+  return FTHMS_OK;
+}
+
+extern "C" {
+
+int fthms_problem_run_dev(fthms_problem *pb, int nk, const double *k_dev, fthms_c64 *U_dev,
+                          fthms_c64 *alpha_tot_dev) {
+  if (!pb || nk < 0 || (nk > 0 && !k_dev)) return fail(pb ? pb->ctx : nullptr, FTHMS_EINVAL,
+                                                        "bad argument to fthms_problem_run_dev");
+  if (nk == 0) return FTHMS_OK;
+  fthms_ctx *ctx = pb->ctx;
+  HIPCK(ctx, hipSetDevice(ctx->device));
+  std::vector<double> k(nk);
+  HIPCK(ctx, hipMemcpyAsync(k.data(), k_dev, sizeof(double) * nk, hipMemcpyDeviceToHost,
+                            ctx->stream));
+  HIPCK(ctx, hipStreamSynchronize(ctx->stream));
+  double kmax = 0.0;
+  for (double v : k) {
+    if (!(v > 0.0) || !std::isfinite(v))
+      return fail(ctx, FTHMS_EINVAL_DATA, "wavenumbers must be finite and > 0");
+    kmax = std::max(kmax, v);
+  }
+  return problem_run_impl(pb, nk, k_dev, kmax, (double2 *)U_dev, (double2 *)alpha_tot_dev);
+}
+
+int fthms_problem_run(fthms_problem *pb, int nk, const double *k, fthms_c64 *U,
+                      fthms_c64 *alpha_tot) {
+  if (!pb || nk < 0 || (nk > 0 && !k)) return fail(pb ? pb->ctx : nullptr, FTHMS_EINVAL,
+                                                    "bad argument to fthms_problem_run");
+  if (nk == 0) return FTHMS_OK;
+  fthms_ctx *ctx = pb->ctx;
+  HIPCK(ctx, hipSetDevice(ctx->device));
+  double kmax = 0.0;
+  for (int i = 0; i < nk; ++i) {
+    if (!(k[i] > 0.0) || !std::isfinite(k[i]))
+      return fail(ctx, FTHMS_EINVAL_DATA, "wavenumbers must be finite and > 0");
+    kmax = std::max(kmax, k[i]);
+  }
+  int nsum = 0;
+  for (auto a : pb->arcs) nsum += a->n;
+  Staging st(ctx);
+  double *dk;
+  double2 *dU = nullptr, *dA = nullptr;
+  int rc;
+  if ((rc = st.get(&dk, sizeof(double) * nk))) return rc;
+  if (U && pb->nobs && (rc = st.get(&dU, sizeof(double2) * (size_t)nk * pb->nobs))) return rc;
+  if (alpha_tot && (rc = st.get(&dA, sizeof(double2) * (size_t)nk * nsum))) return rc;
+  HIPCK(ctx, hipMemcpyAsync(dk, k, sizeof(double) * nk, hipMemcpyHostToDevice, ctx->stream));
+  if ((rc = problem_run_impl(pb, nk, dk, kmax, dU, dA))) return rc;
+  if (dU)
+    HIPCK(ctx, hipMemcpyAsync(U, dU, sizeof(double2) * (size_t)nk * pb->nobs,
+                              hipMemcpyDeviceToHost, ctx->stream));
+  if (dA)
+    HIPCK(ctx, hipMemcpyAsync(alpha_tot, dA, sizeof(double2) * (size_t)nk * nsum,
+                              hipMemcpyDeviceToHost, ctx->stream));
+  HIPCK(ctx, hipStreamSynchronize(ctx->stream));
+  return FTHMS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,58 @@
+"""The device Bessel routines, compiled for the host, against mpmath.
+
+The same header the HIP kernels include is built into a small CPU probe
+(tests/native/bessel_probe.cpp) with hipcc; nothing runs on a GPU.  The
+absolute error bound 1.5e-15 holds uniformly over [0, 1500], covering every
+regime boundary (1e-6, 8, 16.5)."""
+import os
+import shutil
+import subprocess
+import tempfile
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def probe():
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    d = tempfile.mkdtemp(prefix="bprobe")
+    exe = os.path.join(d, "bprobe")
+    subprocess.run([hipcc, "--offload-arch=gfx950", "-O2", "-o", exe,
+                    os.path.join(HERE, "native", "bessel_probe.cpp")],
+                   check=True, capture_output=True)
+    yield exe
+    shutil.rmtree(d, ignore_errors=True)
+
+
+def _run(exe, z):
+    out = subprocess.run([exe], input="\n".join("%.17g" % v for v in z),
+                         capture_output=True, text=True, check=True).stdout
+    return np.array([[float(x) for x in l.split()] for l in out.strip().splitlines()])
+
+
+def test_device_bessel_against_mpmath(probe):
+    mp.mp.dps = 30
+    rng = np.random.default_rng(7)
+    z = np.concatenate([
+        np.geomspace(1e-9, 1e-5, 20),
+        np.array([1e-6 * (1 - 1e-12), 1e-6, 8.0 - 1e-12, 8.0, 16.5 - 1e-12, 16.5]),
+        rng.uniform(0.0, 20.0, 600) + 1e-3,
+        rng.uniform(20.0, 1500.0, 300)])
+    res = _run(probe, z)
+    g = mp.euler
+    worst = 0.0
+    for row in res:
+        zz = mp.mpf(row[0])
+        j0 = mp.besselj(0, zz)
+        y0 = mp.bessely(0, zz)
+        yh = y0 - 2 / mp.pi * (mp.log(zz / 2) + g) * j0
+        e = max(abs(row[1] - j0), abs(row[2] - y0) / max(1, abs(y0)),
+                abs(row[3] - j0), abs(row[4] - yh))
+        worst = max(worst, float(e))
+    assert worst < 1.5e-15
