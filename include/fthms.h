@@ -188,6 +188,34 @@ int fthms_freq_to_time_dev(fthms_ctx *ctx, int nk, const double *omega_dev,
                            const fthms_c64 *U_dev, int nt, const double *t_dev,
                            fthms_c64 *u_dev);
 
+/* ---- single stages (per-kernel access) -------------------------------- */
+
+/* Nystrom matrices of V_Gamma on `arc` for nk wavenumbers (the assembly
+ * stage of fthms_solve): A[nk] of n x n complex128, column-major per matrix
+ * (element (i, j) of matrix b at A[b n^2 + j n + i]). */
+int fthms_assemble_dev(fthms_ctx *ctx, const fthms_arc *arc, int nk,
+                       const double *k_dev, fthms_c64 *A_dev);
+
+/* In-place LU with partial pivoting of nb column-major n x n complex
+ * matrices, 1 <= n <= 1024.  precision FTHMS_FP64: A is complex128;
+ * FTHMS_FP32_REFINED: A is complex64 (interleaved float re, im), factored
+ * with FP32 MFMA updates and FP64 pivoting.  piv[nb][n] receives 0-based
+ * pivot rows in LAPACK order (row i was swapped with piv[i]); info[nb]
+ * (optional) 0, or -2 for an exactly zero pivot. */
+int fthms_lu_dev(fthms_ctx *ctx, int n, int nb, int precision, void *A_dev,
+                 int *piv_dev, int *info_dev);
+
+/* x = A^{-1} b from complex128 factors of fthms_lu_dev (FTHMS_FP64):
+ * b, x: [nb][n]; b and x may alias. */
+int fthms_lu_solve_dev(fthms_ctx *ctx, int n, int nb, const fthms_c64 *LU_dev,
+                       const int *piv_dev, const fthms_c64 *b_dev,
+                       fthms_c64 *x_dev);
+
+/* Device Bessel functions used by the kernels: J0(z) and Y0(z) for nz
+ * arguments z > 0 (FP64). */
+int fthms_bessel_dev(fthms_ctx *ctx, int nz, const double *z_dev,
+                     double *j0_dev, double *y0_dev);
+
 /* ---- multiple scattering over a cyclic partition ---------------------- */
 
 /* A closed curve covered by narcs >= 2 overlapping arcs, cyclically ordered

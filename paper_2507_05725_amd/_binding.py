@@ -72,6 +72,10 @@ _SIGS = {
     "fthms_eval_field_dev": ([_vp, _vp, _i, _vp, _vp, _i, _vp, _vp], _i),
     "fthms_freq_to_time": ([_vp, _i, _vp, _vp, _i, _vp, _i, _vp, _vp], _i),
     "fthms_freq_to_time_dev": ([_vp, _i, _vp, _vp, _i, _vp, _i, _vp, _vp], _i),
+    "fthms_assemble_dev": ([_vp, _vp, _i, _vp, _vp], _i),
+    "fthms_lu_dev": ([_vp, _i, _i, _i, _vp, _vp, _vp], _i),
+    "fthms_lu_solve_dev": ([_vp, _i, _i, _vp, _vp, _vp, _vp], _i),
+    "fthms_bessel_dev": ([_vp, _i, _vp, _vp, _vp], _i),
     "fthms_problem_create": ([_vp, C.POINTER(ProblemDesc), C.POINTER(_vp)], _i),
     "fthms_problem_destroy": ([_vp], _i),
     "fthms_problem_run": ([_vp, _i, _vp, _vp, _vp], _i),
@@ -232,6 +236,26 @@ class Context:
         self.check(_lib.fthms_freq_to_time_dev(self.h, omega.numel(), _dptr(omega), _dptr(w),
                                                U.shape[1], _dptr(U), t.numel(), _dptr(t),
                                                _dptr(out)), "freq_to_time_dev")
+
+
+    # ---- single stages (torch tensors on the device) ----------------------
+    def assemble_dev(self, arc, k, A):
+        self.check(_lib.fthms_assemble_dev(self.h, arc.h, k.numel(), _dptr(k), _dptr(A)),
+                   "assemble_dev")
+
+    def lu_dev(self, A, piv, info=None, precision=FP64):
+        nb, n = A.shape[0], A.shape[-1]
+        self.check(_lib.fthms_lu_dev(self.h, n, nb, precision, _dptr(A), _dptr(piv),
+                                     _dptr(info)), "lu_dev")
+
+    def lu_solve_dev(self, LU, piv, b, x):
+        nb, n = LU.shape[0], LU.shape[-1]
+        self.check(_lib.fthms_lu_solve_dev(self.h, n, nb, _dptr(LU), _dptr(piv), _dptr(b),
+                                           _dptr(x)), "lu_solve_dev")
+
+    def bessel_dev(self, z, j0, y0):
+        self.check(_lib.fthms_bessel_dev(self.h, z.numel(), _dptr(z), _dptr(j0), _dptr(y0)),
+                   "bessel_dev")
 
 
 class Arc:

@@ -802,4 +802,73 @@ int fthms_freq_to_time(fthms_ctx *ctx, int nk, const double *omega, const double
 
 }  // extern "C"
 
+// ---------------------------------------------------------------------------
+// single stages
+// ---------------------------------------------------------------------------
+namespace fthms {
+__global__ void bessel_kernel(int nz, const double *z, double *j0, double *y0) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nz) return;
+  double a, b;
+  bessel_j0_y0(z[i], a, b);
+  j0[i] = a;
+  y0[i] = b;
+}
+}  // namespace fthms
+
+extern "C" {
+
+int fthms_assemble_dev(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double *k_dev,
+                       fthms_c64 *A_dev) {
+  if (!ctx || !arc || nk < 0 || (nk > 0 && (!k_dev || !A_dev)))
+    return fail(ctx, FTHMS_EINVAL, "bad argument to fthms_assemble_dev");
+  if (nk == 0) return FTHMS_OK;
+  HIPCK(ctx, hipSetDevice(ctx->device));
+  tbeg(ctx, "assemble");
+  int rc = assemble_launch(ctx, arc, k_dev, nk, (double2 *)A_dev, nullptr);
+  tend(ctx);
+  return rc;
+}
+
+int fthms_lu_dev(fthms_ctx *ctx, int n, int nb, int precision, void *A_dev, int *piv_dev,
+                 int *info_dev) {
+  if (!ctx || n < 1 || n > kMaxN || nb < 0 || (nb > 0 && (!A_dev || !piv_dev)))
+    return fail(ctx, FTHMS_EINVAL, "bad argument to fthms_lu_dev");
+  if (precision != FTHMS_FP64 && precision != FTHMS_FP32_REFINED)
+    return fail(ctx, FTHMS_EINVAL, "unknown precision");
+  if (nb == 0) return FTHMS_OK;
+  HIPCK(ctx, hipSetDevice(ctx->device));
+  tbeg(ctx, "lu");
+  int rc = launch_lu(ctx, precision == FTHMS_FP32_REFINED, A_dev, n, (long long)n * n, piv_dev,
+                     info_dev, nb);
+  tend(ctx);
+  return rc;
+}
+
+int fthms_lu_solve_dev(fthms_ctx *ctx, int n, int nb, const fthms_c64 *LU_dev, const int *piv_dev,
+                       const fthms_c64 *b_dev, fthms_c64 *x_dev) {
+  if (!ctx || n < 1 || n > kMaxN || nb < 0 ||
+      (nb > 0 && (!LU_dev || !piv_dev || !b_dev || !x_dev)))
+    return fail(ctx, FTHMS_EINVAL, "bad argument to fthms_lu_solve_dev");
+  if (nb == 0) return FTHMS_OK;
+  HIPCK(ctx, hipSetDevice(ctx->device));
+  tbeg(ctx, "solve");
+  lu_solve64_kernel<<<nb, kLuThreads, 0, ctx->stream>>>((const double2 *)LU_dev, piv_dev, n,
+                                                        (long long)n * n, (const double2 *)b_dev,
+                                                        (double2 *)x_dev, n);
+  tend(ctx);
+  return check_launch(ctx, "lu_solve64_kernel");
+}
+
+int fthms_bessel_dev(fthms_ctx *ctx, int nz, const double *z_dev, double *j0_dev, double *y0_dev) {
+  if (!ctx || nz < 0 || (nz > 0 && (!z_dev || !j0_dev || !y0_dev)))
+    return fail(ctx, FTHMS_EINVAL, "bad argument to fthms_bessel_dev");
+  if (nz == 0) return FTHMS_OK;
+  HIPCK(ctx, hipSetDevice(ctx->device));
+  bessel_kernel<<<(nz + 255) / 256, 256, 0, ctx->stream>>>(nz, z_dev, j0_dev, y0_dev);
+  return check_launch(ctx, "bessel_kernel");
+}
+
+}  // extern "C"
+
 #include "problem.h"

@@ -27,17 +27,21 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 template <typename T> struct Mma;
+// Accumulator row of register r in lane group g = lane / 16 (column is
+// lane % 16): interleaved for f64 (g + 4 r), blocked for f32 (4 g + r).
 template <> struct Mma<double> {
   typedef v4d acc;
   static __device__ __forceinline__ acc run(double a, double b, acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int crow(int g, int r) { return g + 4 * r; }
 };
 template <> struct Mma<float> {
   typedef v4f acc;
   static __device__ __forceinline__ acc run(float a, float b, acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int crow(int g, int r) { return 4 * g + r; }
 };
 
 constexpr int kLuThreads = 256;
@@ -60,8 +64,8 @@ struct LuSmem {
 // the tile in accumulator registers for the whole K loop.  No barrier.
 //
 // MFMA 16x16x4 operand layout: lane l holds A[l % 16][l / 16],
-// B[l / 16][l % 16]; the accumulator holds rows 4 (l / 16) + r, r = 0..3,
-// of column l % 16.
+// B[l / 16][l % 16]; accumulator register r holds column l % 16 at row
+// Mma<T>::crow(l / 16, r).
 template <typename T>
 __device__ void wg_gemm_sub(cplx_t<T> *C, const cplx_t<T> *A,
                             const cplx_t<T> *B, int ld, int m, int n, int K) {
@@ -80,7 +84,7 @@ __device__ void wg_gemm_sub(cplx_t<T> *C, const cplx_t<T> *A,
         const int col = tj * 32 + cb * 16 + li;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = ti * 32 + rb * 16 + 4 * lk + r;
+          const int row = ti * 32 + rb * 16 + Mma<T>::crow(lk, r);
           cplx_t<T> v = mk<T>(0, 0);
           if (row < m && col < n) v = C[row + (long long)col * ld];
           cr[rb][cb][r] = v.x;
@@ -141,7 +145,7 @@ __device__ void wg_gemm_sub(cplx_t<T> *C, const cplx_t<T> *A,
         const int col = tj * 32 + cb * 16 + li;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = ti * 32 + rb * 16 + 4 * lk + r;
+          const int row = ti * 32 + rb * 16 + Mma<T>::crow(lk, r);
           if (row < m && col < n)
             C[row + (long long)col * ld] = mk<T>(cr[rb][cb][r], ci[rb][cb][r]);
         }
