@@ -365,47 +365,72 @@ int fthms_arc_size(const fthms_arc *arc) { return arc ? arc->n : FTHMS_EINVAL; }
 // ---------------------------------------------------------------------------
 // batched solve
 // ---------------------------------------------------------------------------
+// Blocked LU of `count` matrices: per block of 64 columns one panel launch
+// (one workgroup per matrix) and one strip launch (XCD-aware, one workgroup
+// per 64-column strip per matrix).  only_failed: factor only the matrices
+// whose status is negative (the FP64 redo of refined solves).
+// Per-matrix LU scratch: the block row permutation and the inverse of the
+// block's unit-lower diagonal part (sized for complex128).
+constexpr size_t kLuScratchBytes = sizeof(int) * kSwapStride + sizeof(double2) * kLuNB * kLuNB;
+
+template <typename T, int R>
+static void lu_blocks(fthms_ctx *ctx, cplx_t<T> *A, int N, long long ms, int *piv, void *scr,
+                      int *status, int count, int only_failed) {
+  int *swp = (int *)scr;
+  cplx_t<T> *linv = (cplx_t<T> *)((char *)scr + sizeof(int) * kSwapStride * (size_t)count);
+  for (int k0 = 0; k0 < N; k0 += kLuNB) {
+    const int nb = std::min(kLuNB, N - k0);
+    lu_panel_kernel<T, R><<<count, kLuThreads, 0, ctx->stream>>>(A, N, ms, k0, piv, swp, linv,
+                                                                 status, only_failed);
+    const int nleft = (k0 + kStripW - 1) / kStripW;
+    const int nright = (N - k0 - nb + kStripW - 1) / kStripW;
+    if (nleft + nright > 0) {
+      const long long blocks = 8LL * ((count + 7) / 8) * (nleft + nright);
+      lu_strip_kernel<T><<<(unsigned)blocks, kLuThreads, 0, ctx->stream>>>(
+          A, N, ms, k0, swp, linv, count, nleft, nright, status, only_failed);
+    }
+  }
+}
+
+// scr: count * kLuScratchBytes of device scratch
 static int launch_lu(fthms_ctx *ctx, bool fp32, void *A, int N, long long ms, int *piv,
-                     int *status, int count) {
+                     void *scr, int *status, int count, int only_failed = 0) {
   const int R = (N + kLuThreads - 1) / kLuThreads;
-  dim3 g(count), b(kLuThreads);
   if (fp32) {
     float2 *a = (float2 *)A;
     switch (R) {
-      case 1: lu_kernel<float, 1><<<g, b, 0, ctx->stream>>>(a, N, ms, piv, status); break;
-      case 2: lu_kernel<float, 2><<<g, b, 0, ctx->stream>>>(a, N, ms, piv, status); break;
-      case 3: lu_kernel<float, 3><<<g, b, 0, ctx->stream>>>(a, N, ms, piv, status); break;
-      default: lu_kernel<float, 4><<<g, b, 0, ctx->stream>>>(a, N, ms, piv, status); break;
+      case 1: lu_blocks<float, 1>(ctx, a, N, ms, piv, scr, status, count, only_failed); break;
+      case 2: lu_blocks<float, 2>(ctx, a, N, ms, piv, scr, status, count, only_failed); break;
+      case 3: lu_blocks<float, 3>(ctx, a, N, ms, piv, scr, status, count, only_failed); break;
+      default: lu_blocks<float, 4>(ctx, a, N, ms, piv, scr, status, count, only_failed); break;
     }
   } else {
     double2 *a = (double2 *)A;
     switch (R) {
-      case 1: lu_kernel<double, 1><<<g, b, 0, ctx->stream>>>(a, N, ms, piv, status); break;
-      case 2: lu_kernel<double, 2><<<g, b, 0, ctx->stream>>>(a, N, ms, piv, status); break;
-      case 3: lu_kernel<double, 3><<<g, b, 0, ctx->stream>>>(a, N, ms, piv, status); break;
-      default: lu_kernel<double, 4><<<g, b, 0, ctx->stream>>>(a, N, ms, piv, status); break;
+      case 1: lu_blocks<double, 1>(ctx, a, N, ms, piv, scr, status, count, only_failed); break;
+      case 2: lu_blocks<double, 2>(ctx, a, N, ms, piv, scr, status, count, only_failed); break;
+      case 3: lu_blocks<double, 3>(ctx, a, N, ms, piv, scr, status, count, only_failed); break;
+      default: lu_blocks<double, 4>(ctx, a, N, ms, piv, scr, status, count, only_failed); break;
     }
   }
-  return check_launch(ctx, "lu_kernel");
+  return check_launch(ctx, "lu kernels");
 }
 
-static int launch_fallback(fthms_ctx *ctx, double2 *A, int N, long long ms, int *piv,
+// FP64 redo of refined solves with negative status: factor A64 in place and
+// solve.
+static int launch_fallback(fthms_ctx *ctx, double2 *A, int N, long long ms, int *piv, void *swp,
                            const double2 *b, double2 *x, int *status, int count) {
-  const int R = (N + kLuThreads - 1) / kLuThreads;
-  dim3 g(count), bl(kLuThreads);
-  switch (R) {
-    case 1: fallback64_kernel<1><<<g, bl, 0, ctx->stream>>>(A, piv, N, ms, b, x, N, status); break;
-    case 2: fallback64_kernel<2><<<g, bl, 0, ctx->stream>>>(A, piv, N, ms, b, x, N, status); break;
-    case 3: fallback64_kernel<3><<<g, bl, 0, ctx->stream>>>(A, piv, N, ms, b, x, N, status); break;
-    default: fallback64_kernel<4><<<g, bl, 0, ctx->stream>>>(A, piv, N, ms, b, x, N, status); break;
-  }
-  return check_launch(ctx, "fallback64_kernel");
+  int rc = launch_lu(ctx, false, A, N, ms, piv, swp, status, count, 1);
+  if (rc) return rc;
+  solve_failed64_kernel<<<count, kLuThreads, 0, ctx->stream>>>(A, piv, N, ms, b, x, N, status);
+  return check_launch(ctx, "solve_failed64_kernel");
 }
 
 struct SolveWs {
   double2 *A64;
   float2 *A32;
   int *piv;
+  void *swp;
   int *status;
   double *relres;
   int chunk;
@@ -414,7 +439,7 @@ struct SolveWs {
 static size_t per_matrix_bytes(int N, bool fp32) {
   const size_t nn = (size_t)N * N;
   return nn * sizeof(double2) + (fp32 ? nn * sizeof(float2) : 0) + sizeof(int) * N +
-         sizeof(int) + sizeof(double) + 256;
+         kLuScratchBytes + sizeof(int) + sizeof(double) + 256;
 }
 
 static int solve_ws(fthms_ctx *ctx, int N, bool fp32, int nk, SolveWs &w) {
@@ -439,6 +464,7 @@ static int solve_ws(fthms_ctx *ctx, int N, bool fp32, int nk, SolveWs &w) {
   const size_t oA64 = take(nn * sizeof(double2) * chunk);
   const size_t oA32 = fp32 ? take(nn * sizeof(float2) * chunk) : 0;
   const size_t oP = take(sizeof(int) * (size_t)N * chunk);
+  const size_t oW = take(kLuScratchBytes * chunk);
   const size_t oS = take(sizeof(int) * chunk);
   const size_t oR = take(sizeof(double) * chunk);
   int rc = ensure_ws(ctx, off);
@@ -447,6 +473,7 @@ static int solve_ws(fthms_ctx *ctx, int N, bool fp32, int nk, SolveWs &w) {
   w.A64 = (double2 *)(base + oA64);
   w.A32 = fp32 ? (float2 *)(base + oA32) : nullptr;
   w.piv = (int *)(base + oP);
+  w.swp = (void *)(base + oW);
   w.status = (int *)(base + oS);
   w.relres = (double *)(base + oR);
   w.chunk = chunk;
@@ -486,7 +513,8 @@ static int solve_dev_impl(fthms_ctx *ctx, const fthms_arc *arc, int nk, const do
     tend(ctx);
     if (rc) return rc;
     tbeg(ctx, "lu");
-    rc = launch_lu(ctx, fp32, fp32 ? (void *)w.A32 : (void *)w.A64, N, ms, w.piv, w.status, c);
+    rc = launch_lu(ctx, fp32, fp32 ? (void *)w.A32 : (void *)w.A64, N, ms, w.piv, w.swp, w.status,
+                   c);
     tend(ctx);
     if (rc) return rc;
     if (!fp32) {
@@ -501,7 +529,7 @@ static int solve_dev_impl(fthms_ctx *ctx, const fthms_arc *arc, int nk, const do
       tend(ctx);
       if ((rc = check_launch(ctx, "refine_kernel"))) return rc;
       tbeg(ctx, "fallback");
-      rc = launch_fallback(ctx, w.A64, N, ms, w.piv, b, x, w.status, c);
+      rc = launch_fallback(ctx, w.A64, N, ms, w.piv, w.swp, b, x, w.status, c);
       tend(ctx);
       if (rc) return rc;
     }
@@ -838,10 +866,17 @@ int fthms_lu_dev(fthms_ctx *ctx, int n, int nb, int precision, void *A_dev, int 
     return fail(ctx, FTHMS_EINVAL, "unknown precision");
   if (nb == 0) return FTHMS_OK;
   HIPCK(ctx, hipSetDevice(ctx->device));
+  int rc = ensure_ws2(ctx, (kLuScratchBytes + sizeof(int)) * (size_t)nb + 256);
+  if (rc) return rc;
+  void *swp = ctx->ws2;
+  int *status = (int *)((char *)ctx->ws2 + kLuScratchBytes * (size_t)nb);
   tbeg(ctx, "lu");
-  int rc = launch_lu(ctx, precision == FTHMS_FP32_REFINED, A_dev, n, (long long)n * n, piv_dev,
-                     info_dev, nb);
+  rc = launch_lu(ctx, precision == FTHMS_FP32_REFINED, A_dev, n, (long long)n * n, piv_dev, swp,
+                 status, nb);
   tend(ctx);
+  if (rc == FTHMS_OK && info_dev)
+    HIPCK(ctx, hipMemcpyAsync(info_dev, status, sizeof(int) * nb, hipMemcpyDeviceToDevice,
+                              ctx->stream));
   return rc;
 }
 

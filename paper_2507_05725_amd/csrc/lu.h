@@ -6,17 +6,21 @@
 // linear algebra or GMRES) is a dense LU.  Layout: column-major, leading
 // dimension N, interleaved complex (re, im).
 //
-// Right-looking blocked LU with two levels of blocking:
-//   outer block NB = 64 columns: row swaps outside the block, blocked TRSM
-//   for U12 and the trailing update A22 -= L21 U12 with K = 64;
-//   inner panels of PW = 8 columns: register-resident factorisation with
-//   partial pivoting (pivot choice |re| + |im|, first index on ties), then
-//   the in-block TRSM and update with K = 8.
-// Every update A -= B C runs on the matrix cores: complex products as four
-// real 16x16x4 MFMA chains (f64 for the FP64 form, f32 with f32
-// accumulation for the refined form).  Pivot search, pivot row, panel
-// scaling and the triangular solves against the 8x8 diagonal blocks are
-// done in FP64 in both forms.
+// Right-looking blocked LU, two kernels per block of NB = 64 columns:
+//
+//   lu_panel_kernel  (one workgroup per matrix)  factors the m x 64 block
+//     in inner panels of PW = 8 columns held in registers (FP64 partial
+//     pivoting: pivot = largest |re| + |im|, first index on ties), with the
+//     in-block triangular solves and updates in FP64 on the VALU, and
+//     writes the block's net row permutation as (destination, source) pairs;
+//   lu_strip_kernel  (one workgroup per 64-column strip of one matrix,
+//     XCD-aware: all strips of a matrix land on the same XCD and share its
+//     L2) applies the permutation to its columns as a gather, solves
+//     U12 = L11^{-1} A12 for its 64 columns into LDS (FP64 arithmetic), and
+//     updates the strip below, A22 -= L21 U12, on the matrix cores: complex
+//     products as four real 16x16x4 MFMA chains (f64 for the FP64 form, f32
+//     with f32 accumulation for the refined form), U12 as the LDS-resident
+//     B operand, L21 fragments streamed from memory.
 #pragma once
 
 #include "common.h"
@@ -48,6 +52,10 @@ constexpr int kLuThreads = 256;
 constexpr int kLuNB = 64;
 constexpr int kLuPW = 8;
 
+constexpr int kMaxN = 1024;
+constexpr int kSwapMax = 2 * kLuNB;          // pairs per block
+constexpr int kSwapStride = 1 + 2 * kSwapMax;  // ints per matrix
+
 struct LuSmem {
   double red_v[4];
   int red_r[4];
@@ -55,172 +63,26 @@ struct LuSmem {
   double2 bufp[kLuPW];
   double2 bufc[kLuPW];
   double2 L[kLuPW][kLuPW];
+  int pr_row[2 * kLuPW], pr_src[2 * kLuPW];  // net permutation of one panel
+  int npr;
+  int count;
   int zero_pivot;
+  union {  // phases of the panel kernel never overlap
+    double2 U[kLuPW][kLuNB];           // in-block update
+    double2 gat[kLuNB][2 * kLuPW];     // in-block row gather
+    int src[kMaxN];                    // block permutation
+    double2 Ld[kLuNB][kLuNB + 1];      // diagonal block for its inverse
+  } big;
 };
 
-// C[m x n] -= A[m x K] * B[K x n]; operands are sub-blocks of column-major
-// storage with leading dimension ld.  Each wave owns 32x32 output tiles
-// (2x2 blocks of 16x16), streams A and B fragments from memory and keeps
-// the tile in accumulator registers for the whole K loop.  No barrier.
-//
-// MFMA 16x16x4 operand layout: lane l holds A[l % 16][l / 16],
-// B[l / 16][l % 16]; accumulator register r holds column l % 16 at row
-// Mma<T>::crow(l / 16, r).
-template <typename T>
-__device__ void wg_gemm_sub(cplx_t<T> *C, const cplx_t<T> *A,
-                            const cplx_t<T> *B, int ld, int m, int n, int K) {
-  typedef typename Mma<T>::acc acc_t;
-  if (m <= 0 || n <= 0 || K <= 0) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  const int tm = (m + 31) >> 5, tn = (n + 31) >> 5;
-  for (int t = wave; t < tm * tn; t += kLuThreads / 64) {
-    const int ti = t % tm, tj = t / tm;
-    acc_t cr[2][2], ci[2][2];
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb) {
-        const int col = tj * 32 + cb * 16 + li;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = ti * 32 + rb * 16 + Mma<T>::crow(lk, r);
-          cplx_t<T> v = mk<T>(0, 0);
-          if (row < m && col < n) v = C[row + (long long)col * ld];
-          cr[rb][cb][r] = v.x;
-          ci[rb][cb][r] = v.y;
-        }
-      }
-    // fragments of the next k-step are loaded while the current one runs
-    cplx_t<T> fa[2], fb[2];
-    auto load_frag = [&](int k0) {
-      const int kk = k0 + lk;
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb) {
-        const int row = ti * 32 + rb * 16 + li;
-        fa[rb] = (row < m && kk < K) ? A[row + (long long)kk * ld] : mk<T>(0, 0);
-      }
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb) {
-        const int col = tj * 32 + cb * 16 + li;
-        fb[cb] = (col < n && kk < K) ? B[kk + (long long)col * ld] : mk<T>(0, 0);
-      }
-    };
-    load_frag(0);
-#pragma unroll 1
-    for (int k0 = 0; k0 < K; k0 += 4) {
-      T ar[2], ai[2], pai[2], br[2], bi[2];
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb) {
-        ar[rb] = -fa[rb].x;
-        ai[rb] = -fa[rb].y;
-        pai[rb] = fa[rb].y;
-      }
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb) {
-        br[cb] = fb[cb].x;
-        bi[cb] = fb[cb].y;
-      }
-      if (k0 + 4 < K) load_frag(k0 + 4);
-      // C - A B:  re += (-Ar) Br + Ai Bi ;  im += (-Ar) Bi + (-Ai) Br
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
-          cr[rb][cb] = Mma<T>::run(ar[rb], br[cb], cr[rb][cb]);
-          ci[rb][cb] = Mma<T>::run(ar[rb], bi[cb], ci[rb][cb]);
-        }
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
-          cr[rb][cb] = Mma<T>::run(pai[rb], bi[cb], cr[rb][cb]);
-          ci[rb][cb] = Mma<T>::run(ai[rb], br[cb], ci[rb][cb]);
-        }
-    }
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb) {
-        const int col = tj * 32 + cb * 16 + li;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = ti * 32 + rb * 16 + Mma<T>::crow(lk, r);
-          if (row < m && col < n)
-            C[row + (long long)col * ld] = mk<T>(cr[rb][cb][r], ci[rb][cb][r]);
-        }
-      }
-  }
-}
-
-// Apply row interchanges spiv[0..cnt) (pivot of row r0 + i is spiv[i],
-// absolute) in order to columns [c0, c1).
-template <typename T>
-__device__ void swap_rows(cplx_t<T> *A, int ld, const int *spiv, int r0, int cnt,
-                          int c0, int c1) {
-  for (int col = c0 + (int)threadIdx.x; col < c1; col += kLuThreads) {
-    cplx_t<T> *a = A + (long long)col * ld;
-    for (int i = 0; i < cnt; ++i) {
-      const int p = spiv[i];
-      if (p != r0 + i) {
-        const cplx_t<T> t = a[r0 + i];
-        a[r0 + i] = a[p];
-        a[p] = t;
-      }
-    }
-  }
-}
-
-// B := L^{-1} B for the unit lower pw x pw block at (r0, r0) and the rows
-// r0..r0+pw of columns [c0, c1); FP64 arithmetic.
-template <typename T>
-__device__ void trsm_small(cplx_t<T> *A, int ld, int r0, int pw, int c0, int c1,
-                           LuSmem &sm) {
-  const int tid = threadIdx.x;
-  if (tid < kLuPW * kLuPW) {
-    const int i = tid % kLuPW, j = tid / kLuPW;
-    sm.L[i][j] = (i < pw && j < pw) ? to_d2(A[(r0 + i) + (long long)(r0 + j) * ld])
-                                    : make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  // L is re-read from LDS for every column (volatile): hoisting the whole
-  // block into registers would cost 112 VGPRs for a loop of a few trips.
-  const volatile double *Lv = (const volatile double *)&sm.L[0][0];
-  for (int col = c0 + tid; col < c1; col += kLuThreads) {
-    cplx_t<T> *a = A + (long long)col * ld + r0;
-    double2 x[kLuPW];
-#pragma unroll
-    for (int i = 0; i < kLuPW; ++i) x[i] = i < pw ? to_d2(a[i]) : make_double2(0.0, 0.0);
-#pragma unroll
-    for (int i = 1; i < kLuPW; ++i)
-#pragma unroll
-      for (int j = 0; j < i; ++j) {
-        const double2 l = make_double2(Lv[2 * (i * kLuPW + j)], Lv[2 * (i * kLuPW + j) + 1]);
-        x[i] = cfms(x[i], l, x[j]);
-      }
-#pragma unroll
-    for (int i = 0; i < kLuPW; ++i)
-      if (i < pw) a[i] = from_d2<T>(x[i]);
-  }
-  __syncthreads();
-}
-
-// Factor the panel A[p0:N, p0:p0+pw] (pw <= PW) with partial pivoting.
-// Rows p0 + tid + 256 q live in registers (FP64).  Pivots (absolute row
-// indices) go to sm.piv[p0 - kb + c] and piv[p0 + c].
-template <typename T, int R>
-__device__ void panel_factor(cplx_t<T> *A, int ld, int N, int p0, int pw, int kb,
-                             int *piv, LuSmem &sm) {
+// Factor columns [p0, p0 + pw) of the rows p0 .. N-1 held in registers:
+// v[q][c] is row p0 + tid + 256 q, column p0 + c.  On return v holds the
+// factored rows (L below the diagonal, U on and above it) and sm.piv[p0 - k0
+// + c] the absolute pivot rows.
+template <int R>
+__device__ __forceinline__ void panel_factor_regs(double2 (&v)[R][kLuPW], int N, int p0,
+                                                  int pw, int k0, int *piv, LuSmem &sm) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double2 v[R][kLuPW];
-#pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const int row = p0 + tid + kLuThreads * q;
-#pragma unroll
-    for (int c = 0; c < kLuPW; ++c)
-      v[q][c] = (row < N && c < pw) ? to_d2(A[row + (long long)(p0 + c) * ld])
-                                    : make_double2(0.0, 0.0);
-  }
 #pragma unroll
   for (int c = 0; c < kLuPW; ++c) {
     if (c < pw) {
@@ -282,7 +144,7 @@ __device__ void panel_factor(cplx_t<T> *A, int ld, int N, int p0, int pw, int kb
             for (int c2 = 0; c2 < kLuPW; ++c2) sm.bufc[c2] = v[q][c2];
       }
       if (tid == 0) {
-        sm.piv[p0 - kb + c] = prow;
+        sm.piv[p0 - k0 + c] = prow;
         piv[col] = prow;
         if (!(best > 0.0) && sm.zero_pivot == 0) sm.zero_pivot = col + 1;
       }
@@ -321,74 +183,356 @@ __device__ void panel_factor(cplx_t<T> *A, int ld, int N, int p0, int pw, int kb
       __syncthreads();
     }
   }
+}
+
+// Factor the block of columns [k0, k0 + nb) of one matrix (all rows >= k0),
+// record the pivots, and emit the block's net row permutation for the
+// columns outside it: swp[0] = count, then count (dst, src) pairs meaning
+// "new row dst = old row src".
+template <typename T, int R>
+__global__ __launch_bounds__(kLuThreads) void lu_panel_kernel(cplx_t<T> *Abase, int N,
+                                                              long long mstride, int k0,
+                                                              int *pivbase, int *swapbase,
+                                                              cplx_t<T> *Linv, int *status,
+                                                              int only_failed) {
+  __shared__ LuSmem sm;
+  const long long mb = blockIdx.x;
+  if (only_failed && status[mb] >= 0) return;
+  cplx_t<T> *A = Abase + mb * mstride;
+  int *piv = pivbase + mb * N;
+  int *swp = swapbase + mb * kSwapStride;
+  const int tid = threadIdx.x;
+  const int nb = min(kLuNB, N - k0);
+  if (tid == 0) sm.zero_pivot = 0;
+  __syncthreads();
+  for (int p0 = k0; p0 < k0 + nb; p0 += kLuPW) {
+    const int pw = min(kLuPW, k0 + nb - p0);
+    double2 v[R][kLuPW];
 #pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const int row = p0 + tid + kLuThreads * q;
-    if (row < N)
+    for (int q = 0; q < R; ++q) {
+      const int row = p0 + tid + kLuThreads * q;
 #pragma unroll
       for (int c = 0; c < kLuPW; ++c)
-        if (c < pw) A[row + (long long)(p0 + c) * ld] = from_d2<T>(v[q][c]);
-  }
-  __syncthreads();
-}
-
-// In-place LU of one N x N matrix by the calling workgroup.
-template <typename T, int R>
-__device__ void lu_factor(cplx_t<T> *A, int N, int *piv, LuSmem &sm) {
-  const int ld = N;
-  if (threadIdx.x == 0) sm.zero_pivot = 0;
-  __syncthreads();
-  for (int k0 = 0; k0 < N; k0 += kLuNB) {
-    const int nb = min(kLuNB, N - k0);
-    for (int p0 = k0; p0 < k0 + nb; p0 += kLuPW) {
-      const int pw = min(kLuPW, k0 + nb - p0);
-      panel_factor<T, R>(A, ld, N, p0, pw, k0, piv, sm);
-      swap_rows<T>(A, ld, sm.piv + (p0 - k0), p0, pw, k0, p0);
-      swap_rows<T>(A, ld, sm.piv + (p0 - k0), p0, pw, p0 + pw, k0 + nb);
-      __syncthreads();
-      if (p0 + pw < k0 + nb) {
-        trsm_small<T>(A, ld, p0, pw, p0 + pw, k0 + nb, sm);
-        wg_gemm_sub<T>(A + (p0 + pw) + (long long)(p0 + pw) * ld,
-                       A + (p0 + pw) + (long long)p0 * ld,
-                       A + p0 + (long long)(p0 + pw) * ld, ld, N - p0 - pw,
-                       k0 + nb - p0 - pw, pw);
-        __syncthreads();
-      }
+        v[q][c] = (row < N && c < pw) ? to_d2(A[row + (long long)(p0 + c) * N])
+                                      : make_double2(0.0, 0.0);
     }
-    swap_rows<T>(A, ld, sm.piv, k0, nb, 0, k0);
-    swap_rows<T>(A, ld, sm.piv, k0, nb, k0 + nb, N);
+    panel_factor_regs<R>(v, N, p0, pw, k0, piv, sm);
+    // write the factored panel back; the diagonal block's unit-lower part
+    // goes to LDS for the in-block triangular solve
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int row = p0 + tid + kLuThreads * q;
+      if (row < N)
+#pragma unroll
+        for (int c = 0; c < kLuPW; ++c)
+          if (c < pw) A[row + (long long)(p0 + c) * N] = from_d2<T>(v[q][c]);
+    }
+    if (tid < kLuPW) {
+#pragma unroll
+      for (int c = 0; c < kLuPW; ++c) sm.L[tid][c] = v[0][c];
+    }
+    // row swaps of this panel inside the block, left and right of it, as a
+    // gather over the panel's net permutation (<= 16 rows)
+    if (tid == 0) {
+      int n = 0;
+      for (int i = 0; i < pw; ++i) {
+        const int r1 = p0 + i, r2 = sm.piv[p0 - k0 + i];
+        int a = -1, b = -1;
+        for (int e = 0; e < n; ++e) {
+          if (sm.pr_row[e] == r1) a = e;
+          if (sm.pr_row[e] == r2) b = e;
+        }
+        if (a < 0) { sm.pr_row[n] = r1; sm.pr_src[n] = r1; a = n++; }
+        if (b < 0) { sm.pr_row[n] = r2; sm.pr_src[n] = r2; b = n++; }
+        const int t = sm.pr_src[a];
+        sm.pr_src[a] = sm.pr_src[b];
+        sm.pr_src[b] = t;
+      }
+      sm.npr = n;
+    }
     __syncthreads();
-    if (k0 + nb < N) {
-      // U12 = L11^{-1} A12, blocked by PW rows
-      for (int s0 = 0; s0 < nb; s0 += kLuPW) {
-        const int sw = min(kLuPW, nb - s0);
-        trsm_small<T>(A, ld, k0 + s0, sw, k0 + nb, N, sm);
-        if (s0 + sw < nb) {
-          wg_gemm_sub<T>(A + (k0 + s0 + sw) + (long long)(k0 + nb) * ld,
-                         A + (k0 + s0 + sw) + (long long)(k0 + s0) * ld,
-                         A + (k0 + s0) + (long long)(k0 + nb) * ld, ld,
-                         nb - s0 - sw, N - k0 - nb, sw);
-          __syncthreads();
+    const int wl = p0 - k0, wr = k0 + nb - p0 - pw;
+    const int npr = sm.npr;
+    for (int e = tid; e < (wl + wr) * npr; e += kLuThreads) {
+      const int ce = e / npr, j = e % npr;
+      const int col = ce < wl ? k0 + ce : p0 + pw + (ce - wl);
+      sm.big.gat[ce][j] = to_d2(A[sm.pr_src[j] + (long long)col * N]);
+    }
+    __syncthreads();
+    for (int e = tid; e < (wl + wr) * npr; e += kLuThreads) {
+      const int ce = e / npr, j = e % npr;
+      const int col = ce < wl ? k0 + ce : p0 + pw + (ce - wl);
+      A[sm.pr_row[j] + (long long)col * N] = from_d2<T>(sm.big.gat[ce][j]);
+    }
+    __syncthreads();
+    if (wr > 0) {
+      // U rows of this panel for the rest of the block: L11^{-1} A12
+      for (int e = tid; e < wr; e += kLuThreads) {
+        const int col = p0 + pw + e;
+        cplx_t<T> *a = A + (long long)col * N + p0;
+        double2 x[kLuPW];
+#pragma unroll
+        for (int i = 0; i < kLuPW; ++i) x[i] = i < pw ? to_d2(a[i]) : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int i = 1; i < kLuPW; ++i)
+#pragma unroll
+          for (int j = 0; j < i; ++j) x[i] = cfms(x[i], sm.L[i][j], x[j]);
+#pragma unroll
+        for (int i = 0; i < kLuPW; ++i) {
+          if (i < pw) a[i] = from_d2<T>(x[i]);
+          sm.big.U[i][e] = x[i];
         }
       }
-      wg_gemm_sub<T>(A + (k0 + nb) + (long long)(k0 + nb) * ld,
-                     A + (k0 + nb) + (long long)k0 * ld,
-                     A + k0 + (long long)(k0 + nb) * ld, ld, N - k0 - nb,
-                     N - k0 - nb, nb);
+      __syncthreads();
+      // rank-pw update of the rest of the block, rows below the panel; four
+      // columns per batch with all loads issued before the stores
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int row = p0 + tid + kLuThreads * q;
+        if (row >= p0 + pw && row < N) {
+          cplx_t<T> *a = A + row + (long long)(p0 + pw) * N;
+          for (int e0 = 0; e0 < wr; e0 += 4) {
+            double2 acc[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              acc[u] = e0 + u < wr ? to_d2(a[(long long)(e0 + u) * N]) : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+              for (int i = 0; i < kLuPW; ++i)
+                if (i < pw) acc[u] = cfms(acc[u], v[q][i], sm.big.U[i][e0 + u]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              if (e0 + u < wr) a[(long long)(e0 + u) * N] = from_d2<T>(acc[u]);
+          }
+        }
+      }
       __syncthreads();
     }
   }
+  // inverse of the block's unit-lower diagonal part, FP64, for the strips'
+  // U12 = L11^{-1} A12 products: four lanes per column j solve L x = e_j,
+  // lane s holding x[k] for k = s (mod 4)
+  {
+    for (int e = tid; e < kLuNB * kLuNB; e += kLuThreads) {
+      const int i = e % kLuNB, j = e / kLuNB;
+      sm.big.Ld[i][j] = (i < nb && j < nb) ? to_d2(A[(k0 + i) + (long long)(k0 + j) * N])
+                                           : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const int j = tid >> 2, sub = tid & 3;
+    double2 x[kLuNB / 4];
+#pragma unroll
+    for (int m = 0; m < kLuNB / 4; ++m) x[m] = make_double2((4 * m + sub == j) ? 1.0 : 0.0, 0.0);
+    for (int i = j + 1; i < nb; ++i) {
+      double2 part = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int m = 0; m < kLuNB / 4; ++m) {
+        const int kk = 4 * m + sub;
+        if (kk >= j && kk < i) part = cfma(part, sm.big.Ld[i][kk], x[m]);
+      }
+      part.x += __shfl_xor(part.x, 1);
+      part.y += __shfl_xor(part.y, 1);
+      part.x += __shfl_xor(part.x, 2);
+      part.y += __shfl_xor(part.y, 2);
+#pragma unroll
+      for (int m = 0; m < kLuNB / 4; ++m)
+        if (4 * m + sub == i) x[m] = make_double2(-part.x, -part.y);
+    }
+    cplx_t<T> *li = Linv + mb * (kLuNB * kLuNB);
+#pragma unroll
+    for (int m = 0; m < kLuNB / 4; ++m) li[(4 * m + sub) + kLuNB * j] = from_d2<T>(x[m]);
+    __syncthreads();
+  }
+  // net permutation of the block for the columns outside it
+  for (int r = k0 + tid; r < N; r += kLuThreads) sm.big.src[r] = r;
+  if (tid == 0) sm.count = 0;
+  __syncthreads();
+  if (tid == 0) {
+    for (int i = 0; i < nb; ++i) {
+      const int p = sm.piv[i];
+      const int t = sm.big.src[k0 + i];
+      sm.big.src[k0 + i] = sm.big.src[p];
+      sm.big.src[p] = t;
+    }
+  }
+  __syncthreads();
+  for (int r = k0 + tid; r < N; r += kLuThreads) {
+    const int s = sm.big.src[r];
+    if (s != r) {
+      const int e = atomicAdd(&sm.count, 1);
+      swp[1 + 2 * e] = r;
+      swp[2 + 2 * e] = s;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    swp[0] = sm.count;
+    // status: 0 ok, -2 exact zero pivot; a redo (only_failed) stays negative
+    // (-1: redone in FP64) so that its solve is redone too
+    if (k0 == 0) status[mb] = sm.zero_pivot ? -2 : (only_failed ? -1 : 0);
+    else if (sm.zero_pivot) status[mb] = -2;
+  }
 }
 
-template <typename T, int R>
-__global__ __launch_bounds__(kLuThreads) void lu_kernel(cplx_t<T> *Abase, int N,
-                                                        long long mstride, int *pivbase,
-                                                        int *status) {
-  __shared__ LuSmem sm;
-  cplx_t<T> *A = Abase + (long long)blockIdx.x * mstride;
-  int *piv = pivbase + (long long)blockIdx.x * N;
-  lu_factor<T, R>(A, N, piv, sm);
-  if (threadIdx.x == 0 && status) status[blockIdx.x] = sm.zero_pivot ? -2 : 0;
+constexpr int kStripW = 64;
+
+// One workgroup per (matrix, 64-column strip).  Strips left of the block
+// only receive the block's row permutation; strips right of it also get
+// U12 = L11^{-1} A12 and the update A22 -= L21 U12 down the whole strip.
+template <typename T>
+__global__ __launch_bounds__(kLuThreads) void lu_strip_kernel(
+    cplx_t<T> *Abase, int N, long long mstride, int k0, const int *swapbase,
+    const cplx_t<T> *Linv, int batch, int nleft, int nright, const int *status,
+    int only_failed) {
+  typedef cplx_t<T> T2;
+  typedef typename Mma<T>::acc acc_t;
+  __shared__ T2 sX[kLuNB][kStripW + 1];
+  __shared__ int spair[2 * kSwapMax];
+  // XCD-aware decode: block b runs on XCD b % 8; matrix m lives on XCD m % 8
+  const int b = blockIdx.x, xcd = b & 7, idx = b >> 3;
+  const int ns = nleft + nright;
+  const int mat = xcd + 8 * (idx / ns), s = idx % ns;
+  if (mat >= batch) return;
+  if (only_failed && status[mat] >= 0) return;
+  T2 *A = Abase + (long long)mat * mstride;
+  const int *swp = swapbase + (long long)mat * kSwapStride;
+  const int tid = threadIdx.x;
+  const int nb = min(kLuNB, N - k0);
+  const bool right = s >= nleft;
+  const int c0 = right ? k0 + nb + (s - nleft) * kStripW : s * kStripW;
+  const int cw = min(kStripW, (right ? N : k0) - c0);
+  // ---- row permutation as a gather (read every source, then write), 32
+  // columns at a time through LDS
+  const int npair = swp[0];
+  for (int e = tid; e < 2 * npair; e += kLuThreads) spair[e] = swp[1 + e];
+  __syncthreads();
+  T2 *tmpb = &sX[0][0];  // viewed as [32][kSwapMax + 2]
+  for (int half = 0; half < 2; ++half) {
+    const int cb0 = half * 32;
+    for (int e = tid; e < 32 * npair; e += kLuThreads) {
+      const int c = e & 31, j = e >> 5;
+      if (cb0 + c < cw) tmpb[c * (kSwapMax + 2) + j] = A[spair[2 * j + 1] + (long long)(c0 + cb0 + c) * N];
+    }
+    __syncthreads();
+    for (int e = tid; e < 32 * npair; e += kLuThreads) {
+      const int c = e & 31, j = e >> 5;
+      if (cb0 + c < cw) A[spair[2 * j] + (long long)(c0 + cb0 + c) * N] = tmpb[c * (kSwapMax + 2) + j];
+    }
+    __syncthreads();
+  }
+  if (!right) return;
+  // ---- U12 for this strip: X = L11^{-1} A12 on the matrix cores, with
+  // the inverse from the panel kernel; A12 in LDS as the B operand, the
+  // product kept in registers, then written over it (and to memory)
+  const int lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int kpad = (nb + 3) & ~3;
+  for (int e = tid; e < kLuNB * kStripW; e += kLuThreads) {
+    const int r = e / kStripW, c = e % kStripW;
+    sX[r][c] = (r < nb && c < cw) ? A[(k0 + r) + (long long)(c0 + c) * N] : mk<T>(0, 0);
+  }
+  __syncthreads();
+  {
+    const T2 *lv = Linv + (long long)mat * (kLuNB * kLuNB);
+    acc_t xr[4], xi[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        xr[cb][r] = 0;
+        xi[cb][r] = 0;
+      }
+    const int arow = 16 * wave + li;
+#pragma unroll 1
+    for (int kk = 0; kk < kpad; kk += 4) {
+      const T2 fa = lv[arow + kLuNB * (kk + lk)];
+      const T ar = fa.x, ai = fa.y, nai = -fa.y;
+      T br[4], bi[4];
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        const T2 bv = sX[kk + lk][cb * 16 + li];
+        br[cb] = bv.x;
+        bi[cb] = bv.y;
+      }
+      // X + Linv A12:  re += Ar Br - Ai Bi ;  im += Ar Bi + Ai Br
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        xr[cb] = Mma<T>::run(ar, br[cb], xr[cb]);
+        xi[cb] = Mma<T>::run(ar, bi[cb], xi[cb]);
+      }
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        xr[cb] = Mma<T>::run(nai, bi[cb], xr[cb]);
+        xi[cb] = Mma<T>::run(ai, br[cb], xi[cb]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * wave + Mma<T>::crow(lk, r), col = cb * 16 + li;
+        const T2 v = mk<T>(xr[cb][r], xi[cb][r]);
+        sX[row][col] = v;
+        if (row < nb && col < cw) A[(k0 + row) + (long long)(c0 + col) * N] = v;
+      }
+    __syncthreads();
+  }
+  // ---- A22 -= L21 U12 down the strip: each wave owns 16 rows x 64 columns
+  for (int r0 = k0 + nb; r0 < N; r0 += 64) {
+    const int rw = r0 + 16 * wave;  // first row of this wave
+    if (rw >= N) continue;
+    acc_t cr[4], ci[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      const int col = cb * 16 + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rw + Mma<T>::crow(lk, r);
+        T2 v = mk<T>(0, 0);
+        if (row < N && col < cw) v = A[row + (long long)(c0 + col) * N];
+        cr[cb][r] = v.x;
+        ci[cb][r] = v.y;
+      }
+    }
+    const int arow = rw + li;
+    const T2 *ap = A + arow + (long long)k0 * N;
+    T2 fa = (arow < N && lk < nb) ? ap[(long long)lk * N] : mk<T>(0, 0);
+#pragma unroll 1
+    for (int kk = 0; kk < kpad; kk += 4) {
+      const T ar = -fa.x, ai = -fa.y, pai = fa.y;
+      const int kn = kk + 4 + lk;
+      if (kk + 4 < kpad) fa = (arow < N && kn < nb) ? ap[(long long)kn * N] : mk<T>(0, 0);
+      T br[4], bi[4];
+      const int krow = kk + lk;
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        const T2 bv = krow < nb ? sX[krow][cb * 16 + li] : mk<T>(0, 0);
+        br[cb] = bv.x;
+        bi[cb] = bv.y;
+      }
+      // C - A B:  re += (-Ar) Br + Ai Bi ;  im += (-Ar) Bi + (-Ai) Br
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        cr[cb] = Mma<T>::run(ar, br[cb], cr[cb]);
+        ci[cb] = Mma<T>::run(ar, bi[cb], ci[cb]);
+      }
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        cr[cb] = Mma<T>::run(pai, bi[cb], cr[cb]);
+        ci[cb] = Mma<T>::run(ai, br[cb], ci[cb]);
+      }
+    }
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      const int col = cb * 16 + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rw + Mma<T>::crow(lk, r);
+        if (row < N && col < cw) A[row + (long long)(c0 + col) * N] = mk<T>(cr[cb][r], ci[cb][r]);
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -459,8 +603,6 @@ __device__ void lu_solve_lds(const cplx_t<T> *LU, const int *piv, double2 *y, in
     __syncthreads();
   }
 }
-
-constexpr int kMaxN = 1024;
 
 // alpha = A^{-1} b from FP64 factors.
 __global__ __launch_bounds__(kLuThreads) void lu_solve64_kernel(
@@ -552,24 +694,20 @@ __global__ __launch_bounds__(kLuThreads) void refine_kernel(
   }
 }
 
-// FP64 redo of the solves whose refined status is negative: factor the
-// FP64 matrix in place and solve.
-template <int R>
-__global__ __launch_bounds__(kLuThreads) void fallback64_kernel(
-    double2 *A64base, int *pivbase, int N, long long mstride, const double2 *b,
-    double2 *x, long long vstride, int *status) {
-  __shared__ LuSmem sm;
+// Solve for the matrices whose status is negative (FP64 redo after a
+// refined solve that did not converge): x = A^{-1} b from FP64 factors.
+__global__ __launch_bounds__(kLuThreads) void solve_failed64_kernel(
+    const double2 *LUbase, const int *pivbase, int N, long long mstride, const double2 *b,
+    double2 *x, long long vstride, const int *status) {
   __shared__ double2 y[kMaxN];
-  const long long mb = (long long)blockIdx.x;
+  const long long mb = blockIdx.x;
   if (status[mb] >= 0) return;
-  double2 *A = A64base + mb * mstride;
-  int *piv = pivbase + mb * N;
-  lu_factor<double, R>(A, N, piv, sm);
+  const double2 *LU = LUbase + mb * mstride;
+  const int *piv = pivbase + mb * N;
   for (int i = threadIdx.x; i < N; i += kLuThreads) y[i] = b[mb * vstride + i];
   __syncthreads();
-  lu_solve_lds<double>(A, piv, y, N);
+  lu_solve_lds<double>(LU, piv, y, N);
   for (int i = threadIdx.x; i < N; i += kLuThreads) x[mb * vstride + i] = y[i];
-  if (threadIdx.x == 0) status[mb] = sm.zero_pivot ? -2 : -1;
 }
 
 }  // namespace fthms

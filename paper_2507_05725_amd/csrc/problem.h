@@ -305,7 +305,7 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
   for (int j = 0; j < J; ++j) {
     const size_t n = pb->arcs[j]->n;
     per += n * n * sizeof(double2) + (fp32 ? n * n * sizeof(float2) : 0) + n * sizeof(int) +
-           4 * n * sizeof(double2) + sizeof(int) + sizeof(double) + 2048;
+           kLuScratchBytes + 4 * n * sizeof(double2) + sizeof(int) + sizeof(double) + 2048;
     nsum += (int)n;
   }
   size_t cap = (size_t)16 << 30;
@@ -322,13 +322,14 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
     double2 *A64;
     float2 *A32;
     int *piv, *status;
+    void *swp;
     double *relres;
     double2 *b, *al, *cr, *tot;
   };
   std::vector<ArcWs> w(J);
   {
     size_t off = 0;
-    std::vector<size_t> o(J * 10);
+    std::vector<size_t> o(J * 11);
     auto take = [&](size_t bytes) {
       size_t r = off;
       off += (bytes + 255) & ~(size_t)255;
@@ -342,6 +343,7 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
       o[10 * j + 3] = take(sizeof(int) * C);
       o[10 * j + 4] = take(sizeof(double) * C);
       for (int v = 0; v < 4; ++v) o[10 * j + 5 + v] = take(n * sizeof(double2) * C);
+      o[10 * j + 9] = take(kLuScratchBytes * C);
     }
     if ((rc = ensure_ws(ctx, off))) return rc;
     char *base = (char *)ctx->ws;
@@ -355,6 +357,7 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
       w[j].al = (double2 *)(base + o[10 * j + 6]);
       w[j].cr = (double2 *)(base + o[10 * j + 7]);
       w[j].tot = (double2 *)(base + o[10 * j + 8]);
+      w[j].swp = (void *)(base + o[10 * j + 9]);
     }
   }
   auto solve_arc = [&](int j, int c) -> int {
@@ -375,7 +378,8 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
     int r = check_launch(ctx, "refine_kernel");
     if (r) return r;
     tbeg(ctx, "fallback");
-    r = launch_fallback(ctx, w[j].A64, n, ms, w[j].piv, w[j].b, w[j].al, w[j].status, c);
+    r = launch_fallback(ctx, w[j].A64, n, ms, w[j].piv, w[j].swp, w[j].b, w[j].al, w[j].status,
+                        c);
     tend(ctx);
     return r;
   };
@@ -392,7 +396,7 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
       if (rc) return rc;
       tbeg(ctx, "lu");
       rc = launch_lu(ctx, fp32, fp32 ? (void *)w[j].A32 : (void *)w[j].A64, n, (long long)n * n,
-                     w[j].piv, w[j].status, c);
+                     w[j].piv, w[j].swp, w[j].status, c);
       tend(ctx);
       if (rc) return rc;
       tbeg(ctx, "rhs");
