@@ -135,6 +135,18 @@ def main():
               ("assemble", "lu", "solve", "fallback", "rhs", "field", "freq_to_time")}
         results[p] = dict(total=total, lat=lat, kt=kt)
 
+    # refinement steps taken, on a sample of 512 wavenumbers
+    ks = k[:: NK // 512].contiguous()
+    rhs_s = torch.empty((ks.numel(), N_ARC), dtype=torch.complex128, device=dev)
+    al_s = torch.empty_like(rhs_s)
+    it_s = torch.empty(ks.numel(), dtype=torch.int32, device=dev)
+    ctx.rhs_dev(arc, ks, case["incident"], rhs_s)
+    ctx.solve_dev(arc, ks, rhs_s, al_s, fth.FP32_REFINED, 0.0, it_s)
+    torch.cuda.synchronize()
+    its = it_s.cpu().numpy()
+    iter_stats = {"mean": round(float(its[its > 0].mean()), 3) if np.any(its > 0) else None,
+                  "max": int(its.max()), "redone_fp64": int(np.sum(its == -1))}
+
     # accuracy of the refined form against the FP64 form, every solve
     a64, a32 = A[fth.FP64], A[fth.FP32_REFINED]
     err = (torch.linalg.vector_norm(a32 - a64, dim=1) /
@@ -193,6 +205,7 @@ def main():
         "refined_over_fp64": round(value / fp64_value, 3),
         "max_rel_err_refined_vs_fp64": err,
         "trace_rel_err_refined_vs_fp64": uerr,
+        "refinement_steps": iter_stats,
         "max_rel_err_vs_oracle_sampled": oracle_err,
         "latency_ms_per_batch": {"p50": round(float(np.percentile(lat32, 50)), 3),
                                  "p99": round(float(np.percentile(lat32, 99)), 3)},

@@ -143,7 +143,7 @@ int fthms_arc_size(const fthms_arc *arc);
  * A alpha = rhs[i].  rhs, alpha: [nk][n].  precision FTHMS_FP64 factors in
  * complex FP64; FTHMS_FP32_REFINED factors in complex FP32 (MFMA trailing
  * updates, FP64 panel pivoting) and refines with FP64 residuals until the
- * predicted relative error of alpha is below tol (tol <= 0: 1e-13), at most
+ * predicted relative error of alpha is below tol (tol <= 0: 1e-12), at most
  * 10 iterations; solves that do not converge are redone in FP64.
  * iters[nk] (optional) receives the refinement steps per solve (0 for
  * FP64, -1 for a solve redone in FP64); relres[nk] (optional) the last

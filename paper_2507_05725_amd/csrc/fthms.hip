@@ -499,7 +499,7 @@ static int solve_dev_impl(fthms_ctx *ctx, const fthms_arc *arc, int nk, const do
                           int *iters_dev, double *relres_dev) {
   const int N = arc->n;
   const bool fp32 = precision == FTHMS_FP32_REFINED;
-  if (tol <= 0.0) tol = 1e-13;
+  if (tol <= 0.0) tol = 1e-12;
   SolveWs w;
   int rc = solve_ws(ctx, N, fp32, nk, w);
   if (rc) return rc;

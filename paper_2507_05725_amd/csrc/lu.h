@@ -67,11 +67,20 @@ struct LuSmem {
   int npr;
   int count;
   int zero_pivot;
-  union {  // phases of the panel kernel never overlap
-    double2 U[kLuPW][kLuNB];           // in-block update
-    double2 gat[kLuNB][2 * kLuPW];     // in-block row gather
-    int src[kMaxN];                    // block permutation
-    double2 Ld[kLuNB][kLuNB + 1];      // diagonal block for its inverse
+  int src[kMaxN];  // cumulative row permutation of the block
+  // running inverse of the block's unit-lower part, packed lower triangle:
+  // element (r, c), c <= r, at r (r + 1) / 2 + c
+  double2 li[kLuNB * (kLuNB + 1) / 2];
+  union {          // phases of one inner panel never overlap
+    struct {
+      double2 top[kLuNB][kLuPW];  // rows k0..p0 of the panel columns
+      double2 ut[kLuNB][kLuPW];   // U rows k0..p0 of the panel columns
+    } a;
+    double2 gat[kLuNB][2 * kLuPW];  // in-block row gather
+    struct {
+      double2 lrow[kLuPW][kLuNB];  // new rows of L11 (previous columns)
+      double2 tm[kLuPW][kLuNB];    // their product with the running inverse
+    } c;
   } big;
 };
 
@@ -185,28 +194,60 @@ __device__ __forceinline__ void panel_factor_regs(double2 (&v)[R][kLuPW], int N,
   }
 }
 
+__device__ __forceinline__ int tri(int r, int c) { return (r * (r + 1) >> 1) + c; }
+
 // Factor the block of columns [k0, k0 + nb) of one matrix (all rows >= k0),
-// record the pivots, and emit the block's net row permutation for the
-// columns outside it: swp[0] = count, then count (dst, src) pairs meaning
-// "new row dst = old row src".
+// left-looking inside the block: each 8-column inner panel first receives
+// every earlier panel's contribution -- its U rows as U = L11inv A (the
+// running inverse of the block's unit-lower part, kept in memory) and its
+// lower rows as A -= L U with all loads of earlier L columns issued in
+// batches -- and is then factored in registers.  The running inverse is
+// extended by the panel's rows with the block-inverse formula
+// [La 0; Lb Lpp]^-1 = [La^-1 0; -Lpp^-1 Lb La^-1  Lpp^-1], and is what the
+// strip kernel multiplies by.  Outputs: factored block, pivots, L11inv
+// (64 x 64, column-major, zero above the diagonal) and the block's net row
+// permutation for the columns outside it: swp[0] = count, then (dst, src)
+// pairs meaning "new row dst = old row src".
 template <typename T, int R>
 __global__ __launch_bounds__(kLuThreads) void lu_panel_kernel(cplx_t<T> *Abase, int N,
                                                               long long mstride, int k0,
                                                               int *pivbase, int *swapbase,
                                                               cplx_t<T> *Linv, int *status,
                                                               int only_failed) {
+  typedef cplx_t<T> T2;
   __shared__ LuSmem sm;
   const long long mb = blockIdx.x;
   if (only_failed && status[mb] >= 0) return;
-  cplx_t<T> *A = Abase + mb * mstride;
+  T2 *A = Abase + mb * mstride;
   int *piv = pivbase + mb * N;
   int *swp = swapbase + mb * kSwapStride;
+  T2 *Li = Linv + mb * (kLuNB * kLuNB);
   const int tid = threadIdx.x;
   const int nb = min(kLuNB, N - k0);
   if (tid == 0) sm.zero_pivot = 0;
+  for (int r = k0 + tid; r < N; r += kLuThreads) sm.src[r] = r;
   __syncthreads();
   for (int p0 = k0; p0 < k0 + nb; p0 += kLuPW) {
     const int pw = min(kLuPW, k0 + nb - p0);
+    const int lead = p0 - k0;
+    if (lead > 0) {
+      // U rows of the panel columns: U = L11inv(lead) A(rows k0..p0)
+      for (int e = tid; e < lead * kLuPW; e += kLuThreads) {
+        const int r = e / kLuPW, c = e % kLuPW;
+        sm.big.a.top[r][c] = c < pw ? to_d2(A[(k0 + r) + (long long)(p0 + c) * N])
+                                    : make_double2(0.0, 0.0);
+      }
+      __syncthreads();
+      for (int e = tid; e < lead * kLuPW; e += kLuThreads) {
+        const int r = e / kLuPW, c = e % kLuPW;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int j = 0; j <= r; ++j) acc = cfma(acc, sm.li[tri(r, j)], sm.big.a.top[j][c]);
+        sm.big.a.ut[r][c] = acc;
+        if (c < pw) A[(k0 + r) + (long long)(p0 + c) * N] = from_d2<T>(acc);
+      }
+      __syncthreads();
+    }
+    // lower rows of the panel: load and apply every earlier panel at once
     double2 v[R][kLuPW];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
@@ -216,9 +257,32 @@ __global__ __launch_bounds__(kLuThreads) void lu_panel_kernel(cplx_t<T> *Abase, 
         v[q][c] = (row < N && c < pw) ? to_d2(A[row + (long long)(p0 + c) * N])
                                       : make_double2(0.0, 0.0);
     }
+    // earlier L columns, 8 at a time (independent read-only loads)
+    for (int j0 = 0; j0 < lead; j0 += kLuPW) {
+      T2 lv[R][kLuPW];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int row = p0 + tid + kLuThreads * q;
+#pragma unroll
+        for (int t = 0; t < kLuPW; ++t)
+          lv[q][t] = row < N ? A[row + (long long)(k0 + j0 + t) * N] : mk<T>(0, 0);
+      }
+#pragma unroll
+      for (int t = 0; t < kLuPW; ++t) {
+        // keep the scheduler from hoisting all 64 LDS reads of U at once
+        asm volatile("" ::: "memory");
+        double2 u[kLuPW];
+#pragma unroll
+        for (int c = 0; c < kLuPW; ++c) u[c] = sm.big.a.ut[j0 + t][c];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const double2 l = to_d2(lv[q][t]);
+#pragma unroll
+          for (int c = 0; c < kLuPW; ++c) v[q][c] = cfms(v[q][c], l, u[c]);
+        }
+      }
+    }
     panel_factor_regs<R>(v, N, p0, pw, k0, piv, sm);
-    // write the factored panel back; the diagonal block's unit-lower part
-    // goes to LDS for the in-block triangular solve
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int row = p0 + tid + kLuThreads * q;
@@ -231,26 +295,55 @@ __global__ __launch_bounds__(kLuThreads) void lu_panel_kernel(cplx_t<T> *Abase, 
 #pragma unroll
       for (int c = 0; c < kLuPW; ++c) sm.L[tid][c] = v[0][c];
     }
-    // row swaps of this panel inside the block, left and right of it, as a
-    // gather over the panel's net permutation (<= 16 rows)
-    if (tid == 0) {
-      int n = 0;
+    // net permutation of this panel (<= 16 rows) by wave 0, one map entry
+    // per lane; also folded into the block's cumulative permutation
+    if (tid < 64) {
+      const int lane = tid;
+      int myrow = -1, mysrc = -1, n = 0;
       for (int i = 0; i < pw; ++i) {
         const int r1 = p0 + i, r2 = sm.piv[p0 - k0 + i];
-        int a = -1, b = -1;
-        for (int e = 0; e < n; ++e) {
-          if (sm.pr_row[e] == r1) a = e;
-          if (sm.pr_row[e] == r2) b = e;
+        unsigned long long m1 = __ballot(myrow == r1);
+        int a;
+        if (m1 == 0ULL) {
+          a = n++;
+          if (lane == a) {
+            myrow = r1;
+            mysrc = r1;
+          }
+        } else {
+          a = __ffsll((long long)m1) - 1;
         }
-        if (a < 0) { sm.pr_row[n] = r1; sm.pr_src[n] = r1; a = n++; }
-        if (b < 0) { sm.pr_row[n] = r2; sm.pr_src[n] = r2; b = n++; }
-        const int t = sm.pr_src[a];
-        sm.pr_src[a] = sm.pr_src[b];
-        sm.pr_src[b] = t;
+        unsigned long long m2 = __ballot(myrow == r2);
+        int b;
+        if (m2 == 0ULL) {
+          b = n++;
+          if (lane == b) {
+            myrow = r2;
+            mysrc = r2;
+          }
+        } else {
+          b = __ffsll((long long)m2) - 1;
+        }
+        const int sa = __shfl(mysrc, a), sb = __shfl(mysrc, b);
+        if (lane == a) mysrc = sb;
+        if (lane == b) mysrc = sa;
       }
-      sm.npr = n;
+      if (lane < n) {
+        sm.pr_row[lane] = myrow;
+        sm.pr_src[lane] = mysrc;
+      }
+      if (lane == 0) {
+        sm.npr = n;
+        for (int i = 0; i < pw; ++i) {
+          const int r1 = p0 + i, r2 = sm.piv[p0 - k0 + i];
+          const int u = sm.src[r1];
+          sm.src[r1] = sm.src[r2];
+          sm.src[r2] = u;
+        }
+      }
     }
     __syncthreads();
+    // the panel's row swaps for the other block columns, as a gather
     const int wl = p0 - k0, wr = k0 + nb - p0 - pw;
     const int npr = sm.npr;
     for (int e = tid; e < (wl + wr) * npr; e += kLuThreads) {
@@ -265,100 +358,52 @@ __global__ __launch_bounds__(kLuThreads) void lu_panel_kernel(cplx_t<T> *Abase, 
       A[sm.pr_row[j] + (long long)col * N] = from_d2<T>(sm.big.gat[ce][j]);
     }
     __syncthreads();
-    if (wr > 0) {
-      // U rows of this panel for the rest of the block: L11^{-1} A12
-      for (int e = tid; e < wr; e += kLuThreads) {
-        const int col = p0 + pw + e;
-        cplx_t<T> *a = A + (long long)col * N + p0;
-        double2 x[kLuPW];
-#pragma unroll
-        for (int i = 0; i < kLuPW; ++i) x[i] = i < pw ? to_d2(a[i]) : make_double2(0.0, 0.0);
-#pragma unroll
-        for (int i = 1; i < kLuPW; ++i)
-#pragma unroll
-          for (int j = 0; j < i; ++j) x[i] = cfms(x[i], sm.L[i][j], x[j]);
-#pragma unroll
-        for (int i = 0; i < kLuPW; ++i) {
-          if (i < pw) a[i] = from_d2<T>(x[i]);
-          sm.big.U[i][e] = x[i];
-        }
-      }
-      __syncthreads();
-      // rank-pw update of the rest of the block, rows below the panel; four
-      // columns per batch with all loads issued before the stores
-#pragma unroll
-      for (int q = 0; q < R; ++q) {
-        const int row = p0 + tid + kLuThreads * q;
-        if (row >= p0 + pw && row < N) {
-          cplx_t<T> *a = A + row + (long long)(p0 + pw) * N;
-          for (int e0 = 0; e0 < wr; e0 += 4) {
-            double2 acc[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-              acc[u] = e0 + u < wr ? to_d2(a[(long long)(e0 + u) * N]) : make_double2(0.0, 0.0);
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-              for (int i = 0; i < kLuPW; ++i)
-                if (i < pw) acc[u] = cfms(acc[u], v[q][i], sm.big.U[i][e0 + u]);
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-              if (e0 + u < wr) a[(long long)(e0 + u) * N] = from_d2<T>(acc[u]);
-          }
-        }
-      }
-      __syncthreads();
+    // extend the running inverse by this panel's rows
+    for (int e = tid; e < pw * lead; e += kLuThreads) {
+      const int t = e / lead, j = e % lead;
+      sm.big.c.lrow[t][j] = to_d2(A[(p0 + t) + (long long)(k0 + j) * N]);
     }
+    __syncthreads();
+    for (int e = tid; e < pw * lead; e += kLuThreads) {
+      const int t = e / lead, cc = e % lead;
+      double2 acc = make_double2(0.0, 0.0);
+      for (int j = cc; j < lead; ++j) acc = cfma(acc, sm.big.c.lrow[t][j], sm.li[tri(j, cc)]);
+      sm.big.c.tm[t][cc] = acc;
+    }
+    __syncthreads();
+    if (tid < lead + pw) {
+      const int cc = tid;
+      double2 x[kLuPW];
+#pragma unroll
+      for (int t = 0; t < kLuPW; ++t) {
+        if (cc < lead) {
+          x[t] = t < pw ? make_double2(-sm.big.c.tm[t][cc].x, -sm.big.c.tm[t][cc].y)
+                        : make_double2(0.0, 0.0);
+        } else {
+          x[t] = make_double2(t == cc - lead ? 1.0 : 0.0, 0.0);
+        }
+      }
+#pragma unroll
+      for (int t = 1; t < kLuPW; ++t)
+#pragma unroll
+        for (int j = 0; j < t; ++j) x[t] = cfms(x[t], sm.L[t][j], x[j]);
+#pragma unroll
+      for (int t = 0; t < kLuPW; ++t)
+        if (t < pw && cc <= lead + t) sm.li[tri(lead + t, cc)] = x[t];
+    }
+    __syncthreads();
   }
-  // inverse of the block's unit-lower diagonal part, FP64, for the strips'
-  // U12 = L11^{-1} A12 products: four lanes per column j solve L x = e_j,
-  // lane s holding x[k] for k = s (mod 4)
-  {
-    for (int e = tid; e < kLuNB * kLuNB; e += kLuThreads) {
-      const int i = e % kLuNB, j = e / kLuNB;
-      sm.big.Ld[i][j] = (i < nb && j < nb) ? to_d2(A[(k0 + i) + (long long)(k0 + j) * N])
-                                           : make_double2(0.0, 0.0);
-    }
-    __syncthreads();
-    const int j = tid >> 2, sub = tid & 3;
-    double2 x[kLuNB / 4];
-#pragma unroll
-    for (int m = 0; m < kLuNB / 4; ++m) x[m] = make_double2((4 * m + sub == j) ? 1.0 : 0.0, 0.0);
-    for (int i = j + 1; i < nb; ++i) {
-      double2 part = make_double2(0.0, 0.0);
-#pragma unroll
-      for (int m = 0; m < kLuNB / 4; ++m) {
-        const int kk = 4 * m + sub;
-        if (kk >= j && kk < i) part = cfma(part, sm.big.Ld[i][kk], x[m]);
-      }
-      part.x += __shfl_xor(part.x, 1);
-      part.y += __shfl_xor(part.y, 1);
-      part.x += __shfl_xor(part.x, 2);
-      part.y += __shfl_xor(part.y, 2);
-#pragma unroll
-      for (int m = 0; m < kLuNB / 4; ++m)
-        if (4 * m + sub == i) x[m] = make_double2(-part.x, -part.y);
-    }
-    cplx_t<T> *li = Linv + mb * (kLuNB * kLuNB);
-#pragma unroll
-    for (int m = 0; m < kLuNB / 4; ++m) li[(4 * m + sub) + kLuNB * j] = from_d2<T>(x[m]);
-    __syncthreads();
+  // the inverse for the strips: full 64 x 64, column-major, zero above the
+  // diagonal and outside the block
+  for (int e = tid; e < kLuNB * kLuNB; e += kLuThreads) {
+    const int r = e % kLuNB, c = e / kLuNB;
+    Li[e] = (c <= r && r < nb) ? from_d2<T>(sm.li[tri(r, c)]) : mk<T>(0, 0);
   }
   // net permutation of the block for the columns outside it
-  for (int r = k0 + tid; r < N; r += kLuThreads) sm.big.src[r] = r;
   if (tid == 0) sm.count = 0;
   __syncthreads();
-  if (tid == 0) {
-    for (int i = 0; i < nb; ++i) {
-      const int p = sm.piv[i];
-      const int t = sm.big.src[k0 + i];
-      sm.big.src[k0 + i] = sm.big.src[p];
-      sm.big.src[p] = t;
-    }
-  }
-  __syncthreads();
   for (int r = k0 + tid; r < N; r += kLuThreads) {
-    const int s = sm.big.src[r];
+    const int s = sm.src[r];
     if (s != r) {
       const int e = atomicAdd(&sm.count, 1);
       swp[1 + 2 * e] = r;
@@ -380,8 +425,10 @@ constexpr int kStripW = 64;
 // One workgroup per (matrix, 64-column strip).  Strips left of the block
 // only receive the block's row permutation; strips right of it also get
 // U12 = L11^{-1} A12 and the update A22 -= L21 U12 down the whole strip.
+// occupancy target: FP64 strips are LDS-bound at 2 workgroups per CU, FP32
+// strips fit 4 (register budget 256 and 128 per lane)
 template <typename T>
-__global__ __launch_bounds__(kLuThreads) void lu_strip_kernel(
+__global__ __launch_bounds__(kLuThreads, sizeof(T) == 8 ? 2 : 4) void lu_strip_kernel(
     cplx_t<T> *Abase, int N, long long mstride, int k0, const int *swapbase,
     const cplx_t<T> *Linv, int batch, int nleft, int nright, const int *status,
     int only_failed) {
@@ -495,32 +542,39 @@ __global__ __launch_bounds__(kLuThreads) void lu_strip_kernel(
         ci[cb][r] = v.y;
       }
     }
+    // all L21 fragments of this tile in one round trip
     const int arow = rw + li;
     const T2 *ap = A + arow + (long long)k0 * N;
-    T2 fa = (arow < N && lk < nb) ? ap[(long long)lk * N] : mk<T>(0, 0);
-#pragma unroll 1
-    for (int kk = 0; kk < kpad; kk += 4) {
-      const T ar = -fa.x, ai = -fa.y, pai = fa.y;
-      const int kn = kk + 4 + lk;
-      if (kk + 4 < kpad) fa = (arow < N && kn < nb) ? ap[(long long)kn * N] : mk<T>(0, 0);
-      T br[4], bi[4];
-      const int krow = kk + lk;
+    T2 fa[kLuNB / 4];
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
-        const T2 bv = krow < nb ? sX[krow][cb * 16 + li] : mk<T>(0, 0);
-        br[cb] = bv.x;
-        bi[cb] = bv.y;
-      }
-      // C - A B:  re += (-Ar) Br + Ai Bi ;  im += (-Ar) Bi + (-Ai) Br
+    for (int st = 0; st < kLuNB / 4; ++st) {
+      const int kc = 4 * st + lk;
+      fa[st] = (arow < N && kc < nb) ? ap[(long long)kc * N] : mk<T>(0, 0);
+    }
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
-        cr[cb] = Mma<T>::run(ar, br[cb], cr[cb]);
-        ci[cb] = Mma<T>::run(ar, bi[cb], ci[cb]);
-      }
+    for (int st = 0; st < kLuNB / 4; ++st) {
+      const int kk = 4 * st;
+      if (kk < kpad) {
+        const T ar = -fa[st].x, ai = -fa[st].y, pai = fa[st].y;
+        T br[4], bi[4];
+        const int krow = kk + lk;
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
-        cr[cb] = Mma<T>::run(pai, bi[cb], cr[cb]);
-        ci[cb] = Mma<T>::run(ai, br[cb], ci[cb]);
+        for (int cb = 0; cb < 4; ++cb) {
+          const T2 bv = sX[krow][cb * 16 + li];
+          br[cb] = bv.x;
+          bi[cb] = bv.y;
+        }
+        // C - A B:  re += (-Ar) Br + Ai Bi ;  im += (-Ar) Bi + (-Ai) Br
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          cr[cb] = Mma<T>::run(ar, br[cb], cr[cb]);
+          ci[cb] = Mma<T>::run(ar, bi[cb], ci[cb]);
+        }
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          cr[cb] = Mma<T>::run(pai, bi[cb], cr[cb]);
+          ci[cb] = Mma<T>::run(ai, br[cb], ci[cb]);
+        }
       }
     }
 #pragma unroll
@@ -543,9 +597,40 @@ __device__ __forceinline__ double2 ld2(const cplx_t<T> *p) {
   return to_d2(*p);
 }
 
+// acc -= sum_{c < n} col[c * stride] * y[c]: column sweep of one row with
+// the next 8-element batch of loads in flight while the current one is used
+template <typename P>
+__device__ __forceinline__ double2 row_sweep(double2 acc, const P *col, long long stride,
+                                             const double2 *y, int n) {
+  constexpr int B = 8;
+  P cur[B], nxt[B];
+#pragma unroll
+  for (int u = 0; u < B; ++u)
+    if (u < n) nxt[u] = col[(long long)u * stride];
+#pragma unroll 1
+  for (int c0 = 0; c0 < n; c0 += B) {
+#pragma unroll
+    for (int u = 0; u < B; ++u) cur[u] = nxt[u];
+    if (c0 + B < n) {
+#pragma unroll
+      for (int u = 0; u < B; ++u)
+        if (c0 + B + u < n) nxt[u] = col[(long long)(c0 + B + u) * stride];
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+      if (c0 + u < n) acc = cfms(acc, to_d2(cur[u]), y[c0 + u]);
+  }
+  return acc;
+}
+
 // y := U^{-1} L^{-1} P y for the factors in LU (column-major, ld = N).
+// Each 64 x 64 diagonal block is staged in LDS (D, element (r, c) at
+// D[r][(c + r) & 63] so that column reads are bank-conflict free) with one
+// coalesced load, so wave 0's 64-step substitution reads only LDS; the
+// off-diagonal block columns are applied by all threads with batched loads.
 template <typename T>
-__device__ void lu_solve_lds(const cplx_t<T> *LU, const int *piv, double2 *y, int N) {
+__device__ void lu_solve_lds(const cplx_t<T> *LU, const int *piv, double2 *y, int N,
+                             cplx_t<T> (*D)[64]) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) {
     for (int i = 0; i < N; ++i) {
@@ -557,63 +642,52 @@ __device__ void lu_solve_lds(const cplx_t<T> *LU, const int *piv, double2 *y, in
       }
     }
   }
-  __syncthreads();
-  for (int jb = 0; jb < N; jb += 64) {
-    const int nb = min(64, N - jb);
-    if (wave == 0) {
-      double2 yi = lane < nb ? y[jb + lane] : make_double2(0.0, 0.0);
-      for (int c = 0; c < nb - 1; ++c) {
-        const double2 yc = make_double2(__shfl(yi.x, c), __shfl(yi.y, c));
-        if (lane > c && lane < nb)
-          yi = cfms(yi, ld2<T>(LU + (jb + lane) + (long long)(jb + c) * N), yc);
-      }
-      if (lane < nb) y[jb + lane] = yi;
-    }
-    __syncthreads();
-    for (int r = jb + nb + tid; r < N; r += kLuThreads) {
-      double2 acc = y[r];
-      for (int c = 0; c < nb; ++c)
-        acc = cfms(acc, ld2<T>(LU + r + (long long)(jb + c) * N), y[jb + c]);
-      y[r] = acc;
-    }
-    __syncthreads();
-  }
   const int nblk = (N + 63) / 64;
-  for (int bi = nblk - 1; bi >= 0; --bi) {
-    const int jb = bi * 64;
+  for (int bi = 0; bi < 2 * nblk; ++bi) {
+    const bool fwd = bi < nblk;
+    const int jb = (fwd ? bi : 2 * nblk - 1 - bi) * 64;
     const int nb = min(64, N - jb);
+    for (int e = tid; e < 64 * 64; e += kLuThreads) {
+      const int r = e & 63, c = e >> 6;
+      D[r][(c + r) & 63] = (r < nb && c < nb) ? LU[(jb + r) + (long long)(jb + c) * N] : mk<T>(0, 0);
+    }
+    __syncthreads();
     if (wave == 0) {
       double2 yi = lane < nb ? y[jb + lane] : make_double2(0.0, 0.0);
-      for (int c = nb - 1; c >= 0; --c) {
-        if (lane == c)
-          yi = cmul(yi, crcp(ld2<T>(LU + (jb + c) + (long long)(jb + c) * N)));
-        const double2 yc = make_double2(__shfl(yi.x, c), __shfl(yi.y, c));
-        if (lane < c)
-          yi = cfms(yi, ld2<T>(LU + (jb + lane) + (long long)(jb + c) * N), yc);
+      if (fwd) {
+        for (int c = 0; c < nb - 1; ++c) {
+          const double2 yc = make_double2(__shfl(yi.x, c), __shfl(yi.y, c));
+          if (lane > c && lane < nb) yi = cfms(yi, to_d2(D[lane][(c + lane) & 63]), yc);
+        }
+      } else {
+        for (int c = nb - 1; c >= 0; --c) {
+          if (lane == c) yi = cmul(yi, crcp(to_d2(D[c][(2 * c) & 63])));
+          const double2 yc = make_double2(__shfl(yi.x, c), __shfl(yi.y, c));
+          if (lane < c) yi = cfms(yi, to_d2(D[lane][(c + lane) & 63]), yc);
+        }
       }
       if (lane < nb) y[jb + lane] = yi;
     }
     __syncthreads();
-    for (int r = tid; r < jb; r += kLuThreads) {
-      double2 acc = y[r];
-      for (int c = 0; c < nb; ++c)
-        acc = cfms(acc, ld2<T>(LU + r + (long long)(jb + c) * N), y[jb + c]);
-      y[r] = acc;
-    }
+    // rows below (forward) or above (backward) the block
+    const int r0 = fwd ? jb + nb : 0, r1 = fwd ? N : jb;
+    for (int r = r0 + tid; r < r1; r += kLuThreads)
+      y[r] = row_sweep(y[r], LU + r + (long long)jb * N, N, y + jb, nb);
     __syncthreads();
   }
 }
 
 // alpha = A^{-1} b from FP64 factors.
-__global__ __launch_bounds__(kLuThreads) void lu_solve64_kernel(
+__global__ __launch_bounds__(kLuThreads, 2) void lu_solve64_kernel(
     const double2 *LUbase, const int *pivbase, int N, long long mstride,
     const double2 *b, double2 *x, long long vstride) {
   __shared__ double2 y[kMaxN];
+  __shared__ double2 D[64][64];
   const double2 *LU = LUbase + (long long)blockIdx.x * mstride;
   const int *piv = pivbase + (long long)blockIdx.x * N;
   for (int i = threadIdx.x; i < N; i += kLuThreads) y[i] = b[(long long)blockIdx.x * vstride + i];
   __syncthreads();
-  lu_solve_lds<double>(LU, piv, y, N);
+  lu_solve_lds<double>(LU, piv, y, N, D);
   for (int i = threadIdx.x; i < N; i += kLuThreads) x[(long long)blockIdx.x * vstride + i] = y[i];
 }
 
@@ -636,12 +710,13 @@ __device__ double block_sum(double v, double *red) {
 // rho = |d_k| / |d_{k-1}| (observed contraction), is below tol |x|.
 // status[b] = steps taken, or -1 when the cap was hit or the iteration did
 // not contract (the caller then redoes the solve in FP64).
-__global__ __launch_bounds__(kLuThreads) void refine_kernel(
+__global__ __launch_bounds__(kLuThreads, 2) void refine_kernel(
     const float2 *LUbase, const int *pivbase, const double2 *A64base, int N,
     long long mstride, const double2 *b, double2 *x, long long vstride, double tol,
     int max_iter, int *status, double *relres) {
   __shared__ double2 xs[kMaxN];
   __shared__ double2 rs[kMaxN];
+  __shared__ float2 D[64][64];
   __shared__ double red[4];
   const long long mb = (long long)blockIdx.x;
   const float2 *LU = LUbase + mb * mstride;
@@ -655,18 +730,14 @@ __global__ __launch_bounds__(kLuThreads) void refine_kernel(
   }
   for (int i = tid; i < N; i += kLuThreads) xs[i] = bb[i];
   __syncthreads();
-  lu_solve_lds<float>(LU, piv, xs, N);
+  lu_solve_lds<float>(LU, piv, xs, N, D);
   double prev = -1.0, last = 0.0;
   int it = 0, done = 0;
   for (; it < max_iter && !done; ++it) {
     // r = b - A x  (each thread owns rows; column sweep, coalesced)
-    for (int r = tid; r < N; r += kLuThreads) {
-      double2 acc = bb[r];
-      for (int c = 0; c < N; ++c) acc = cfms(acc, A[r + (long long)c * N], xs[c]);
-      rs[r] = acc;
-    }
+    for (int r = tid; r < N; r += kLuThreads) rs[r] = row_sweep(bb[r], A + r, N, xs, N);
     __syncthreads();
-    lu_solve_lds<float>(LU, piv, rs, N);
+    lu_solve_lds<float>(LU, piv, rs, N, D);
     double dn = 0.0, xn = 0.0;
     for (int i = tid; i < N; i += kLuThreads) {
       const double2 xi = cadd(xs[i], rs[i]);
@@ -696,17 +767,18 @@ __global__ __launch_bounds__(kLuThreads) void refine_kernel(
 
 // Solve for the matrices whose status is negative (FP64 redo after a
 // refined solve that did not converge): x = A^{-1} b from FP64 factors.
-__global__ __launch_bounds__(kLuThreads) void solve_failed64_kernel(
+__global__ __launch_bounds__(kLuThreads, 2) void solve_failed64_kernel(
     const double2 *LUbase, const int *pivbase, int N, long long mstride, const double2 *b,
     double2 *x, long long vstride, const int *status) {
   __shared__ double2 y[kMaxN];
+  __shared__ double2 D[64][64];
   const long long mb = blockIdx.x;
   if (status[mb] >= 0) return;
   const double2 *LU = LUbase + mb * mstride;
   const int *piv = pivbase + mb * N;
   for (int i = threadIdx.x; i < N; i += kLuThreads) y[i] = b[mb * vstride + i];
   __syncthreads();
-  lu_solve_lds<double>(LU, piv, y, N);
+  lu_solve_lds<double>(LU, piv, y, N, D);
   for (int i = threadIdx.x; i < N; i += kLuThreads) x[mb * vstride + i] = y[i];
 }
 

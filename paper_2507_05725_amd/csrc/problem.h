@@ -203,7 +203,7 @@ int fthms_problem_create(fthms_ctx *ctx, const fthms_problem_desc *d, fthms_prob
   pb->narcs = d->narcs;
   pb->M = d->narcs > 1 ? d->M : 1;
   pb->precision = d->precision;
-  pb->tol = d->tol > 0.0 ? d->tol : 1e-13;
+  pb->tol = d->tol > 0.0 ? d->tol : 1e-12;
   pb->period = d->period;
   pb->c0 = d->c0;
   pb->c1 = d->c1;
