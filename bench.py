@@ -42,6 +42,50 @@ def lu_flops(n):
     return 8.0 / 3.0 * n ** 3
 
 
+def lu_block_flops(n, nb=64):
+    """Algorithmic real flops of one complex LU split by kernel: the panel
+    kernel factors each (n-k0) x 64 column block, 4(m b^2 - b^3/3) flops; the
+    strip kernel applies the block's triangular solve to the columns on its
+    right (4 b^2 r) and the trailing update (8 b r^2), r = n - k0 - b.  The
+    two sums add up to (8/3) n^3 up to O(n^2) terms."""
+    panel = strip = 0.0
+    for k0 in range(0, n, nb):
+        b = min(nb, n - k0)
+        m = n - k0
+        r = m - b
+        panel += 4.0 * (m * b * b - b ** 3 / 3.0)
+        strip += 4.0 * b * b * r + 8.0 * b * r * r
+    return panel, strip
+
+
+def source_digest():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2507_05725_amd", "csrc", "lu.h")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when the summary is absent or the kernel source has changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "lu_strip_f512_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith(" "):
+                key, val = line.split(":", 1)
+                rec[key.strip()] = val.strip()
+    if rec.get("kernel") != kernel or rec.get("lu.h sha256") != source_digest():
+        return None
+    try:
+        return float(rec["hbm bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(case, k_sample, alpha_gpu_rows):
     """The oracle (as it stands) on host cores for a bounded sample of the
     same workload; returns the baseline record and the sampled GPU error."""
@@ -79,6 +123,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one plain 1 GiB device copy first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only (the solve path shards by frequency; "
@@ -114,6 +160,13 @@ def main():
         probs[p].run_dev(k, U[p], A[p])
         ctx.freq_to_time_dev(k, w, U[p], t, u[p])
 
+    if args.calib_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     results = {}
     for p in (fth.FP64, fth.FP32_REFINED):
         for _ in range(args.warmup):
@@ -132,7 +185,8 @@ def main():
         total = time.perf_counter() - t_all
         ctx.timing(False)
         kt = {name: ctx.timing_read(name) for name in
-              ("assemble", "lu", "solve", "fallback", "rhs", "field", "freq_to_time")}
+              ("assemble", "lu", "lu_panel", "lu_strip", "solve", "fallback",
+                            "rhs", "field", "freq_to_time")}
         results[p] = dict(total=total, lat=lat, kt=kt)
 
     # refinement steps taken, on a sample of 512 wavenumbers
@@ -158,19 +212,40 @@ def main():
     ms_step = 1000.0 * r32["total"] / args.steps
     value = NK * args.steps / r32["total"]
     fp64_value = NK * args.steps / r64["total"]
-    lu_ms, lu_n = r32["kt"]["lu"]
-    lu64_ms, lu64_n = r64["kt"]["lu"]
-    # each LU launch factors the same number of matrices (even chunks)
-    per_launch32 = NK * args.steps / max(lu_n, 1)
-    per_launch64 = NK * args.steps / max(lu64_n, 1)
-    ach32 = lu_flops(N_ARC) * per_launch32 / (lu_ms / max(lu_n, 1) / 1e3) / 1e12
-    ach64 = lu_flops(N_ARC) * per_launch64 / (lu64_ms / max(lu64_n, 1) / 1e3) / 1e12
-    roof = {"bound": "mfma", "achieved": round(ach32, 3),
+    panel_f, strip_f = lu_block_flops(N_ARC)
+    nsteps = args.steps
+
+    def lu_kernels(r, peak):
+        out = {}
+        for name, fl in (("lu_panel", panel_f), ("lu_strip", strip_f)):
+            ms, n = r["kt"][name]
+            avg = ms / max(n, 1)
+            flops_launch = fl * NK * nsteps / max(n, 1)
+            ach = flops_launch / (avg / 1e3) / 1e12 if n else 0.0
+            out[name + "_kernel"] = {"launches": n, "avg_launch_ms": round(avg, 4),
+                                     "alg_gflop_per_launch": round(flops_launch / 1e9, 3),
+                                     "achieved_tflops": round(ach, 3),
+                                     "frac_of_mfma_peak": round(ach / peak, 4)}
+        ms, n = r["kt"]["lu"]
+        ach = lu_flops(N_ARC) * NK * nsteps / (ms / 1e3) / 1e12 if n else 0.0
+        out["whole_lu"] = {"ms_per_step": round(ms / nsteps, 3),
+                           "achieved_tflops": round(ach, 3),
+                           "frac_of_mfma_peak": round(ach / peak, 4)}
+        return out
+
+    k32 = lu_kernels(r32, PEAK["fp32_mfma_tflops"])
+    k64 = lu_kernels(r64, PEAK["fp64_mfma_tflops"])
+    strip = k32["lu_strip_kernel"]
+    strip_name = "lu_strip_kernel<float>"
+    traffic = recorded_traffic(strip_name)
+    roof = {"bound": "mfma", "achieved": strip["achieved_tflops"],
             "peak": PEAK["fp32_mfma_tflops"], "unit": "TFLOP/s",
-            "frac": round(ach32 / PEAK["fp32_mfma_tflops"], 4), "traffic": None,
-            "kernel": "lu_kernel<float> (complex LU, FP32 MFMA updates)",
-            "avg_launch_ms": round(lu_ms / max(lu_n, 1), 4),
-            "matrices_per_launch": int(per_launch32)}
+            "frac": strip["frac_of_mfma_peak"],
+            "traffic": traffic,
+            "kernel": strip_name + " (block triangular solve + trailing update, "
+                      "FP32 MFMA)",
+            "avg_launch_ms": strip["avg_launch_ms"],
+            "alg_gflop_per_launch": strip["alg_gflop_per_launch"]}
 
     base = None
     oracle_err = None
@@ -200,8 +275,8 @@ def main():
                    "parallelism": "single GPU"},
         "fp64": {"value": round(fp64_value, 2), "unit": "solves/s",
                  "ms_per_step": round(1000.0 * r64["total"] / args.steps, 3),
-                 "lu_achieved_tflops": round(ach64, 3),
-                 "lu_frac_of_fp64_mfma_peak": round(ach64 / PEAK["fp64_mfma_tflops"], 4)},
+                 "lu_kernels": k64},
+        "lu_kernels_refined": k32,
         "refined_over_fp64": round(value / fp64_value, 3),
         "max_rel_err_refined_vs_fp64": err,
         "trace_rel_err_refined_vs_fp64": uerr,

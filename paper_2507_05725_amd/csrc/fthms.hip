@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <new>
@@ -15,6 +16,7 @@
 #include "field.h"
 #include "lu.h"
 #include "nearfield.h"
+#include "panel.h"
 
 using namespace fthms;
 
@@ -22,6 +24,10 @@ struct fthms_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // second stream (default priority) for the other half of a batched LU,
+  // forked from and joined back into `stream` inside each call
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_lead = nullptr, ev_join = nullptr;
   size_t budget = 0;
   size_t held = 0;
   std::string err;
@@ -35,8 +41,10 @@ struct fthms_ctx {
   struct Pending {
     std::string name;
     hipEvent_t a, b;
+    hipStream_t st;
   };
   std::vector<Pending> pending;
+  std::vector<size_t> open;  // indices into `pending` of unfinished ranges
   std::map<std::string, std::pair<double, int>> times;
 };
 
@@ -109,22 +117,32 @@ static int ensure_ws2(fthms_ctx *ctx, size_t bytes) {
   return FTHMS_OK;
 }
 
-static void tbeg(fthms_ctx *ctx, const char *name) {
+static void tbeg(fthms_ctx *ctx, const char *name, hipStream_t st = nullptr) {
   if (!ctx->timing) return;
+  if (!st) st = ctx->stream;
   fthms_ctx::Pending p;
   p.name = name;
-  if (hipEventCreate(&p.a) != hipSuccess) return;
-  if (hipEventCreate(&p.b) != hipSuccess) {
-    (void)hipEventDestroy(p.a);
+  if (hipEventCreate(&p.a) != hipSuccess) {
+    ctx->open.push_back(SIZE_MAX);  // keeps tbeg/tend paired
     return;
   }
-  (void)hipEventRecord(p.a, ctx->stream);
+  if (hipEventCreate(&p.b) != hipSuccess) {
+    (void)hipEventDestroy(p.a);
+    ctx->open.push_back(SIZE_MAX);
+    return;
+  }
+  (void)hipEventRecord(p.a, st);
+  p.st = st;
+  ctx->open.push_back(ctx->pending.size());
   ctx->pending.push_back(p);
 }
 
+// closes the innermost range opened by tbeg (ranges nest)
 static void tend(fthms_ctx *ctx) {
-  if (!ctx->timing || ctx->pending.empty()) return;
-  (void)hipEventRecord(ctx->pending.back().b, ctx->stream);
+  if (!ctx->timing || ctx->open.empty()) return;
+  const size_t i = ctx->open.back();
+  ctx->open.pop_back();
+  if (i != SIZE_MAX) (void)hipEventRecord(ctx->pending[i].b, ctx->pending[i].st);
 }
 
 static void timing_collect(fthms_ctx *ctx) {
@@ -185,6 +203,13 @@ int fthms_create(fthms_ctx **out, int device, size_t hbm_budget_bytes, void *hip
     }
     ctx->own_stream = true;
   }
+  if (hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_lead, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess) {
+    fthms_destroy(ctx);
+    return fail(nullptr, FTHMS_EDEVICE, "hipStreamCreate/hipEventCreate failed");
+  }
   *out = ctx;
   return FTHMS_OK;
 }
@@ -196,6 +221,13 @@ int fthms_destroy(fthms_ctx *ctx) {
   timing_collect(ctx);
   dev_free(ctx, ctx->ws, ctx->ws_bytes);
   dev_free(ctx, ctx->ws2, ctx->ws2_bytes);
+  if (ctx->aux) {
+    (void)hipStreamSynchronize(ctx->aux);
+    (void)hipStreamDestroy(ctx->aux);
+  }
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_lead) (void)hipEventDestroy(ctx->ev_lead);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return FTHMS_OK;
@@ -373,23 +405,99 @@ int fthms_arc_size(const fthms_arc *arc) { return arc ? arc->n : FTHMS_EINVAL; }
 // block's unit-lower diagonal part (sized for complex128).
 constexpr size_t kLuScratchBytes = sizeof(int) * kSwapStride + sizeof(double2) * kLuNB * kLuNB;
 
+// Panel of the block at k0: register-resident kernel when the block fits
+// (m = N - k0 <= 512 in FP32, <= 256 in FP64), else the LDS/global kernel.
+template <typename T, int R>
+static void launch_panel(hipStream_t st, cplx_t<T> *A, int N, long long ms, int k0, int *piv,
+                         int *swp, cplx_t<T> *linv, int *status, int count, int only_failed) {
+  const int m = N - k0;
+  const int rl = (m + 63) / 64;
+  const int rl_max = sizeof(T) == 4 ? 8 : 4;
+#define FTHMS_PANEL_REG(RL)                                                            \
+  lu_panel_reg_kernel<T, RL><<<count, kPrThreads, 0, st>>>(A, N, ms, k0, piv, swp, linv, \
+                                                           status, only_failed)
+  if (rl <= rl_max) {
+    switch (rl) {
+      case 1: FTHMS_PANEL_REG(1); return;
+      case 2: FTHMS_PANEL_REG(2); return;
+      case 3: FTHMS_PANEL_REG(3); return;
+      case 4: FTHMS_PANEL_REG(4); return;
+      default: break;
+    }
+    if constexpr (sizeof(T) == 4) {
+      switch (rl) {
+        case 5: FTHMS_PANEL_REG(5); return;
+        case 6: FTHMS_PANEL_REG(6); return;
+        case 7: FTHMS_PANEL_REG(7); return;
+        default: FTHMS_PANEL_REG(8); return;
+      }
+    }
+  }
+#undef FTHMS_PANEL_REG
+  lu_panel_kernel<T, R><<<count, kLuThreads, 0, st>>>(A, N, ms, k0, piv, swp, linv, status,
+                                                      only_failed);
+}
+
+// One block step (panel, then strips) of `count` matrices on stream `st`.
+template <typename T, int R>
+static void lu_step(fthms_ctx *ctx, hipStream_t st, cplx_t<T> *A, int N, long long ms, int k0,
+                    int *piv, int *swp, cplx_t<T> *linv, int *status, int count,
+                    int only_failed) {
+  // per-kernel timing ranges, except in the redo pass (timed as a whole)
+  const bool tk = !only_failed;
+  const int nb = std::min(kLuNB, N - k0);
+  if (tk) tbeg(ctx, "lu_panel", st);
+  launch_panel<T, R>(st, A, N, ms, k0, piv, swp, linv, status, count, only_failed);
+  if (tk) tend(ctx);
+  const int nleft = (k0 + kStripW - 1) / kStripW;
+  const int nright = (N - k0 - nb + kStripW - 1) / kStripW;
+  if (nleft + nright > 0) {
+    const long long blocks = 8LL * ((count + 7) / 8) * (nleft + nright);
+    if (tk) tbeg(ctx, "lu_strip", st);
+    lu_strip_kernel<T><<<(unsigned)blocks, kLuThreads, 0, st>>>(
+        A, N, ms, k0, swp, linv, count, nleft, nright, status, only_failed);
+    if (tk) tend(ctx);
+  }
+}
+
+// Batches of at least this many matrices are factored as two halves on two
+// streams, the second half one panel behind the first, so that the
+// latency-bound panel kernel of one half runs beside the MFMA-bound strip
+// kernel of the other.
+constexpr int kLuSplitMin = 256;
+
 template <typename T, int R>
 static void lu_blocks(fthms_ctx *ctx, cplx_t<T> *A, int N, long long ms, int *piv, void *scr,
                       int *status, int count, int only_failed) {
   int *swp = (int *)scr;
   cplx_t<T> *linv = (cplx_t<T> *)((char *)scr + sizeof(int) * kSwapStride * (size_t)count);
+  if (only_failed || count < kLuSplitMin) {
+    for (int k0 = 0; k0 < N; k0 += kLuNB)
+      lu_step<T, R>(ctx, ctx->stream, A, N, ms, k0, piv, swp, linv, status, count, only_failed);
+    return;
+  }
+  // halves aligned to 8 so the XCD placement of every matrix is unchanged
+  const int h = ((count / 2) + 7) & ~7;
+  const int c2 = count - h;
+  cplx_t<T> *A2 = A + (long long)h * ms;
+  int *piv2 = piv + (long long)h * N;
+  int *swp2 = swp + (long long)h * kSwapStride;
+  cplx_t<T> *linv2 = linv + (long long)h * kLuNB * kLuNB;
+  int *status2 = status + h;
+  (void)hipEventRecord(ctx->ev_fork, ctx->stream);
+  (void)hipStreamWaitEvent(ctx->aux, ctx->ev_fork, 0);
   for (int k0 = 0; k0 < N; k0 += kLuNB) {
-    const int nb = std::min(kLuNB, N - k0);
-    lu_panel_kernel<T, R><<<count, kLuThreads, 0, ctx->stream>>>(A, N, ms, k0, piv, swp, linv,
-                                                                 status, only_failed);
-    const int nleft = (k0 + kStripW - 1) / kStripW;
-    const int nright = (N - k0 - nb + kStripW - 1) / kStripW;
-    if (nleft + nright > 0) {
-      const long long blocks = 8LL * ((count + 7) / 8) * (nleft + nright);
-      lu_strip_kernel<T><<<(unsigned)blocks, kLuThreads, 0, ctx->stream>>>(
-          A, N, ms, k0, swp, linv, count, nleft, nright, status, only_failed);
+    lu_step<T, R>(ctx, ctx->stream, A, N, ms, k0, piv, swp, linv, status, h, 0);
+    if (k0 == 0) {
+      // start the second half once the first half's first panel is done
+      (void)hipEventRecord(ctx->ev_lead, ctx->stream);
+      (void)hipStreamWaitEvent(ctx->aux, ctx->ev_lead, 0);
     }
   }
+  for (int k0 = 0; k0 < N; k0 += kLuNB)
+    lu_step<T, R>(ctx, ctx->aux, A2, N, ms, k0, piv2, swp2, linv2, status2, c2, 0);
+  (void)hipEventRecord(ctx->ev_join, ctx->aux);
+  (void)hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0);
 }
 
 // scr: count * kLuScratchBytes of device scratch

@@ -1,0 +1,383 @@
+// Register-resident panel factorisation for the batched LU (one 1024-thread
+// workgroup per matrix).
+//
+// The m x 64 column block at k0 (m = N - k0 <= 64 RL) is held entirely in
+// registers: wave w owns columns 4w .. 4w+3, lane l the block rows l + 64 i
+// (i < RL).  Right-looking partial pivoting inside the block with one
+// workgroup barrier per column.  Rows are never moved during the
+// factorisation: each lane keeps a mask of its rows already chosen as
+// pivots, the pivot of column c is the largest |re| + |im| among the rows
+// not yet chosen (lowest row index on ties), and the rows are written to
+// their final positions when the block is stored.  The wave owning column c
+// finds the pivot with a wave reduction, forms the multipliers, publishes
+// them and the pivot row in LDS (double-buffered) and updates its own later
+// columns; after the barrier the waves owning later columns fetch the pivot
+// row's values with readlane and apply the rank-1 update.  Wave 0 keeps the
+// row bookkeeping (position of every row, row at every position), from
+// which the LAPACK-style pivot sequence and the block's net permutation
+// follow.  The block is loaded once and stored once.
+//
+// Outputs match lu_panel_kernel (up to the choice among exactly tied pivot
+// candidates): the factored block, absolute pivots, the
+// block's net row permutation as (dst, src) pairs, and L11^{-1} (64 x 64,
+// column-major, zero above the diagonal), computed at the end by forward
+// substitution from L11 staged in LDS.
+//
+// Arithmetic is in the storage precision T.  Register budget: RL x 4
+// complex values of T per lane; the launch bound of 1024 threads leaves 128
+// VGPRs per lane, so FP32 blocks up to m = 512 and FP64 blocks up to m = 256
+// take this path (larger ones use lu_panel_kernel).
+#pragma once
+
+#include "lu.h"
+
+namespace fthms {
+
+constexpr int kPrThreads = 1024;
+constexpr int kPrWaves = kPrThreads / 64;  // 16 waves x 4 columns = 64
+
+__device__ __forceinline__ float rdlane(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ __forceinline__ double rdlane(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename T2> __device__ __forceinline__ T2 rdlane2(T2 v, int l) {
+  T2 r;
+  r.x = rdlane(v.x, l);
+  r.y = rdlane(v.y, l);
+  return r;
+}
+
+// Lane permutations for the pivot search, all without LDS: DPP quad
+// permutations and row mirrors inside 16-lane rows, then the gfx950
+// row-swap instructions across rows and across the two 32-lane halves.
+// After each step a lane holds its own value and its partner's.
+template <int CTRL> __device__ __forceinline__ int dpp_i(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL> __device__ __forceinline__ float dpp_v(float x) {
+  return __int_as_float(dpp_i<CTRL>(__float_as_int(x)));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_v(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = dpp_i<CTRL>((int)(b & 0xffffffffLL)), hi = dpp_i<CTRL>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename T>
+__device__ __forceinline__ void argmax_merge(T &best, int &brow, T ob, int orow) {
+  // branch-free: bitwise operators on the comparison masks
+  const bool take = (ob > best) | ((ob == best) & (orow < brow));
+  best = take ? ob : best;
+  brow = take ? orow : brow;
+}
+template <typename T> __device__ __forceinline__ void swap_pair16(T &a, T &b);
+template <> __device__ __forceinline__ void swap_pair16<int>(int &a, int &b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(a, a, false, false);
+  a = r[0];
+  b = r[1];
+}
+template <> __device__ __forceinline__ void swap_pair16<float>(float &a, float &b) {
+  int x = __float_as_int(a), y;
+  swap_pair16<int>(x, y);
+  a = __int_as_float(x);
+  b = __int_as_float(y);
+}
+template <> __device__ __forceinline__ void swap_pair16<double>(double &a, double &b) {
+  const long long v = __double_as_longlong(a);
+  int lo = (int)(v & 0xffffffffLL), hi = (int)(v >> 32), lo2, hi2;
+  swap_pair16<int>(lo, lo2);
+  swap_pair16<int>(hi, hi2);
+  a = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  b = __longlong_as_double(((long long)hi2 << 32) | (unsigned int)lo2);
+}
+template <typename T> __device__ __forceinline__ void swap_pair32(T &a, T &b);
+template <> __device__ __forceinline__ void swap_pair32<int>(int &a, int &b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(a, a, false, false);
+  a = r[0];
+  b = r[1];
+}
+template <> __device__ __forceinline__ void swap_pair32<float>(float &a, float &b) {
+  int x = __float_as_int(a), y;
+  swap_pair32<int>(x, y);
+  a = __int_as_float(x);
+  b = __int_as_float(y);
+}
+template <> __device__ __forceinline__ void swap_pair32<double>(double &a, double &b) {
+  const long long v = __double_as_longlong(a);
+  int lo = (int)(v & 0xffffffffLL), hi = (int)(v >> 32), lo2, hi2;
+  swap_pair32<int>(lo, lo2);
+  swap_pair32<int>(hi, hi2);
+  a = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  b = __longlong_as_double(((long long)hi2 << 32) | (unsigned int)lo2);
+}
+// Wave-wide argmax of (best, brow): largest value, smallest row on ties;
+// every lane ends with the result.
+template <typename T> __device__ __forceinline__ void wave_argmax(T &best, int &brow) {
+  argmax_merge(best, brow, dpp_v<0xB1>(best), dpp_i<0xB1>(brow));    // lane ^ 1
+  argmax_merge(best, brow, dpp_v<0x4E>(best), dpp_i<0x4E>(brow));    // lane ^ 2
+  argmax_merge(best, brow, dpp_v<0x141>(best), dpp_i<0x141>(brow));  // mirror in 8
+  argmax_merge(best, brow, dpp_v<0x140>(best), dpp_i<0x140>(brow));  // mirror in 16
+  T b2;
+  int r2;
+  swap_pair16<T>(best, b2);
+  swap_pair16<int>(brow, r2);
+  argmax_merge(best, brow, b2, r2);
+  swap_pair32<T>(best, b2);
+  swap_pair32<int>(brow, r2);
+  argmax_merge(best, brow, b2, r2);
+}
+
+template <typename T> __device__ __forceinline__ cplx_t<T> tmul(cplx_t<T> a, cplx_t<T> b) {
+  return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a - b c
+template <typename T>
+__device__ __forceinline__ cplx_t<T> tfms(cplx_t<T> a, cplx_t<T> b, cplx_t<T> c) {
+  return mk<T>(a.x - b.x * c.x + b.y * c.y, a.y - b.x * c.y - b.y * c.x);
+}
+// 1 / a from the hardware reciprocal (about 1 ulp; FP64 refined by two
+// Newton steps), scaled by max(|re|, |im|) against over- and underflow.
+__device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double hw_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return fma(fma(-x, r, 1.0), r, r);
+}
+template <typename T> __device__ __forceinline__ cplx_t<T> trcp(cplx_t<T> a) {
+  const T s = fabs(a.x) > fabs(a.y) ? fabs(a.x) : fabs(a.y);
+  const T rs = hw_rcp(s);
+  const T ar = a.x * rs, ai = a.y * rs;
+  const T rd = hw_rcp(ar * ar + ai * ai) * rs;
+  return mk<T>(ar * rd, -ai * rd);
+}
+
+template <typename T, int RL> struct PanelRegSmem {
+  cplx_t<T> lbuf[2][64 * RL];  // multipliers of the current column
+  int pinfo[2];                // its pivot row (block row index)
+  int ipiv[kLuNB];             // LAPACK-style pivots (block positions)
+  int posv[64 * RL];           // final position of every block row
+  int zero_pivot;
+  int count;
+  cplx_t<T> lt[kLuNB][kLuNB];  // L11 transposed: lt[s][r] = L(r, s)
+};
+
+// Value of row p (slot p >> 6, lane p & 63) of column J, as a scalar.  The
+// slot is uniform; readlane is convergent, so the compiler keeps the slot
+// test as a scalar branch rather than selecting across all slots.
+template <typename T, int RL, int J>
+__device__ __forceinline__ cplx_t<T> row_value(const cplx_t<T> (&a)[RL][4], int p) {
+  const int sp = p >> 6, lp = p & 63;
+  cplx_t<T> y = rdlane2(a[0][J], lp);
+#pragma unroll
+  for (int i = 1; i < RL; ++i)
+    if (i == sp) y = rdlane2(a[i][J], lp);
+  return y;
+}
+
+// Integer register array version: v[idx] as a scalar / v[idx] = val.
+template <int RL> __device__ __forceinline__ int iget(const int (&v)[RL], int idx) {
+  const int s = idx >> 6, l = idx & 63;
+  int y = __builtin_amdgcn_readlane(v[0], l);
+#pragma unroll
+  for (int i = 1; i < RL; ++i)
+    if (i == s) y = __builtin_amdgcn_readlane(v[i], l);
+  return y;
+}
+template <int RL> __device__ __forceinline__ void iset(int (&v)[RL], int idx, int val, int lane) {
+  const int s = idx >> 6, l = idx & 63;
+#pragma unroll
+  for (int i = 0; i < RL; ++i) v[i] = (i == s && lane == l) ? val : v[i];
+}
+
+// One column c = 4 cw + J of the block.  used: bit i set if row lane + 64 i
+// has been chosen as a pivot.  rowat/pos (wave 0): row at each position,
+// position of each row.
+template <typename T, int RL, int J>
+__device__ __forceinline__ void panel_reg_column(cplx_t<T> (&a)[RL][4], int &used,
+                                                 int (&rowat)[RL], int (&pos)[RL], int w, int cw,
+                                                 int m, int &zero_col, PanelRegSmem<T, RL> &sm) {
+  typedef cplx_t<T> T2;
+  const int lane = threadIdx.x & 63;
+  const int c = 4 * cw + J, b = c & 1;
+  int p;
+  if (w == cw) {
+    // the owner's work is the critical path: raise its issue priority
+    __builtin_amdgcn_s_setprio(2);
+    // pivot search in column J over the rows not yet chosen; a NaN entry
+    // ranks below every number so that a row is always found
+    T best = T(-1);
+    int brow = 0x7fffffff;
+#pragma unroll
+    for (int i = 0; i < RL; ++i) {
+      const bool ok = ((used >> i) & 1) == 0 && lane < m - 64 * i;
+      T mag = fabs(a[i][J].x) + fabs(a[i][J].y);
+      mag = mag == mag ? mag : T(-0.5);
+      const bool take = ok & (mag > best);
+      best = take ? mag : best;
+      brow = take ? lane + 64 * i : brow;
+    }
+    wave_argmax<T>(best, brow);
+    p = __builtin_amdgcn_readfirstlane(brow);
+    used |= lane == (p & 63) ? 1 << (p >> 6) : 0;
+    if (lane == 0) sm.pinfo[b] = p;
+    T2 u[4];
+    u[0] = row_value<T, RL, 0>(a, p);
+    u[1] = row_value<T, RL, 1>(a, p);
+    u[2] = row_value<T, RL, 2>(a, p);
+    u[3] = row_value<T, RL, 3>(a, p);
+    const bool nz = best > T(0);
+    const T2 inv = nz ? trcp<T>(u[J]) : mk<T>(T(0), T(0));
+#pragma unroll
+    for (int i = 0; i < RL; ++i) {
+      const bool below = ((used >> i) & 1) == 0 && lane < m - 64 * i;
+      const T2 l = below ? tmul<T>(a[i][J], inv) : mk<T>(T(0), T(0));
+      if (below) a[i][J] = l;
+      sm.lbuf[b][lane + 64 * i] = l;
+#pragma unroll
+      for (int j = J + 1; j < 4; ++j) a[i][j] = tfms<T>(a[i][j], l, u[j]);
+    }
+    // first exactly zero pivot of this wave's columns (1-based, 0: none)
+    if (!nz && zero_col == 0) zero_col = c + 1;
+    __builtin_amdgcn_s_setprio(0);
+  }
+  __syncthreads();
+  if (w != cw) {
+    p = __builtin_amdgcn_readfirstlane(sm.pinfo[b]);
+    used |= lane == (p & 63) ? 1 << (p >> 6) : 0;
+    if (w > cw) {
+      T2 u[4];
+      u[0] = row_value<T, RL, 0>(a, p);
+      u[1] = row_value<T, RL, 1>(a, p);
+      u[2] = row_value<T, RL, 2>(a, p);
+      u[3] = row_value<T, RL, 3>(a, p);
+#pragma unroll
+      for (int i = 0; i < RL; ++i) {
+        const T2 l = sm.lbuf[b][lane + 64 * i];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a[i][j] = tfms<T>(a[i][j], l, u[j]);
+      }
+    }
+  }
+  if (w == 0) {
+    // bookkeeping: row p moves to position c, the row there to p's position
+    const int r = iget<RL>(pos, p);
+    const int x = __builtin_amdgcn_readlane(rowat[0], c);
+    iset<RL>(rowat, r, x, lane);
+    iset<RL>(rowat, c, p, lane);
+    iset<RL>(pos, x, r, lane);
+    iset<RL>(pos, p, c, lane);
+    if (lane == 0) sm.ipiv[c] = r;
+  }
+}
+
+template <typename T, int RL>
+__global__ __launch_bounds__(kPrThreads) void lu_panel_reg_kernel(
+    cplx_t<T> *Abase, int N, long long mstride, int k0, int *pivbase, int *swapbase,
+    cplx_t<T> *Linv, int *status, int only_failed) {
+  typedef cplx_t<T> T2;
+  __shared__ PanelRegSmem<T, RL> sm;
+  const long long mb = blockIdx.x;
+  if (only_failed && status[mb] >= 0) return;
+  T2 *A = Abase + mb * mstride;
+  int *piv = pivbase + mb * N;
+  int *swp = swapbase + mb * kSwapStride;
+  T2 *Li = Linv + mb * (kLuNB * kLuNB);
+  const int tid = threadIdx.x, lane = tid & 63;
+  // wave index as a scalar, so that owner/follower branches are uniform
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int m = N - k0, nb = min(kLuNB, m);
+  // this wave's first column, row k0 (a scalar base; lanes add row offsets)
+  T2 *colp = A + k0 + (long long)(k0 + 4 * w) * N;
+  T2 a[RL][4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int col = 4 * w + j;
+#pragma unroll
+    for (int i = 0; i < RL; ++i)
+      a[i][j] = (lane < m - 64 * i && col < nb) ? colp[lane + 64 * i + (long long)j * N]
+                                                : mk<T>(T(0), T(0));
+  }
+  int used = 0, rowat[RL], pos[RL];
+#pragma unroll
+  for (int i = 0; i < RL; ++i) rowat[i] = pos[i] = lane + 64 * i;
+  if (tid == 0) sm.zero_pivot = 0x7fffffff;
+  int zero_col = 0;
+  __syncthreads();
+  // the column loop touches no global memory, so its barriers wait on LDS only
+  for (int cw = 0; 4 * cw < nb; ++cw) {
+    // nb is a multiple of 4 except in a last, partial block
+    panel_reg_column<T, RL, 0>(a, used, rowat, pos, w, cw, m, zero_col, sm);
+    if (4 * cw + 1 < nb) panel_reg_column<T, RL, 1>(a, used, rowat, pos, w, cw, m, zero_col, sm);
+    if (4 * cw + 2 < nb) panel_reg_column<T, RL, 2>(a, used, rowat, pos, w, cw, m, zero_col, sm);
+    if (4 * cw + 3 < nb) panel_reg_column<T, RL, 3>(a, used, rowat, pos, w, cw, m, zero_col, sm);
+  }
+  // wave 0 publishes the final positions and the block's net permutation
+  // (pairs "new row dst = old row src"; at most 2 x 64 rows move)
+  if (tid == 0) sm.count = 0;
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int i = 0; i < RL; ++i) {
+      const int r = lane + 64 * i;
+      if (r < m) {
+        sm.posv[r] = pos[i];
+        if (rowat[i] != r) {
+          const int e = atomicAdd(&sm.count, 1);
+          if (e < kSwapMax) {
+            swp[1 + 2 * e] = k0 + r;
+            swp[2 + 2 * e] = k0 + rowat[i];
+          }
+        }
+      }
+    }
+  }
+  if (lane == 0 && zero_col) atomicMin(&sm.zero_pivot, zero_col);
+  __syncthreads();
+  if (tid < nb) piv[k0 + tid] = k0 + sm.ipiv[tid];
+  // store every row at its final position; stage L11 (strictly lower part)
+  // transposed, by final position
+#pragma unroll
+  for (int i = 0; i < RL; ++i) {
+    if (lane < m - 64 * i) {
+      const int fp = sm.posv[lane + 64 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = 4 * w + j;
+        if (col < nb) {
+          colp[fp + (long long)j * N] = a[i][j];
+          if (fp < kLuNB) sm.lt[col][fp] = fp > col ? a[i][j] : mk<T>(T(0), T(0));
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // L11^{-1} by forward substitution, four columns per wave (lane = row)
+  T2 x[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    x[j] = mk<T>(lane == 4 * w + j ? T(1) : T(0), T(0));
+  for (int s = 4 * w; s < nb - 1; ++s) {
+    const T2 l = lane < nb ? sm.lt[s][lane] : mk<T>(T(0), T(0));
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[j] = tfms<T>(x[j], l, rdlane2(x[j], s));
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int col = 4 * w + j;
+    Li[lane + kLuNB * col] = (col < nb && lane < nb) ? x[j] : mk<T>(T(0), T(0));
+  }
+  if (tid == 0) {
+    swp[0] = min(sm.count, kSwapMax);
+    // status: 0 ok, -2 exact zero pivot; a redo (only_failed) stays negative
+    // (-1: redone in FP64) so that its solve is redone too
+    const bool zero = sm.zero_pivot != 0x7fffffff;
+    if (k0 == 0) status[mb] = zero ? -2 : (only_failed ? -1 : 0);
+    else if (zero) status[mb] = -2;
+  }
+}
+
+}  // namespace fthms

@@ -124,3 +124,26 @@ def test_lu_solve(env, n):
     for b in range(nb):
         ref = np.linalg.solve(M[b], bvec[b])
         assert np.linalg.norm(xs[b] - ref) / np.linalg.norm(ref) < 1e-12
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batched_lu_split_batch_bitwise(env, prec):
+    """Large batches are factored as two halves on two streams; every matrix
+    must come out bit-identical to factoring it alone."""
+    fth, ctx, torch = env
+    n, nb = 70, 301
+    rng = np.random.default_rng(7)
+    M = rng.standard_normal((nb, n, n)) + 1j * rng.standard_normal((nb, n, n))
+    say("lu split batch", nb, "prec", prec)
+    dt = torch.complex128 if prec == 0 else torch.complex64
+    A = torch.tensor(np.ascontiguousarray(M.transpose(0, 2, 1)), dtype=dt, device="cuda")
+    A1 = A.clone()
+    piv = torch.empty((nb, n), dtype=torch.int32, device="cuda")
+    ctx.lu_dev(A, piv, precision=prec)
+    piv1 = torch.empty((1, n), dtype=torch.int32, device="cuda")
+    for b in (0, 1, 150, 151, 152, 153, 299, 300):
+        one = A1[b:b + 1].clone()
+        ctx.lu_dev(one, piv1, precision=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(one[0], A[b]), b
+        assert torch.equal(piv1[0], piv[b]), b
