@@ -123,6 +123,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tol", type=float, default=1e-11,
+                    help="refinement stop: predicted relative error (the metric's 1e-10 "
+                         "with a 10x margin); every solve's error is measured")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (counter calibration)")
     args = ap.parse_args()
@@ -150,7 +153,8 @@ def main():
     w = torch.tensor(w_np, dtype=torch.float64, device=dev)
     t = torch.tensor(t_np, dtype=torch.float64, device=dev)
     nobs = case["obs"].shape[0]
-    probs = {p: fth.Problem(ctx, [arc], case["incident"], case["obs"], M=1, precision=p)
+    probs = {p: fth.Problem(ctx, [arc], case["incident"], case["obs"], M=1, precision=p,
+                            tol=args.tol)
              for p in (fth.FP64, fth.FP32_REFINED)}
     U = {p: torch.empty((NK, nobs), dtype=torch.complex128, device=dev) for p in probs}
     A = {p: torch.empty((NK, N_ARC), dtype=torch.complex128, device=dev) for p in probs}
@@ -195,7 +199,7 @@ def main():
     al_s = torch.empty_like(rhs_s)
     it_s = torch.empty(ks.numel(), dtype=torch.int32, device=dev)
     ctx.rhs_dev(arc, ks, case["incident"], rhs_s)
-    ctx.solve_dev(arc, ks, rhs_s, al_s, fth.FP32_REFINED, 0.0, it_s)
+    ctx.solve_dev(arc, ks, rhs_s, al_s, fth.FP32_REFINED, args.tol, it_s)
     torch.cuda.synchronize()
     its = it_s.cpu().numpy()
     iter_stats = {"mean": round(float(its[its > 0].mean()), 3) if np.any(its > 0) else None,
@@ -272,7 +276,7 @@ def main():
         "config": {"workload": "circular arc R=1 span 2.5 rad, N=512, 4096 wavenumbers "
                                "in [1,120], plane wave 30 deg, 256 field points, 1001 "
                                "time samples", "n": N_ARC, "n_freq": NK,
-                   "parallelism": "single GPU"},
+                   "refine_tol": args.tol, "parallelism": "single GPU"},
         "fp64": {"value": round(fp64_value, 2), "unit": "solves/s",
                  "ms_per_step": round(1000.0 * r64["total"] / args.steps, 3),
                  "lu_kernels": k64},

@@ -142,9 +142,11 @@ int fthms_arc_size(const fthms_arc *arc);
  * V_Gamma on `arc`, factor it (LU with partial pivoting) and solve
  * A alpha = rhs[i].  rhs, alpha: [nk][n].  precision FTHMS_FP64 factors in
  * complex FP64; FTHMS_FP32_REFINED factors in complex FP32 (MFMA trailing
- * updates, FP64 panel pivoting) and refines with FP64 residuals until the
- * predicted relative error of alpha is below tol (tol <= 0: 1e-12), at most
- * 10 iterations; solves that do not converge are redone in FP64.
+ * updates, pivots chosen on FP64 magnitudes) and refines with FP64
+ * residuals until the predicted relative error of alpha is below tol
+ * (tol <= 0: 1e-12; the prediction is |d_k|^2 / |d_{k-1}| for successive
+ * corrections d, the initial solve counting as d_0), at most 10
+ * iterations; solves that do not converge are redone in FP64.
  * iters[nk] (optional) receives the refinement steps per solve (0 for
  * FP64, -1 for a solve redone in FP64); relres[nk] (optional) the last
  * relative correction |delta|/|alpha|.  FTHMS_ESINGULAR if a pivot is

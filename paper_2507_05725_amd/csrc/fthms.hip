@@ -403,7 +403,31 @@ int fthms_arc_size(const fthms_arc *arc) { return arc ? arc->n : FTHMS_EINVAL; }
 // whose status is negative (the FP64 redo of refined solves).
 // Per-matrix LU scratch: the block row permutation and the inverse of the
 // block's unit-lower diagonal part (sized for complex128).
-constexpr size_t kLuScratchBytes = sizeof(int) * kSwapStride + sizeof(double2) * kLuNB * kLuNB;
+// Regions, each `count` matrices long: [block permutation pairs][L11^{-1}]
+// [row permutation of the finished factorisation (kMaxN ints)].
+constexpr size_t kLuScratchHead = sizeof(int) * kSwapStride + sizeof(double2) * kLuNB * kLuNB;
+constexpr size_t kLuScratchBytes = kLuScratchHead + sizeof(int) * kMaxN;
+
+// Gather form of the factorisation's row interchanges in LU scratch `scr`
+// of `count` matrices.
+static int *lu_perm(void *scr, int count) {
+  return (int *)((char *)scr + kLuScratchHead * (size_t)count);
+}
+
+static void launch_perm(hipStream_t st, const int *piv, int N, int *perm, const int *status,
+                        int count, int only_failed) {
+  const int S = (N + 63) / 64;
+  if (S <= 1)
+    perm_from_piv_kernel<1><<<count, 64, 0, st>>>(piv, N, perm, status, only_failed);
+  else if (S <= 2)
+    perm_from_piv_kernel<2><<<count, 64, 0, st>>>(piv, N, perm, status, only_failed);
+  else if (S <= 4)
+    perm_from_piv_kernel<4><<<count, 64, 0, st>>>(piv, N, perm, status, only_failed);
+  else if (S <= 8)
+    perm_from_piv_kernel<8><<<count, 64, 0, st>>>(piv, N, perm, status, only_failed);
+  else
+    perm_from_piv_kernel<16><<<count, 64, 0, st>>>(piv, N, perm, status, only_failed);
+}
 
 // Panel of the block at k0: register-resident kernel when the block fits
 // (m = N - k0 <= 512 in FP32, <= 256 in FP64), else the LDS/global kernel.
@@ -521,6 +545,7 @@ static int launch_lu(fthms_ctx *ctx, bool fp32, void *A, int N, long long ms, in
       default: lu_blocks<double, 4>(ctx, a, N, ms, piv, scr, status, count, only_failed); break;
     }
   }
+  launch_perm(ctx->stream, piv, N, lu_perm(scr, count), status, count, only_failed);
   return check_launch(ctx, "lu kernels");
 }
 
@@ -530,7 +555,8 @@ static int launch_fallback(fthms_ctx *ctx, double2 *A, int N, long long ms, int 
                            const double2 *b, double2 *x, int *status, int count) {
   int rc = launch_lu(ctx, false, A, N, ms, piv, swp, status, count, 1);
   if (rc) return rc;
-  solve_failed64_kernel<<<count, kLuThreads, 0, ctx->stream>>>(A, piv, N, ms, b, x, N, status);
+  solve_failed64_kernel<<<count, kLuThreads, 0, ctx->stream>>>(A, lu_perm(swp, count), N, ms, b,
+                                                               x, N, status);
   return check_launch(ctx, "solve_failed64_kernel");
 }
 
@@ -627,13 +653,14 @@ static int solve_dev_impl(fthms_ctx *ctx, const fthms_arc *arc, int nk, const do
     if (rc) return rc;
     if (!fp32) {
       tbeg(ctx, "solve");
-      lu_solve64_kernel<<<c, kLuThreads, 0, ctx->stream>>>(w.A64, w.piv, N, ms, b, x, N);
+      lu_solve64_kernel<<<c, kLuThreads, 0, ctx->stream>>>(w.A64, lu_perm(w.swp, c), N, ms, b, x,
+                                                           N);
       tend(ctx);
       if ((rc = check_launch(ctx, "lu_solve64_kernel"))) return rc;
     } else {
       tbeg(ctx, "solve");
-      refine_kernel<<<c, kLuThreads, 0, ctx->stream>>>(w.A32, w.piv, w.A64, N, ms, b, x, N, tol,
-                                                        10, w.status, w.relres);
+      refine_kernel<<<c, kLuThreads, 2 * N * sizeof(double2), ctx->stream>>>(
+          w.A32, lu_perm(w.swp, c), w.A64, N, ms, b, x, N, tol, 10, w.status, w.relres);
       tend(ctx);
       if ((rc = check_launch(ctx, "refine_kernel"))) return rc;
       tbeg(ctx, "fallback");
@@ -995,8 +1022,12 @@ int fthms_lu_solve_dev(fthms_ctx *ctx, int n, int nb, const fthms_c64 *LU_dev, c
     return fail(ctx, FTHMS_EINVAL, "bad argument to fthms_lu_solve_dev");
   if (nb == 0) return FTHMS_OK;
   HIPCK(ctx, hipSetDevice(ctx->device));
+  int rc = ensure_ws2(ctx, sizeof(int) * kMaxN * (size_t)nb + 256);
+  if (rc) return rc;
+  int *perm = (int *)ctx->ws2;
   tbeg(ctx, "solve");
-  lu_solve64_kernel<<<nb, kLuThreads, 0, ctx->stream>>>((const double2 *)LU_dev, piv_dev, n,
+  launch_perm(ctx->stream, piv_dev, n, perm, nullptr, nb, 0);
+  lu_solve64_kernel<<<nb, kLuThreads, 0, ctx->stream>>>((const double2 *)LU_dev, perm, n,
                                                         (long long)n * n, (const double2 *)b_dev,
                                                         (double2 *)x_dev, n);
   tend(ctx);

@@ -48,6 +48,38 @@ template <> struct Mma<float> {
   static __device__ __forceinline__ int crow(int g, int r) { return 4 * g + r; }
 };
 
+// readlane of FP32/FP64 values and complex pairs (lane index uniform)
+__device__ __forceinline__ float rdlane(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ __forceinline__ double rdlane(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename T2> __device__ __forceinline__ T2 rdlane2(T2 v, int l) {
+  T2 r;
+  r.x = rdlane(v.x, l);
+  r.y = rdlane(v.y, l);
+  return r;
+}
+
+// Integer register array version: v[idx] as a scalar / v[idx] = val.
+template <int RL> __device__ __forceinline__ int iget(const int (&v)[RL], int idx) {
+  const int s = idx >> 6, l = idx & 63;
+  int y = __builtin_amdgcn_readlane(v[0], l);
+#pragma unroll
+  for (int i = 1; i < RL; ++i)
+    if (i == s) y = __builtin_amdgcn_readlane(v[i], l);
+  return y;
+}
+template <int RL> __device__ __forceinline__ void iset(int (&v)[RL], int idx, int val, int lane) {
+  const int s = idx >> 6, l = idx & 63;
+#pragma unroll
+  for (int i = 0; i < RL; ++i) v[i] = (i == s && lane == l) ? val : v[i];
+}
+
 constexpr int kLuThreads = 256;
 constexpr int kLuNB = 64;
 constexpr int kLuPW = 8;
@@ -598,7 +630,7 @@ __device__ __forceinline__ double2 ld2(const cplx_t<T> *p) {
 }
 
 // acc -= sum_{c < n} col[c * stride] * y[c]: column sweep of one row with
-// the next 8-element batch of loads in flight while the current one is used
+// the next batch of 8 loads in flight while the current one is used
 template <typename P>
 __device__ __forceinline__ double2 row_sweep(double2 acc, const P *col, long long stride,
                                              const double2 *y, int n) {
@@ -623,24 +655,66 @@ __device__ __forceinline__ double2 row_sweep(double2 acc, const P *col, long lon
   return acc;
 }
 
-// y := U^{-1} L^{-1} P y for the factors in LU (column-major, ld = N).
-// Each 64 x 64 diagonal block is staged in LDS (D, element (r, c) at
-// D[r][(c + r) & 63] so that column reads are bank-conflict free) with one
-// coalesced load, so wave 0's 64-step substitution reads only LDS; the
-// off-diagonal block columns are applied by all threads with batched loads.
-template <typename T>
-__device__ void lu_solve_lds(const cplx_t<T> *LU, const int *piv, double2 *y, int N,
-                             cplx_t<T> (*D)[64]) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid == 0) {
-    for (int i = 0; i < N; ++i) {
-      const int p = piv[i];
+// perm[i] = the original row of row i of P A, for the LAPACK-style row
+// interchanges piv (row i swapped with row piv[i], i = 0, 1, ...), so that
+// P y is the gather y[perm[i]].  One wave per matrix, the row indices in
+// registers (S per lane, N <= 64 S); matrices with status >= 0 are skipped
+// when only_failed is set.
+template <int S>
+__global__ __launch_bounds__(64) void perm_from_piv_kernel(const int *pivbase, int N, int *permbase,
+                                                           const int *status, int only_failed) {
+  const long long mb = blockIdx.x;
+  if (only_failed && status[mb] >= 0) return;
+  const int *piv = pivbase + mb * N;
+  int *perm = permbase + mb * kMaxN;
+  const int lane = threadIdx.x;
+  int v[S], pv[S];
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    v[q] = lane + 64 * q;
+    pv[q] = lane + 64 * q < N ? piv[lane + 64 * q] : 0;
+  }
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    const int nq = min(64, N - 64 * q);
+    for (int l = 0; l < nq; ++l) {
+      const int i = 64 * q + l;
+      const int p = __builtin_amdgcn_readlane(pv[q], l);
       if (p != i) {
-        const double2 t = y[i];
-        y[i] = y[p];
-        y[p] = t;
+        const int x = __builtin_amdgcn_readlane(v[q], l);
+        const int y = iget<S>(v, p);
+        v[q] = lane == l ? y : v[q];
+        iset<S>(v, p, x, lane);
       }
     }
+  }
+#pragma unroll
+  for (int q = 0; q < S; ++q)
+    if (lane + 64 * q < N) perm[lane + 64 * q] = v[q];
+}
+
+// y := U^{-1} L^{-1} P y for the factors in LU (column-major, ld = N), P
+// given as the gather perm.  Each 64 x 64 diagonal block is staged in LDS
+// (D, element (r, c) at D[r][(c + r) & 63] so that column reads are
+// bank-conflict free) with one coalesced load, and wave 0 substitutes with
+// the solution values passed between lanes by readlane; the off-diagonal
+// block columns are applied by all threads with batched loads.
+template <typename T>
+__device__ void lu_solve_lds(const cplx_t<T> *LU, const int *perm, double2 *y, int N,
+                             cplx_t<T> (*D)[64]) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  {
+    // y := P y as a gather, four rows per thread (kMaxN = 4 x 256)
+    static_assert(kMaxN == 4 * kLuThreads, "gather assumes four rows per thread");
+    const int i0 = tid, i1 = tid + kLuThreads, i2 = tid + 2 * kLuThreads,
+              i3 = tid + 3 * kLuThreads;
+    const double2 g0 = y[i0 < N ? perm[i0] : 0], g1 = y[i1 < N ? perm[i1] : 0],
+                  g2 = y[i2 < N ? perm[i2] : 0], g3 = y[i3 < N ? perm[i3] : 0];
+    __syncthreads();
+    if (i0 < N) y[i0] = g0;
+    if (i1 < N) y[i1] = g1;
+    if (i2 < N) y[i2] = g2;
+    if (i3 < N) y[i3] = g3;
   }
   const int nblk = (N + 63) / 64;
   for (int bi = 0; bi < 2 * nblk; ++bi) {
@@ -656,13 +730,15 @@ __device__ void lu_solve_lds(const cplx_t<T> *LU, const int *piv, double2 *y, in
       double2 yi = lane < nb ? y[jb + lane] : make_double2(0.0, 0.0);
       if (fwd) {
         for (int c = 0; c < nb - 1; ++c) {
-          const double2 yc = make_double2(__shfl(yi.x, c), __shfl(yi.y, c));
-          if (lane > c && lane < nb) yi = cfms(yi, to_d2(D[lane][(c + lane) & 63]), yc);
+          const double2 yc = rdlane2(yi, c);
+          if (lane > c) yi = cfms(yi, to_d2(D[lane][(c + lane) & 63]), yc);
         }
       } else {
+        const double2 dinv =
+            lane < nb ? crcp(to_d2(D[lane][(2 * lane) & 63])) : make_double2(0.0, 0.0);
         for (int c = nb - 1; c >= 0; --c) {
-          if (lane == c) yi = cmul(yi, crcp(to_d2(D[c][(2 * c) & 63])));
-          const double2 yc = make_double2(__shfl(yi.x, c), __shfl(yi.y, c));
+          if (lane == c) yi = cmul(yi, dinv);
+          const double2 yc = rdlane2(yi, c);
           if (lane < c) yi = cfms(yi, to_d2(D[lane][(c + lane) & 63]), yc);
         }
       }
@@ -679,12 +755,12 @@ __device__ void lu_solve_lds(const cplx_t<T> *LU, const int *piv, double2 *y, in
 
 // alpha = A^{-1} b from FP64 factors.
 __global__ __launch_bounds__(kLuThreads, 2) void lu_solve64_kernel(
-    const double2 *LUbase, const int *pivbase, int N, long long mstride,
+    const double2 *LUbase, const int *permbase, int N, long long mstride,
     const double2 *b, double2 *x, long long vstride) {
   __shared__ double2 y[kMaxN];
   __shared__ double2 D[64][64];
   const double2 *LU = LUbase + (long long)blockIdx.x * mstride;
-  const int *piv = pivbase + (long long)blockIdx.x * N;
+  const int *piv = permbase + (long long)blockIdx.x * kMaxN;
   for (int i = threadIdx.x; i < N; i += kLuThreads) y[i] = b[(long long)blockIdx.x * vstride + i];
   __syncthreads();
   lu_solve_lds<double>(LU, piv, y, N, D);
@@ -707,20 +783,22 @@ __device__ double block_sum(double v, double *red) {
 // Refined solve: x0 from the FP32 factors, then repeat
 //   r = b - A64 x (FP64), d = LU32^{-1} r, x += d
 // and stop once the predicted error of the updated x, |d_k| * rho with
-// rho = |d_k| / |d_{k-1}| (observed contraction), is below tol |x|.
+// rho = |d_k| / |d_{k-1}| (observed contraction; d_0 = x0), is below tol |x|.
 // status[b] = steps taken, or -1 when the cap was hit or the iteration did
 // not contract (the caller then redoes the solve in FP64).
-__global__ __launch_bounds__(kLuThreads, 2) void refine_kernel(
-    const float2 *LUbase, const int *pivbase, const double2 *A64base, int N,
+__global__ __launch_bounds__(kLuThreads, 3) void refine_kernel(
+    const float2 *LUbase, const int *permbase, const double2 *A64base, int N,
     long long mstride, const double2 *b, double2 *x, long long vstride, double tol,
     int max_iter, int *status, double *relres) {
-  __shared__ double2 xs[kMaxN];
-  __shared__ double2 rs[kMaxN];
+  // dynamic LDS: x and r, N complex128 each (sized at launch), so that
+  // three workgroups fit on a CU at N = 512
+  extern __shared__ double2 refine_dyn[];
+  double2 *xs = refine_dyn, *rs = refine_dyn + N;
   __shared__ float2 D[64][64];
   __shared__ double red[4];
   const long long mb = (long long)blockIdx.x;
   const float2 *LU = LUbase + mb * mstride;
-  const int *piv = pivbase + mb * N;
+  const int *piv = permbase + mb * kMaxN;
   const double2 *A = A64base + mb * mstride;
   const double2 *bb = b + mb * vstride;
   const int tid = threadIdx.x;
@@ -731,7 +809,11 @@ __global__ __launch_bounds__(kLuThreads, 2) void refine_kernel(
   for (int i = tid; i < N; i += kLuThreads) xs[i] = bb[i];
   __syncthreads();
   lu_solve_lds<float>(LU, piv, xs, N, D);
-  double prev = -1.0, last = 0.0;
+  // the initial solve counts as the first correction (from x = 0), so the
+  // contraction can be estimated, and the loop stopped, after one step
+  double x0n = 0.0;
+  for (int i = tid; i < N; i += kLuThreads) x0n += cnorm2(xs[i]);
+  double prev = sqrt(block_sum(x0n, red)), last = 0.0;
   int it = 0, done = 0;
   for (; it < max_iter && !done; ++it) {
     // r = b - A x  (each thread owns rows; column sweep, coalesced)
@@ -768,14 +850,14 @@ __global__ __launch_bounds__(kLuThreads, 2) void refine_kernel(
 // Solve for the matrices whose status is negative (FP64 redo after a
 // refined solve that did not converge): x = A^{-1} b from FP64 factors.
 __global__ __launch_bounds__(kLuThreads, 2) void solve_failed64_kernel(
-    const double2 *LUbase, const int *pivbase, int N, long long mstride, const double2 *b,
+    const double2 *LUbase, const int *permbase, int N, long long mstride, const double2 *b,
     double2 *x, long long vstride, const int *status) {
   __shared__ double2 y[kMaxN];
   __shared__ double2 D[64][64];
   const long long mb = blockIdx.x;
   if (status[mb] >= 0) return;
   const double2 *LU = LUbase + mb * mstride;
-  const int *piv = pivbase + mb * N;
+  const int *piv = permbase + mb * kMaxN;
   for (int i = threadIdx.x; i < N; i += kLuThreads) y[i] = b[mb * vstride + i];
   __syncthreads();
   lu_solve_lds<double>(LU, piv, y, N, D);

@@ -36,22 +36,6 @@ namespace fthms {
 constexpr int kPrThreads = 1024;
 constexpr int kPrWaves = kPrThreads / 64;  // 16 waves x 4 columns = 64
 
-__device__ __forceinline__ float rdlane(float x, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
-}
-__device__ __forceinline__ double rdlane(double x, int l) {
-  const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-template <typename T2> __device__ __forceinline__ T2 rdlane2(T2 v, int l) {
-  T2 r;
-  r.x = rdlane(v.x, l);
-  r.y = rdlane(v.y, l);
-  return r;
-}
-
 // Lane permutations for the pivot search, all without LDS: DPP quad
 // permutations and row mirrors inside 16-lane rows, then the gfx950
 // row-swap instructions across rows and across the two 32-lane halves.
@@ -178,21 +162,6 @@ __device__ __forceinline__ cplx_t<T> row_value(const cplx_t<T> (&a)[RL][4], int 
   return y;
 }
 
-// Integer register array version: v[idx] as a scalar / v[idx] = val.
-template <int RL> __device__ __forceinline__ int iget(const int (&v)[RL], int idx) {
-  const int s = idx >> 6, l = idx & 63;
-  int y = __builtin_amdgcn_readlane(v[0], l);
-#pragma unroll
-  for (int i = 1; i < RL; ++i)
-    if (i == s) y = __builtin_amdgcn_readlane(v[i], l);
-  return y;
-}
-template <int RL> __device__ __forceinline__ void iset(int (&v)[RL], int idx, int val, int lane) {
-  const int s = idx >> 6, l = idx & 63;
-#pragma unroll
-  for (int i = 0; i < RL; ++i) v[i] = (i == s && lane == l) ? val : v[i];
-}
-
 // One column c = 4 cw + J of the block.  used: bit i set if row lane + 64 i
 // has been chosen as a pivot.  rowat/pos (wave 0): row at each position,
 // position of each row.
@@ -207,20 +176,21 @@ __device__ __forceinline__ void panel_reg_column(cplx_t<T> (&a)[RL][4], int &use
   if (w == cw) {
     // the owner's work is the critical path: raise its issue priority
     __builtin_amdgcn_s_setprio(2);
-    // pivot search in column J over the rows not yet chosen; a NaN entry
-    // ranks below every number so that a row is always found
-    T best = T(-1);
+    // pivot search in column J over the rows not yet chosen, with the
+    // magnitudes |re| + |im| formed in FP64 whatever the storage precision;
+    // a NaN entry ranks below every number so that a row is always found
+    double best = -1.0;
     int brow = 0x7fffffff;
 #pragma unroll
     for (int i = 0; i < RL; ++i) {
       const bool ok = ((used >> i) & 1) == 0 && lane < m - 64 * i;
-      T mag = fabs(a[i][J].x) + fabs(a[i][J].y);
-      mag = mag == mag ? mag : T(-0.5);
+      double mag = fabs((double)a[i][J].x) + fabs((double)a[i][J].y);
+      mag = mag == mag ? mag : -0.5;
       const bool take = ok & (mag > best);
       best = take ? mag : best;
       brow = take ? lane + 64 * i : brow;
     }
-    wave_argmax<T>(best, brow);
+    wave_argmax<double>(best, brow);
     p = __builtin_amdgcn_readfirstlane(brow);
     used |= lane == (p & 63) ? 1 << (p >> 6) : 0;
     if (lane == 0) sm.pinfo[b] = p;
@@ -229,8 +199,9 @@ __device__ __forceinline__ void panel_reg_column(cplx_t<T> (&a)[RL][4], int &use
     u[1] = row_value<T, RL, 1>(a, p);
     u[2] = row_value<T, RL, 2>(a, p);
     u[3] = row_value<T, RL, 3>(a, p);
-    const bool nz = best > T(0);
-    const T2 inv = nz ? trcp<T>(u[J]) : mk<T>(T(0), T(0));
+    const bool nz = best > 0.0;
+    // pivot reciprocal in FP64, rounded once to the storage precision
+    const T2 inv = nz ? from_d2<T>(trcp<double>(to_d2(u[J]))) : mk<T>(T(0), T(0));
 #pragma unroll
     for (int i = 0; i < RL; ++i) {
       const bool below = ((used >> i) & 1) == 0 && lane < m - 64 * i;

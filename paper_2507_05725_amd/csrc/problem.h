@@ -365,15 +365,15 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
     const long long ms = (long long)n * n;
     if (!fp32) {
       tbeg(ctx, "solve");
-      lu_solve64_kernel<<<c, kLuThreads, 0, ctx->stream>>>(w[j].A64, w[j].piv, n, ms, w[j].b,
-                                                           w[j].al, n);
+      lu_solve64_kernel<<<c, kLuThreads, 0, ctx->stream>>>(w[j].A64, lu_perm(w[j].swp, c), n, ms,
+                                                           w[j].b, w[j].al, n);
       tend(ctx);
       return check_launch(ctx, "lu_solve64_kernel");
     }
     tbeg(ctx, "solve");
-    refine_kernel<<<c, kLuThreads, 0, ctx->stream>>>(w[j].A32, w[j].piv, w[j].A64, n, ms, w[j].b,
-                                                      w[j].al, n, pb->tol, 10, w[j].status,
-                                                      w[j].relres);
+    refine_kernel<<<c, kLuThreads, 2 * n * sizeof(double2), ctx->stream>>>(
+        w[j].A32, lu_perm(w[j].swp, c), w[j].A64, n, ms, w[j].b, w[j].al, n, pb->tol, 10,
+        w[j].status, w[j].relres);
     tend(ctx);
     int r = check_launch(ctx, "refine_kernel");
     if (r) return r;
