@@ -169,7 +169,7 @@ def _gl(order):
     return _GL[order]
 
 
-def adaptive_gl(f, a, b, breaks=(), tol_abs=1e-15, tol_rel=1e-14, order=16,
+def adaptive_gl(f, a, b, breaks=(), tol_abs=0.0, tol_rel=1e-14, order=16,
                 max_rounds=120):
     """Integral of the vectorised complex function f over [a, b].
 
@@ -177,7 +177,10 @@ def adaptive_gl(f, a, b, breaks=(), tol_abs=1e-15, tol_rel=1e-14, order=16,
     the whole and on its two halves; an interval is accepted when the two
     estimates agree to its share of the tolerance (or to a small fixed
     fraction of the whole budget, which is what ends the bisection next to
-    an integrable endpoint singularity), else it is bisected.
+    an integrable endpoint singularity), else it is bisected.  The tolerance
+    is relative to the scale of the integrand, tol_rel * int |f| (first-round
+    estimate), so that it means the same for a field of size 1e-12 as for
+    one of size 1; tol_abs is an optional absolute floor.
     ``breaks`` are interior points (e.g. the nearest point of a curve to a
     target) at which the interval is split up front.
     """
@@ -187,23 +190,31 @@ def adaptive_gl(f, a, b, breaks=(), tol_abs=1e-15, tol_rel=1e-14, order=16,
     hi = np.array(pts[1:], dtype=float)
     span = b - a
 
-    def rule(l, h):
+    def rule(l, h, with_abs=False):
         c = 0.5 * (l + h)
         r = 0.5 * (h - l)
         x = c[:, None] + r[:, None] * g[None, :]
-        return (f(x.ravel()).reshape(x.shape) @ w) * r
+        fx = f(x.ravel()).reshape(x.shape)
+        if with_abs:
+            return (fx @ w) * r, (np.abs(fx) @ w) * r
+        return (fx @ w) * r
 
     total = 0.0 + 0.0j
-    est = None
+    tol = None
     for _ in range(max_rounds):
         if lo.size == 0:
             break
         mid = 0.5 * (lo + hi)
         whole = rule(lo, hi)
-        halves = rule(lo, mid) + rule(mid, hi)
-        if est is None:
-            est = abs(np.sum(halves))
-        tol = max(tol_abs, tol_rel * est)
+        if tol is None:
+            h1, s1 = rule(lo, mid, True)
+            h2, s2 = rule(mid, hi, True)
+            halves = h1 + h2
+            tol = max(tol_abs, tol_rel * float(np.sum(s1 + s2)))
+            if tol == 0.0:
+                return 0.0 + 0.0j
+        else:
+            halves = rule(lo, mid) + rule(mid, hi)
         err = np.abs(halves - whole)
         ok = (err <= tol * (hi - lo) / span) | (err <= 1e-3 * tol)
         ok |= (hi - lo) <= 1e-15 * span
