@@ -210,4 +210,17 @@ __global__ __launch_bounds__(256) void freq_to_time_kernel(
     }
 }
 
+// Device copy of a near-target quadrature plan (built on the host by
+// plan_near): per point class, near target list, quadrature offsets, points,
+// weights and cos(phi) values.
+struct NearPlan {
+  int np = 0, ntgt = 0, nq = 0;
+  unsigned char *d_cls = nullptr;
+  int *d_tgt = nullptr;
+  int *d_qoff = nullptr;
+  double2 *d_xq = nullptr;
+  double *d_wq = nullptr;
+  double *d_cq = nullptr;
+};
+
 }  // namespace fthms

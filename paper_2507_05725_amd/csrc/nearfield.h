@@ -183,14 +183,4 @@ inline void plan_near(int n, const double *node_xy, const std::vector<double> &c
   }
 }
 
-struct NearPlan {
-  int np = 0, ntgt = 0, nq = 0;
-  unsigned char *d_cls = nullptr;
-  int *d_tgt = nullptr;
-  int *d_qoff = nullptr;
-  double2 *d_xq = nullptr;
-  double *d_wq = nullptr;
-  double *d_cq = nullptr;
-};
-
 }  // namespace fthms
