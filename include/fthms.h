@@ -258,6 +258,52 @@ int fthms_problem_run_dev(fthms_problem *pb, int nk, const double *k_dev,
 int fthms_problem_run(fthms_problem *pb, int nk, const double *k, fthms_c64 *U,
                       fthms_c64 *alpha_tot);
 
+/* ---- uneven batches ------------------------------------------------------ */
+
+/* nb independent solves of the sound-soft single-arc problem (Section 3.2,
+ * eq. FDBIEk-interior with G = -u^i): solve i on arcs[i] at wavenumber
+ * k[i] > 0 with incident field inc[i].  The arcs may have different node
+ * counts -- the uneven (arc, frequency) batches of multi-arc, many-frequency
+ * workloads, where n follows the wavenumber.  Solves of equal n form groups
+ * that are assembled, factored and solved together; the whole batch runs as
+ * one HIP graph, captured at the first run and replayed afterwards.  The
+ * batch copies its tables to the device and owns a workspace for its largest
+ * group (groups are cut to fit 16 GiB or half the context's free budget;
+ * FTHMS_ENOMEM if one matrix does not fit).  The arcs must outlive the batch.
+ * Densities are packed: solve i occupies alpha[off_i, off_i + n_i) with
+ * off_i = n_0 + ... + n_{i-1}.  precision and tol as in fthms_solve. */
+typedef struct fthms_batch fthms_batch;
+int fthms_batch_create(fthms_ctx *ctx, int nb, const fthms_arc *const *arcs,
+                       const double *k, const fthms_incident *inc,
+                       int precision, double tol, fthms_batch **out);
+int fthms_batch_destroy(fthms_batch *batch);
+
+/* total = sum of n_i; offsets[nb] (optional) = off_i. */
+int fthms_batch_layout(const fthms_batch *batch, long long *total,
+                       long long *offsets);
+
+/* Enqueue the batch on the context's stream: alpha_dev[total] (device),
+ * iters_dev[nb] (optional, device) as fthms_solve's iters, -2 for an
+ * exactly zero pivot. */
+int fthms_batch_run_dev(fthms_batch *batch, fthms_c64 *alpha_dev,
+                        int *iters_dev);
+/* Host form (synchronous); FTHMS_ESINGULAR if a pivot is exactly zero. */
+int fthms_batch_run(fthms_batch *batch, fthms_c64 *alpha, int *iters);
+
+/* Autotuner: for every group, time each launch variant of the batched LU on
+ * the batch's own matrices (two half batches on two streams or one launch
+ * sequence; register-resident or LDS panel where both apply), reps times
+ * each (reps < 1: 2), keep the fastest, and capture a new graph at the next
+ * run.  Only the launches change; the register and LDS panels may pick
+ * different pivots among exactly tied candidates and round differently. */
+int fthms_batch_tune(fthms_batch *batch, int reps);
+
+/* Group structure: *ngroups and, per group (arrays of ngroups entries,
+ * optional), its n, number of solves and chosen variant (split: two
+ * streams; reg_panel: register-resident panel). */
+int fthms_batch_buckets(const fthms_batch *batch, int *ngroups, int *n,
+                        int *count, int *split, int *reg_panel);
+
 #ifdef __cplusplus
 }
 #endif

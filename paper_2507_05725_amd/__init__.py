@@ -7,7 +7,7 @@ use of any name below; it raises ImportError when the library is missing
 (there is no CPU fallback).
 """
 _NAMES = ("FP64", "FP32_REFINED", "INC_PLANE", "INC_GPLANE", "INC_POINT",
-          "Arc", "Context", "FthmsError", "Problem", "cheb_nodes",
+          "Arc", "Batch", "Context", "FthmsError", "Problem", "cheb_nodes",
           "incident_struct", "lib", "EXPORTED")
 
 __all__ = list(_NAMES)

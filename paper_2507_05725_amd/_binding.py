@@ -80,6 +80,14 @@ _SIGS = {
     "fthms_problem_destroy": ([_vp], _i),
     "fthms_problem_run": ([_vp, _i, _vp, _vp, _vp], _i),
     "fthms_problem_run_dev": ([_vp, _i, _vp, _vp, _vp], _i),
+    "fthms_batch_create": ([_vp, _i, _vp, _vp, C.POINTER(Incident), _i, _d, C.POINTER(_vp)],
+                           _i),
+    "fthms_batch_destroy": ([_vp], _i),
+    "fthms_batch_layout": ([_vp, C.POINTER(C.c_longlong), _vp], _i),
+    "fthms_batch_run_dev": ([_vp, _vp, _vp], _i),
+    "fthms_batch_run": ([_vp, _vp, _vp], _i),
+    "fthms_batch_tune": ([_vp, _i], _i),
+    "fthms_batch_buckets": ([_vp, C.POINTER(_i), _vp, _vp, _vp, _vp], _i),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -321,6 +329,69 @@ class Problem:
     def close(self):
         if self.h:
             _lib.fthms_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Uneven batch of single-arc solves (see fthms_batch_create): solve i
+    on arcs[i] at k[i] with incidents[i] (one spec for all, or a list)."""
+
+    def __init__(self, ctx, arcs, k, incidents, precision=FP64, tol=0.0):
+        self.ctx = ctx
+        self.arcs = list(arcs)
+        k = np.ascontiguousarray(k, dtype=np.float64)
+        nb = k.size
+        if len(self.arcs) != nb:
+            raise ValueError("one arc per wavenumber required")
+        if not isinstance(incidents, (list, tuple)):
+            incidents = [incidents] * nb
+        self._inc = (Incident * nb)(*[incident_struct(s) for s in incidents])
+        self._arr = (C.c_void_p * nb)(*[a.h.value for a in self.arcs])
+        h = C.c_void_p()
+        ctx.check(_lib.fthms_batch_create(ctx.h, nb, self._arr, _ptr(k), self._inc, precision,
+                                          tol, C.byref(h)), "batch_create")
+        self.h = h
+        self.nb = nb
+        total = C.c_longlong()
+        self.offsets = np.empty(nb, dtype=np.int64)
+        ctx.check(_lib.fthms_batch_layout(h, C.byref(total), _ptr(self.offsets)), "batch_layout")
+        self.total = total.value
+
+    def run(self):
+        alpha = np.empty(self.total, dtype=np.complex128)
+        iters = np.empty(self.nb, dtype=np.int32)
+        self.ctx.check(_lib.fthms_batch_run(self.h, _ptr(alpha), _ptr(iters)), "batch_run")
+        return alpha, iters
+
+    def run_dev(self, alpha, iters=None):
+        self.ctx.check(_lib.fthms_batch_run_dev(self.h, _dptr(alpha), _dptr(iters)),
+                       "batch_run_dev")
+
+    def tune(self, reps=2):
+        self.ctx.check(_lib.fthms_batch_tune(self.h, int(reps)), "batch_tune")
+
+    def buckets(self):
+        ng = C.c_int()
+        self.ctx.check(_lib.fthms_batch_buckets(self.h, C.byref(ng), None, None, None, None),
+                       "batch_buckets")
+        arr = [np.empty(ng.value, dtype=np.int32) for _ in range(4)]
+        self.ctx.check(_lib.fthms_batch_buckets(self.h, C.byref(ng), *[_ptr(a) for a in arr]),
+                       "batch_buckets")
+        return dict(n=arr[0], count=arr[1], split=arr[2], reg_panel=arr[3])
+
+    def density(self, alpha, i):
+        o = int(self.offsets[i])
+        return alpha[o:o + self.arcs[i].n]
+
+    def close(self):
+        if self.h:
+            _lib.fthms_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -25,14 +25,19 @@
 namespace fthms {
 
 // Upper-triangular 32x32 tiles; each block computes one tile for one
-// wavenumber and writes it and its mirror (A is complex symmetric).
+// wavenumber and writes it and its mirror (A is complex symmetric).  With
+// ylist / Glist (uneven batches) matrix b takes its own arc's nodes and
+// table; otherwise every matrix uses y0 / G0.
 template <bool W32>
 __global__ __launch_bounds__(256) void assemble_kernel(
-    const double2 *__restrict__ y, const double *__restrict__ G, int N,
+    const double2 *__restrict__ y0, const double *__restrict__ G0, int N,
     const double *__restrict__ kvec, double2 *__restrict__ A64,
-    float2 *__restrict__ A32, long long mstride) {
+    float2 *__restrict__ A32, long long mstride, const double2 *const *ylist,
+    const double *const *Glist) {
   __shared__ double2 tile[32][33];
   const int b = blockIdx.y;
+  const double2 *__restrict__ y = ylist ? ylist[b] : y0;
+  const double *__restrict__ G = Glist ? Glist[b] : G0;
   const double k = kvec[b];
   const int t = blockIdx.x;
   int J = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
@@ -124,6 +129,19 @@ __global__ __launch_bounds__(256) void incident_kernel(
   double2 u = incident_at(in, kvec[b], p[i]);
   const double s = chi ? scale * chi[i] : scale;
   out[(long long)b * ostride + i] = make_double2(s * u.x, s * u.y);
+}
+
+// Right-hand sides of an uneven batch: out[b][i] = -U^inc_b(y_b[i], k_b).
+__global__ __launch_bounds__(256) void batch_rhs_kernel(const IncidentDev *__restrict__ inc,
+                                                        const double2 *const *ylist,
+                                                        const double *__restrict__ kvec, int n,
+                                                        double2 *__restrict__ out,
+                                                        long long ostride) {
+  const int b = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 u = incident_at(inc[b], kvec[b], ylist[b][i]);
+  out[(long long)b * ostride + i] = make_double2(-u.x, -u.y);
 }
 
 }  // namespace fthms

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdint>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <new>
 #include <string>
@@ -36,8 +37,9 @@ struct fthms_ctx {
   size_t ws_bytes = 0;
   void *ws2 = nullptr;
   size_t ws2_bytes = 0;
-  // kernel timing with HIP events on `stream`
+  // kernel timing with HIP events on `stream` (off while a graph is captured)
   bool timing = false;
+  bool capturing = false;
   struct Pending {
     std::string name;
     hipEvent_t a, b;
@@ -118,7 +120,7 @@ static int ensure_ws2(fthms_ctx *ctx, size_t bytes) {
 }
 
 static void tbeg(fthms_ctx *ctx, const char *name, hipStream_t st = nullptr) {
-  if (!ctx->timing) return;
+  if (!ctx->timing || ctx->capturing) return;
   if (!st) st = ctx->stream;
   fthms_ctx::Pending p;
   p.name = name;
@@ -139,7 +141,7 @@ static void tbeg(fthms_ctx *ctx, const char *name, hipStream_t st = nullptr) {
 
 // closes the innermost range opened by tbeg (ranges nest)
 static void tend(fthms_ctx *ctx) {
-  if (!ctx->timing || ctx->open.empty()) return;
+  if (!ctx->timing || ctx->capturing || ctx->open.empty()) return;
   const size_t i = ctx->open.back();
   ctx->open.pop_back();
   if (i != SIZE_MAX) (void)hipEventRecord(ctx->pending[i].b, ctx->pending[i].st);
@@ -429,14 +431,22 @@ static void launch_perm(hipStream_t st, const int *piv, int N, int *perm, const 
     perm_from_piv_kernel<16><<<count, 64, 0, st>>>(piv, N, perm, status, only_failed);
 }
 
+// Launch choices of the batched LU (the batch autotuner picks them per
+// matrix size; every other caller uses the defaults).
+struct LuOpts {
+  bool split = true;      // two half batches on two streams (large batches)
+  bool reg_panel = true;  // register-resident panel where the block fits
+};
+
 // Panel of the block at k0: register-resident kernel when the block fits
 // (m = N - k0 <= 512 in FP32, <= 256 in FP64), else the LDS/global kernel.
 template <typename T, int R>
 static void launch_panel(hipStream_t st, cplx_t<T> *A, int N, long long ms, int k0, int *piv,
-                         int *swp, cplx_t<T> *linv, int *status, int count, int only_failed) {
+                         int *swp, cplx_t<T> *linv, int *status, int count, int only_failed,
+                         bool reg_panel) {
   const int m = N - k0;
   const int rl = (m + 63) / 64;
-  const int rl_max = sizeof(T) == 4 ? 8 : 4;
+  const int rl_max = !reg_panel ? 0 : sizeof(T) == 4 ? 8 : 4;
 #define FTHMS_PANEL_REG(RL)                                                            \
   lu_panel_reg_kernel<T, RL><<<count, kPrThreads, 0, st>>>(A, N, ms, k0, piv, swp, linv, \
                                                            status, only_failed)
@@ -466,12 +476,13 @@ static void launch_panel(hipStream_t st, cplx_t<T> *A, int N, long long ms, int 
 template <typename T, int R>
 static void lu_step(fthms_ctx *ctx, hipStream_t st, cplx_t<T> *A, int N, long long ms, int k0,
                     int *piv, int *swp, cplx_t<T> *linv, int *status, int count,
-                    int only_failed) {
+                    int only_failed, const LuOpts &o) {
   // per-kernel timing ranges, except in the redo pass (timed as a whole)
   const bool tk = !only_failed;
   const int nb = std::min(kLuNB, N - k0);
   if (tk) tbeg(ctx, "lu_panel", st);
-  launch_panel<T, R>(st, A, N, ms, k0, piv, swp, linv, status, count, only_failed);
+  launch_panel<T, R>(st, A, N, ms, k0, piv, swp, linv, status, count, only_failed,
+                     o.reg_panel);
   if (tk) tend(ctx);
   const int nleft = (k0 + kStripW - 1) / kStripW;
   const int nright = (N - k0 - nb + kStripW - 1) / kStripW;
@@ -492,12 +503,13 @@ constexpr int kLuSplitMin = 256;
 
 template <typename T, int R>
 static void lu_blocks(fthms_ctx *ctx, cplx_t<T> *A, int N, long long ms, int *piv, void *scr,
-                      int *status, int count, int only_failed) {
+                      int *status, int count, int only_failed, const LuOpts &o) {
   int *swp = (int *)scr;
   cplx_t<T> *linv = (cplx_t<T> *)((char *)scr + sizeof(int) * kSwapStride * (size_t)count);
-  if (only_failed || count < kLuSplitMin) {
+  if (only_failed || count < kLuSplitMin || !o.split) {
     for (int k0 = 0; k0 < N; k0 += kLuNB)
-      lu_step<T, R>(ctx, ctx->stream, A, N, ms, k0, piv, swp, linv, status, count, only_failed);
+      lu_step<T, R>(ctx, ctx->stream, A, N, ms, k0, piv, swp, linv, status, count, only_failed,
+                    o);
     return;
   }
   // halves aligned to 8 so the XCD placement of every matrix is unchanged
@@ -511,7 +523,7 @@ static void lu_blocks(fthms_ctx *ctx, cplx_t<T> *A, int N, long long ms, int *pi
   (void)hipEventRecord(ctx->ev_fork, ctx->stream);
   (void)hipStreamWaitEvent(ctx->aux, ctx->ev_fork, 0);
   for (int k0 = 0; k0 < N; k0 += kLuNB) {
-    lu_step<T, R>(ctx, ctx->stream, A, N, ms, k0, piv, swp, linv, status, h, 0);
+    lu_step<T, R>(ctx, ctx->stream, A, N, ms, k0, piv, swp, linv, status, h, 0, o);
     if (k0 == 0) {
       // start the second half once the first half's first panel is done
       (void)hipEventRecord(ctx->ev_lead, ctx->stream);
@@ -519,30 +531,31 @@ static void lu_blocks(fthms_ctx *ctx, cplx_t<T> *A, int N, long long ms, int *pi
     }
   }
   for (int k0 = 0; k0 < N; k0 += kLuNB)
-    lu_step<T, R>(ctx, ctx->aux, A2, N, ms, k0, piv2, swp2, linv2, status2, c2, 0);
+    lu_step<T, R>(ctx, ctx->aux, A2, N, ms, k0, piv2, swp2, linv2, status2, c2, 0, o);
   (void)hipEventRecord(ctx->ev_join, ctx->aux);
   (void)hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0);
 }
 
 // scr: count * kLuScratchBytes of device scratch
 static int launch_lu(fthms_ctx *ctx, bool fp32, void *A, int N, long long ms, int *piv,
-                     void *scr, int *status, int count, int only_failed = 0) {
+                     void *scr, int *status, int count, int only_failed = 0,
+                     const LuOpts &o = LuOpts()) {
   const int R = (N + kLuThreads - 1) / kLuThreads;
   if (fp32) {
     float2 *a = (float2 *)A;
     switch (R) {
-      case 1: lu_blocks<float, 1>(ctx, a, N, ms, piv, scr, status, count, only_failed); break;
-      case 2: lu_blocks<float, 2>(ctx, a, N, ms, piv, scr, status, count, only_failed); break;
-      case 3: lu_blocks<float, 3>(ctx, a, N, ms, piv, scr, status, count, only_failed); break;
-      default: lu_blocks<float, 4>(ctx, a, N, ms, piv, scr, status, count, only_failed); break;
+      case 1: lu_blocks<float, 1>(ctx, a, N, ms, piv, scr, status, count, only_failed, o); break;
+      case 2: lu_blocks<float, 2>(ctx, a, N, ms, piv, scr, status, count, only_failed, o); break;
+      case 3: lu_blocks<float, 3>(ctx, a, N, ms, piv, scr, status, count, only_failed, o); break;
+      default: lu_blocks<float, 4>(ctx, a, N, ms, piv, scr, status, count, only_failed, o); break;
     }
   } else {
     double2 *a = (double2 *)A;
     switch (R) {
-      case 1: lu_blocks<double, 1>(ctx, a, N, ms, piv, scr, status, count, only_failed); break;
-      case 2: lu_blocks<double, 2>(ctx, a, N, ms, piv, scr, status, count, only_failed); break;
-      case 3: lu_blocks<double, 3>(ctx, a, N, ms, piv, scr, status, count, only_failed); break;
-      default: lu_blocks<double, 4>(ctx, a, N, ms, piv, scr, status, count, only_failed); break;
+      case 1: lu_blocks<double, 1>(ctx, a, N, ms, piv, scr, status, count, only_failed, o); break;
+      case 2: lu_blocks<double, 2>(ctx, a, N, ms, piv, scr, status, count, only_failed, o); break;
+      case 3: lu_blocks<double, 3>(ctx, a, N, ms, piv, scr, status, count, only_failed, o); break;
+      default: lu_blocks<double, 4>(ctx, a, N, ms, piv, scr, status, count, only_failed, o); break;
     }
   }
   launch_perm(ctx->stream, piv, N, lu_perm(scr, count), status, count, only_failed);
@@ -621,9 +634,11 @@ static int assemble_launch(fthms_ctx *ctx, const fthms_arc *arc, const double *k
   dim3 g(T * (T + 1) / 2, count), b(256);
   const long long ms = (long long)N * N;
   if (A32)
-    assemble_kernel<true><<<g, b, 0, ctx->stream>>>(arc->d_y, arc->d_G, N, k_dev, A64, A32, ms);
+    assemble_kernel<true><<<g, b, 0, ctx->stream>>>(arc->d_y, arc->d_G, N, k_dev, A64, A32, ms,
+                                                     nullptr, nullptr);
   else
-    assemble_kernel<false><<<g, b, 0, ctx->stream>>>(arc->d_y, arc->d_G, N, k_dev, A64, nullptr, ms);
+    assemble_kernel<false><<<g, b, 0, ctx->stream>>>(arc->d_y, arc->d_G, N, k_dev, A64, nullptr,
+                                                      ms, nullptr, nullptr);
   return check_launch(ctx, "assemble_kernel");
 }
 
@@ -1046,3 +1061,4 @@ int fthms_bessel_dev(fthms_ctx *ctx, int nz, const double *z_dev, double *j0_dev
 }  // extern "C"
 
 #include "problem.h"
+#include "batch.h"

@@ -167,9 +167,12 @@ def _sine_length(ell, amp_ratio, nu):
 
 
 def uneven_batch_case(seed=3, narcs=8, nk=2048, kmin=1.0, kmax=120.0,
-                      nmax=1024, nmin=64, ppw=10.0):
+                      nmax=1024, nmin=64, ppw=10.0, quantum=1):
     """Eight arcs of three kinds with lengths U[0.5, 4]; N per (arc, k) from
-    ppw points per wavelength, clamped to [nmin, nmax]."""
+    ppw points per wavelength, clamped to [nmin, nmax], then rounded up to a
+    multiple of `quantum` (1: the rule as stated; the GPU runs use 16 so that
+    one frequency-independent table per (arc, N) serves a band of
+    frequencies)."""
     rng = np.random.default_rng(seed)
     arcs = []
     for i in range(narcs):
@@ -210,5 +213,6 @@ def uneven_batch_case(seed=3, narcs=8, nk=2048, kmin=1.0, kmax=120.0,
     k = kmin + (kmax - kmin) * np.arange(nk) / max(nk - 1, 1)
     for a in arcs:
         n = np.ceil(ppw * k * a["length"] / (2.0 * math.pi)).astype(int)
-        a["n"] = np.minimum(nmax, np.maximum(nmin, n))
+        n = np.minimum(nmax, np.maximum(nmin, n))
+        a["n"] = np.minimum(nmax, quantum * ((n + quantum - 1) // quantum))
     return dict(arcs=arcs, k=k, name="uneven%d_k%d" % (narcs, nk))
