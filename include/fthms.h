@@ -221,7 +221,12 @@ int fthms_bessel_dev(fthms_ctx *ctx, int nz, const double *z_dev,
 /* ---- multiple scattering over a cyclic partition ---------------------- */
 
 /* A closed curve covered by narcs >= 2 overlapping arcs, cyclically ordered
- * (arc j overlaps arcs j-1 and j+1 only).  interval[2j], interval[2j+1] are
+ * (arc j overlaps arcs j-1 and j+1 only) -- or several closed curves
+ * (obstacles of an exterior problem, Section 3.3): group[j] (optional;
+ * NULL: one curve) names the curve of arc j, the arcs of one curve are
+ * cyclic in the order given, and an arc alone in its group is a plain open
+ * arc (chi = 1).  Every arc scatters onto every other one; the overlap
+ * masking applies to neighbours on the same curve.  interval[2j], interval[2j+1] are
  * the parameter bounds of arc j on the parent closed curve of period
  * `period` (arc j's local t = -1 maps to interval[2j]); they decide overlap
  * membership.  c0, c1 are the POU constants of eq. POU1 (the paper uses
@@ -242,6 +247,7 @@ typedef struct {
   fthms_incident incident;
   int nobs;
   const double *obs_xy;
+  const int *group;
 } fthms_problem_desc;
 
 int fthms_problem_create(fthms_ctx *ctx, const fthms_problem_desc *desc,
@@ -257,6 +263,21 @@ int fthms_problem_run_dev(fthms_problem *pb, int nk, const double *k_dev,
                           fthms_c64 *U_dev, fthms_c64 *alpha_tot_dev);
 int fthms_problem_run(fthms_problem *pb, int nk, const double *k, fthms_c64 *U,
                       fthms_c64 *alpha_tot);
+
+/* The recursion with time-domain output (eq. TDsol-interior with one
+ * window): after each step m the traces u_m(x_p, t_n) = (1/2pi) sum_l w_l
+ * U_m(x_p, k_l) e^{-i k_l t_n} at the observation points are updated, and the
+ * run stops once |u_m - u_{m-1}| <= stop_tol |u_m| (L2 over all points and
+ * times) or after the problem's M steps (stop_tol <= 0: always M).  w[nk]:
+ * quadrature weights of the frequencies (e.g. trapezoid); traces[nt][nobs];
+ * *steps (host, optional): steps taken.  All nk frequencies must fit the
+ * workspace at once (FTHMS_ENOMEM otherwise). */
+int fthms_problem_traces_dev(fthms_problem *pb, int nk, const double *k_dev,
+                             const double *w_dev, int nt, const double *t_dev,
+                             double stop_tol, fthms_c64 *traces_dev, int *steps);
+int fthms_problem_traces(fthms_problem *pb, int nk, const double *k,
+                         const double *w, int nt, const double *t,
+                         double stop_tol, fthms_c64 *traces, int *steps);
 
 /* ---- uneven batches ------------------------------------------------------ */
 

@@ -20,6 +20,10 @@ Readings taken where the text is silent or loose:
   * Overlap membership of a node is decided by the parent-curve parameter
     interval of each arc, not by geometric distance.
   * The second line of eq. vtilde ("k = j-1 and k = j+1") means "or".
+  * Several closed curves (the exterior problem of Section 3.3): every arc
+    scatters onto every other one; the masking of eq. vtilde and the
+    windows chi_j involve the neighbours on the same curve only, and an arc
+    alone on its curve has chi = 1.
 """
 from __future__ import annotations
 
@@ -50,12 +54,22 @@ def in_interval(tau, a, b, period):
 
 
 class Layout:
-    """Node sets, overlap membership and POU values of a cyclic partition."""
+    """Node sets, overlap membership and POU values of cyclic partitions of
+    one or several closed curves."""
 
     def __init__(self, problem):
         self.p = problem
         self.arcs = [a.curve for a in problem.arcs]
         self.J = len(self.arcs)
+        self.group = [getattr(a, "group", 0) for a in problem.arcs]
+        # cyclic neighbours on the same curve (None for an arc alone)
+        self.nxt, self.prv = [None] * self.J, [None] * self.J
+        for j in range(self.J):
+            mem = [i for i in range(self.J) if self.group[i] == self.group[j]]
+            if len(mem) > 1:
+                q = mem.index(j)
+                self.nxt[j] = mem[(q + 1) % len(mem)]
+                self.prv[j] = mem[(q - 1) % len(mem)]
         self.nodes = [ny.arc_nodes(a.curve, a.n) for a in problem.arcs]
         self.tau = [c.parent_param(nd["t"]) for c, nd in zip(self.arcs,
                                                               self.nodes)]
@@ -67,7 +81,7 @@ class Layout:
                 if k == j:
                     continue
                 m = np.ones(self.nodes[j]["n"], dtype=bool)
-                if k in ((j - 1) % self.J, (j + 1) % self.J):
+                if k in (self.prv[j], self.nxt[j]):
                     a, b = self.arcs[k].interval
                     m &= ~in_interval(self.tau[j], a, b, problem.period)
                 self.mask[k][j] = m
@@ -78,9 +92,11 @@ class Layout:
     def chi_at(self, j, tau, y):
         """chi_j (eq. POU1) at points y of the closed curve with parent
         parameters tau; zero off Gamma_j."""
-        p, J = self.p, self.J
-        nxt, prv = (j + 1) % J, (j - 1) % J
+        p = self.p
+        nxt, prv = self.nxt[j], self.prv[j]
         c = self.arcs[j]
+        if nxt is None:
+            return np.ones(np.shape(tau))
         a0, b0 = c.interval
         chi = np.where(in_interval(tau, a0, b0, p.period), 1.0, 0.0)
         # overlap with the next arc: eta(A - d; c0 A, c1 A), d = chord to
@@ -90,6 +106,11 @@ class Layout:
         A = math.hypot(*(xs - xe))
         a, b = self.arcs[nxt].interval
         on = in_interval(tau, a, b, p.period) & (chi > 0)
+        xs0 = c.x(np.array([-1.0]))[0]
+        if nxt == prv:
+            # two arcs on a curve overlap at both ends: the nearer end decides
+            on &= (np.hypot(y[:, 0] - xe[0], y[:, 1] - xe[1])
+                   <= np.hypot(y[:, 0] - xs0[0], y[:, 1] - xs0[1]))
         d = np.hypot(y[on, 0] - xe[0], y[on, 1] - xe[1])
         chi[on] = eta(A - d, p.c0 * A, p.c1 * A)
         # overlap with the previous arc: 1 - eta(A' - d'; c0 A', c1 A'),
@@ -98,7 +119,7 @@ class Layout:
         xs2 = c.x(np.array([-1.0]))[0]
         A2 = math.hypot(*(xs2 - xe2))
         a2, b2 = self.arcs[prv].interval
-        on2 = in_interval(tau, a2, b2, p.period) & (chi > 0)
+        on2 = in_interval(tau, a2, b2, p.period) & (chi > 0) & ~on
         d2 = np.hypot(y[on2, 0] - xe2[0], y[on2, 1] - xe2[1])
         chi[on2] = 1.0 - eta(A2 - d2, p.c0 * A2, p.c1 * A2)
         return chi
@@ -119,7 +140,10 @@ class Layout:
             for k in range(self.J):
                 if k == j:
                     continue
-                out = ~in_interval(taus[k], a, b, self.p.period)
+                if self.group[k] == self.group[j]:
+                    out = ~in_interval(taus[k], a, b, self.p.period)
+                else:
+                    out = np.ones(taus[k].shape, dtype=bool)
                 q = pts[k][out]
                 if q.shape[0] == 0 or tr.shape[0] == 0:
                     continue
@@ -164,3 +188,31 @@ def run_frequency(layout, k, keep_steps=False):
     for j in range(J):
         U += ny.field(k, p.obs, layout.arcs[j], nodes[j], tot[j])
     return dict(alpha_tot=tot, U=U, steps=steps)
+
+
+def run_traces(layout, omegas, weights, times, stop_tol=0.0):
+    """Time traces of the MS sum at the observation points with the stop rule
+    of the series in the time domain (reading of the 'update norm' stop: the
+    increment of step m, F^{-1}[U of that step's densities] over all points
+    and times, relative to the sum so far).  The recursion runs per frequency
+    (eqs. criterion_int1/2, vtilde), each step's field is transformed with
+    the trapezoid rule (eq. TDsol-interior), and the sum stops after the
+    first step m with |u_m - u_{m-1}| <= stop_tol |u_m| or after M steps.
+    Returns (traces [nt][nobs], steps taken)."""
+    from .transform import freq_to_time
+    p = layout.p
+    nobs = p.obs.shape[0]
+    per = np.zeros((p.M, len(omegas), nobs), dtype=complex)
+    for l, k in enumerate(omegas):
+        out = run_frequency(layout, k, keep_steps=True)
+        for m, st in enumerate(out["steps"]):
+            for j in range(layout.J):
+                per[m, l] += ny.field(k, p.obs, layout.arcs[j], layout.nodes[j],
+                                      st["alpha"][j])
+    u = np.zeros((len(times), nobs), dtype=complex)
+    for m in range(p.M):
+        du = freq_to_time(omegas, weights, per[m], times)
+        u = u + du
+        if stop_tol > 0.0 and np.linalg.norm(du) <= stop_tol * np.linalg.norm(u):
+            return u, m + 1
+    return u, p.M

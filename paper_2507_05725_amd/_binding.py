@@ -42,7 +42,7 @@ class ProblemDesc(C.Structure):
                 ("c0", C.c_double), ("c1", C.c_double), ("M", C.c_int),
                 ("precision", C.c_int), ("tol", C.c_double),
                 ("incident", Incident), ("nobs", C.c_int),
-                ("obs_xy", C.POINTER(C.c_double))]
+                ("obs_xy", C.POINTER(C.c_double)), ("group", C.POINTER(C.c_int))]
 
 
 if not os.path.exists(LIB_PATH):
@@ -80,6 +80,8 @@ _SIGS = {
     "fthms_problem_destroy": ([_vp], _i),
     "fthms_problem_run": ([_vp, _i, _vp, _vp, _vp], _i),
     "fthms_problem_run_dev": ([_vp, _i, _vp, _vp, _vp], _i),
+    "fthms_problem_traces": ([_vp, _i, _vp, _vp, _i, _vp, _d, _vp, C.POINTER(_i)], _i),
+    "fthms_problem_traces_dev": ([_vp, _i, _vp, _vp, _i, _vp, _d, _vp, C.POINTER(_i)], _i),
     "fthms_batch_create": ([_vp, _i, _vp, _vp, C.POINTER(Incident), _i, _d, C.POINTER(_vp)],
                            _i),
     "fthms_batch_destroy": ([_vp], _i),
@@ -292,7 +294,7 @@ class Problem:
     """Cyclic multi-arc (or single-arc) problem; see fthms_problem_desc."""
 
     def __init__(self, ctx, arcs, incident, obs, intervals=None, period=2 * np.pi,
-                 c0=1.0 / 3.0, c1=2.0 / 3.0, M=1, precision=FP64, tol=0.0):
+                 c0=1.0 / 3.0, c1=2.0 / 3.0, M=1, precision=FP64, tol=0.0, groups=None):
         self.ctx = ctx
         self.arcs = list(arcs)
         self.nsum = sum(a.n for a in self.arcs)
@@ -310,6 +312,10 @@ class Problem:
         d.incident = incident_struct(incident)
         d.nobs = self.obs.shape[0]
         d.obs_xy = self.obs.ctypes.data_as(C.POINTER(C.c_double))
+        self._grp = None
+        if groups is not None:
+            self._grp = np.ascontiguousarray(groups, dtype=np.int32)
+            d.group = self._grp.ctypes.data_as(C.POINTER(C.c_int))
         h = C.c_void_p()
         ctx.check(_lib.fthms_problem_create(ctx.h, C.byref(d), C.byref(h)), "problem_create")
         self.h = h
@@ -321,6 +327,18 @@ class Problem:
         self.ctx.check(_lib.fthms_problem_run(self.h, k.size, _ptr(k), _ptr(U), _ptr(A)),
                        "problem_run")
         return (U, A) if want_alpha else U
+
+    def traces(self, k, w, t, stop_tol=0.0):
+        """Time traces u_m at the observation points; returns (traces, steps)."""
+        k = np.ascontiguousarray(k, dtype=np.float64)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        t = np.ascontiguousarray(t, dtype=np.float64)
+        out = np.empty((t.size, self.obs.shape[0]), dtype=np.complex128)
+        steps = C.c_int()
+        self.ctx.check(_lib.fthms_problem_traces(self.h, k.size, _ptr(k), _ptr(w), t.size, _ptr(t),
+                                                 stop_tol, _ptr(out), C.byref(steps)),
+                       "problem_traces")
+        return out, steps.value
 
     def run_dev(self, k, U, alpha=None):
         self.ctx.check(_lib.fthms_problem_run_dev(self.h, k.numel(), _dptr(k), _dptr(U),

@@ -54,6 +54,19 @@ __global__ void place_kernel(const double2 *src, int n, int nb, double2 *dst, lo
 
 }  // namespace fthms
 
+// out[0] += sum |x|^2 (block partial sums, one atomic add per block)
+__global__ __launch_bounds__(256) void norm2_kernel(const double2 *__restrict__ x, long long n,
+                                                    double *out) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x)
+    s += x[i].x * x[i].x + x[i].y * x[i].y;
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(out, red[0] + red[1] + red[2] + red[3]);
+}
+
 static dim3 grid1d(long long n) {
   long long b = (n + 255) / 256;
   return dim3((unsigned)std::max<long long>(1, std::min<long long>(b, 65535)));
@@ -110,6 +123,8 @@ struct fthms_problem {
   double tol = 1e-13, period = 0.0, c0 = 1.0 / 3.0, c1 = 2.0 / 3.0;
   IncidentDev inc;
   std::vector<const fthms_arc *> arcs;
+  std::vector<int> group;           // obstacle (closed curve) of each arc
+  std::vector<int> nxt, prv;        // cyclic neighbours within the group (-1: none)
   std::vector<double> interval;
   std::vector<double *> d_chi;
   std::vector<std::vector<unsigned char>> skip;  // [k * narcs + j][i]
@@ -228,15 +243,42 @@ int fthms_problem_create(fthms_ctx *ctx, const fthms_problem_desc *d, fthms_prob
   if (pb->nobs)
     HIPCK(ctx, hipMemcpy(pb->d_obs, pb->obs.data(), sizeof(double2) * pb->nobs,
                          hipMemcpyHostToDevice));
+  // groups: arcs of one closed curve in cyclic order (d->group NULL: one curve)
+  pb->group.assign(J, 0);
+  if (d->group)
+    for (int j = 0; j < J; ++j) pb->group[j] = d->group[j];
+  pb->nxt.assign(J, -1);
+  pb->prv.assign(J, -1);
+  for (int j = 0; j < J; ++j) {
+    std::vector<int> mem;
+    for (int i = 0; i < J; ++i)
+      if (pb->group[i] == pb->group[j]) mem.push_back(i);
+    const int sz = (int)mem.size();
+    if (sz < 2) continue;
+    const int pos = (int)(std::find(mem.begin(), mem.end(), j) - mem.begin());
+    pb->nxt[j] = mem[(pos + 1) % sz];
+    pb->prv[j] = mem[(pos + sz - 1) % sz];
+  }
   if (J > 1) {
     // chi_j at the nodes (eq. POU1, chord reading) and overlap masks
     pb->d_chi.assign(J, nullptr);
     pb->skip.assign((size_t)J * J, std::vector<unsigned char>());
     for (int j = 0; j < J; ++j) {
       const fthms_arc *a = pb->arcs[j];
-      const int nxt = (j + 1) % J, prv = (j + J - 1) % J;
+      const int nxt = pb->nxt[j], prv = pb->prv[j];
+      std::vector<double> chi(a->n, 1.0), tau(a->n);
+      if (nxt < 0) {  // an arc alone in its group: chi = 1, nothing masked
+        if ((rc = dev_alloc(ctx, (void **)&pb->d_chi[j], sizeof(double) * a->n))) {
+          fthms_problem_destroy(pb);
+          return rc;
+        }
+        HIPCK(ctx, hipMemcpy(pb->d_chi[j], chi.data(), sizeof(double) * a->n,
+                             hipMemcpyHostToDevice));
+        for (int k = 0; k < J; ++k)
+          if (k != j) pb->skip[(size_t)k * J + j].assign(a->n, 0);
+        continue;
+      }
       const double aj = pb->interval[2 * j], bj = pb->interval[2 * j + 1];
-      std::vector<double> tau(a->n), chi(a->n, 1.0);
       for (int i = 0; i < a->n; ++i) tau[i] = 0.5 * (aj + bj) + 0.5 * (bj - aj) * a->t[i];
       double xe, ye, xs, ys;
       arc_end(a, +1, xe, ye);                // end of Gamma_j (in overlap with next)
@@ -248,11 +290,17 @@ int fthms_problem_create(fthms_ctx *ctx, const fthms_problem_desc *d, fthms_prob
       const double A2 = std::hypot(xs2 - xe2, ys2 - ye2);
       for (int i = 0; i < a->n; ++i) {
         const double px = a->xy[2 * i], py = a->xy[2 * i + 1];
-        if (in_interval(tau[i], pb->interval[2 * nxt], pb->interval[2 * nxt + 1], pb->period)) {
+        const bool on_nxt =
+            in_interval(tau[i], pb->interval[2 * nxt], pb->interval[2 * nxt + 1], pb->period);
+        const bool on_prv =
+            in_interval(tau[i], pb->interval[2 * prv], pb->interval[2 * prv + 1], pb->period);
+        // two arcs in a group overlap at both ends: the nearer end decides
+        const bool use_nxt = on_nxt && (nxt != prv || std::hypot(px - xe, py - ye) <=
+                                                          std::hypot(px - xs2, py - ys2));
+        if (use_nxt) {
           const double dd = std::hypot(px - xe, py - ye);
           chi[i] = eta_window(A - dd, pb->c0 * A, pb->c1 * A);
-        } else if (in_interval(tau[i], pb->interval[2 * prv], pb->interval[2 * prv + 1],
-                               pb->period)) {
+        } else if (on_prv) {
           const double dd = std::hypot(px - xe2, py - ye2);
           chi[i] = 1.0 - eta_window(A2 - dd, pb->c0 * A2, pb->c1 * A2);
         }
@@ -292,8 +340,21 @@ int fthms_problem_destroy(fthms_problem *pb) {
 
 }  // extern "C"
 
+// Time-domain output of a run: traces[nt][nobs] of u_m = F^{-1}[U_m] at the
+// observation points (trapezoid weights w), updated after every step m, and
+// the stop rule |u_m - u_{m-1}| <= stop_tol |u_m| (stop_tol <= 0: run all M
+// steps); steps receives the number of steps taken.
+struct TraceReq {
+  const double *w;
+  int nt;
+  const double *t;
+  double stop_tol;
+  double2 *traces;
+  int *steps;
+};
+
 static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, double kmax,
-                            double2 *U, double2 *alpha_tot) {
+                            double2 *U, double2 *alpha_tot, const TraceReq *tr = nullptr) {
   fthms_ctx *ctx = pb->ctx;
   const int J = pb->narcs;
   const bool fp32 = pb->precision == FTHMS_FP32_REFINED;
@@ -318,6 +379,9 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
   if (C < 1) return fail(ctx, FTHMS_ENOMEM, "no room for one wavenumber");
   const int nchunks = (nk + C - 1) / C;  // even split of the batch
   C = (nk + nchunks - 1) / nchunks;
+  if (tr && nchunks > 1)
+    return fail(ctx, FTHMS_ENOMEM, "the time-domain stop rule needs every frequency resident "
+                                   "(" + std::to_string(nk) + " do not fit)");
   struct ArcWs {
     double2 *A64;
     float2 *A32;
@@ -327,9 +391,11 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
     double2 *b, *al, *cr, *tot;
   };
   std::vector<ArcWs> w(J);
+  double2 *Ustep = nullptr, *du = nullptr;
+  double *nrm = nullptr;
   {
     size_t off = 0;
-    std::vector<size_t> o(J * 11);
+    std::vector<size_t> o((size_t)J * 10);
     auto take = [&](size_t bytes) {
       size_t r = off;
       off += (bytes + 255) & ~(size_t)255;
@@ -345,6 +411,11 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
       for (int v = 0; v < 4; ++v) o[10 * j + 5 + v] = take(n * sizeof(double2) * C);
       o[10 * j + 9] = take(kLuScratchBytes * C);
     }
+    if (tr) {
+      o.push_back(take(sizeof(double2) * (size_t)C * std::max(1, pb->nobs)));   // U of a step
+      o.push_back(take(sizeof(double2) * (size_t)tr->nt * std::max(1, pb->nobs)));  // its trace
+      o.push_back(take(sizeof(double2)));                                            // two norms
+    }
     if ((rc = ensure_ws(ctx, off))) return rc;
     char *base = (char *)ctx->ws;
     for (int j = 0; j < J; ++j) {
@@ -358,6 +429,11 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
       w[j].cr = (double2 *)(base + o[10 * j + 7]);
       w[j].tot = (double2 *)(base + o[10 * j + 8]);
       w[j].swp = (void *)(base + o[10 * j + 9]);
+    }
+    if (tr) {
+      Ustep = (double2 *)(base + o[(size_t)10 * J]);
+      du = (double2 *)(base + o[(size_t)10 * J + 1]);
+      nrm = (double *)(base + o[(size_t)10 * J + 2]);
     }
   }
   auto solve_arc = [&](int j, int c) -> int {
@@ -382,6 +458,41 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
                         c);
     tend(ctx);
     return r;
+  };
+  // fold the densities of the step just solved into the traces; returns 1
+  // once the step's change is below the stop tolerance
+  auto trace_step = [&](int c, const double *kc, bool first, int &stop) -> int {
+    stop = 0;
+    const int P = pb->nobs;
+    if (P == 0 || tr->nt == 0) return FTHMS_OK;
+    zero_kernel<<<grid1d((long long)c * P), 256, 0, ctx->stream>>>(Ustep, (long long)c * P);
+    int r;
+    for (int j = 0; j < J; ++j) {
+      const fthms_arc *a = pb->arcs[j];
+      if ((r = field_dev_impl(ctx, a, c, kc, w[j].al, a->n, P, pb->d_obs, pb->obs_plan[j], Ustep,
+                              P, 1)))
+        return r;
+    }
+    dim3 g((P + kFtTile - 1) / kFtTile, (tr->nt + kFtTile - 1) / kFtTile);
+    freq_to_time_kernel<<<g, 256, 0, ctx->stream>>>(c, kc, tr->w, P, Ustep, tr->nt, tr->t, du);
+    if ((r = check_launch(ctx, "freq_to_time_kernel"))) return r;
+    const long long nn = (long long)tr->nt * P;
+    if (first)
+      HIPCK(ctx, hipMemcpyAsync(tr->traces, du, sizeof(double2) * nn, hipMemcpyDeviceToDevice,
+                                ctx->stream));
+    else
+      axpy_kernel<<<grid1d(nn), 256, 0, ctx->stream>>>(tr->traces, du, nn);
+    if (tr->stop_tol <= 0.0) return FTHMS_OK;
+    zero_kernel<<<1, 256, 0, ctx->stream>>>((double2 *)nrm, 1);
+    const int nb = (int)std::min<long long>(1024, (nn + 255) / 256);
+    norm2_kernel<<<nb, 256, 0, ctx->stream>>>(du, nn, nrm);
+    norm2_kernel<<<nb, 256, 0, ctx->stream>>>(tr->traces, nn, nrm + 1);
+    if ((r = check_launch(ctx, "norm2_kernel"))) return r;
+    double h[2];
+    HIPCK(ctx, hipMemcpyAsync(h, nrm, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCK(ctx, hipStreamSynchronize(ctx->stream));
+    stop = std::sqrt(h[0]) <= tr->stop_tol * std::sqrt(h[1]) ? 1 : 0;
+    return FTHMS_OK;
   };
   long long aoff = 0;
   for (int f0 = 0; f0 < nk; f0 += C) {
@@ -409,7 +520,9 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
       HIPCK(ctx, hipMemcpyAsync(w[j].tot, w[j].al, sizeof(double2) * n * c,
                                 hipMemcpyDeviceToDevice, ctx->stream));
     }
-    for (int m = 1; m < pb->M; ++m) {
+    int steps = 1, stop = 0;
+    if (tr && (rc = trace_step(c, kc, true, stop))) return rc;
+    for (int m = 1; m < pb->M && !stop; ++m) {
       for (int j = 0; j < J; ++j) {
         const long long nn = (long long)pb->arcs[j]->n * c;
         zero_kernel<<<grid1d(nn), 256, 0, ctx->stream>>>(w[j].cr, nn);
@@ -433,7 +546,10 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
         axpy_kernel<<<grid1d(nn), 256, 0, ctx->stream>>>(w[j].tot, w[j].al, nn);
         if ((rc = check_launch(ctx, "axpy_kernel"))) return rc;
       }
+      steps = m + 1;
+      if (tr && (rc = trace_step(c, kc, false, stop))) return rc;
     }
+    if (tr && tr->steps) *tr->steps = steps;
     if (pb->nobs > 0 && U) {
       double2 *Uc = U + (long long)f0 * pb->nobs;
       zero_kernel<<<grid1d((long long)c * pb->nobs), 256, 0, ctx->stream>>>(
@@ -482,6 +598,54 @@ int fthms_problem_run_dev(fthms_problem *pb, int nk, const double *k_dev, fthms_
     kmax = std::max(kmax, v);
   }
   return problem_run_impl(pb, nk, k_dev, kmax, (double2 *)U_dev, (double2 *)alpha_tot_dev);
+}
+
+int fthms_problem_traces_dev(fthms_problem *pb, int nk, const double *k_dev,
+                             const double *w_dev, int nt, const double *t_dev, double stop_tol,
+                             fthms_c64 *traces_dev, int *steps) {
+  if (!pb || nk < 1 || !k_dev || !w_dev || nt < 0 || (nt > 0 && (!t_dev || !traces_dev)))
+    return fail(pb ? pb->ctx : nullptr, FTHMS_EINVAL, "bad argument to fthms_problem_traces_dev");
+  fthms_ctx *ctx = pb->ctx;
+  HIPCK(ctx, hipSetDevice(ctx->device));
+  std::vector<double> k(nk);
+  HIPCK(ctx, hipMemcpyAsync(k.data(), k_dev, sizeof(double) * nk, hipMemcpyDeviceToHost,
+                            ctx->stream));
+  HIPCK(ctx, hipStreamSynchronize(ctx->stream));
+  double kmax = 0.0;
+  for (double v : k) {
+    if (!(v > 0.0) || !std::isfinite(v))
+      return fail(ctx, FTHMS_EINVAL_DATA, "wavenumbers must be finite and > 0");
+    kmax = std::max(kmax, v);
+  }
+  TraceReq tr{w_dev, nt, t_dev, stop_tol, (double2 *)traces_dev, steps};
+  return problem_run_impl(pb, nk, k_dev, kmax, nullptr, nullptr, &tr);
+}
+
+int fthms_problem_traces(fthms_problem *pb, int nk, const double *k, const double *w, int nt,
+                         const double *t, double stop_tol, fthms_c64 *traces, int *steps) {
+  if (!pb || nk < 1 || !k || !w || nt < 0 || (nt > 0 && (!t || !traces)))
+    return fail(pb ? pb->ctx : nullptr, FTHMS_EINVAL, "bad argument to fthms_problem_traces");
+  fthms_ctx *ctx = pb->ctx;
+  HIPCK(ctx, hipSetDevice(ctx->device));
+  Staging st(ctx);
+  double *dk, *dw, *dt = nullptr;
+  double2 *du = nullptr;
+  int rc;
+  if ((rc = st.get(&dk, sizeof(double) * nk)) || (rc = st.get(&dw, sizeof(double) * nk)) ||
+      (rc = st.get(&dt, sizeof(double) * std::max(nt, 1))) ||
+      (rc = st.get(&du, sizeof(double2) * std::max(nt, 1) * std::max(pb->nobs, 1))))
+    return rc;
+  HIPCK(ctx, hipMemcpyAsync(dk, k, sizeof(double) * nk, hipMemcpyHostToDevice, ctx->stream));
+  HIPCK(ctx, hipMemcpyAsync(dw, w, sizeof(double) * nk, hipMemcpyHostToDevice, ctx->stream));
+  if (nt > 0)
+    HIPCK(ctx, hipMemcpyAsync(dt, t, sizeof(double) * nt, hipMemcpyHostToDevice, ctx->stream));
+  if ((rc = fthms_problem_traces_dev(pb, nk, dk, dw, nt, dt, stop_tol, (fthms_c64 *)du, steps)))
+    return rc;
+  if (nt > 0 && pb->nobs > 0)
+    HIPCK(ctx, hipMemcpyAsync(traces, du, sizeof(double2) * (size_t)nt * pb->nobs,
+                              hipMemcpyDeviceToHost, ctx->stream));
+  HIPCK(ctx, hipStreamSynchronize(ctx->stream));
+  return FTHMS_OK;
 }
 
 int fthms_problem_run(fthms_problem *pb, int nk, const double *k, fthms_c64 *U,

@@ -229,6 +229,45 @@ def test_ms_kite_cavity_full(ctx, fth):
     assert early < 1e-6 * np.abs(u).max(), early
 
 
+def test_ms_exterior_two_obstacles(ctx, fth):
+    """Exterior problem with two closed obstacles (4 arcs each, cyclic within
+    each obstacle, every arc scattering onto every other one): fields and
+    summed densities against the oracle's recursion."""
+    from workloads import two_obstacle_case
+    pb = two_obstacle_case(n=20, omegas=np.array([7.25]), M=5)
+    pb.incident = IncidentSpec("gplane", theta=0.4, omega0=7.5, sigma=1.5, tau0=3.0)
+    say("ms two obstacles")
+    arcs = [ctx.arc_from_curve(a.curve, a.n) for a in pb.arcs]
+    iv = np.array([a.curve.interval for a in pb.arcs])
+    prob = fth.Problem(ctx, arcs, pb.incident, pb.obs, intervals=iv, M=pb.M,
+                       groups=[a.group for a in pb.arcs])
+    U, A = prob.run(np.asarray(pb.omegas, dtype=float), want_alpha=True)
+    ref = oms.run_frequency(oms.Layout(pb), pb.omegas[0])
+    assert rel(U[0], ref["U"]) < TOL, rel(U[0], ref["U"])
+    assert rel(A[0], np.concatenate(ref["alpha_tot"])) < TOL
+
+
+def test_ms_exterior_traces_stop_rule(ctx, fth):
+    """Two facing open arcs as separate scatterers: time traces with the
+    time-domain stop rule (tolerance 0.1: the increments of steps 1-4 are
+    1, 0.66, 0.24, 0.019 of the running sum), the step count, and the full
+    M-step traces, against the oracle."""
+    from workloads import two_arc_exterior_case
+    pb = two_arc_exterior_case()
+    om = np.asarray(pb.omegas, dtype=float)
+    w = otr.trapezoid_weights(om)
+    arcs = [ctx.arc_from_curve(a.curve, a.n) for a in pb.arcs]
+    iv = np.array([a.curve.interval for a in pb.arcs])
+    prob = fth.Problem(ctx, arcs, pb.incident, pb.obs, intervals=iv, M=pb.M, groups=[0, 1])
+    lay = oms.Layout(pb)
+    for tol, want in ((0.1, 4), (0.0, pb.M)):
+        u, steps = prob.traces(om, w, pb.times, stop_tol=tol)
+        ref, ref_steps = oms.run_traces(lay, om, w, pb.times, stop_tol=tol)
+        say("two arcs: tol", tol, "steps", steps, "oracle", ref_steps)
+        assert steps == ref_steps == want
+        assert rel(u, ref) < TOL, rel(u, ref)
+
+
 def test_error_paths(ctx, fth):
     curve = Segment((-1.0, 0.0), (1.0, 0.0))
     arc = ctx.arc_from_curve(curve, 16)

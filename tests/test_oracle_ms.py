@@ -114,3 +114,46 @@ def test_ms_converges_in_M_at_complex_frequency():
     d1 = np.max(np.abs(vals[1] - vals[0]))
     d2 = np.max(np.abs(vals[2] - vals[1]))
     assert d2 < 0.05 * d1
+
+
+def test_exterior_two_obstacles_complex_frequency_exact():
+    """Exterior problem (Section 3.3) with two obstacles, each a closed curve
+    split into 4 arcs, and a point source inside the first: outside both the
+    scattered field is exactly -U^i (the exact-solution idea of the paper's
+    exterior geometry).  At a complex wavenumber the MS steps decay
+    geometrically and the sum approaches -U^i under refinement (algebraically,
+    as for the interior cavities)."""
+    from workloads import two_obstacle_case
+    k = 5.0 + 2.0j
+    errs = []
+    for n in (24, 48):
+        pb = two_obstacle_case(n=n, omegas=(k,), M=10)
+        lay = ms.Layout(pb)
+        assert lay.nxt[0] == 1 and lay.prv[0] == 3 and lay.nxt[4] == 5 and lay.prv[4] == 7
+        ui = inc.incident(pb.incident, k, pb.obs)
+        out = ms.run_frequency(lay, k, keep_steps=True)
+        errs.append(np.max(np.abs(out["U"] + ui)) / np.max(np.abs(ui)))
+        # no masking across obstacles
+        assert np.all(lay.mask[4][0]) and np.all(lay.mask[0][4])
+    assert errs[0] < 5e-3
+    assert errs[1] < 1e-3
+    assert errs[1] < 0.5 * errs[0]
+
+
+def test_traces_sum_of_steps_and_stop_rule():
+    """run_traces: without a stop it is the time transform of the whole MS
+    sum (the field is linear in the densities, eq. mult-scatt-int); with a
+    loose stop tolerance it ends early with the partial sum whose last
+    increment met the rule."""
+    from oracle import transform as tr
+    pb = small_kite_case(n=16, omegas=(2.0, 2.5, 3.0, 3.5), M=4, nobs=4, nt=12, dt=0.3)
+    lay = ms.Layout(pb)
+    om = np.asarray(pb.omegas, dtype=float)
+    w = tr.trapezoid_weights(om)
+    u_all, steps = ms.run_traces(lay, om, w, pb.times, stop_tol=0.0)
+    assert steps == pb.M
+    U = np.array([ms.run_frequency(lay, k)["U"] for k in om])
+    ref = tr.freq_to_time(om, w, U, pb.times)
+    assert np.linalg.norm(u_all - ref) <= 1e-13 * np.linalg.norm(ref)
+    u_part, s2 = ms.run_traces(lay, om, w, pb.times, stop_tol=0.9)
+    assert 1 <= s2 < pb.M

@@ -36,12 +36,15 @@ class IncidentSpec:
 class ArcSpec:
     curve: Curve
     n: int
+    group: int = 0  # closed curve (obstacle) the arc belongs to
 
 
 @dataclass
 class MSProblem:
-    """Closed curve split into overlapping arcs, cyclically ordered: arc j
-    overlaps arcs j-1 and j+1 only (indices modulo the arc count)."""
+    """Closed curves split into overlapping arcs.  The arcs of one curve
+    (equal ``group``) are cyclically ordered in list order: arc j overlaps
+    its predecessor and successor on the same curve only.  A problem with
+    several groups is an exterior problem with several obstacles."""
     arcs: list
     incident: IncidentSpec
     omegas: np.ndarray
@@ -78,14 +81,53 @@ def fixed512_case(nk=4096, n=512):
                 obs=_circle_points(256, 3.0), name="arc512_k%d" % nk)
 
 
-def _kite_arcs(n, scale=1.0, center=(0.0, 0.0), rot=0.0):
+def _kite_arcs(n, scale=1.0, center=(0.0, 0.0), rot=0.0, group=0):
     d = math.pi / 180.0
     arcs = []
     for j in range(4):
         a = (90.0 * j - 15.0) * d
         b = (90.0 * (j + 1) + 15.0) * d
-        arcs.append(ArcSpec(KiteArc(a, b, scale, center, rot), n))
+        arcs.append(ArcSpec(KiteArc(a, b, scale, center, rot), n, group))
     return arcs
+
+
+def _ellipse_arcs(n, ea, eb, center=(0.0, 0.0), rot=0.0, group=0):
+    """Ellipse split like the kite: 4 arcs of 120 degrees of parameter with
+    30 degree overlaps."""
+    d = math.pi / 180.0
+    return [ArcSpec(EllipseArc(ea, eb, (90.0 * j - 15.0) * d, (90.0 * (j + 1) + 15.0) * d,
+                               center=center, rot=rot), n, group) for j in range(4)]
+
+
+def two_arc_exterior_case(n=24, nobs=8):
+    """Two facing circular arcs (open scatterers, one per group) 2.5 apart,
+    a Gaussian-modulated plane wave (omega0 = 6, sigma = 1.5, tau0 = 4), 37
+    frequencies on [1.5, 10.5] resolving the time window [0, 14], and
+    observation points on the radius-4 circle: the multiple-scattering series
+    settles within a few steps in the time domain."""
+    arcs = [ArcSpec(CircularArc(0.8, 2.2, 4.1, center=(-1.3, 0.0)), n, 0),
+            ArcSpec(CircularArc(0.7, -0.9, 0.9, center=(1.2, 0.2)), n, 1)]
+    return MSProblem(arcs=arcs,
+                     incident=IncidentSpec("gplane", theta=0.3, omega0=6.0, sigma=1.5,
+                                           tau0=4.0),
+                     omegas=np.arange(1.5, 10.51, 0.25), M=10,
+                     obs=_circle_points(nobs, 4.0), times=np.linspace(0.0, 14.0, 57),
+                     name="two_arcs_n%d" % n)
+
+
+def two_obstacle_case(n=32, omegas=(5.0 + 2.0j,), M=8, nobs=8, times=None):
+    """Exterior problem with two obstacles (an ellipse and a scaled kite,
+    each split into 4 arcs), point source inside the ellipse -- the exact
+    scattered field outside both is -u^i (the exact-solution idea of the
+    paper's exterior geometry with a source inside an obstacle) -- and
+    observation points on a circle around both."""
+    arcs = _ellipse_arcs(n, 0.8, 0.5, center=(-1.0, 0.0), rot=0.3, group=0)
+    arcs += _kite_arcs(n, scale=0.5, center=(1.2, 0.3), rot=-0.4, group=1)
+    return MSProblem(arcs=arcs,
+                     incident=IncidentSpec("point", z0=(-1.05, 0.1), sigma=0.0),
+                     omegas=np.asarray(omegas), M=M, obs=_circle_points(nobs, 3.0),
+                     times=np.zeros(0) if times is None else np.asarray(times),
+                     name="two_obstacles_n%d" % n)
 
 
 def _inside_polygon(pts, poly):
