@@ -178,6 +178,53 @@ def uneven_batch(fth, ctx, torch, steps, tol):
     return rec
 
 
+def serving(fth, workers=8, count=32, seed=5):
+    """Serving loop: exterior scattering requests (1-3 obstacles of 4 arcs,
+    n 32..96, 48..128 frequencies, time-domain stop 1e-8 within 100 steps)
+    submitted to a server with `workers` concurrent slots.  The saturated
+    rate comes from a burst of `count` requests; then `count` requests arrive
+    as a Poisson stream at 0.5 and 0.8 of that rate, and the latency from
+    arrival to traces in host memory is reported (p50/p99)."""
+    from workloads import serving_requests
+    reqs = [fth.request_from_workload(r) for r in serving_requests(seed=seed, count=3 * count)]
+    solves = lambda q, steps: len(q["xy"]) * len(q["k"]) * steps
+    srv = fth.Server(0, workers=workers)
+    # warm up (first touches of the device and of every worker)
+    for t in [srv.submit(q) for q in reqs[:workers]]:
+        srv.wait(t)
+    burst = reqs[:count]
+    t0 = time.perf_counter()
+    tickets = [srv.submit(q) for q in burst]
+    res = [srv.wait(t) for t in tickets]
+    dt = time.perf_counter() - t0
+    sat = count / dt
+    rec = {"workload": "exterior requests, 1-3 obstacles x 4 arcs (ellipses or kites), n 32..96, "
+                       "48..128 frequencies on (0, 2 w0], w0 in [3, 8], Gaussian plane wave, 32 "
+                       "points, stop 1e-8 (at most 100 steps); seed %d" % seed,
+           "workers": workers, "saturated_requests_per_s": round(sat, 2),
+           "saturated_solves_per_s": round(sum(solves(q, r[1]) for q, r in zip(burst, res)) / dt, 1),
+           "mean_steps": round(float(np.mean([r[1] for r in res])), 2), "poisson": []}
+    rng = np.random.default_rng(seed + 1)
+    for frac, sl in ((0.5, slice(count, 2 * count)), (0.8, slice(2 * count, 3 * count))):
+        lam = frac * sat
+        gaps = rng.exponential(1.0 / lam, count)
+        start = time.perf_counter()
+        due = start + np.cumsum(gaps)
+        tickets = []
+        for q, tdue in zip(reqs[sl], due):
+            now = time.perf_counter()
+            if tdue > now:
+                time.sleep(tdue - now)
+            tickets.append(srv.submit(q))
+        lat = np.array([srv.wait(t)[2] for t in tickets])
+        rec["poisson"].append({"rate_fraction": frac, "lambda_per_s": round(lam, 3),
+                               "requests": count,
+                               "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+                               "p99_latency_s": round(float(np.percentile(lat, 99)), 4)})
+    srv.close()
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -187,6 +234,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-11,
                     help="refinement stop: predicted relative error (the metric's 1e-10 "
                          "with a 10x margin); every solve's error is measured")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving loop measurement (Poisson arrivals, p50/p99)")
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the uneven multi-arc batch (reported beside the headline)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -318,6 +367,10 @@ def main():
     if not args.no_uneven:
         uneven = uneven_batch(fth, ctx, torch, max(1, args.steps), args.tol)
 
+    serve = None
+    if not args.no_serving:
+        serve = serving(fth)
+
     base = None
     oracle_err = None
     if not args.no_cpu_baseline:
@@ -361,6 +414,7 @@ def main():
                                     for n, v in r64["kt"].items()},
         "roofline": roof,
         "uneven_batch": uneven,
+        "serving": serve,
         "cpu_baseline": base,
     }
     print(json.dumps(line), flush=True)

@@ -65,7 +65,9 @@ enum {
   FTHMS_ENOMEM = -3,      /* request exceeds the context's HBM budget    */
   FTHMS_ESINGULAR = -4,   /* exactly zero pivot in a factorisation       */
   FTHMS_ENOCONV = -5,     /* refinement hit its cap; results still valid */
-  FTHMS_EDEVICE = -6      /* HIP runtime error (text in last_error)      */
+  FTHMS_EDEVICE = -6,     /* HIP runtime error (text in last_error)      */
+  FTHMS_EAGAIN = -7,      /* served request not finished yet             */
+  FTHMS_ECANCELLED = -8   /* served request was cancelled                */
 };
 
 enum { FTHMS_FP64 = 0, FTHMS_FP32_REFINED = 1 };
@@ -324,6 +326,74 @@ int fthms_batch_tune(fthms_batch *batch, int reps);
  * streams; reg_panel: register-resident panel). */
 int fthms_batch_buckets(const fthms_batch *batch, int *ngroups, int *n,
                         int *count, int *split, int *reg_panel);
+
+/* ---- serving -------------------------------------------------------------- */
+
+/* A request: one multiple-scattering problem answered with its time traces
+ * (the arguments of fthms_problem_create + fthms_problem_traces in one
+ * self-contained record; everything is copied at submission).  narcs arcs of
+ * n nodes each: xy, dxy [narcs][n][2] samples of x(t), x'(t) at
+ * fthms_cheb_nodes(n); interval [narcs][2] and group [narcs] (NULL: one
+ * curve) as in fthms_problem_desc; k, w [nk] frequencies and quadrature
+ * weights; obs_xy [nobs][2]; t [nt]; at most max_steps steps with the
+ * time-domain stop tolerance stop_tol.  Solves run in FP64. */
+typedef struct {
+  int narcs;
+  int n;
+  const double *xy;
+  const double *dxy;
+  const double *interval;
+  const int *group;
+  double period;
+  int nk;
+  const double *k;
+  const double *w;
+  fthms_incident incident;
+  int nobs;
+  const double *obs_xy;
+  int nt;
+  const double *t;
+  int max_steps;
+  double stop_tol;
+} fthms_request;
+
+enum {
+  FTHMS_JOB_QUEUED = 0,
+  FTHMS_JOB_RUNNING = 1,
+  FTHMS_JOB_DONE = 2,
+  FTHMS_JOB_FAILED = 3,
+  FTHMS_JOB_CANCELLED = 4
+};
+
+/* A server on one GPU: `workers` (1..64) worker threads, each with its own
+ * context and stream; requests are admitted first come first served when a
+ * worker is free and their device-memory estimate fits beside the running
+ * ones within hbm_budget (0: 90% of the free memory).  Admitted requests
+ * run concurrently and their kernels overlap on the device; each request's
+ * result is independent of the others'. */
+typedef struct fthms_server fthms_server;
+int fthms_server_create(int device, size_t hbm_budget, int workers,
+                        fthms_server **out);
+/* Waits for running requests; queued ones are cancelled. */
+int fthms_server_destroy(fthms_server *server);
+const char *fthms_server_error(const fthms_server *server);
+
+/* Queue a request; *ticket identifies it.  FTHMS_ENOMEM if its estimate
+ * exceeds the server budget (refused outright), FTHMS_EINVAL(_DATA) for a
+ * malformed request. */
+int fthms_submit(fthms_server *server, const fthms_request *req,
+                 uint64_t *ticket);
+/* *state: one of FTHMS_JOB_*. */
+int fthms_poll(fthms_server *server, uint64_t ticket, int *state);
+/* For a finished request: traces [nt][nobs] (host), steps taken and the
+ * latency from submission to the traces being in host memory (seconds);
+ * releases the ticket.  FTHMS_EAGAIN while queued or running, the
+ * request's error code if it failed, FTHMS_ECANCELLED if cancelled. */
+int fthms_fetch(fthms_server *server, uint64_t ticket, fthms_c64 *traces,
+                int *steps, double *latency_s);
+/* Cancel: a queued request leaves the queue; a running one completes and
+ * its result is dropped. */
+int fthms_cancel(fthms_server *server, uint64_t ticket);
 
 #ifdef __cplusplus
 }

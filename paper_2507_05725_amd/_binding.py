@@ -21,7 +21,8 @@ FP32_REFINED = 1
 INC_PLANE, INC_GPLANE, INC_POINT = 0, 1, 2
 
 _ERR = {0: "OK", -1: "EINVAL", -2: "EINVAL_DATA", -3: "ENOMEM",
-        -4: "ESINGULAR", -5: "ENOCONV", -6: "EDEVICE"}
+        -4: "ESINGULAR", -5: "ENOCONV", -6: "EDEVICE", -7: "EAGAIN", -8: "ECANCELLED"}
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED, JOB_CANCELLED = 0, 1, 2, 3, 4
 
 
 class FthmsError(RuntimeError):
@@ -43,6 +44,16 @@ class ProblemDesc(C.Structure):
                 ("precision", C.c_int), ("tol", C.c_double),
                 ("incident", Incident), ("nobs", C.c_int),
                 ("obs_xy", C.POINTER(C.c_double)), ("group", C.POINTER(C.c_int))]
+
+
+class Request(C.Structure):
+    _fields_ = [("narcs", C.c_int), ("n", C.c_int), ("xy", C.POINTER(C.c_double)),
+                ("dxy", C.POINTER(C.c_double)), ("interval", C.POINTER(C.c_double)),
+                ("group", C.POINTER(C.c_int)), ("period", C.c_double), ("nk", C.c_int),
+                ("k", C.POINTER(C.c_double)), ("w", C.POINTER(C.c_double)),
+                ("incident", Incident), ("nobs", C.c_int), ("obs_xy", C.POINTER(C.c_double)),
+                ("nt", C.c_int), ("t", C.POINTER(C.c_double)), ("max_steps", C.c_int),
+                ("stop_tol", C.c_double)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -90,6 +101,13 @@ _SIGS = {
     "fthms_batch_run": ([_vp, _vp, _vp], _i),
     "fthms_batch_tune": ([_vp, _i], _i),
     "fthms_batch_buckets": ([_vp, C.POINTER(_i), _vp, _vp, _vp, _vp], _i),
+    "fthms_server_create": ([_i, _sz, _i, C.POINTER(_vp)], _i),
+    "fthms_server_destroy": ([_vp], _i),
+    "fthms_server_error": ([_vp], C.c_char_p),
+    "fthms_submit": ([_vp, C.POINTER(Request), C.POINTER(C.c_uint64)], _i),
+    "fthms_poll": ([_vp, C.c_uint64, C.POINTER(_i)], _i),
+    "fthms_fetch": ([_vp, C.c_uint64, _vp, C.POINTER(_i), C.POINTER(_d)], _i),
+    "fthms_cancel": ([_vp, C.c_uint64], _i),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -417,3 +435,115 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Server:
+    """Request loop on one GPU (see fthms_server_create).  Requests are dicts
+    of NumPy arrays: xy, dxy [narcs, n, 2], interval [narcs, 2], group
+    [narcs], k, w [nk], incident (IncidentSpec), obs [nobs, 2], t [nt],
+    max_steps, stop_tol, period."""
+
+    def __init__(self, device=0, hbm_budget=0, workers=4):
+        h = C.c_void_p()
+        rc = _lib.fthms_server_create(int(device), int(hbm_budget), int(workers), C.byref(h))
+        if rc:
+            raise FthmsError(rc, _lib.fthms_last_error(None).decode())
+        self.h = h
+        self._shape = {}
+
+    def _err(self, rc, what):
+        raise FthmsError(rc, "%s: %s" % (what, _lib.fthms_server_error(self.h).decode()))
+
+    def submit(self, req):
+        keep = dict(xy=np.ascontiguousarray(req["xy"], dtype=np.float64),
+                    dxy=np.ascontiguousarray(req["dxy"], dtype=np.float64),
+                    iv=np.ascontiguousarray(req["interval"], dtype=np.float64),
+                    grp=np.ascontiguousarray(req["group"], dtype=np.int32),
+                    k=np.ascontiguousarray(req["k"], dtype=np.float64),
+                    w=np.ascontiguousarray(req["w"], dtype=np.float64),
+                    obs=np.ascontiguousarray(req["obs"], dtype=np.float64),
+                    t=np.ascontiguousarray(req["t"], dtype=np.float64))
+        r = Request()
+        r.narcs, r.n = keep["xy"].shape[0], keep["xy"].shape[1]
+        r.xy, r.dxy, r.interval = _dp(keep["xy"]), _dp(keep["dxy"]), _dp(keep["iv"])
+        r.group = keep["grp"].ctypes.data_as(C.POINTER(C.c_int))
+        r.period = float(req.get("period", 2 * np.pi))
+        r.nk, r.k, r.w = keep["k"].size, _dp(keep["k"]), _dp(keep["w"])
+        r.incident = incident_struct(req["incident"])
+        r.nobs, r.obs_xy = keep["obs"].shape[0], _dp(keep["obs"])
+        r.nt, r.t = keep["t"].size, _dp(keep["t"])
+        r.max_steps = int(req.get("max_steps", 100))
+        r.stop_tol = float(req.get("stop_tol", 1e-8))
+        ticket = C.c_uint64()
+        rc = _lib.fthms_submit(self.h, C.byref(r), C.byref(ticket))
+        if rc:
+            self._err(rc, "submit")
+        self._shape[ticket.value] = (r.nt, r.nobs)
+        return ticket.value
+
+    def poll(self, ticket):
+        st = C.c_int()
+        rc = _lib.fthms_poll(self.h, ticket, C.byref(st))
+        if rc:
+            self._err(rc, "poll")
+        return st.value
+
+    def fetch(self, ticket):
+        """(traces [nt, nobs], steps, latency seconds); raises FthmsError
+        with code EAGAIN while the request is not finished."""
+        nt, nobs = self._shape[ticket]
+        out = np.empty((nt, nobs), dtype=np.complex128)
+        steps, lat = C.c_int(), C.c_double()
+        rc = _lib.fthms_fetch(self.h, ticket, _ptr(out), C.byref(steps), C.byref(lat))
+        if rc:
+            if rc != -7:
+                self._shape.pop(ticket, None)
+            self._err(rc, "fetch")
+        self._shape.pop(ticket, None)
+        return out, steps.value, lat.value
+
+    def wait(self, ticket, poll_s=0.001):
+        import time
+        while self.poll(ticket) in (JOB_QUEUED, JOB_RUNNING):
+            time.sleep(poll_s)
+        return self.fetch(ticket)
+
+    def cancel(self, ticket):
+        rc = _lib.fthms_cancel(self.h, ticket)
+        if rc:
+            self._err(rc, "cancel")
+
+    def close(self):
+        if self.h:
+            _lib.fthms_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def request_from_workload(req):
+    """Server request dict from a workloads.serving_requests entry: node
+    samples of every arc at the Chebyshev nodes, parent intervals, groups,
+    and trapezoid weights on the uniform frequency grid (half weight at the
+    ends)."""
+    arcs = req["arcs"]
+    n = arcs[0].n
+    t = cheb_nodes(n)
+    om = np.asarray(req["omegas"], dtype=np.float64)
+    w = np.full(om.size, om[1] - om[0] if om.size > 1 else 1.0)
+    w[0] *= 0.5
+    w[-1] *= 0.5
+    return dict(xy=np.stack([a.curve.x(t) for a in arcs]),
+                dxy=np.stack([a.curve.dx(t) for a in arcs]),
+                interval=np.array([a.curve.interval for a in arcs]),
+                group=np.array([a.group for a in arcs]), k=om, w=w,
+                incident=req["incident"], obs=req["obs"], t=req["times"],
+                max_steps=req["max_steps"], stop_tol=req["stop_tol"])

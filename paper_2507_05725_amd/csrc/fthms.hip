@@ -1062,3 +1062,4 @@ int fthms_bessel_dev(fthms_ctx *ctx, int nz, const double *z_dev, double *j0_dev
 
 #include "problem.h"
 #include "batch.h"
+#include "serve.h"

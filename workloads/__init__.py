@@ -16,12 +16,12 @@ from .curves import (Curve, Segment, CircularArc, KiteArc, EllipseArc,
                      SineArc, kite_point, kite_deriv)
 from .configs import (plain_segment_case, kite_cavity_case, uneven_batch_case,
                       fixed512_case, small_kite_case, disc_interior_case,
-                      two_obstacle_case, two_arc_exterior_case, IncidentSpec, ArcSpec, MSProblem)
+                      two_obstacle_case, two_arc_exterior_case, serving_requests, IncidentSpec, ArcSpec, MSProblem)
 
 __all__ = [
     "Curve", "Segment", "CircularArc", "KiteArc", "EllipseArc", "SineArc",
     "kite_point", "kite_deriv",
     "plain_segment_case", "kite_cavity_case", "uneven_batch_case",
     "fixed512_case", "small_kite_case", "disc_interior_case",
-    "two_obstacle_case", "two_arc_exterior_case", "IncidentSpec", "ArcSpec", "MSProblem",
+    "two_obstacle_case", "two_arc_exterior_case", "serving_requests", "IncidentSpec", "ArcSpec", "MSProblem",
 ]

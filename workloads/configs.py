@@ -55,6 +55,9 @@ class MSProblem:
     c1: float = 2.0 / 3.0
     period: float = 2.0 * math.pi
     name: str = ""
+    # "cheb": one weighted-Chebyshev panel per arc, n nodes; "panels": each
+    # arc cut at the ends of its truncated overlap, n nodes per panel
+    scheme: str = "cheb"
 
 
 def _circle_points(n, radius, center=(0.0, 0.0)):
@@ -258,3 +261,61 @@ def uneven_batch_case(seed=3, narcs=8, nk=2048, kmin=1.0, kmax=120.0,
         n = np.minimum(nmax, np.maximum(nmin, n))
         a["n"] = np.minimum(nmax, quantum * ((n + quantum - 1) // quantum))
     return dict(arcs=arcs, k=k, name="uneven%d_k%d" % (narcs, nk))
+
+
+def serving_requests(seed=5, count=32, max_obstacles=3, n_range=(32, 96),
+                     nk_range=(48, 128), omega0_range=(3.0, 8.0), nobs=32,
+                     dt=0.05, max_steps=100, stop_tol=1e-8):
+    """Exterior scattering requests of different sizes for the serving loop
+    (the shape of the serving workload at reduced size): 1..max_obstacles
+    obstacles, each an ellipse (probability 1/2; semi-axes U[0.2, 1], random
+    rotation) or a kite scaled by U[0.3, 1], centres rejection-sampled so
+    that the obstacles keep a boundary distance of at least 0.5, each split
+    into 4 arcs; n nodes per arc; J frequencies omega_l = 2 omega0 l / J;
+    a Gaussian plane wave with sigma = 0.2 omega0, random direction and
+    tau0 = R_cluster + 12 / sigma; observation points on the circle of radius
+    R_cluster + 1; times 0 .. tau0 + 10 in steps of dt."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(count):
+        nob = int(rng.integers(1, max_obstacles + 1))
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        shapes, centres, radii = [], [], []
+        while len(shapes) < nob:
+            if rng.random() < 0.5:
+                ea = rng.uniform(0.2, 1.0)
+                eb = rng.uniform(0.2, 1.0)
+                shp = ("ellipse", ea, eb, rng.uniform(0.0, math.pi))
+                rad = max(ea, eb)
+            else:
+                sc = rng.uniform(0.3, 1.0)
+                shp = ("kite", sc, rng.uniform(0.0, 2.0 * math.pi))
+                rad = 1.65 * sc
+            c = rng.uniform(-3.0, 3.0, 2)
+            if all(math.hypot(*(c - c2)) - rad - r2 >= 0.5 for c2, r2 in zip(centres, radii)):
+                shapes.append(shp)
+                centres.append(c)
+                radii.append(rad)
+        arcs = []
+        for g, (shp, c) in enumerate(zip(shapes, centres)):
+            if shp[0] == "ellipse":
+                arcs += _ellipse_arcs(n, shp[1], shp[2], center=tuple(c), rot=shp[3], group=g)
+            else:
+                arcs += _kite_arcs(n, scale=shp[1], center=tuple(c), rot=shp[2], group=g)
+        cc = np.mean(centres, axis=0)
+        rcl = max(math.hypot(*(c - cc)) + r for c, r in zip(centres, radii))
+        omega0 = rng.uniform(*omega0_range)
+        sigma = 0.2 * omega0
+        nk = int(rng.integers(nk_range[0], nk_range[1] + 1))
+        tau0 = rcl + 12.0 / sigma
+        p = 2.0 * np.pi * np.arange(nobs) / nobs
+        obs = np.stack([cc[0] + (rcl + 1.0) * np.cos(p), cc[1] + (rcl + 1.0) * np.sin(p)],
+                       axis=-1)
+        out.append(dict(arcs=arcs,
+                        incident=IncidentSpec("gplane", theta=rng.uniform(0.0, 2.0 * math.pi),
+                                              omega0=omega0, sigma=sigma, tau0=tau0),
+                        omegas=2.0 * omega0 * np.arange(1, nk + 1) / nk, obs=obs,
+                        times=dt * np.arange(int((tau0 + 10.0) / dt) + 1),
+                        max_steps=max_steps, stop_tol=stop_tol, n=n, obstacles=nob,
+                        name="request%d" % q))
+    return out
