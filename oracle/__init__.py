@@ -4,6 +4,8 @@ A plain, slow, FP64 / complex128 NumPy+SciPy implementation of every step of
 the frequency-domain FTH-MS hot path, written from the paper:
 
   nodes, weights, Nystrom matrix ........ ``oracle.nystrom``
+  composite panels with changes of
+  variables (eq. cov) .................... ``oracle.panels``
   incident fields ....................... ``oracle.incident``
   multiple-scattering recursion ......... ``oracle.ms``
   frequency-to-time transform ........... ``oracle.transform``
@@ -18,4 +20,4 @@ against closed forms, textbook identities, brute-force quadrature or
 library routines (see the pin tests under tests/).  None is "parity
 unpinned".
 """
-from . import nystrom, incident, ms, transform  # noqa: F401
+from . import nystrom, incident, ms, panels, transform  # noqa: F401

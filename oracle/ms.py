@@ -24,6 +24,11 @@ Readings taken where the text is silent or loose:
     scatters onto every other one; the masking of eq. vtilde and the
     windows chi_j involve the neighbours on the same curve only, and an arc
     alone on its curve has chi = 1.
+  * Discretisation: ``problem.scheme`` "cheb" is the single-panel
+    weighted-Chebyshev scheme (``oracle.nystrom``); "panels" cuts each arc
+    at the ends of its truncated overlap into three panels, each with the
+    two-sided change of variables of eq. cov (``oracle.panels``), n nodes per
+    panel.
 """
 from __future__ import annotations
 
@@ -32,6 +37,7 @@ import math
 import numpy as np
 
 from . import nystrom as ny
+from . import panels as pn
 from .incident import incident
 
 
@@ -70,7 +76,14 @@ class Layout:
                 q = mem.index(j)
                 self.nxt[j] = mem[(q + 1) % len(mem)]
                 self.prv[j] = mem[(q - 1) % len(mem)]
-        self.nodes = [ny.arc_nodes(a.curve, a.n) for a in problem.arcs]
+        self.scheme = getattr(problem, "scheme", "cheb")
+        if self.scheme == "panels":
+            self.parcs = [pn.PanelArc(a.curve, a.n, self.panel_breaks(j))
+                          for j, a in enumerate(problem.arcs)]
+            self.nodes = [pa.nodes() for pa in self.parcs]
+        else:
+            self.nodes = [ny.arc_nodes(a.curve, a.n) for a in problem.arcs]
+        self._tables = {}
         self.tau = [c.parent_param(nd["t"]) for c, nd in zip(self.arcs,
                                                               self.nodes)]
         self.chi = [self._chi(j) for j in range(self.J)]
@@ -85,6 +98,33 @@ class Layout:
                     a, b = self.arcs[k].interval
                     m &= ~in_interval(self.tau[j], a, b, problem.period)
                 self.mask[k][j] = m
+
+    def panel_breaks(self, j):
+        """Breakpoints (arc parameter t) of arc j: its ends and the ends of
+        its truncated overlap, where the overlaps with the neighbours on the
+        same curve end."""
+        br = [-1.0, 1.0]
+        if self.nxt[j] is not None:
+            a, b = self.arcs[j].interval
+            for e in (self.arcs[self.prv[j]].interval[1], self.arcs[self.nxt[j]].interval[0]):
+                u = (e - a) % self.p.period
+                if 0.0 < u < b - a:
+                    br.append(-1.0 + 2.0 * u / (b - a))
+        return sorted(br)
+
+    def assemble(self, j, k):
+        """Matrix of arc j at wavenumber k in the problem's scheme."""
+        if self.scheme == "panels":
+            if j not in self._tables:
+                self._tables[j] = pn.log_table(self.parcs[j])
+            return pn.assemble(self.nodes[j], k, self._tables[j])
+        return ny.assemble(self.nodes[j], k)
+
+    def field(self, j, k, z, alpha):
+        """Potential of arc j's density at targets z."""
+        if self.scheme == "panels":
+            return pn.field(k, z, self.nodes[j], alpha)
+        return ny.field(k, z, self.arcs[j], self.nodes[j], alpha)
 
     def _chi(self, j):
         return self.chi_at(j, self.tau[j], self.nodes[j]["y"])
@@ -159,7 +199,7 @@ def run_frequency(layout, k, keep_steps=False):
     every step's right-hand sides, densities and cross-arc fields."""
     p, J = layout.p, layout.J
     nodes = layout.nodes
-    A = [ny.assemble(nodes[j], k) for j in range(J)]
+    A = [layout.assemble(j, k) for j in range(J)]
     b = [-layout.chi[j] * incident(p.incident, k, nodes[j]["y"])
          for j in range(J)]
     alpha = [ny.solve(A[j], b[j]) for j in range(J)]
@@ -174,8 +214,7 @@ def run_frequency(layout, k, keep_steps=False):
                 msk = layout.mask[kk][j]
                 tgt = nodes[j]["y"][msk]
                 if tgt.shape[0]:
-                    cross[j][msk] += ny.field(k, tgt, layout.arcs[kk],
-                                              nodes[kk], alpha[kk])
+                    cross[j][msk] += layout.field(kk, k, tgt, alpha[kk])
         if keep_steps:
             steps.append(dict(b=b, alpha=alpha, cross=cross))
         b = [-layout.chi[j] * cross[j] for j in range(J)]
@@ -186,7 +225,7 @@ def run_frequency(layout, k, keep_steps=False):
         steps.append(dict(b=b, alpha=alpha, cross=None))
     U = np.zeros(p.obs.shape[0], dtype=complex)
     for j in range(J):
-        U += ny.field(k, p.obs, layout.arcs[j], nodes[j], tot[j])
+        U += layout.field(j, k, p.obs, tot[j])
     return dict(alpha_tot=tot, U=U, steps=steps)
 
 
@@ -207,8 +246,7 @@ def run_traces(layout, omegas, weights, times, stop_tol=0.0):
         out = run_frequency(layout, k, keep_steps=True)
         for m, st in enumerate(out["steps"]):
             for j in range(layout.J):
-                per[m, l] += ny.field(k, p.obs, layout.arcs[j], layout.nodes[j],
-                                      st["alpha"][j])
+                per[m, l] += layout.field(j, k, p.obs, st["alpha"][j])
     u = np.zeros((len(times), nobs), dtype=complex)
     for m in range(p.M):
         du = freq_to_time(omegas, weights, per[m], times)
