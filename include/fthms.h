@@ -136,7 +136,58 @@ int fthms_cheb_nodes(int n, double *t_out);
 int fthms_arc_create(fthms_ctx *ctx, int n, const double *xy,
                      const double *dxy, fthms_arc **out);
 int fthms_arc_destroy(fthms_arc *arc);
+/* Number of unknowns of the arc (n, or npan * n_per for panel arcs). */
 int fthms_arc_size(const fthms_arc *arc);
+
+/* ---- composite-panel arcs (Section 4.3, eqs. cov and psi-tilde) ----------
+ *
+ * The arc is cut at breaks[0] = -1 < breaks[1] < ... < breaks[npan] = 1 (in
+ * its parameter t) into npan panels (1..16), so that no end of the arc or of
+ * its truncated overlap lies inside a panel.  Panel p has a variable theta in
+ * [-1, 1], t = breaks[p] + (breaks[p+1] - breaks[p]) (1 + theta) / 2, and
+ * theta = theta(s) is the cosine change of variables of eq. cov given by
+ * kinds[p]: FTHMS_COV_NONE (theta = s), FTHMS_COV_BOTH (singular ends at
+ * both sides), FTHMS_COV_LEFT (at theta = -1), FTHMS_COV_RIGHT (at +1).
+ * In s each panel has n_per first-kind Chebyshev nodes
+ * s_i = cos((2i + 1) pi / (2 n_per)), i = 0..n_per-1, and the unknown is the
+ * density per unit s, mu = psi |dx/ds| (the Jacobian-carrying density of
+ * eq. psi-tilde): densities, right-hand sides and fields of such an arc are
+ * [.][npan * n_per], panel by panel.  The matrix is
+ * A_ij = -(1/2pi) J0(k r_ij) W_ij + w_j S_k(r_ij), where W is the
+ * frequency-independent product-integration table of log|y_i - y(s)|
+ * against each panel's interpolant, w the Fejer weights and S_k the smooth
+ * part of the fundamental solution; fields use w for far targets and the
+ * panel interpolants near the arc.  Composite-panel arcs work in
+ * fthms_solve, fthms_eval_field, fthms_rhs, the stage entry points and
+ * problems; batches (fthms_batch_create) take single-panel arcs only. */
+enum { FTHMS_COV_NONE = 0, FTHMS_COV_BOTH = 1, FTHMS_COV_LEFT = 2, FTHMS_COV_RIGHT = 3 };
+
+/* Arc parameters t at which to sample x(t) and dx/dt for a panel arc:
+ * t_out[npan * n_per], panel by panel, nodes in the order above. */
+int fthms_panel_nodes(int npan, const double *breaks, const int *kinds, int n_per,
+                      double *t_out);
+
+/* Register a composite-panel arc from samples xy, dxy [npan * n_per][2] of
+ * x(t) and dx/dt at fthms_panel_nodes(); npan * n_per <= 1024.  Builds the
+ * table W on the host (once per arc) and uploads it.  FTHMS_EINVAL for a bad
+ * panel layout, FTHMS_EINVAL_DATA for non-finite samples, coincident nodes
+ * or a vanishing speed. */
+int fthms_arc_create_panels(fthms_ctx *ctx, int npan, const double *breaks, const int *kinds,
+                            int n_per, const double *xy, const double *dxy, fthms_arc **out);
+
+/* Panel breakpoints of the arcs of cyclic partitions (the layout of
+ * fthms_problem_desc: interval [narcs][2] on the parent curve of period
+ * `period`, group [narcs] or NULL for one curve): arc j is cut where the
+ * overlaps with its neighbours on the same curve end, i.e. at the ends of
+ * its truncated overlap (Section 4.3).  breaks [narcs][4] receives
+ * -1 = t_0 < ... < t_npan = 1 (unused entries 1), npan [narcs] the panel
+ * count (3, or 1 for an arc alone on its curve). */
+int fthms_tov_breaks(int narcs, const double *interval, const int *group, double period,
+                     double *breaks, int *npan);
+
+/* Copy out a panel arc's table W [n][n] (row i = target node, row-major)
+ * and weights w [n] (either may be NULL).  FTHMS_EINVAL for other arcs. */
+int fthms_arc_panel_table(const fthms_arc *arc, double *W, double *w);
 
 /* ---- the per-(arc, k) solve --------------------------------------------- */
 

@@ -97,6 +97,41 @@ class PanelArc:
         t, _ = self.t_of(p, s)
         return self.curve.x(t)
 
+    def dt(self, p, s, s0):
+        """t(s) - t(s0) on panel p without cancellation: the cosine maps'
+        differences are formed as products of sines
+        (cos a - cos b = -2 sin((a+b)/2) sin((a-b)/2))."""
+        s = np.asarray(s, dtype=float)
+        kind = self.kinds[p]
+        h = 0.5 * (self.breaks[p + 1] - self.breaks[p])
+        if kind == COV_NONE:
+            return h * (s - s0)
+        if kind == COV_BOTH:
+            a, a0, f = 0.5 * math.pi * (1.0 - s), 0.5 * math.pi * (1.0 - s0), 1.0
+        elif kind == COV_LEFT:
+            a, a0, f = 0.25 * math.pi * (1.0 + s), 0.25 * math.pi * (1.0 + s0), -2.0
+        else:
+            a, a0, f = 0.25 * math.pi * (1.0 - s), 0.25 * math.pi * (1.0 - s0), 2.0
+        return h * f * (-2.0 * np.sin(0.5 * (a + a0)) * np.sin(0.5 * (a - a0)))
+
+    def ydiff(self, p, s, s0):
+        """x(t(s)) - x(t(s0)) on panel p: for |t - t0| < 0.05 as
+        (t - t0) times the mean of x' over [t0, t] (8-point Gauss-Legendre),
+        which keeps full relative precision for nearby points; else by
+        subtraction."""
+        s = np.asarray(s, dtype=float)
+        t0, _ = self.t_of(p, np.array([s0]))
+        d = self.dt(p, s, s0)
+        out = self.y(p, s) - self.curve.x(t0)[0]
+        small = np.abs(d) < 0.05
+        if np.any(small):
+            g, w = np.polynomial.legendre.leggauss(8)
+            u = 0.5 * (g + 1.0)
+            ds = d[small]
+            mean = sum(0.5 * wq * self.curve.dx(t0[0] + uq * ds) for uq, wq in zip(u, w))
+            out[small] = ds[:, None] * mean
+        return out
+
     def speed(self, p, s):
         """|dx/ds| on panel p."""
         t, dt = self.t_of(p, s)
@@ -167,7 +202,10 @@ def log_table(arc, tol=1e-14):
     """W_ij = int_{panel(j)} log|y_i - y(s)| l_j(s) ds for every node i of
     the arc and node j: adaptive Gauss-Legendre quadrature of the vector of
     Chebyshev moments int log|y_i - y(s)| T_m(s) ds, split at the target
-    when it lies on the panel, then l_j = sum_m C[m, j] T_m."""
+    when it lies on the panel, then l_j = sum_m C[m, j] T_m.  On the
+    target's own panel the distances come from ``PanelArc.ydiff``: where the
+    cosine maps cluster the nodes, plain subtraction of nearly equal points
+    would lose ~1e-10 of the table."""
     nd = arc.nodes()
     N, n = nd["n"], arc.n
     C = _coef_matrix(arc.phi)
@@ -177,13 +215,19 @@ def log_table(arc, tol=1e-14):
         yi = nd["y"][i]
         for p in range(arc.P):
 
-            def f(s, p=p, yi=yi):
-                y = arc.y(p, s)
-                r = np.hypot(y[:, 0] - yi[0], y[:, 1] - yi[1])
+            own = nd["panel"][i] == p
+            si = float(arc.s[i % n])
+
+            def f(s, p=p, yi=yi, own=own, si=si):
+                if own:
+                    d = arc.ydiff(p, s, si)
+                else:
+                    d = arc.y(p, s) - yi
+                r = np.hypot(d[:, 0], d[:, 1])
                 T = np.cos(np.outer(np.arccos(np.clip(s, -1.0, 1.0)), m))
                 return np.log(np.maximum(r, 1e-300))[:, None] * T
 
-            brk = (float(arc.s[i % n]),) if nd["panel"][i] == p else ()
+            brk = (si,) if own else ()
             W[i, p * n:(p + 1) * n] = adaptive_gl_vec(f, -1.0, 1.0, brk, tol) @ C
     return W
 
@@ -217,8 +261,10 @@ def panel_coeffs(arc, mu):
 
 
 def near_radius(nodes):
-    """10 x the largest distance between consecutive nodes of the arc."""
-    return ny.NEAR_FACTOR * ny.max_spacing(nodes["y"])
+    """10 x the largest distance between nodes adjacent along the arc (in
+    order of the arc parameter t; within a panel the node order runs
+    against t, and consecutive panels follow each other)."""
+    return ny.NEAR_FACTOR * ny.max_spacing(nodes["y"][np.argsort(nodes["t"])])
 
 
 def field(k, z, nodes, mu, tol_rel=1e-14):

@@ -9,7 +9,8 @@ use of any name below; it raises ImportError when the library is missing
 _NAMES = ("FP64", "FP32_REFINED", "INC_PLANE", "INC_GPLANE", "INC_POINT",
           "Arc", "Batch", "Context", "FthmsError", "Problem", "Server", "cheb_nodes",
           "JOB_QUEUED", "JOB_RUNNING", "JOB_DONE", "JOB_FAILED", "JOB_CANCELLED",
-          "incident_struct", "lib", "EXPORTED", "request_from_workload")
+          "incident_struct", "lib", "EXPORTED", "request_from_workload", "panel_nodes", "tov_breaks",
+          "COV_NONE", "COV_BOTH", "COV_LEFT", "COV_RIGHT")
 
 __all__ = list(_NAMES)
 

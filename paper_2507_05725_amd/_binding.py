@@ -75,6 +75,10 @@ _SIGS = {
     "fthms_arc_create": ([_vp, _i, _vp, _vp, C.POINTER(_vp)], _i),
     "fthms_arc_destroy": ([_vp], _i),
     "fthms_arc_size": ([_vp], _i),
+    "fthms_panel_nodes": ([_i, _vp, _vp, _i, _vp], _i),
+    "fthms_arc_create_panels": ([_vp, _i, _vp, _vp, _i, _vp, _vp, C.POINTER(_vp)], _i),
+    "fthms_arc_panel_table": ([_vp, _vp, _vp], _i),
+    "fthms_tov_breaks": ([_i, _vp, _vp, _d, _vp, _vp], _i),
     "fthms_solve": ([_vp, _vp, _i, _vp, _vp, _vp, _i, _d, _vp, _vp], _i),
     "fthms_solve_dev": ([_vp, _vp, _i, _vp, _vp, _vp, _i, _d, _vp, _vp], _i),
     "fthms_rhs": ([_vp, _vp, _i, _vp, C.POINTER(Incident), _vp], _i),
@@ -145,6 +149,34 @@ def cheb_nodes(n):
     return t
 
 
+COV_NONE, COV_BOTH, COV_LEFT, COV_RIGHT = 0, 1, 2, 3
+
+
+def tov_breaks(intervals, groups=None, period=2 * np.pi):
+    """Per arc: the panel breakpoints at the ends of its truncated overlap
+    (list of arrays, 2 or 4 entries)."""
+    iv = np.ascontiguousarray(intervals, dtype=np.float64).reshape(-1, 2)
+    na = iv.shape[0]
+    gr = None if groups is None else np.ascontiguousarray(groups, dtype=np.int32)
+    br = np.empty((na, 4))
+    npan = np.empty(na, dtype=np.int32)
+    rc = _lib.fthms_tov_breaks(na, _ptr(iv), _ptr(gr), float(period), _ptr(br), _ptr(npan))
+    if rc:
+        raise FthmsError(rc, "fthms_tov_breaks")
+    return [br[j, :npan[j] + 1].copy() for j in range(na)]
+
+
+def panel_nodes(breaks, kinds, n_per):
+    """Arc parameters t of a composite-panel arc's nodes (panel by panel)."""
+    br = np.ascontiguousarray(breaks, dtype=np.float64)
+    kd = np.ascontiguousarray(kinds, dtype=np.int32)
+    t = np.empty((br.size - 1) * n_per)
+    rc = _lib.fthms_panel_nodes(br.size - 1, _ptr(br), _ptr(kd), n_per, _ptr(t))
+    if rc:
+        raise FthmsError(rc, "fthms_panel_nodes")
+    return t
+
+
 def incident_struct(spec):
     """workloads.IncidentSpec -> fthms_incident."""
     kind = {"plane": INC_PLANE, "gplane": INC_GPLANE, "point": INC_POINT}[spec.kind]
@@ -205,6 +237,15 @@ class Context:
     def arc_from_curve(self, curve, n):
         t = cheb_nodes(n)
         return Arc(self, curve.x(t), curve.dx(t))
+
+    def panel_arc_from_curve(self, curve, n_per, breaks, kinds=None):
+        """Composite-panel arc sampled at panel_nodes (default: the two-sided
+        change of variables on every panel)."""
+        breaks = np.asarray(breaks, dtype=np.float64)
+        if kinds is None:
+            kinds = [COV_BOTH] * (breaks.size - 1)
+        t = panel_nodes(breaks, kinds, n_per)
+        return Arc(self, curve.x(t), curve.dx(t), breaks=breaks, kinds=kinds, n_per=n_per)
 
     def solve(self, arc, k, rhs, precision=FP64, tol=0.0):
         k = np.ascontiguousarray(k, dtype=np.float64)
@@ -287,14 +328,32 @@ class Context:
 
 
 class Arc:
-    def __init__(self, ctx, xy, dxy):
+    """An arc from samples at fthms_cheb_nodes (one weighted panel), or with
+    ``breaks``/``kinds``/``n_per`` a composite-panel arc sampled at
+    panel_nodes(breaks, kinds, n_per)."""
+
+    def __init__(self, ctx, xy, dxy, breaks=None, kinds=None, n_per=None):
         xy = np.ascontiguousarray(xy, dtype=np.float64)
         dxy = np.ascontiguousarray(dxy, dtype=np.float64)
         n = xy.shape[0]
         h = C.c_void_p()
-        ctx.check(_lib.fthms_arc_create(ctx.h, n, _ptr(xy), _ptr(dxy), C.byref(h)),
-                  "arc_create")
+        if breaks is None:
+            ctx.check(_lib.fthms_arc_create(ctx.h, n, _ptr(xy), _ptr(dxy), C.byref(h)),
+                      "arc_create")
+        else:
+            br = np.ascontiguousarray(breaks, dtype=np.float64)
+            kd = np.ascontiguousarray(kinds, dtype=np.int32)
+            ctx.check(_lib.fthms_arc_create_panels(ctx.h, br.size - 1, _ptr(br), _ptr(kd),
+                                                   int(n_per), _ptr(xy), _ptr(dxy), C.byref(h)),
+                      "arc_create_panels")
         self.ctx, self.h, self.n = ctx, h, n
+
+    def panel_table(self):
+        """(W [n][n], w [n]) of a composite-panel arc."""
+        W = np.empty((self.n, self.n))
+        w = np.empty(self.n)
+        self.ctx.check(_lib.fthms_arc_panel_table(self.h, _ptr(W), _ptr(w)), "arc_panel_table")
+        return W, w
 
     def close(self):
         if self.h:

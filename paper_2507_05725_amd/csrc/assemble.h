@@ -17,6 +17,13 @@
 //     z = k r_ij,  c_k = (gamma + log(k/2)) / (2N),
 // and A_ii = G_ii - c_k + i pi/(4N).  Y0hat = Y0 - (2/pi)(log(z/2)+gamma) J0
 // removes the log|t_i - t_j| cancellation near the diagonal exactly.
+//
+// Composite-panel arcs (Section 4.3, eqs. cov, psi-tilde) replace pi/N by
+// the Fejer weight w_j of column j and G by -W/(2pi), W the product-
+// integration table of log|y_i - y(s)| on the panels:
+//   A_ij = J0(z)(G_ij - w_j c) - (w_j/4) Y0hat(z) + i (w_j/4) J0(z),
+//   c = (gamma + log(k/2)) / (2pi);
+// A is then no longer symmetric, but J0 and Y0hat of a node pair are.
 #pragma once
 
 #include "bessel.h"
@@ -25,15 +32,16 @@
 namespace fthms {
 
 // Upper-triangular 32x32 tiles; each block computes one tile for one
-// wavenumber and writes it and its mirror (A is complex symmetric).  With
-// ylist / Glist (uneven batches) matrix b takes its own arc's nodes and
-// table; otherwise every matrix uses y0 / G0.
-template <bool W32>
+// wavenumber and writes it and its mirror (A is complex symmetric; with
+// column weights (WCOL) the mirror reuses the pair's Bessel values with its
+// own table entry and weight).  With ylist / Glist (uneven batches) matrix b
+// takes its own arc's nodes and table; otherwise every matrix uses y0 / G0.
+template <bool W32, bool WCOL>
 __global__ __launch_bounds__(256) void assemble_kernel(
     const double2 *__restrict__ y0, const double *__restrict__ G0, int N,
     const double *__restrict__ kvec, double2 *__restrict__ A64,
     float2 *__restrict__ A32, long long mstride, const double2 *const *ylist,
-    const double *const *Glist) {
+    const double *const *Glist, const double *__restrict__ wcol) {
   __shared__ double2 tile[32][33];
   const int b = blockIdx.y;
   const double2 *__restrict__ y = ylist ? ylist[b] : y0;
@@ -53,6 +61,42 @@ __global__ __launch_bounds__(256) void assemble_kernel(
   const int i = i0 + tx;
   double2 yi = make_double2(0.0, 0.0);
   if (i < N) yi = y[i];
+  if (WCOL) {
+    // tile holds (J0, Y0hat) of each pair; both writes form their own value
+    const double c = (kEulerGamma + log(0.5 * k)) / (2.0 * kPi);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = j0 + ty + 8 * q;
+      double2 jy = make_double2(1.0, 0.0);
+      if (i < N && j < N) {
+        if (i != j) {
+          const double2 yj = y[j];
+          const double dx = yi.x - yj.x, dy = yi.y - yj.y;
+          bessel_j0_y0hat(k * sqrt(dx * dx + dy * dy), jy.x, jy.y);
+        }
+        const double g = G[i + (long long)j * N], w = wcol[j];
+        const double2 v = make_double2(jy.x * (g - w * c) - 0.25 * w * jy.y, 0.25 * w * jy.x);
+        A[i + (long long)j * N] = v;
+        if (W32) Af[i + (long long)j * N] = make_float2((float)v.x, (float)v.y);
+      }
+      tile[ty + 8 * q][tx] = jy;
+    }
+    if (I != J) {
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = j0 + tx, col = i0 + ty + 8 * q;
+        if (row < N && col < N) {
+          const double2 jy = tile[tx][ty + 8 * q];
+          const double g = G[row + (long long)col * N], w = wcol[col];
+          const double2 v = make_double2(jy.x * (g - w * c) - 0.25 * w * jy.y, 0.25 * w * jy.x);
+          A[row + (long long)col * N] = v;
+          if (W32) Af[row + (long long)col * N] = make_float2((float)v.x, (float)v.y);
+        }
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int j = j0 + ty + 8 * q;

@@ -108,11 +108,11 @@ static int batch_factor(fthms_batch *bt, const fthms_batch::Bucket &bk, const Bu
   dim3 g(T * (T + 1) / 2, c), blk(256);
   tbeg(ctx, "assemble");
   if (fp32)
-    assemble_kernel<true><<<g, blk, 0, ctx->stream>>>(nullptr, nullptr, n, bk.d_k, w.A64, w.A32,
-                                                       ms, bk.d_y, bk.d_G);
+    assemble_kernel<true, false><<<g, blk, 0, ctx->stream>>>(
+        nullptr, nullptr, n, bk.d_k, w.A64, w.A32, ms, bk.d_y, bk.d_G, nullptr);
   else
-    assemble_kernel<false><<<g, blk, 0, ctx->stream>>>(nullptr, nullptr, n, bk.d_k, w.A64,
-                                                        nullptr, ms, bk.d_y, bk.d_G);
+    assemble_kernel<false, false><<<g, blk, 0, ctx->stream>>>(
+        nullptr, nullptr, n, bk.d_k, w.A64, nullptr, ms, bk.d_y, bk.d_G, nullptr);
   tend(ctx);
   int rc = check_launch(ctx, "assemble_kernel (batch)");
   if (rc) return rc;
@@ -207,6 +207,9 @@ int fthms_batch_create(fthms_ctx *ctx, int nb, const fthms_arc *const *arcs, con
   for (int i = 0; i < nb; ++i) {
     if (!arcs[i] || arcs[i]->ctx != ctx)
       return fail(ctx, FTHMS_EINVAL, "solve " + std::to_string(i) + ": arc missing or of another context");
+    if (arcs[i]->d_w)
+      return fail(ctx, FTHMS_EINVAL,
+                  "solve " + std::to_string(i) + ": composite-panel arcs are not batched");
     if (!(k[i] > 0.0) || !std::isfinite(k[i]))
       return fail(ctx, FTHMS_EINVAL_DATA, "solve " + std::to_string(i) + ": wavenumber must be > 0");
     int rc = to_incident(ctx, &inc[i], incd[i]);
@@ -412,11 +415,11 @@ int fthms_batch_tune(fthms_batch *bt, int reps) {
       for (int r = 0; r < reps && rc == FTHMS_OK; ++r) {
         // fresh matrices, then the factorisation alone between events
         if (fp32)
-          assemble_kernel<true><<<g, blk, 0, ctx->stream>>>(nullptr, nullptr, n, bk.d_k, w.A64,
-                                                             w.A32, ms, bk.d_y, bk.d_G);
+          assemble_kernel<true, false><<<g, blk, 0, ctx->stream>>>(
+              nullptr, nullptr, n, bk.d_k, w.A64, w.A32, ms, bk.d_y, bk.d_G, nullptr);
         else
-          assemble_kernel<false><<<g, blk, 0, ctx->stream>>>(nullptr, nullptr, n, bk.d_k, w.A64,
-                                                              nullptr, ms, bk.d_y, bk.d_G);
+          assemble_kernel<false, false><<<g, blk, 0, ctx->stream>>>(
+              nullptr, nullptr, n, bk.d_k, w.A64, nullptr, ms, bk.d_y, bk.d_G, nullptr);
         if ((rc = check_launch(ctx, "assemble_kernel (tune)"))) break;
         (void)hipEventRecord(e0, ctx->stream);
         rc = launch_lu(ctx, fp32, fp32 ? (void *)w.A32 : (void *)w.A64, n, ms, w.piv, w.scr,

@@ -3,7 +3,9 @@
 //
 // Far targets (Section 3.2, eq. FDsolk-interior; Gauss-Chebyshev rule of the
 // weighted density):  U(z) = (pi/N) sum_j Phi_k(z, y_j) alpha_j
-//                          = (pi/4N) sum_j (i J0 - Y0)(k|z - y_j|) alpha_j.
+//                          = (pi/4N) sum_j (i J0 - Y0)(k|z - y_j|) alpha_j;
+// composite-panel arcs (Section 4.3) use their Fejer weights w_j in place of
+// pi/N and integrate each panel's interpolant in s near the arc.
 // Near targets: U(z) = sum_q w_q Phi_k(z, x_q) alpha_N(cos phi_q), the exact
 // potential of the density interpolant alpha_N = sum_m a_m T_m, by a
 // composite Gauss-Legendre rule in phi (t = cos phi) graded toward the point
@@ -22,9 +24,11 @@ namespace fthms {
 constexpr int kFieldThreads = 256;
 
 // One block: up to 256 targets for one wavenumber; nodes and density in LDS.
+// Composite-panel arcs pass their Fejer weights: U(z) = sum_j w_j Phi_k(z,
+// y_j) mu_j; otherwise the weight is pi/N.
 __global__ __launch_bounds__(kFieldThreads) void field_far_kernel(
-    const double2 *__restrict__ ynodes, int N, const double *__restrict__ kvec,
-    const double2 *__restrict__ alpha, long long astride,
+    const double2 *__restrict__ ynodes, int N, const double *__restrict__ wnode,
+    const double *__restrict__ kvec, const double2 *__restrict__ alpha, long long astride,
     const double2 *__restrict__ pts, int np, const unsigned char *__restrict__ cls,
     double2 *__restrict__ U, long long ustride, int accumulate) {
   __shared__ double2 sy[1024];
@@ -32,7 +36,9 @@ __global__ __launch_bounds__(kFieldThreads) void field_far_kernel(
   const int b = blockIdx.y;
   for (int j = threadIdx.x; j < N; j += kFieldThreads) {
     sy[j] = ynodes[j];
-    sa[j] = alpha[(long long)b * astride + j];
+    double2 a = alpha[(long long)b * astride + j];
+    if (wnode) a = make_double2(wnode[j] * a.x, wnode[j] * a.y);
+    sa[j] = a;
   }
   __syncthreads();
   const int p = blockIdx.x * kFieldThreads + threadIdx.x;
@@ -50,7 +56,7 @@ __global__ __launch_bounds__(kFieldThreads) void field_far_kernel(
     accr += -y0v * a.x - j0v * a.y;
     acci += j0v * a.x - y0v * a.y;
   }
-  const double s = kPi / (4.0 * N);
+  const double s = wnode ? 0.25 : kPi / (4.0 * N);
   double2 *u = U + (long long)b * ustride + p;
   if (accumulate) {
     const double2 o = *u;
@@ -60,37 +66,43 @@ __global__ __launch_bounds__(kFieldThreads) void field_far_kernel(
   }
 }
 
-// Chebyshev coefficients of the density interpolant for each wavenumber:
-//   a_m = ((2 - delta_m0) / N) sum_j cos(m theta_j) alpha_j,
-// cosT[j][m] = cos(m theta_j).  One block per wavenumber, threads over m.
+// Chebyshev coefficients of the density interpolant for each wavenumber,
+// per panel of n = nper nodes (one panel: nper = N):
+//   a_{p,m} = ((2 - delta_m0) / n) sum_j cos(m theta_j) alpha_{p n + j},
+// cosT[j][m] = cos(m theta_j).  One block per wavenumber, threads over
+// (p, m).
 __global__ __launch_bounds__(kFieldThreads) void cheb_coeff_kernel(
-    const double *__restrict__ cosT, int N, const double2 *__restrict__ alpha,
+    const double *__restrict__ cosT, int N, int nper, const double2 *__restrict__ alpha,
     long long astride, double2 *__restrict__ coef) {
   __shared__ double2 sa[1024];
   const int b = blockIdx.x;
   for (int j = threadIdx.x; j < N; j += kFieldThreads) sa[j] = alpha[(long long)b * astride + j];
   __syncthreads();
-  for (int m = threadIdx.x; m < N; m += kFieldThreads) {
+  for (int e = threadIdx.x; e < N; e += kFieldThreads) {
+    const int p = e / nper, m = e - p * nper;
+    const double2 *a = sa + p * nper;
     double ar = 0.0, ai = 0.0;
-    for (int j = 0; j < N; ++j) {
-      const double c = cosT[(long long)j * N + m];
-      ar += c * sa[j].x;
-      ai += c * sa[j].y;
+    for (int j = 0; j < nper; ++j) {
+      const double c = cosT[(long long)j * nper + m];
+      ar += c * a[j].x;
+      ai += c * a[j].y;
     }
-    const double f = (m == 0 ? 1.0 : 2.0) / N;
-    coef[(long long)b * N + m] = make_double2(f * ar, f * ai);
+    const double f = (m == 0 ? 1.0 : 2.0) / nper;
+    coef[(long long)b * N + e] = make_double2(f * ar, f * ai);
   }
 }
 
 // Near targets: one block per (target, wavenumber).
 //   U(z) = sum_q w_q (i/4) H0(k |z - x_q|) alpha_N(c_q),
-//   alpha_N(c) = sum_m a_m T_m(c) by Clenshaw's recurrence, c_q = cos(phi_q).
+//   alpha_N(c) = sum_m a_m T_m(c) by Clenshaw's recurrence, c_q = cos(phi_q),
+// with the coefficients of point q's panel (pq[q]; none: one panel).
 __global__ __launch_bounds__(kFieldThreads) void field_near_kernel(
     const int *__restrict__ tgt_index, const int *__restrict__ qoff,
     const double2 *__restrict__ xq, const double *__restrict__ wq,
-    const double *__restrict__ cq, int N, const double2 *__restrict__ coef,
-    const double *__restrict__ kvec, const double2 *__restrict__ pts,
-    double2 *__restrict__ U, long long ustride, int accumulate) {
+    const double *__restrict__ cq, const int *__restrict__ pq, int N, int nper,
+    const double2 *__restrict__ coef, const double *__restrict__ kvec,
+    const double2 *__restrict__ pts, double2 *__restrict__ U, long long ustride,
+    int accumulate) {
   __shared__ double2 sa[1024];
   __shared__ double red[2][kFieldThreads / 64];
   const int t = blockIdx.x, b = blockIdx.y;
@@ -103,17 +115,18 @@ __global__ __launch_bounds__(kFieldThreads) void field_near_kernel(
   double accr = 0.0, acci = 0.0;
   for (int q = q0 + threadIdx.x; q < q1; q += kFieldThreads) {
     const double c = cq[q], c2 = 2.0 * c;
+    const double2 *a = pq ? sa + pq[q] * nper : sa;
     double b1r = 0.0, b1i = 0.0, b2r = 0.0, b2i = 0.0;
-    for (int m = N - 1; m >= 1; --m) {
-      const double nr = sa[m].x + c2 * b1r - b2r;
-      const double ni = sa[m].y + c2 * b1i - b2i;
+    for (int m = nper - 1; m >= 1; --m) {
+      const double nr = a[m].x + c2 * b1r - b2r;
+      const double ni = a[m].y + c2 * b1i - b2i;
       b2r = b1r;
       b2i = b1i;
       b1r = nr;
       b1i = ni;
     }
-    const double dr = sa[0].x + c * b1r - b2r;
-    const double di = sa[0].y + c * b1i - b2i;
+    const double dr = a[0].x + c * b1r - b2r;
+    const double di = a[0].y + c * b1i - b2i;
     const double2 x = xq[q];
     const double dx = z.x - x.x, dy = z.y - x.y;
     double j0v, y0v;
@@ -221,6 +234,7 @@ struct NearPlan {
   double2 *d_xq = nullptr;
   double *d_wq = nullptr;
   double *d_cq = nullptr;
+  int *d_pq = nullptr;  // panel of each point (composite-panel arcs)
 };
 
 }  // namespace fthms

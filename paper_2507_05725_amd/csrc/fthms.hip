@@ -18,6 +18,7 @@
 #include "lu.h"
 #include "nearfield.h"
 #include "panel.h"
+#include "panels.h"
 
 using namespace fthms;
 
@@ -50,15 +51,24 @@ struct fthms_ctx {
   std::map<std::string, std::pair<double, int>> times;
 };
 
+// An arc: one weighted Chebyshev panel (npan = 1, nper = n), or a
+// composite-panel arc (npan panels of nper nodes, per-node weights w / d_w).
+// theta: node angles within the panel; t: arc parameter of each node; s:
+// speed |dx/dt| (one panel) or |dx/ds| (panels); cgx, cgy: Chebyshev
+// coefficients of the geometry, [npan][nper].
 struct fthms_arc {
   fthms_ctx *ctx = nullptr;
   int n = 0;
+  int npan = 1, nper = 0;
   std::vector<double> theta, t, xy, dxy, s;
-  std::vector<double> cgx, cgy;  // Chebyshev coefficients of x(t), y(t)
+  std::vector<double> cgx, cgy;
+  std::vector<double> breaks, w;
+  std::vector<int> kinds;
   double hmax = 0.0;
   double2 *d_y = nullptr;
   double *d_G = nullptr;
-  double *d_cos = nullptr;  // [n][n] cos(m theta_j), row j
+  double *d_cos = nullptr;  // [nper][nper] cos(m theta_j), row j
+  double *d_w = nullptr;    // composite-panel arcs: Fejer weights
   size_t bytes = 0;
 };
 
@@ -289,6 +299,7 @@ int fthms_arc_create(fthms_ctx *ctx, int n, const double *xy, const double *dxy,
   if (!arc) return fail(ctx, FTHMS_ENOMEM, "host allocation failed");
   arc->ctx = ctx;
   arc->n = n;
+  arc->nper = n;
   arc->theta.resize(n);
   arc->t.resize(n);
   arc->s.resize(n);
@@ -380,13 +391,181 @@ int fthms_arc_create(fthms_ctx *ctx, int n, const double *xy, const double *dxy,
   return FTHMS_OK;
 }
 
+static bool panel_layout_ok(int npan, const double *breaks, const int *kinds, int n_per) {
+  if (npan < 1 || npan > kMaxPanels || !breaks || !kinds || n_per < 2 ||
+      (long long)npan * n_per > kMaxN)
+    return false;
+  if (breaks[0] != -1.0 || breaks[npan] != 1.0) return false;
+  for (int p = 0; p < npan; ++p) {
+    if (!(breaks[p + 1] > breaks[p])) return false;
+    if (kinds[p] < kCovNone || kinds[p] > kCovRight) return false;
+  }
+  return true;
+}
+
+// arc parameter of node i of panel p: t_p + (t_{p+1} - t_p)(1 + theta(s_i))/2
+static void panel_node_params(int npan, const double *breaks, const int *kinds, int n,
+                              double *t, double *dtds) {
+  for (int p = 0; p < npan; ++p)
+    for (int i = 0; i < n; ++i) {
+      const double si = std::cos((2.0 * i + 1.0) * kPi / (2.0 * n));
+      double th, dth;
+      cov_map(kinds[p], si, th, dth);
+      const double h = 0.5 * (breaks[p + 1] - breaks[p]);
+      t[p * n + i] = breaks[p] + h * (1.0 + th);
+      if (dtds) dtds[p * n + i] = h * dth;
+    }
+}
+
+int fthms_panel_nodes(int npan, const double *breaks, const int *kinds, int n_per,
+                      double *t_out) {
+  if (!t_out || !panel_layout_ok(npan, breaks, kinds, n_per)) return FTHMS_EINVAL;
+  panel_node_params(npan, breaks, kinds, n_per, t_out, nullptr);
+  return FTHMS_OK;
+}
+
+int fthms_arc_create_panels(fthms_ctx *ctx, int npan, const double *breaks, const int *kinds,
+                            int n_per, const double *xy, const double *dxy, fthms_arc **out) {
+  if (!ctx || !xy || !dxy || !out) return fail(ctx, FTHMS_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (!panel_layout_ok(npan, breaks, kinds, n_per))
+    return fail(ctx, FTHMS_EINVAL,
+                "panels: need 1..16 panels, breaks -1 = t_0 < ... < t_P = 1, kinds 0..3, "
+                "2 <= n_per and npan * n_per <= 1024");
+  const int n = npan * n_per;
+  for (int i = 0; i < 2 * n; ++i)
+    if (!std::isfinite(xy[i]) || !std::isfinite(dxy[i]))
+      return fail(ctx, FTHMS_EINVAL_DATA, "non-finite arc sample");
+  fthms_arc *arc = new (std::nothrow) fthms_arc;
+  if (!arc) return fail(ctx, FTHMS_ENOMEM, "host allocation failed");
+  arc->ctx = ctx;
+  arc->n = n;
+  arc->npan = npan;
+  arc->nper = n_per;
+  arc->breaks.assign(breaks, breaks + npan + 1);
+  arc->kinds.assign(kinds, kinds + npan);
+  arc->xy.assign(xy, xy + 2 * n);
+  arc->dxy.assign(dxy, dxy + 2 * n);
+  arc->theta.resize(n);
+  arc->t.resize(n);
+  arc->s.resize(n);
+  std::vector<double> dtds(n), w1;
+  panel_node_params(npan, breaks, kinds, n_per, arc->t.data(), dtds.data());
+  fejer_weights(n_per, w1);
+  arc->w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    arc->theta[i] = (2.0 * (i % n_per) + 1.0) * kPi / (2.0 * n_per);
+    arc->s[i] = std::hypot(dxy[2 * i], dxy[2 * i + 1]) * std::fabs(dtds[i]);
+    arc->w[i] = w1[i % n_per];
+    if (!(std::hypot(dxy[2 * i], dxy[2 * i + 1]) > 0.0)) {
+      delete arc;
+      return fail(ctx, FTHMS_EINVAL_DATA, "vanishing speed |x'(t)| at a node");
+    }
+  }
+  // largest distance between nodes adjacent along the arc (order of t)
+  std::vector<int> ord(n);
+  for (int i = 0; i < n; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](int a, int b) { return arc->t[a] < arc->t[b]; });
+  double hmax = 0.0;
+  for (int q = 0; q + 1 < n; ++q) {
+    const int i = ord[q], j = ord[q + 1];
+    const double h = std::hypot(xy[2 * j] - xy[2 * i], xy[2 * j + 1] - xy[2 * i + 1]);
+    if (!(h > 0.0)) {
+      delete arc;
+      return fail(ctx, FTHMS_EINVAL_DATA, "coincident nodes");
+    }
+    hmax = std::max(hmax, h);
+  }
+  arc->hmax = hmax;
+  // per-panel Chebyshev coefficients of the geometry in s
+  const PanelGeom geom = panel_geom_from_samples(npan, n_per, xy, dxy, breaks, kinds);
+  arc->cgx = geom.cx;
+  arc->cgy = geom.cy;
+  std::vector<double> G;
+  panel_log_table(geom, arc->xy, G);
+  for (double g : G)
+    if (!std::isfinite(g)) {
+      delete arc;
+      return fail(ctx, FTHMS_EINVAL_DATA, "log table: non-finite entry (degenerate geometry)");
+    }
+  std::vector<double> cosT((size_t)n_per * n_per);
+  for (int j = 0; j < n_per; ++j)
+    for (int m = 0; m < n_per; ++m) cosT[(size_t)j * n_per + m] = std::cos(m * arc->theta[j]);
+  int rc;
+  arc->bytes = sizeof(double2) * n + sizeof(double) * ((size_t)n * n + (size_t)n_per * n_per + n);
+  if ((rc = dev_alloc(ctx, (void **)&arc->d_y, sizeof(double2) * n)) ||
+      (rc = dev_alloc(ctx, (void **)&arc->d_G, sizeof(double) * (size_t)n * n)) ||
+      (rc = dev_alloc(ctx, (void **)&arc->d_cos, sizeof(double) * (size_t)n_per * n_per)) ||
+      (rc = dev_alloc(ctx, (void **)&arc->d_w, sizeof(double) * n))) {
+    fthms_arc_destroy(arc);
+    return rc;
+  }
+  if (hipMemcpy(arc->d_y, xy, sizeof(double2) * n, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(arc->d_G, G.data(), sizeof(double) * (size_t)n * n, hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(arc->d_cos, cosT.data(), sizeof(double) * (size_t)n_per * n_per,
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(arc->d_w, arc->w.data(), sizeof(double) * n, hipMemcpyHostToDevice) !=
+          hipSuccess) {
+    fthms_arc_destroy(arc);
+    return fail(ctx, FTHMS_EDEVICE, "hipMemcpy of the arc tables failed");
+  }
+  *out = arc;
+  return FTHMS_OK;
+}
+
+int fthms_tov_breaks(int narcs, const double *interval, const int *group, double period,
+                     double *breaks, int *npan) {
+  if (narcs < 1 || !interval || !(period > 0.0) || !breaks || !npan) return FTHMS_EINVAL;
+  for (int j = 0; j < narcs; ++j) {
+    if (!(interval[2 * j + 1] > interval[2 * j])) return FTHMS_EINVAL;
+    // cyclic neighbours within the arc's group, in list order
+    const int gj = group ? group[j] : 0;
+    std::vector<int> mem;
+    for (int i = 0; i < narcs; ++i)
+      if ((group ? group[i] : 0) == gj) mem.push_back(i);
+    std::vector<double> br = {-1.0, 1.0};
+    if (mem.size() > 1) {
+      const int q = (int)(std::find(mem.begin(), mem.end(), j) - mem.begin());
+      const int m = (int)mem.size();
+      const int prv = mem[(q + m - 1) % m], nxt = mem[(q + 1) % m];
+      const double a = interval[2 * j], b = interval[2 * j + 1];
+      // the truncated overlap ends where the previous arc ends and the next begins
+      for (double e : {interval[2 * prv + 1], interval[2 * nxt]}) {
+        double u = std::fmod(e - a, period);
+        if (u < 0.0) u += period;
+        if (u > 0.0 && u < b - a) br.push_back(-1.0 + 2.0 * u / (b - a));
+      }
+    }
+    std::sort(br.begin(), br.end());
+    npan[j] = (int)br.size() - 1;
+    for (int e = 0; e < 4; ++e) breaks[4 * j + e] = e < (int)br.size() ? br[e] : 1.0;
+  }
+  return FTHMS_OK;
+}
+
+int fthms_arc_panel_table(const fthms_arc *arc, double *W, double *w) {
+  if (!arc || !arc->d_w) return FTHMS_EINVAL;
+  fthms_ctx *ctx = arc->ctx;
+  const int n = arc->n;
+  if (W) {
+    std::vector<double> G((size_t)n * n);
+    HIPCK(ctx, hipMemcpy(G.data(), arc->d_G, sizeof(double) * G.size(), hipMemcpyDeviceToHost));
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) W[(size_t)i * n + j] = -2.0 * kPi * G[(size_t)i + (size_t)j * n];
+  }
+  if (w) std::memcpy(w, arc->w.data(), sizeof(double) * n);
+  return FTHMS_OK;
+}
+
 int fthms_arc_destroy(fthms_arc *arc) {
   if (!arc) return FTHMS_EINVAL;
   fthms_ctx *ctx = arc->ctx;
   if (ctx) {
     dev_free(ctx, arc->d_y, sizeof(double2) * arc->n);
     dev_free(ctx, arc->d_G, sizeof(double) * (size_t)arc->n * arc->n);
-    dev_free(ctx, arc->d_cos, sizeof(double) * (size_t)arc->n * arc->n);
+    dev_free(ctx, arc->d_cos, sizeof(double) * (size_t)arc->nper * arc->nper);
+    dev_free(ctx, arc->d_w, sizeof(double) * arc->n);
   }
   delete arc;
   return FTHMS_OK;
@@ -633,12 +812,20 @@ static int assemble_launch(fthms_ctx *ctx, const fthms_arc *arc, const double *k
   const int T = (N + 31) / 32;
   dim3 g(T * (T + 1) / 2, count), b(256);
   const long long ms = (long long)N * N;
-  if (A32)
-    assemble_kernel<true><<<g, b, 0, ctx->stream>>>(arc->d_y, arc->d_G, N, k_dev, A64, A32, ms,
-                                                     nullptr, nullptr);
-  else
-    assemble_kernel<false><<<g, b, 0, ctx->stream>>>(arc->d_y, arc->d_G, N, k_dev, A64, nullptr,
-                                                      ms, nullptr, nullptr);
+  if (arc->d_w) {
+    if (A32)
+      assemble_kernel<true, true><<<g, b, 0, ctx->stream>>>(arc->d_y, arc->d_G, N, k_dev, A64,
+                                                            A32, ms, nullptr, nullptr, arc->d_w);
+    else
+      assemble_kernel<false, true><<<g, b, 0, ctx->stream>>>(
+          arc->d_y, arc->d_G, N, k_dev, A64, nullptr, ms, nullptr, nullptr, arc->d_w);
+  } else if (A32) {
+    assemble_kernel<true, false><<<g, b, 0, ctx->stream>>>(arc->d_y, arc->d_G, N, k_dev, A64,
+                                                           A32, ms, nullptr, nullptr, nullptr);
+  } else {
+    assemble_kernel<false, false><<<g, b, 0, ctx->stream>>>(
+        arc->d_y, arc->d_G, N, k_dev, A64, nullptr, ms, nullptr, nullptr, nullptr);
+  }
   return check_launch(ctx, "assemble_kernel");
 }
 
@@ -847,21 +1034,21 @@ int field_dev_impl(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double *k
                    const NearPlan &plan, double2 *U, long long ustride, int accumulate) {
   if (nk == 0 || np == 0) return FTHMS_OK;
   dim3 g((np + kFieldThreads - 1) / kFieldThreads, nk);
-  field_far_kernel<<<g, kFieldThreads, 0, ctx->stream>>>(arc->d_y, arc->n, k_dev, alpha, astride,
-                                                        pts_dev, np, plan.d_cls, U, ustride,
-                                                        accumulate);
+  field_far_kernel<<<g, kFieldThreads, 0, ctx->stream>>>(arc->d_y, arc->n, arc->d_w, k_dev,
+                                                        alpha, astride, pts_dev, np, plan.d_cls,
+                                                        U, ustride, accumulate);
   int rc = check_launch(ctx, "field_far_kernel");
   if (rc) return rc;
   if (plan.ntgt > 0) {
     if ((rc = ensure_ws2(ctx, sizeof(double2) * (size_t)nk * arc->n))) return rc;
     double2 *coef = (double2 *)ctx->ws2;
-    cheb_coeff_kernel<<<nk, kFieldThreads, 0, ctx->stream>>>(arc->d_cos, arc->n, alpha, astride,
-                                                             coef);
+    cheb_coeff_kernel<<<nk, kFieldThreads, 0, ctx->stream>>>(arc->d_cos, arc->n, arc->nper,
+                                                             alpha, astride, coef);
     if ((rc = check_launch(ctx, "cheb_coeff_kernel"))) return rc;
     dim3 gn(plan.ntgt, nk);
     field_near_kernel<<<gn, kFieldThreads, 0, ctx->stream>>>(
-        plan.d_tgt, plan.d_qoff, plan.d_xq, plan.d_wq, plan.d_cq, arc->n, coef, k_dev, pts_dev,
-        U, ustride, accumulate);
+        plan.d_tgt, plan.d_qoff, plan.d_xq, plan.d_wq, plan.d_cq, plan.d_pq, arc->n, arc->nper,
+        coef, k_dev, pts_dev, U, ustride, accumulate);
     rc = check_launch(ctx, "field_near_kernel");
   }
   return rc;

@@ -82,15 +82,25 @@ void near_plan_free(fthms_ctx *ctx, NearPlan &p) {
   dev_free(ctx, p.d_xq, sizeof(double2) * p.nq);
   dev_free(ctx, p.d_wq, sizeof(double) * p.nq);
   dev_free(ctx, p.d_cq, sizeof(double) * p.nq);
+  dev_free(ctx, p.d_pq, sizeof(int) * p.nq);
   p = NearPlan();
 }
 
 int near_plan_build(fthms_ctx *ctx, const fthms_arc *arc, int np, const double *xy,
                     NearPlan &plan, const unsigned char *skip, double kmax) {
   NearPlanHost h;
-  double smax = 0.0;
-  for (double v : arc->s) smax = std::max(smax, v);
-  plan_near(arc->n, arc->xy.data(), arc->cgx, arc->cgy, arc->hmax, smax, kmax, np, xy, skip, h);
+  if (arc->d_w) {
+    std::vector<double> smax(arc->npan, 0.0);
+    for (int i = 0; i < arc->n; ++i)
+      smax[i / arc->nper] = std::max(smax[i / arc->nper], arc->s[i]);
+    plan_near_panels(arc->npan, arc->nper, arc->xy.data(), arc->cgx.data(), arc->cgy.data(),
+                     arc->hmax, smax.data(), kmax, np, xy, skip, h);
+  } else {
+    double smax = 0.0;
+    for (double v : arc->s) smax = std::max(smax, v);
+    plan_near(arc->n, arc->xy.data(), arc->cgx, arc->cgy, arc->hmax, smax, kmax, np, xy, skip,
+              h);
+  }
   plan.np = np;
   plan.ntgt = (int)h.tgt.size();
   plan.nq = (int)h.wq.size();
@@ -110,6 +120,10 @@ int near_plan_build(fthms_ctx *ctx, const fthms_arc *arc, int np, const double *
     HIPCK(ctx, hipMemcpy(plan.d_xq, h.xq.data(), sizeof(double2) * plan.nq, hipMemcpyHostToDevice));
     HIPCK(ctx, hipMemcpy(plan.d_wq, h.wq.data(), sizeof(double) * plan.nq, hipMemcpyHostToDevice));
     HIPCK(ctx, hipMemcpy(plan.d_cq, h.cq.data(), sizeof(double) * plan.nq, hipMemcpyHostToDevice));
+    if (!h.pq.empty()) {
+      if ((rc = dev_alloc(ctx, (void **)&plan.d_pq, sizeof(int) * plan.nq))) return rc;
+      HIPCK(ctx, hipMemcpy(plan.d_pq, h.pq.data(), sizeof(int) * plan.nq, hipMemcpyHostToDevice));
+    }
   }
   return FTHMS_OK;
 }
@@ -151,13 +165,18 @@ static double eta_window(double t, double t0, double t1) {
   return std::exp(2.0 * std::exp(-1.0 / s) / (s - 1.0));
 }
 
+// End point x(-1) (side < 0) or x(+1) of an arc from its geometry
+// coefficients: the start of the first panel (s = -1) or the end of the
+// last (s = +1).
 static void arc_end(const fthms_arc *a, int side, double &x, double &y) {
   x = 0.0;
   y = 0.0;
-  for (int m = 0; m < a->n; ++m) {
+  const int n = a->nper;
+  const size_t off = side < 0 ? 0 : (size_t)(a->npan - 1) * n;
+  for (int m = 0; m < n; ++m) {
     const double sg = (side < 0 && (m & 1)) ? -1.0 : 1.0;
-    x += sg * a->cgx[m];
-    y += sg * a->cgy[m];
+    x += sg * a->cgx[off + m];
+    y += sg * a->cgy[off + m];
   }
 }
 
