@@ -178,6 +178,47 @@ def uneven_batch(fth, ctx, torch, steps, tol):
     return rec
 
 
+def kite_cavity(fth, ctx, reps=3, n_per=86):
+    """The kite cavity (4 arcs, 512 frequencies up to 80, M = 6, 64 interior
+    points, 2001 time samples) with single-panel arcs of N = 256 and with
+    composite-panel arcs (each arc cut at the ends of its truncated overlap,
+    three panels of n_per nodes): set-up time (tables, plans) and warm time
+    per run (all frequencies, all steps, fields and the time transform)."""
+    from workloads import kite_cavity_case
+    pb = kite_cavity_case()
+    om = np.asarray(pb.omegas, dtype=float)
+    w = np.full(om.size, om[1] - om[0])
+    w[0] *= 0.5
+    w[-1] *= 0.5
+    iv = np.array([a.curve.interval for a in pb.arcs])
+    rec = {"workload": "kite cavity, 4 arcs (120 deg, 30 deg overlaps), 512 frequencies on (0, 80], "
+                       "M = 6, 64 interior points, 2001 time samples"}
+    for name in ("single_panel", "panels"):
+        t0 = time.perf_counter()
+        if name == "panels":
+            brs = fth.tov_breaks(iv, None, pb.period)
+            arcs = [ctx.panel_arc_from_curve(a.curve, n_per, b) for a, b in zip(pb.arcs, brs)]
+        else:
+            arcs = [ctx.arc_from_curve(a.curve, a.n) for a in pb.arcs]
+        prob = fth.Problem(ctx, arcs, pb.incident, pb.obs, intervals=iv, M=pb.M)
+        U = prob.run(om)
+        ctx.freq_to_time(om, w, U, pb.times)
+        setup = time.perf_counter() - t0
+        ts = []
+        for _ in range(reps):
+            t1 = time.perf_counter()
+            U = prob.run(om)
+            ctx.freq_to_time(om, w, U, pb.times)
+            ts.append(time.perf_counter() - t1)
+        rec[name] = {"n_per_arc": arcs[0].n, "first_run_with_setup_s": round(setup, 3),
+                     "ms_per_run": round(1e3 * min(ts), 2),
+                     "solves_per_s": round(len(arcs) * om.size * pb.M / min(ts), 1)}
+        prob.close()
+        for a in arcs:
+            a.close()
+    return rec
+
+
 def serving(fth, workers=8, count=32, seed=5):
     """Serving loop: exterior scattering requests (1-3 obstacles of 4 arcs,
     n 32..96, 48..128 frequencies, time-domain stop 1e-8 within 100 steps)
@@ -234,6 +275,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-11,
                     help="refinement stop: predicted relative error (the metric's 1e-10 "
                          "with a 10x margin); every solve's error is measured")
+    ap.add_argument("--no-cavity", action="store_true",
+                    help="skip the kite cavity runs (single-panel and composite-panel arcs)")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving loop measurement (Poisson arrivals, p50/p99)")
     ap.add_argument("--no-uneven", action="store_true",
@@ -367,6 +410,10 @@ def main():
     if not args.no_uneven:
         uneven = uneven_batch(fth, ctx, torch, max(1, args.steps), args.tol)
 
+    cavity = None
+    if not args.no_cavity:
+        cavity = kite_cavity(fth, ctx)
+
     serve = None
     if not args.no_serving:
         serve = serving(fth)
@@ -414,6 +461,7 @@ def main():
                                     for n, v in r64["kt"].items()},
         "roofline": roof,
         "uneven_batch": uneven,
+        "kite_cavity": cavity,
         "serving": serve,
         "cpu_baseline": base,
     }

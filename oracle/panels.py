@@ -41,6 +41,7 @@ import numpy as np
 from . import nystrom as ny
 
 COV_NONE, COV_BOTH, COV_LEFT, COV_RIGHT = 0, 1, 2, 3
+_GL8 = np.polynomial.legendre.leggauss(8)
 
 
 # --------------------------------------------------------------------------
@@ -125,11 +126,11 @@ class PanelArc:
         out = self.y(p, s) - self.curve.x(t0)[0]
         small = np.abs(d) < 0.05
         if np.any(small):
-            g, w = np.polynomial.legendre.leggauss(8)
-            u = 0.5 * (g + 1.0)
+            g, w = _GL8
             ds = d[small]
-            mean = sum(0.5 * wq * self.curve.dx(t0[0] + uq * ds) for uq, wq in zip(u, w))
-            out[small] = ds[:, None] * mean
+            tt = t0[0] + np.outer(ds, 0.5 * (g + 1.0))
+            xd = self.curve.dx(tt.ravel()).reshape(tt.shape + (2,))
+            out[small] = ds[:, None] * np.einsum("mqk,q->mk", xd, 0.5 * w)
         return out
 
     def speed(self, p, s):
@@ -159,6 +160,19 @@ def _coef_matrix(phi):
     return C
 
 
+def chebyshev_T(s, n):
+    """[T_0(s), ..., T_{n-1}(s)] for points s in [-1, 1] (three-term
+    recurrence), shape [len(s), n]."""
+    s = np.asarray(s, dtype=float)
+    T = np.empty((s.size, n))
+    T[:, 0] = 1.0
+    if n > 1:
+        T[:, 1] = s
+    for k in range(2, n):
+        T[:, k] = 2.0 * s * T[:, k - 1] - T[:, k - 2]
+    return T
+
+
 def adaptive_gl_vec(f, a, b, breaks=(), tol=1e-14, order=16, max_rounds=200):
     """Integral over [a, b] of a vector-valued function f (f maps an array of
     points [q] to values [q, m]).  Each interval is integrated by an
@@ -183,17 +197,20 @@ def adaptive_gl_vec(f, a, b, breaks=(), tol=1e-14, order=16, max_rounds=200):
         return np.einsum("iq...,q->i...", fx, w) * r.reshape((-1,) + (1,) * (fx.ndim - 2))
 
     total = 0.0
+    whole = rule(lo, hi)
     for _ in range(max_rounds):
         if lo.size == 0:
             return total
         mid = 0.5 * (lo + hi)
-        whole = rule(lo, hi)
-        halves = rule(lo, mid) + rule(mid, hi)
+        left, right = rule(lo, mid), rule(mid, hi)
+        halves = left + right
         err = np.abs(halves - whole).reshape(lo.size, -1).max(axis=1)
         ok = (err <= tol * (hi - lo) / span) | (err <= 1e-3 * tol)
         ok |= (hi - lo) <= 1e-12 * span
         total = total + halves[ok].sum(axis=0)
+        # the halves of a bisected interval are its children's whole rules
         lo, hi, mid = lo[~ok], hi[~ok], mid[~ok]
+        whole = np.concatenate([left[~ok], right[~ok]])
         lo, hi = np.concatenate([lo, mid]), np.concatenate([mid, hi])
     raise RuntimeError("adaptive_gl_vec: no convergence")
 
@@ -209,7 +226,6 @@ def log_table(arc, tol=1e-14):
     nd = arc.nodes()
     N, n = nd["n"], arc.n
     C = _coef_matrix(arc.phi)
-    m = np.arange(n)
     W = np.empty((N, N))
     for i in range(N):
         yi = nd["y"][i]
@@ -224,8 +240,7 @@ def log_table(arc, tol=1e-14):
                 else:
                     d = arc.y(p, s) - yi
                 r = np.hypot(d[:, 0], d[:, 1])
-                T = np.cos(np.outer(np.arccos(np.clip(s, -1.0, 1.0)), m))
-                return np.log(np.maximum(r, 1e-300))[:, None] * T
+                return np.log(np.maximum(r, 1e-300))[:, None] * chebyshev_T(s, n)
 
             brk = (si,) if own else ()
             W[i, p * n:(p + 1) * n] = adaptive_gl_vec(f, -1.0, 1.0, brk, tol) @ C

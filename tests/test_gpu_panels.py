@@ -99,6 +99,24 @@ def test_panel_ms_disc(ctx, fth):
     assert rel(A[0], np.concatenate(ref["alpha_tot"])) < TOL
 
 
+def test_panel_ms_kite(ctx, fth):
+    """The four-arc kite (120 degree arcs, 30 degree overlaps) with panel
+    arcs of 3 x 32 nodes: a point source inside, M = 2."""
+    from workloads import small_kite_case
+    pb = small_kite_case(n=32, omegas=(6.0,), M=2, nobs=6)
+    pb.scheme = "panels"
+    say("panel ms kite n_per=32")
+    iv = np.array([a.curve.interval for a in pb.arcs])
+    brs = fth.tov_breaks(iv, None, pb.period)
+    arcs = [ctx.panel_arc_from_curve(a.curve, a.n, b) for a, b in zip(pb.arcs, brs)]
+    prob = fth.Problem(ctx, arcs, pb.incident, pb.obs, intervals=iv, M=pb.M)
+    om = np.real(np.asarray(pb.omegas)).astype(float)
+    U, A = prob.run(om, want_alpha=True)
+    ref = oms.run_frequency(oms.Layout(pb), om[0])
+    assert rel(U[0], ref["U"]) < TOL, rel(U[0], ref["U"])
+    assert rel(A[0], np.concatenate(ref["alpha_tot"])) < TOL
+
+
 def test_panel_error_paths(ctx, fth):
     curve = CircularArc(1.0, 0.0, 1.5)
     with pytest.raises(fth.FthmsError):
