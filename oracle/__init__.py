@@ -6,6 +6,8 @@ the frequency-domain FTH-MS hot path, written from the paper:
   nodes, weights, Nystrom matrix ........ ``oracle.nystrom``
   composite panels with changes of
   variables (eq. cov) .................... ``oracle.panels``
+  closed patches, combined-field
+  equation (Section 3.3) ................. ``oracle.closed``
   incident fields ....................... ``oracle.incident``
   multiple-scattering recursion ......... ``oracle.ms``
   frequency-to-time transform ........... ``oracle.transform``
@@ -20,4 +22,4 @@ against closed forms, textbook identities, brute-force quadrature or
 library routines (see the pin tests under tests/).  None is "parity
 unpinned".
 """
-from . import nystrom, incident, ms, panels, transform  # noqa: F401
+from . import closed, nystrom, incident, ms, panels, transform  # noqa: F401

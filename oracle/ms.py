@@ -24,6 +24,9 @@ Readings taken where the text is silent or loose:
     scatters onto every other one; the masking of eq. vtilde and the
     windows chi_j involve the neighbours on the same curve only, and an arc
     alone on its curve has chi = 1.
+  * A closed curve may also be one patch of its own (Section 3.3): its
+    density solves the combined-field equation and its field is
+    (D - i eta S) Psi (``oracle.closed``); chi = 1 and nothing is masked.
   * Discretisation: ``problem.scheme`` "cheb" is the single-panel
     weighted-Chebyshev scheme (``oracle.nystrom``); "panels" cuts each arc
     at the ends of its truncated overlap into three panels, each with the
@@ -36,6 +39,7 @@ import math
 
 import numpy as np
 
+from . import closed as cl
 from . import nystrom as ny
 from . import panels as pn
 from .incident import incident
@@ -77,12 +81,22 @@ class Layout:
                 self.nxt[j] = mem[(q + 1) % len(mem)]
                 self.prv[j] = mem[(q - 1) % len(mem)]
         self.scheme = getattr(problem, "scheme", "cheb")
-        if self.scheme == "panels":
-            self.parcs = [pn.PanelArc(a.curve, a.n, self.panel_breaks(j))
-                          for j, a in enumerate(problem.arcs)]
-            self.nodes = [pa.nodes() for pa in self.parcs]
-        else:
-            self.nodes = [ny.arc_nodes(a.curve, a.n) for a in problem.arcs]
+        self.closed = [bool(getattr(a.curve, "closed", False)) for a in problem.arcs]
+        for j in range(self.J):
+            if self.closed[j] and self.nxt[j] is not None:
+                raise ValueError("a closed patch is alone on its curve")
+        self.nodes = []
+        self.parcs = [None] * self.J
+        for j, a in enumerate(problem.arcs):
+            if self.closed[j]:
+                nd = cl.nodes(a.curve, a.n)
+                nd["t"] = nd["tau"]
+            elif self.scheme == "panels":
+                self.parcs[j] = pn.PanelArc(a.curve, a.n, self.panel_breaks(j))
+                nd = self.parcs[j].nodes()
+            else:
+                nd = ny.arc_nodes(a.curve, a.n)
+            self.nodes.append(nd)
         self._tables = {}
         self.tau = [c.parent_param(nd["t"]) for c, nd in zip(self.arcs,
                                                               self.nodes)]
@@ -114,6 +128,8 @@ class Layout:
 
     def assemble(self, j, k):
         """Matrix of arc j at wavenumber k in the problem's scheme."""
+        if self.closed[j]:
+            return cl.assemble(self.nodes[j], k)
         if self.scheme == "panels":
             if j not in self._tables:
                 self._tables[j] = pn.log_table(self.parcs[j])
@@ -122,6 +138,8 @@ class Layout:
 
     def field(self, j, k, z, alpha):
         """Potential of arc j's density at targets z."""
+        if self.closed[j]:
+            return cl.field(k, z, self.nodes[j], alpha)
         if self.scheme == "panels":
             return pn.field(k, z, self.nodes[j], alpha)
         return ny.field(k, z, self.arcs[j], self.nodes[j], alpha)

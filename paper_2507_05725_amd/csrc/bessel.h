@@ -119,4 +119,101 @@ FTHMS_HD void bessel_j0_y0(double z, double &j0, double &y0) {
   }
 }
 
+// ---- order one (the double-layer kernel of closed curves) ----------------
+//
+//   z < 1e-6     leading terms: J1 = z/2, Y1 = -2/(pi z) + (z/pi)(log(z/2)
+//                + gamma - 1/2)  (DLMF 10.8.1, 10.8.2 at n = 1)
+//   z < 16.5     the same backward recurrence; J1 from it, and
+//                Y1 = -Y0' = -(2/(pi z)) J0 + (2/pi)(log(z/2) + gamma) J1
+//                     + (2/pi) sum_k (-1)^k (J_{2k-1} - J_{2k+1}) / k
+//                (differentiating the Neumann series of Y0 term by term with
+//                J_n' = (J_{n-1} - J_{n+1})/2), summed as sum_k c_k J_{2k-1},
+//                c_1 = -1, c_k = (-1)^k (2k - 1) / (k (k - 1))
+//   z >= 16.5    Hankel's expansion at nu = 1 (DLMF 10.17.3, 10.17.4).
+
+// a_k(1) = prod_{j=1..k} (4 - (2j-1)^2) / (k! 8^k)   (DLMF 10.17.1 at nu = 1)
+constexpr HankelAsymCoef make_hankel_asym_coef1() {
+  HankelAsymCoef c{};
+  double a[28] = {};
+  a[0] = 1.0;
+  for (int k = 1; k < 28; ++k)
+    a[k] = a[k - 1] * (4.0 - (double)((2 * k - 1) * (2 * k - 1))) / (8.0 * k);
+  for (int k = 0; k < 14; ++k) {
+    c.p[k] = ((k & 1) ? -1.0 : 1.0) * a[2 * k];
+    c.q[k] = ((k & 1) ? -1.0 : 1.0) * a[2 * k + 1];
+  }
+  return c;
+}
+
+template <int NS>
+FTHMS_HD void bessel_miller01(double z, double &j0, double &j1, double &y0, double &y1) {
+  const double rz = 2.0 / z;
+  double jp1 = 0.0, jn = 1.0e-250, even = 0.0, neu = 0.0, odd = 0.0, j1u = 0.0;
+#pragma unroll
+  for (int n = NS; n >= 1; --n) {
+    const double jm1 = ((double)n * rz) * jn - jp1;
+    jp1 = jn;
+    jn = jm1;  // J_{n-1}, unnormalised
+    const int m = n - 1;
+    if (m > 0 && (m & 1) == 0) {
+      const int k = m >> 1;
+      even += jn;
+      neu += (((k & 1) ? -1.0 : 1.0) / (double)k) * jn;
+    }
+    if (m & 1) {
+      const int k = (m + 1) >> 1;  // m = 2k - 1
+      const double ck = (k == 1) ? -1.0
+                                 : ((k & 1) ? -1.0 : 1.0) * (double)(2 * k - 1) /
+                                       ((double)k * (double)(k - 1));
+      odd += ck * jn;
+      if (m == 1) j1u = jn;
+    }
+  }
+  const double inv = 1.0 / (jn + 2.0 * even);
+  j0 = jn * inv;
+  j1 = j1u * inv;
+  const double lp = bessel_logpart(z);
+  y0 = lp * j0 - (4.0 / kPi) * neu * inv;
+  y1 = -(2.0 / kPi) * j0 / z + lp * j1 + (2.0 / kPi) * odd * inv;
+}
+
+// J1 and Y1 from Hankel's expansion, phase z - 3pi/4:
+// cos(z - 3pi/4) = (sin z - cos z)/sqrt2, sin(z - 3pi/4) = -(sin z + cos z)/sqrt2.
+FTHMS_HD void bessel_asym1(double z, double &j1, double &y1) {
+  constexpr HankelAsymCoef c = make_hankel_asym_coef1();
+  const double iz = 1.0 / z;
+  const double w = iz * iz;
+  double P = c.p[13], Q = c.q[13];
+#pragma unroll
+  for (int k = 12; k >= 0; --k) {
+    P = P * w + c.p[k];
+    Q = Q * w + c.q[k];
+  }
+  Q *= iz;
+  const double s = sin(z), co = cos(z);
+  const double r2 = 0.70710678118654752440084436210484904;
+  const double cm = (s - co) * r2, sm = -(s + co) * r2;
+  const double f = sqrt((2.0 / kPi) * iz);
+  j1 = f * (P * cm - Q * sm);
+  y1 = f * (P * sm + Q * cm);
+}
+
+// J0, Y0, J1, Y1 at z > 0.
+FTHMS_HD void bessel_01(double z, double &j0, double &y0, double &j1, double &y1) {
+  if (z < 1.0e-6) {
+    const double q = 0.25 * z * z;
+    j0 = 1.0 - q;
+    y0 = bessel_logpart(z) * j0 + (2.0 / kPi) * q;
+    j1 = 0.5 * z;
+    y1 = -(2.0 / kPi) / z + (z / kPi) * (log(0.5 * z) + kEulerGamma - 0.5);
+  } else if (z < 8.0) {
+    bessel_miller01<32>(z, j0, j1, y0, y1);
+  } else if (z < kBesselAsymFrom) {
+    bessel_miller01<48>(z, j0, j1, y0, y1);
+  } else {
+    bessel_asym(z, j0, y0);
+    bessel_asym1(z, j1, y1);
+  }
+}
+
 }  // namespace fthms

@@ -56,3 +56,25 @@ def test_device_bessel_against_mpmath(probe):
                 abs(row[3] - j0), abs(row[4] - yh))
         worst = max(worst, float(e))
     assert worst < 1.5e-15
+
+
+def test_device_bessel_order_one_against_mpmath(probe):
+    """J1, Y1 (and J0, Y0 from the same routine) of the double-layer kernel:
+    absolute error, relative where |Y| > 1 (Y1 ~ -2/(pi z) at small z)."""
+    mp.mp.dps = 30
+    rng = np.random.default_rng(8)
+    z = np.concatenate([
+        np.geomspace(1e-9, 1e-5, 20),
+        np.array([1e-6 * (1 - 1e-12), 1e-6, 8.0 - 1e-12, 8.0, 16.5 - 1e-12, 16.5]),
+        rng.uniform(0.0, 20.0, 600) + 1e-3,
+        rng.uniform(20.0, 1500.0, 300)])
+    res = _run(probe, z)
+    worst = 0.0
+    for row in res:
+        zz = mp.mpf(row[0])
+        j0, y0 = mp.besselj(0, zz), mp.bessely(0, zz)
+        j1, y1 = mp.besselj(1, zz), mp.bessely(1, zz)
+        e = max(abs(row[5] - j0), abs(row[6] - y0) / max(1, abs(y0)),
+                abs(row[7] - j1), abs(row[8] - y1) / max(1, abs(y1)))
+        worst = max(worst, float(e))
+    assert worst < 2e-15

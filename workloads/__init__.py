@@ -13,7 +13,8 @@ hundreds to thousands of frequencies).  The paper prints no dataset; every
 workload here is synthetic and seeded.
 """
 from .curves import (Curve, Segment, CircularArc, KiteArc, EllipseArc,
-                     SineArc, kite_point, kite_deriv)
+                     SineArc, kite_point, kite_deriv, ClosedCurve, ClosedEllipse,
+                     ClosedKite)
 from .configs import (plain_segment_case, kite_cavity_case, uneven_batch_case,
                       fixed512_case, small_kite_case, disc_interior_case,
                       two_obstacle_case, two_arc_exterior_case, serving_requests, IncidentSpec, ArcSpec, MSProblem)

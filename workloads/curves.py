@@ -177,3 +177,71 @@ class SineArc(Curve):
         t = np.asarray(t, dtype=float)[..., None]
         doff = self.amp * np.pi * self.nu * np.cos(np.pi * self.nu * (1.0 + t))
         return 0.5 * self.ell * self.e + doff * self.n
+
+
+class ClosedCurve:
+    """Smooth closed curve x(tau), tau in [0, 2 pi), counter-clockwise, with
+    first and second derivatives (inputs for closed patches; vectorised)."""
+
+    closed = True
+    interval = (0.0, 2.0 * math.pi)
+
+    def x(self, tau):  # pragma: no cover - abstract
+        raise NotImplementedError
+
+    def dx(self, tau):  # pragma: no cover - abstract
+        raise NotImplementedError
+
+    def ddx(self, tau):  # pragma: no cover - abstract
+        raise NotImplementedError
+
+    def parent_param(self, tau):
+        return np.asarray(tau, dtype=float)
+
+
+class ClosedEllipse(ClosedCurve):
+    """(a cos tau, b sin tau) rotated by ``rot`` about ``center``."""
+
+    def __init__(self, a, b, center=(0.0, 0.0), rot=0.0):
+        self.ea, self.eb = float(a), float(b)
+        self.center = np.asarray(center, dtype=float)
+        self.rot = float(rot)
+
+    def _rot(self, px, py):
+        c, s = math.cos(self.rot), math.sin(self.rot)
+        return _stack(c * px - s * py, s * px + c * py)
+
+    def x(self, tau):
+        tau = np.asarray(tau, dtype=float)
+        return self.center + self._rot(self.ea * np.cos(tau), self.eb * np.sin(tau))
+
+    def dx(self, tau):
+        tau = np.asarray(tau, dtype=float)
+        return self._rot(-self.ea * np.sin(tau), self.eb * np.cos(tau))
+
+    def ddx(self, tau):
+        tau = np.asarray(tau, dtype=float)
+        return self._rot(-self.ea * np.cos(tau), -self.eb * np.sin(tau))
+
+
+class ClosedKite(ClosedCurve):
+    """The kite (cos t + 0.65 cos 2t - 0.65, 1.5 sin t), scaled, rotated and
+    shifted."""
+
+    def __init__(self, scale=1.0, center=(0.0, 0.0), rot=0.0):
+        self.scale = float(scale)
+        self.center = tuple(float(v) for v in center)
+        self.rot = float(rot)
+
+    def x(self, tau):
+        return kite_point(tau, self.scale, self.center, self.rot)
+
+    def dx(self, tau):
+        return kite_deriv(tau, self.scale, self.rot)
+
+    def ddx(self, tau):
+        tau = np.asarray(tau, dtype=float)
+        px = -np.cos(tau) - 2.6 * np.cos(2.0 * tau)
+        py = -1.5 * np.sin(tau)
+        c, s = math.cos(self.rot), math.sin(self.rot)
+        return _stack(self.scale * (c * px - s * py), self.scale * (s * px + c * py))
