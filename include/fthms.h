@@ -175,6 +175,22 @@ int fthms_panel_nodes(int npan, const double *breaks, const int *kinds, int n_pe
 int fthms_arc_create_panels(fthms_ctx *ctx, int npan, const double *breaks, const int *kinds,
                             int n_per, const double *xy, const double *dxy, fthms_arc **out);
 
+/* ---- closed patches (Section 3.3, eqs. FDsolk-closed, FDBIEk-closed) -------
+ *
+ * A closed curve treated as one patch: its density solves the combined-field
+ * equation (1/2 I + K - i eta V) Psi = G on the curve, with eta = k, and its
+ * field is (D - i eta S) Psi outside (D, K double-layer potential/operator
+ * with the outward normal).  Nystrom method for 2pi-periodic kernels with a
+ * logarithmic singularity on n equispaced nodes (n even, 4..1024): sample a
+ * counter-clockwise parametrisation x(tau) at tau_j = 2 pi j / n, giving
+ * xy, dxy, ddxy [n][2] = x, x', x''.  Densities are per unit length at the
+ * nodes.  Such an arc works in fthms_solve, fthms_rhs, fthms_eval_field and
+ * problems (where it must be alone in its group: chi = 1, nothing masked);
+ * fields are the trapezoid rule and refuse targets closer than 5 node
+ * spacings (FTHMS_EINVAL_DATA).  Not for batches. */
+int fthms_closed_create(fthms_ctx *ctx, int n, const double *xy, const double *dxy,
+                        const double *ddxy, fthms_arc **out);
+
 /* Panel breakpoints of the arcs of cyclic partitions (the layout of
  * fthms_problem_desc: interval [narcs][2] on the parent curve of period
  * `period`, group [narcs] or NULL for one curve): arc j is cut where the

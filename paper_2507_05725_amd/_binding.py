@@ -79,6 +79,7 @@ _SIGS = {
     "fthms_arc_create_panels": ([_vp, _i, _vp, _vp, _i, _vp, _vp, C.POINTER(_vp)], _i),
     "fthms_arc_panel_table": ([_vp, _vp, _vp], _i),
     "fthms_tov_breaks": ([_i, _vp, _vp, _d, _vp, _vp], _i),
+    "fthms_closed_create": ([_vp, _i, _vp, _vp, _vp, C.POINTER(_vp)], _i),
     "fthms_solve": ([_vp, _vp, _i, _vp, _vp, _vp, _i, _d, _vp, _vp], _i),
     "fthms_solve_dev": ([_vp, _vp, _i, _vp, _vp, _vp, _i, _d, _vp, _vp], _i),
     "fthms_rhs": ([_vp, _vp, _i, _vp, C.POINTER(Incident), _vp], _i),
@@ -238,6 +239,11 @@ class Context:
         t = cheb_nodes(n)
         return Arc(self, curve.x(t), curve.dx(t))
 
+    def closed_from_curve(self, curve, n):
+        """Closed patch sampled at tau_j = 2 pi j / n (curve: x, dx, ddx)."""
+        tau = 2.0 * np.pi * np.arange(n) / n
+        return Arc(self, curve.x(tau), curve.dx(tau), ddxy=curve.ddx(tau))
+
     def panel_arc_from_curve(self, curve, n_per, breaks, kinds=None):
         """Composite-panel arc sampled at panel_nodes (default: the two-sided
         change of variables on every panel)."""
@@ -328,16 +334,21 @@ class Context:
 
 
 class Arc:
-    """An arc from samples at fthms_cheb_nodes (one weighted panel), or with
+    """An arc from samples at fthms_cheb_nodes (one weighted panel); with
     ``breaks``/``kinds``/``n_per`` a composite-panel arc sampled at
-    panel_nodes(breaks, kinds, n_per)."""
+    panel_nodes(breaks, kinds, n_per); with ``ddxy`` a closed patch sampled at
+    tau_j = 2 pi j / n."""
 
-    def __init__(self, ctx, xy, dxy, breaks=None, kinds=None, n_per=None):
+    def __init__(self, ctx, xy, dxy, breaks=None, kinds=None, n_per=None, ddxy=None):
         xy = np.ascontiguousarray(xy, dtype=np.float64)
         dxy = np.ascontiguousarray(dxy, dtype=np.float64)
         n = xy.shape[0]
         h = C.c_void_p()
-        if breaks is None:
+        if ddxy is not None:
+            ddxy = np.ascontiguousarray(ddxy, dtype=np.float64)
+            ctx.check(_lib.fthms_closed_create(ctx.h, n, _ptr(xy), _ptr(dxy), _ptr(ddxy),
+                                               C.byref(h)), "closed_create")
+        elif breaks is None:
             ctx.check(_lib.fthms_arc_create(ctx.h, n, _ptr(xy), _ptr(dxy), C.byref(h)),
                       "arc_create")
         else:

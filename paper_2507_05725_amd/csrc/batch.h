@@ -207,9 +207,9 @@ int fthms_batch_create(fthms_ctx *ctx, int nb, const fthms_arc *const *arcs, con
   for (int i = 0; i < nb; ++i) {
     if (!arcs[i] || arcs[i]->ctx != ctx)
       return fail(ctx, FTHMS_EINVAL, "solve " + std::to_string(i) + ": arc missing or of another context");
-    if (arcs[i]->d_w)
-      return fail(ctx, FTHMS_EINVAL,
-                  "solve " + std::to_string(i) + ": composite-panel arcs are not batched");
+    if (arcs[i]->d_w || arcs[i]->closed)
+      return fail(ctx, FTHMS_EINVAL, "solve " + std::to_string(i) +
+                                         ": composite-panel arcs and closed patches are not batched");
     if (!(k[i] > 0.0) || !std::isfinite(k[i]))
       return fail(ctx, FTHMS_EINVAL_DATA, "solve " + std::to_string(i) + ": wavenumber must be > 0");
     int rc = to_incident(ctx, &inc[i], incd[i]);

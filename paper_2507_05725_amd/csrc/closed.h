@@ -1,0 +1,132 @@
+// Closed curves as single patches (Section 3.3, eqs. FDsolk-closed and
+// FDBIEk-closed): the combined-field equation
+//     (1/2 I + K - i eta V) Psi = G   on Gamma,   field (D - i eta S) Psi,
+// eta = k, by the Nystrom method for 2pi-periodic kernels with a logarithmic
+// singularity (the method the paper cites for closed curves).  N = 2n nodes
+// tau_j = 2 pi j / N on a counter-clockwise parametrisation; with
+// q = x2'(tau_j)(x1(t_i) - x1(tau_j)) - x1'(tau_j)(x2(t_i) - x2(tau_j)) and
+// r = |x(t_i) - x(tau_j)|:
+//   K  = (ik/4) H1(kr) q/r,       K1 = -(k/4pi) J1(kr) q/r,
+//   V  = (i/4) H0(kr) |x'_j|,     V1 = -(1/4pi) J0(kr) |x'_j|,
+//   K2 = K - K1 L_ij, V2 = V - V1 L_ij,  L_ij = log(4 sin^2((t_i - tau_j)/2)),
+// diagonal K1 = 0, K2 = (x2' x1'' - x1' x2'') / (4 pi |x'|^2),
+// V1 = -|x'|/(4pi), V2 = |x'| (i/4 - (log(k |x'|/2) + gamma)/(2pi));
+//   A_ij = delta_ij / 2 + R_{i-j} (K1 - i eta V1) + (pi/n)(K2 - i eta V2),
+// with the weights of the logarithmic quadrature
+//   R_d = -(2pi/n) sum_{m=1}^{n-1} cos(m d pi/n)/m - (pi/n^2) cos(d pi)
+// (they depend on (i - j) mod N only: one table of N values per curve, as
+// are L_d).  The field is the trapezoid rule for (D - i eta S) Psi, valid
+// for targets a few node spacings away; closer targets are refused.
+#pragma once
+
+#include "bessel.h"
+#include "common.h"
+
+namespace fthms {
+
+// One block per 32x32 tile of the full matrix (not symmetric) and wavenumber.
+template <bool W32>
+__global__ __launch_bounds__(256) void cfie_assemble_kernel(
+    const double2 *__restrict__ y, const double2 *__restrict__ dy,
+    const double *__restrict__ Rw, const double *__restrict__ Lw,
+    const double *__restrict__ kdiag, int N, const double *__restrict__ kvec,
+    double2 *__restrict__ A64, float2 *__restrict__ A32, long long mstride) {
+  const int b = blockIdx.z;
+  const double k = kvec[b], eta = k;
+  const int i = blockIdx.x * 32 + (threadIdx.x & 31);
+  const double h = 2.0 * kPi / N;  // pi / n
+  double2 *A = A64 + (long long)b * mstride;
+  float2 *Af = W32 ? A32 + (long long)b * mstride : nullptr;
+  if (i >= N) return;
+  const double2 yi = y[i];
+#pragma unroll
+  for (int q4 = 0; q4 < 4; ++q4) {
+    const int j = blockIdx.y * 32 + (threadIdx.x >> 5) + 8 * q4;
+    if (j >= N) continue;
+    const double2 dj = dy[j];
+    const double sp = sqrt(dj.x * dj.x + dj.y * dj.y);
+    int d = i - j;
+    if (d < 0) d += N;
+    double k1, v1, k2r, k2i, v2r, v2i;
+    if (i == j) {
+      k1 = 0.0;
+      v1 = -sp / (4.0 * kPi);
+      k2r = kdiag[i];
+      k2i = 0.0;
+      v2r = -sp * (log(0.5 * k * sp) + kEulerGamma) / (2.0 * kPi);
+      v2i = 0.25 * sp;
+    } else {
+      const double2 yj = y[j];
+      const double ex = yi.x - yj.x, ey = yi.y - yj.y;
+      const double r = sqrt(ex * ex + ey * ey);
+      const double q = dj.y * ex - dj.x * ey;
+      double j0, y0, j1, y1;
+      bessel_01(k * r, j0, y0, j1, y1);
+      const double L = Lw[d];
+      const double qr = q / r;
+      k1 = -(k / (4.0 * kPi)) * j1 * qr;
+      v1 = -(sp / (4.0 * kPi)) * j0;
+      // K = (k/4)(-Y1 + i J1) q/r,  V = (|x'|/4)(-Y0 + i J0)
+      k2r = -0.25 * k * y1 * qr - k1 * L;
+      k2i = 0.25 * k * j1 * qr;
+      v2r = -0.25 * sp * y0 - v1 * L;
+      v2i = 0.25 * sp * j0;
+    }
+    const double R = Rw[d];
+    // R (K1 - i eta V1) + h (K2 - i eta V2), K1, V1 real
+    double ar = R * k1 + h * (k2r + eta * v2i);
+    const double ai = -R * eta * v1 + h * (k2i - eta * v2r);
+    if (i == j) ar += 0.5;
+    const double2 v = make_double2(ar, ai);
+    A[i + (long long)j * N] = v;
+    if (W32) Af[i + (long long)j * N] = make_float2((float)v.x, (float)v.y);
+  }
+}
+
+// (D - i eta S)[Psi] at targets by the trapezoid rule: one block per 256
+// targets and wavenumber; nodes, tangents and density in LDS.
+//   kernel = (k/4)(q/r)(-Y1 + i J1) + (eta |x'_j| / 4)(J0 + i Y0),
+//   q = x2'_j (z1 - y1_j) - x1'_j (z2 - y2_j).
+__global__ __launch_bounds__(256) void closed_field_kernel(
+    const double2 *__restrict__ ynodes, const double2 *__restrict__ dy, int N,
+    const double *__restrict__ kvec, const double2 *__restrict__ psi, long long pstride,
+    const double2 *__restrict__ pts, int np, const unsigned char *__restrict__ cls,
+    double2 *__restrict__ U, long long ustride, int accumulate) {
+  __shared__ double2 sy[1024], sd[1024], sp[1024];
+  const int b = blockIdx.y;
+  for (int j = threadIdx.x; j < N; j += 256) {
+    sy[j] = ynodes[j];
+    sd[j] = dy[j];
+    sp[j] = psi[(long long)b * pstride + j];
+  }
+  __syncthreads();
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= np) return;
+  if (cls && cls[p] != 1) return;
+  const double k = kvec[b], eta = k;
+  const double2 z = pts[p];
+  double accr = 0.0, acci = 0.0;
+  for (int j = 0; j < N; ++j) {
+    const double ex = z.x - sy[j].x, ey = z.y - sy[j].y;
+    const double r = sqrt(ex * ex + ey * ey);
+    const double q = sd[j].y * ex - sd[j].x * ey;
+    const double s = sqrt(sd[j].x * sd[j].x + sd[j].y * sd[j].y);
+    double j0, y0, j1, y1;
+    bessel_01(k * r, j0, y0, j1, y1);
+    const double a = 0.25 * k * q / r, c = 0.25 * eta * s;
+    const double kr = -a * y1 + c * j0, ki = a * j1 + c * y0;
+    const double2 w = sp[j];
+    accr += kr * w.x - ki * w.y;
+    acci += kr * w.y + ki * w.x;
+  }
+  const double h = 2.0 * kPi / N;
+  double2 *u = U + (long long)b * ustride + p;
+  if (accumulate) {
+    const double2 o = *u;
+    *u = make_double2(o.x + h * accr, o.y + h * acci);
+  } else {
+    *u = make_double2(h * accr, h * acci);
+  }
+}
+
+}  // namespace fthms

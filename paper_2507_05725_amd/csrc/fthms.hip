@@ -19,6 +19,7 @@
 #include "nearfield.h"
 #include "panel.h"
 #include "panels.h"
+#include "closed.h"
 
 using namespace fthms;
 
@@ -69,6 +70,11 @@ struct fthms_arc {
   double *d_G = nullptr;
   double *d_cos = nullptr;  // [nper][nper] cos(m theta_j), row j
   double *d_w = nullptr;    // composite-panel arcs: Fejer weights
+  // closed patches (combined-field equation): tangents, log-quadrature
+  // weights R_d and log(4 sin^2(pi d / N)), diagonal of K2
+  bool closed = false;
+  double2 *d_dy = nullptr;
+  double *d_R = nullptr, *d_L = nullptr, *d_kd = nullptr;
   size_t bytes = 0;
 };
 
@@ -558,6 +564,78 @@ int fthms_arc_panel_table(const fthms_arc *arc, double *W, double *w) {
   return FTHMS_OK;
 }
 
+int fthms_closed_create(fthms_ctx *ctx, int n, const double *xy, const double *dxy,
+                        const double *ddxy, fthms_arc **out) {
+  if (!ctx || !xy || !dxy || !ddxy || !out) return fail(ctx, FTHMS_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (n < 4 || n > kMaxN || (n & 1))
+    return fail(ctx, FTHMS_EINVAL, "closed patch: node count must be even, in [4, 1024]");
+  for (int i = 0; i < 2 * n; ++i)
+    if (!std::isfinite(xy[i]) || !std::isfinite(dxy[i]) || !std::isfinite(ddxy[i]))
+      return fail(ctx, FTHMS_EINVAL_DATA, "non-finite closed-curve sample");
+  fthms_arc *arc = new (std::nothrow) fthms_arc;
+  if (!arc) return fail(ctx, FTHMS_ENOMEM, "host allocation failed");
+  arc->ctx = ctx;
+  arc->n = n;
+  arc->nper = n;
+  arc->closed = true;
+  arc->xy.assign(xy, xy + 2 * n);
+  arc->dxy.assign(dxy, dxy + 2 * n);
+  arc->theta.resize(n);
+  arc->t.resize(n);
+  arc->s.resize(n);
+  std::vector<double> kd(n), R(n), L(n, 0.0);
+  double hmax = 0.0;
+  for (int i = 0; i < n; ++i) {
+    arc->theta[i] = 2.0 * kPi * i / n;
+    arc->t[i] = -1.0 + (2.0 * i + 1.0) / n;  // parameter position, for bookkeeping only
+    const double d1 = dxy[2 * i], d2 = dxy[2 * i + 1];
+    const double s2 = d1 * d1 + d2 * d2;
+    arc->s[i] = std::sqrt(s2);
+    if (!(s2 > 0.0)) {
+      delete arc;
+      return fail(ctx, FTHMS_EINVAL_DATA, "vanishing speed |x'| at a node");
+    }
+    kd[i] = (d2 * ddxy[2 * i] - d1 * ddxy[2 * i + 1]) / (4.0 * kPi * s2);
+    const int nx = (i + 1) % n;
+    const double h = std::hypot(xy[2 * nx] - xy[2 * i], xy[2 * nx + 1] - xy[2 * i + 1]);
+    if (!(h > 0.0)) {
+      delete arc;
+      return fail(ctx, FTHMS_EINVAL_DATA, "coincident consecutive nodes");
+    }
+    hmax = std::max(hmax, h);
+  }
+  arc->hmax = hmax;
+  // R_d = -(2pi/m) sum_{l=1}^{m-1} cos(l d pi/m)/l - (pi/m^2) cos(d pi), m = n/2
+  const int m = n / 2;
+  for (int d = 0; d < n; ++d) {
+    double acc = 0.0;
+    for (int l = m - 1; l >= 1; --l) acc += std::cos(kPi * (double)((long long)l * d % n) / m) / l;
+    R[d] = -(2.0 * kPi / m) * acc - (kPi / ((double)m * m)) * ((d & 1) ? -1.0 : 1.0);
+    if (d) L[d] = std::log(4.0 * std::pow(std::sin(kPi * d / n), 2));
+  }
+  int rc;
+  arc->bytes = sizeof(double2) * 2 * n + sizeof(double) * 3 * n;
+  if ((rc = dev_alloc(ctx, (void **)&arc->d_y, sizeof(double2) * n)) ||
+      (rc = dev_alloc(ctx, (void **)&arc->d_dy, sizeof(double2) * n)) ||
+      (rc = dev_alloc(ctx, (void **)&arc->d_R, sizeof(double) * n)) ||
+      (rc = dev_alloc(ctx, (void **)&arc->d_L, sizeof(double) * n)) ||
+      (rc = dev_alloc(ctx, (void **)&arc->d_kd, sizeof(double) * n))) {
+    fthms_arc_destroy(arc);
+    return rc;
+  }
+  if (hipMemcpy(arc->d_y, xy, sizeof(double2) * n, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(arc->d_dy, dxy, sizeof(double2) * n, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(arc->d_R, R.data(), sizeof(double) * n, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(arc->d_L, L.data(), sizeof(double) * n, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(arc->d_kd, kd.data(), sizeof(double) * n, hipMemcpyHostToDevice) != hipSuccess) {
+    fthms_arc_destroy(arc);
+    return fail(ctx, FTHMS_EDEVICE, "hipMemcpy of the closed-patch tables failed");
+  }
+  *out = arc;
+  return FTHMS_OK;
+}
+
 int fthms_arc_destroy(fthms_arc *arc) {
   if (!arc) return FTHMS_EINVAL;
   fthms_ctx *ctx = arc->ctx;
@@ -566,6 +644,10 @@ int fthms_arc_destroy(fthms_arc *arc) {
     dev_free(ctx, arc->d_G, sizeof(double) * (size_t)arc->n * arc->n);
     dev_free(ctx, arc->d_cos, sizeof(double) * (size_t)arc->nper * arc->nper);
     dev_free(ctx, arc->d_w, sizeof(double) * arc->n);
+    dev_free(ctx, arc->d_dy, sizeof(double2) * arc->n);
+    dev_free(ctx, arc->d_R, sizeof(double) * arc->n);
+    dev_free(ctx, arc->d_L, sizeof(double) * arc->n);
+    dev_free(ctx, arc->d_kd, sizeof(double) * arc->n);
   }
   delete arc;
   return FTHMS_OK;
@@ -812,6 +894,18 @@ static int assemble_launch(fthms_ctx *ctx, const fthms_arc *arc, const double *k
   const int T = (N + 31) / 32;
   dim3 g(T * (T + 1) / 2, count), b(256);
   const long long ms = (long long)N * N;
+  if (arc->closed) {
+    dim3 gc(T, T, count);
+    if (A32)
+      cfie_assemble_kernel<true><<<gc, b, 0, ctx->stream>>>(arc->d_y, arc->d_dy, arc->d_R,
+                                                            arc->d_L, arc->d_kd, N, k_dev, A64,
+                                                            A32, ms);
+    else
+      cfie_assemble_kernel<false><<<gc, b, 0, ctx->stream>>>(arc->d_y, arc->d_dy, arc->d_R,
+                                                             arc->d_L, arc->d_kd, N, k_dev, A64,
+                                                             nullptr, ms);
+    return check_launch(ctx, "cfie_assemble_kernel");
+  }
   if (arc->d_w) {
     if (A32)
       assemble_kernel<true, true><<<g, b, 0, ctx->stream>>>(arc->d_y, arc->d_G, N, k_dev, A64,
@@ -1034,6 +1128,12 @@ int field_dev_impl(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double *k
                    const NearPlan &plan, double2 *U, long long ustride, int accumulate) {
   if (nk == 0 || np == 0) return FTHMS_OK;
   dim3 g((np + kFieldThreads - 1) / kFieldThreads, nk);
+  if (arc->closed) {
+    closed_field_kernel<<<g, 256, 0, ctx->stream>>>(arc->d_y, arc->d_dy, arc->n, k_dev, alpha,
+                                                   astride, pts_dev, np, plan.d_cls, U, ustride,
+                                                   accumulate);
+    return check_launch(ctx, "closed_field_kernel");
+  }
   field_far_kernel<<<g, kFieldThreads, 0, ctx->stream>>>(arc->d_y, arc->n, arc->d_w, k_dev,
                                                         alpha, astride, pts_dev, np, plan.d_cls,
                                                         U, ustride, accumulate);

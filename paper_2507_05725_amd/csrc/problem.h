@@ -89,7 +89,22 @@ void near_plan_free(fthms_ctx *ctx, NearPlan &p) {
 int near_plan_build(fthms_ctx *ctx, const fthms_arc *arc, int np, const double *xy,
                     NearPlan &plan, const unsigned char *skip, double kmax) {
   NearPlanHost h;
-  if (arc->d_w) {
+  if (arc->closed) {
+    // trapezoid rule only: every target must lie a few node spacings away
+    h.cls.assign(np, 0);
+    h.qoff.assign(1, 0);
+    const double rad = 5.0 * arc->hmax;
+    for (int p = 0; p < np; ++p) {
+      if (skip && skip[p]) continue;
+      double dmin = 1e300;
+      for (int j = 0; j < arc->n; ++j)
+        dmin = std::min(dmin, std::hypot(xy[2 * p] - arc->xy[2 * j], xy[2 * p + 1] - arc->xy[2 * j + 1]));
+      if (!(dmin >= rad))
+        return fail(ctx, FTHMS_EINVAL_DATA,
+                    "target closer than 5 node spacings to a closed patch (trapezoid rule only)");
+      h.cls[p] = 1;
+    }
+  } else if (arc->d_w) {
     std::vector<double> smax(arc->npan, 0.0);
     for (int i = 0; i < arc->n; ++i)
       smax[i / arc->nper] = std::max(smax[i / arc->nper], arc->s[i]);
@@ -278,6 +293,11 @@ int fthms_problem_create(fthms_ctx *ctx, const fthms_problem_desc *d, fthms_prob
     pb->nxt[j] = mem[(pos + 1) % sz];
     pb->prv[j] = mem[(pos + sz - 1) % sz];
   }
+  for (int j = 0; j < J; ++j)
+    if (pb->arcs[j]->closed && pb->nxt[j] >= 0) {
+      fthms_problem_destroy(pb);
+      return fail(ctx, FTHMS_EINVAL, "a closed patch must be alone in its group");
+    }
   if (J > 1) {
     // chi_j at the nodes (eq. POU1, chord reading) and overlap masks
     pb->d_chi.assign(J, nullptr);

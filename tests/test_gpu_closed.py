@@ -1,0 +1,111 @@
+"""GPU parity of closed patches (Section 3.3, eqs. FDsolk-closed,
+FDBIEk-closed): the combined-field Nystrom solve and field through the C-ABI
+against ``oracle.closed``, alone and inside multiple-scattering problems
+(two closed obstacles; a closed obstacle beside one split into open arcs).
+
+Bar: relative L2 error <= 1e-10 per solve, field and summed density, in FP64
+and in the FP32-refined form."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import closed as ocl
+from oracle import incident as oinc
+from oracle import ms as oms
+from workloads import (ClosedEllipse, ClosedKite, IncidentSpec, closed_obstacles_case)
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def say(*a):
+    print("[gpu-case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def fth():
+    import paper_2507_05725_amd as m  # raises if the HIP library is missing
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(fth):
+    return fth.Context(0)
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
+
+
+@pytest.mark.parametrize("curve,n", [(ClosedEllipse(1.0, 0.6, (0.2, -0.1), 0.3), 64),
+                                     (ClosedKite(1.0), 128), (ClosedKite(1.0), 250)],
+                         ids=["ellipse64", "kite128", "kite250"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_closed_solve_and_field(ctx, fth, curve, n, prec):
+    """Point source inside: solve and far field against the oracle, and the
+    field against the exact -u^i outside (resolved sizes)."""
+    spec = IncidentSpec("point", z0=(0.05, 0.1), sigma=0.0)
+    ks = np.array([2.0, 7.5, 11.0])
+    say("closed solve", n, "prec", prec)
+    arc = ctx.closed_from_curve(curve, n)
+    rhs = ctx.rhs(arc, ks, spec)
+    psi, iters, relres = ctx.solve(arc, ks, rhs, prec)
+    nd = ocl.nodes(curve, n)
+    z = np.array([[3.0 * math.cos(a), 3.0 * math.sin(a)] for a in np.linspace(0, 6, 8)])
+    U = ctx.eval_field(arc, ks, psi, z)
+    for i, k in enumerate(ks):
+        b = -oinc.incident(spec, k, nd["y"])
+        assert rel(rhs[i], b) < 1e-14
+        ref = np.linalg.solve(ocl.assemble(nd, k), b)
+        assert rel(psi[i], ref) < TOL, (k, rel(psi[i], ref))
+        Uref = ocl.field(k, z, nd, ref)
+        assert rel(U[i], Uref) < TOL, (k, rel(U[i], Uref))
+        if n >= 128:
+            ui = oinc.incident(spec, k, z)
+            assert rel(U[i], -ui) < 1e-11
+
+
+@pytest.mark.parametrize("mixed", [False, True], ids=["two_closed", "closed_and_arcs"])
+def test_closed_ms_problem(ctx, fth, mixed):
+    """Exterior MS with closed patches: fields and summed densities of the
+    GPU recursion against the oracle's (96 nodes per closed patch: the
+    obstacles are 0.49 apart, beyond 5 node spacings)."""
+    pb = closed_obstacles_case(n=96, omegas=(5.5,), M=4, mixed=mixed)
+    say("closed ms mixed" if mixed else "closed ms two closed")
+    arcs = []
+    for a in pb.arcs:
+        if getattr(a.curve, "closed", False):
+            arcs.append(ctx.closed_from_curve(a.curve, a.n))
+        else:
+            arcs.append(ctx.arc_from_curve(a.curve, a.n))
+    iv = np.array([a.curve.interval for a in pb.arcs])
+    prob = fth.Problem(ctx, arcs, pb.incident, pb.obs, intervals=iv, M=pb.M,
+                       groups=[a.group for a in pb.arcs])
+    om = np.real(np.asarray(pb.omegas)).astype(float)
+    U, A = prob.run(om, want_alpha=True)
+    ref = oms.run_frequency(oms.Layout(pb), om[0])
+    assert rel(U[0], ref["U"]) < TOL, rel(U[0], ref["U"])
+    assert rel(A[0], np.concatenate(ref["alpha_tot"])) < TOL
+
+
+def test_closed_error_paths(ctx, fth):
+    curve = ClosedEllipse(1.0, 0.6)
+    arc = ctx.closed_from_curve(curve, 32)
+    psi = np.ones((1, 32), dtype=complex)
+    # a target on the curve: refused (trapezoid rule only)
+    with pytest.raises(fth.FthmsError):
+        ctx.eval_field(arc, np.array([3.0]), psi, np.array([[1.0, 0.0]]))
+    # odd node count
+    tau = 2 * np.pi * np.arange(31) / 31
+    with pytest.raises(fth.FthmsError):
+        fth.Arc(ctx, curve.x(tau), curve.dx(tau), ddxy=curve.ddx(tau))
+    # not for batches
+    with pytest.raises(fth.FthmsError):
+        fth.Batch(ctx, [arc], np.array([3.0]), [IncidentSpec("plane", theta=0.1)])
+    # a closed patch shares its group with nobody
+    other = ctx.closed_from_curve(ClosedKite(0.3, (3.0, 0.0)), 32)
+    with pytest.raises(fth.FthmsError):
+        fth.Problem(ctx, [arc, other], IncidentSpec("plane"), np.array([[5.0, 5.0]]),
+                    intervals=np.array([[0, 2 * np.pi]] * 2), M=2, groups=[0, 0])

@@ -17,11 +17,13 @@ from .curves import (Curve, Segment, CircularArc, KiteArc, EllipseArc,
                      ClosedKite)
 from .configs import (plain_segment_case, kite_cavity_case, uneven_batch_case,
                       fixed512_case, small_kite_case, disc_interior_case,
-                      two_obstacle_case, two_arc_exterior_case, serving_requests, IncidentSpec, ArcSpec, MSProblem)
+                      two_obstacle_case, two_arc_exterior_case, serving_requests, IncidentSpec, ArcSpec, MSProblem,
+                      closed_obstacles_case)
 
 __all__ = [
     "Curve", "Segment", "CircularArc", "KiteArc", "EllipseArc", "SineArc",
-    "kite_point", "kite_deriv",
+    "kite_point", "kite_deriv", "ClosedCurve", "ClosedEllipse", "ClosedKite",
+    "closed_obstacles_case",
     "plain_segment_case", "kite_cavity_case", "uneven_batch_case",
     "fixed512_case", "small_kite_case", "disc_interior_case",
     "two_obstacle_case", "two_arc_exterior_case", "serving_requests", "IncidentSpec", "ArcSpec", "MSProblem",

@@ -133,6 +133,24 @@ def two_obstacle_case(n=32, omegas=(5.0 + 2.0j,), M=8, nobs=8, times=None):
                      name="two_obstacles_n%d" % n)
 
 
+def closed_obstacles_case(n=64, omegas=(5.0 + 2.0j,), M=10, nobs=8, mixed=False, n_arc=32):
+    """Exterior problem with two obstacles treated as closed patches (the
+    combined-field option of Section 3.3): an ellipse and a scaled kite, a
+    point source inside the ellipse (exact scattered field -u^i outside).
+    With ``mixed`` the kite is split into 4 overlapping arcs of n_arc nodes
+    instead, so closed and open patches interact."""
+    from .curves import ClosedEllipse, ClosedKite
+    arcs = [ArcSpec(ClosedEllipse(0.8, 0.5, (-1.0, 0.0), 0.3), n, group=0)]
+    if mixed:
+        arcs += _kite_arcs(n_arc, scale=0.5, center=(1.2, 0.3), rot=-0.4, group=1)
+    else:
+        arcs.append(ArcSpec(ClosedKite(0.5, (1.2, 0.3), -0.4), n, group=1))
+    return MSProblem(arcs=arcs,
+                     incident=IncidentSpec("point", z0=(-1.05, 0.1), sigma=0.0),
+                     omegas=np.asarray(omegas), M=M, obs=_circle_points(nobs, 3.0),
+                     times=np.zeros(0), name="closed_obstacles_n%d" % n)
+
+
 def _inside_polygon(pts, poly):
     """Even-odd ray casting (input helper for sampling interior points)."""
     x, y = pts[:, 0][:, None], pts[:, 1][:, None]
