@@ -219,6 +219,54 @@ def kite_cavity(fth, ctx, reps=3, n_per=86):
     return rec
 
 
+def closed_obstacles(fth, ctx, reps=3, n=256):
+    """Two obstacles (ellipse and kite, 0.49 apart), Gaussian plane wave
+    (w0 = 15, sigma = 3), 512 frequencies on (0, 30], M = 10, 32 points on
+    the radius-3 circle, 601 time samples: each obstacle as one closed
+    combined-field patch of n nodes, and split into 4 overlapping open arcs
+    of n/4 nodes (the same unknown count)."""
+    from workloads import IncidentSpec, closed_obstacles_case
+    rec = {"workload": "two obstacles (ellipse 0.8 x 0.5, kite x 0.5), Gaussian plane wave "
+                       "w0 = 15, sigma = 3, 512 frequencies on (0, 30], M = 10, 32 points, "
+                       "601 time samples"}
+    om = 30.0 * np.arange(1, 513) / 512.0
+    w = np.full(om.size, om[1] - om[0])
+    w[-1] *= 0.5
+    times = np.linspace(0.0, 30.0, 601)
+    for name in ("closed_patches", "split_arcs"):
+        pb = closed_obstacles_case(n=n, omegas=om, M=10, nobs=32, mixed=(name == "split_arcs"),
+                                   n_arc=n // 4)
+        if name == "split_arcs":
+            # the ellipse split as well
+            from workloads.configs import _ellipse_arcs
+            pb.arcs = _ellipse_arcs(n // 4, 0.8, 0.5, center=(-1.0, 0.0), rot=0.3, group=0) + \
+                pb.arcs[1:]
+        pb.incident = IncidentSpec("gplane", theta=0.3, omega0=15.0, sigma=3.0, tau0=6.0)
+        t0 = time.perf_counter()
+        arcs = [ctx.closed_from_curve(a.curve, a.n) if getattr(a.curve, "closed", False)
+                else ctx.arc_from_curve(a.curve, a.n) for a in pb.arcs]
+        iv = np.array([a.curve.interval for a in pb.arcs])
+        prob = fth.Problem(ctx, arcs, pb.incident, pb.obs, intervals=iv, M=pb.M,
+                           groups=[a.group for a in pb.arcs])
+        U = prob.run(om)
+        ctx.freq_to_time(om, w, U, times)
+        setup = time.perf_counter() - t0
+        ts = []
+        for _ in range(reps):
+            t1 = time.perf_counter()
+            U = prob.run(om)
+            ctx.freq_to_time(om, w, U, times)
+            ts.append(time.perf_counter() - t1)
+        rec[name] = {"patches": len(arcs), "nodes_per_obstacle": n,
+                     "first_run_with_setup_s": round(setup, 3),
+                     "ms_per_run": round(1e3 * min(ts), 2),
+                     "solves_per_s": round(len(arcs) * om.size * pb.M / min(ts), 1)}
+        prob.close()
+        for a in arcs:
+            a.close()
+    return rec
+
+
 def serving(fth, workers=8, count=32, seed=5):
     """Serving loop: exterior scattering requests (1-3 obstacles of 4 arcs,
     n 32..96, 48..128 frequencies, time-domain stop 1e-8 within 100 steps)
@@ -276,7 +324,7 @@ def main():
                     help="refinement stop: predicted relative error (the metric's 1e-10 "
                          "with a 10x margin); every solve's error is measured")
     ap.add_argument("--no-cavity", action="store_true",
-                    help="skip the kite cavity runs (single-panel and composite-panel arcs)")
+                    help="skip the kite cavity and closed-obstacle runs")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving loop measurement (Poisson arrivals, p50/p99)")
     ap.add_argument("--no-uneven", action="store_true",
@@ -411,8 +459,10 @@ def main():
         uneven = uneven_batch(fth, ctx, torch, max(1, args.steps), args.tol)
 
     cavity = None
+    closed = None
     if not args.no_cavity:
         cavity = kite_cavity(fth, ctx)
+        closed = closed_obstacles(fth, ctx)
 
     serve = None
     if not args.no_serving:
@@ -462,6 +512,7 @@ def main():
         "roofline": roof,
         "uneven_batch": uneven,
         "kite_cavity": cavity,
+        "closed_obstacles": closed,
         "serving": serve,
         "cpu_baseline": base,
     }
