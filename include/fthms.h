@@ -70,7 +70,7 @@ enum {
   FTHMS_ECANCELLED = -8   /* served request was cancelled                */
 };
 
-enum { FTHMS_FP64 = 0, FTHMS_FP32_REFINED = 1 };
+enum { FTHMS_FP64 = 0, FTHMS_FP32_REFINED = 1, FTHMS_GMRES = 2 };
 
 enum { FTHMS_INC_PLANE = 0, FTHMS_INC_GPLANE = 1, FTHMS_INC_POINT = 2 };
 
@@ -175,6 +175,15 @@ int fthms_panel_nodes(int npan, const double *breaks, const int *kinds, int n_pe
 int fthms_arc_create_panels(fthms_ctx *ctx, int npan, const double *breaks, const int *kinds,
                             int n_per, const double *xy, const double *dxy, fthms_arc **out);
 
+/* GMRES on nb dense systems A[nb][n][n] (column-major, complex128) with
+ * right-hand sides b[nb][n] (device pointers, context stream): x[nb][n],
+ * iterations iters[nb] and final relative residual estimates relres[nb];
+ * the method of FTHMS_GMRES above, 1 <= maxit <= min(n, 256).  Stage entry
+ * point for measurements on given matrices. */
+int fthms_gmres_dev(fthms_ctx *ctx, int n, int nb, const fthms_c64 *A_dev,
+                    const fthms_c64 *b_dev, fthms_c64 *x_dev, double tol, int maxit,
+                    int *iters_dev, double *relres_dev);
+
 /* ---- closed patches (Section 3.3, eqs. FDsolk-closed, FDBIEk-closed) -------
  *
  * A closed curve treated as one patch: its density solves the combined-field
@@ -219,7 +228,14 @@ int fthms_arc_panel_table(const fthms_arc *arc, double *W, double *w);
  * iters[nk] (optional) receives the refinement steps per solve (0 for
  * FP64, -1 for a solve redone in FP64); relres[nk] (optional) the last
  * relative correction |delta|/|alpha|.  FTHMS_ESINGULAR if a pivot is
- * exactly zero (alpha is then not meaningful for that k). */
+ * exactly zero (alpha is then not meaningful for that k).
+ * precision FTHMS_GMRES solves each assembled system with GMRES in FP64
+ * instead (x0 = 0, modified Gram-Schmidt Arnoldi, Givens rotations, no
+ * restart; the iterative solver the paper names beside direct ones, §5
+ * Geometries 5) until the residual estimate is below tol |rhs| (tol <= 0:
+ * 1e-12) or min(n, 256) iterations; iters receives the GMRES iterations,
+ * relres the final relative residual estimate; the host entry point
+ * returns FTHMS_ENOCONV (results written) if a system did not converge. */
 int fthms_solve(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double *k,
                 const fthms_c64 *rhs, fthms_c64 *alpha, int precision,
                 double tol, int *iters, double *relres);

@@ -8,6 +8,7 @@ the frequency-domain FTH-MS hot path, written from the paper:
   variables (eq. cov) .................... ``oracle.panels``
   closed patches, combined-field
   equation (Section 3.3) ................. ``oracle.closed``
+  GMRES for the dense systems ............ ``oracle.gmres``
   incident fields ....................... ``oracle.incident``
   multiple-scattering recursion ......... ``oracle.ms``
   frequency-to-time transform ........... ``oracle.transform``
@@ -22,4 +23,4 @@ against closed forms, textbook identities, brute-force quadrature or
 library routines (see the pin tests under tests/).  None is "parity
 unpinned".
 """
-from . import closed, nystrom, incident, ms, panels, transform  # noqa: F401
+from . import closed, gmres, nystrom, incident, ms, panels, transform  # noqa: F401

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(PKG, "libfthms.so")
 
 FP64 = 0
 FP32_REFINED = 1
+GMRES = 2
 INC_PLANE, INC_GPLANE, INC_POINT = 0, 1, 2
 
 _ERR = {0: "OK", -1: "EINVAL", -2: "EINVAL_DATA", -3: "ENOMEM",
@@ -80,6 +81,7 @@ _SIGS = {
     "fthms_arc_panel_table": ([_vp, _vp, _vp], _i),
     "fthms_tov_breaks": ([_i, _vp, _vp, _d, _vp, _vp], _i),
     "fthms_closed_create": ([_vp, _i, _vp, _vp, _vp, C.POINTER(_vp)], _i),
+    "fthms_gmres_dev": ([_vp, _i, _i, _vp, _vp, _vp, _d, _i, _vp, _vp], _i),
     "fthms_solve": ([_vp, _vp, _i, _vp, _vp, _vp, _i, _d, _vp, _vp], _i),
     "fthms_solve_dev": ([_vp, _vp, _i, _vp, _vp, _vp, _i, _d, _vp, _vp], _i),
     "fthms_rhs": ([_vp, _vp, _i, _vp, C.POINTER(Incident), _vp], _i),
@@ -322,6 +324,12 @@ class Context:
         nb, n = A.shape[0], A.shape[-1]
         self.check(_lib.fthms_lu_dev(self.h, n, nb, precision, _dptr(A), _dptr(piv),
                                      _dptr(info)), "lu_dev")
+
+    def gmres_dev(self, A, b, x, iters, relres, tol=1e-12, maxit=None):
+        nb, n = A.shape[0], A.shape[-1]
+        maxit = min(n, 256) if maxit is None else maxit
+        self.check(_lib.fthms_gmres_dev(self.h, n, nb, _dptr(A), _dptr(b), _dptr(x), tol,
+                                        int(maxit), _dptr(iters), _dptr(relres)), "gmres_dev")
 
     def lu_solve_dev(self, LU, piv, b, x):
         nb, n = LU.shape[0], LU.shape[-1]

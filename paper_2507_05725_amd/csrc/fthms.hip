@@ -20,6 +20,7 @@
 #include "panel.h"
 #include "panels.h"
 #include "closed.h"
+#include "gmres.h"
 
 using namespace fthms;
 
@@ -923,6 +924,68 @@ static int assemble_launch(fthms_ctx *ctx, const fthms_arc *arc, const double *k
   return check_launch(ctx, "assemble_kernel");
 }
 
+// GMRES workspace per system: the basis [maxit + 1][N] and the triangular
+// factor [maxit][maxit + 1] (double2 units)
+static long long gmres_wstride(int N, int maxit) {
+  return (long long)(maxit + 1) * N + (long long)maxit * (maxit + 1);
+}
+
+static int gmres_launch(fthms_ctx *ctx, const double2 *A, long long mstride, int N, int nb,
+                        const double2 *b, long long bstride, double2 *x, long long xstride,
+                        int maxit, double tol, double2 *work, int *iters, double *relres) {
+  gmres_kernel<<<nb, kGmresThreads, 0, ctx->stream>>>(A, mstride, N, b, bstride, x, xstride,
+                                                       maxit, tol, work,
+                                                       gmres_wstride(N, maxit), iters, relres);
+  return check_launch(ctx, "gmres_kernel");
+}
+
+// Assembly + GMRES (FP64) for nk wavenumbers, chunked to the budget.
+static int gmres_solve_impl(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double *k_dev,
+                            const double2 *rhs, double2 *alpha, double tol, int *iters_dev,
+                            double *relres_dev) {
+  const int N = arc->n;
+  const int maxit = std::min(N, kGmresMaxIt);
+  const size_t per = sizeof(double2) * ((size_t)N * N + (size_t)gmres_wstride(N, maxit)) +
+                     sizeof(int) + sizeof(double) + 1024;
+  size_t cap = (size_t)16 << 30;
+  if (ctx->budget) {
+    const size_t avail = ctx->budget > ctx->held ? ctx->budget - ctx->held + ctx->ws_bytes : 0;
+    cap = std::min(cap, avail);
+  }
+  int chunk = (int)std::min<size_t>((size_t)nk, std::max<size_t>(1, cap / per));
+  chunk = std::min(chunk, 4096);
+  const int nchunks = (nk + chunk - 1) / chunk;
+  chunk = (nk + nchunks - 1) / nchunks;
+  if ((size_t)chunk * per > cap) return fail(ctx, FTHMS_ENOMEM, "no room for one matrix");
+  const size_t oA = 0;
+  const size_t oW = (sizeof(double2) * (size_t)N * N * chunk + 255) & ~(size_t)255;
+  const size_t oI = oW + ((sizeof(double2) * (size_t)gmres_wstride(N, maxit) * chunk + 255) &
+                          ~(size_t)255);
+  const size_t oR = oI + ((sizeof(int) * chunk + 255) & ~(size_t)255);
+  const size_t total = oR + sizeof(double) * chunk;
+  int rc = ensure_ws(ctx, total);
+  if (rc) return rc;
+  char *base = (char *)ctx->ws;
+  double2 *A64 = (double2 *)(base + oA);
+  double2 *work = (double2 *)(base + oW);
+  int *it = (int *)(base + oI);
+  double *rr = (double *)(base + oR);
+  for (int f0 = 0; f0 < nk; f0 += chunk) {
+    const int c = std::min(chunk, nk - f0);
+    tbeg(ctx, "assemble");
+    rc = assemble_launch(ctx, arc, k_dev + f0, c, A64, nullptr);
+    tend(ctx);
+    if (rc) return rc;
+    tbeg(ctx, "gmres");
+    rc = gmres_launch(ctx, A64, (long long)N * N, N, c, rhs + (long long)f0 * N, N,
+                      alpha + (long long)f0 * N, N, maxit, tol, work,
+                      iters_dev ? iters_dev + f0 : it, relres_dev ? relres_dev + f0 : rr);
+    tend(ctx);
+    if (rc) return rc;
+  }
+  return FTHMS_OK;
+}
+
 // Internal: solve for nk wavenumbers, device pointers, on ctx->stream.
 static int solve_dev_impl(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double *k_dev,
                           const double2 *rhs, double2 *alpha, int precision, double tol,
@@ -930,6 +993,8 @@ static int solve_dev_impl(fthms_ctx *ctx, const fthms_arc *arc, int nk, const do
   const int N = arc->n;
   const bool fp32 = precision == FTHMS_FP32_REFINED;
   if (tol <= 0.0) tol = 1e-12;
+  if (precision == FTHMS_GMRES)
+    return gmres_solve_impl(ctx, arc, nk, k_dev, rhs, alpha, tol, iters_dev, relres_dev);
   SolveWs w;
   int rc = solve_ws(ctx, N, fp32, nk, w);
   if (rc) return rc;
@@ -1010,7 +1075,7 @@ int fthms_solve_dev(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double *
                     double tol, int *iters_dev, double *relres_dev) {
   if (!ctx || !arc || !k_dev || !rhs_dev || !alpha_dev || nk < 0)
     return fail(ctx, FTHMS_EINVAL, "bad argument to fthms_solve_dev");
-  if (precision != FTHMS_FP64 && precision != FTHMS_FP32_REFINED)
+  if (precision != FTHMS_FP64 && precision != FTHMS_FP32_REFINED && precision != FTHMS_GMRES)
     return fail(ctx, FTHMS_EINVAL, "unknown precision");
   if (nk == 0) return FTHMS_OK;
   HIPCK(ctx, hipSetDevice(ctx->device));
@@ -1054,12 +1119,45 @@ int fthms_solve(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double *k,
   if (relres)
     HIPCK(ctx, hipMemcpyAsync(relres, drr, sizeof(double) * nk, hipMemcpyDeviceToHost,
                               ctx->stream));
+  std::vector<double> rr(nk);
+  HIPCK(ctx, hipMemcpyAsync(rr.data(), drr, sizeof(double) * nk, hipMemcpyDeviceToHost,
+                            ctx->stream));
   HIPCK(ctx, hipStreamSynchronize(ctx->stream));
   if (iters) std::copy(it.begin(), it.end(), iters);
+  if (precision == FTHMS_GMRES) {
+    const double t = tol > 0.0 ? tol : 1e-12;
+    for (int i = 0; i < nk; ++i)
+      if (!(rr[i] <= t))
+        return fail(ctx, FTHMS_ENOCONV, "GMRES did not reach the tolerance at wavenumber index " +
+                                            std::to_string(i) + " within " +
+                                            std::to_string(std::min(N, kGmresMaxIt)) +
+                                            " iterations");
+    return FTHMS_OK;
+  }
   for (int i = 0; i < nk; ++i)
     if (it[i] == -2) return fail(ctx, FTHMS_ESINGULAR, "zero pivot at wavenumber index " +
                                                            std::to_string(i));
   return FTHMS_OK;
+}
+
+int fthms_gmres_dev(fthms_ctx *ctx, int n, int nb, const fthms_c64 *A_dev,
+                    const fthms_c64 *b_dev, fthms_c64 *x_dev, double tol, int maxit,
+                    int *iters_dev, double *relres_dev) {
+  if (!ctx || n < 1 || n > kMaxN || nb < 0 ||
+      (nb > 0 && (!A_dev || !b_dev || !x_dev || !iters_dev || !relres_dev)))
+    return fail(ctx, FTHMS_EINVAL, "bad argument to fthms_gmres_dev");
+  if (maxit < 1 || maxit > std::min(n, kGmresMaxIt))
+    return fail(ctx, FTHMS_EINVAL, "maxit must be in [1, min(n, 256)]");
+  if (nb == 0) return FTHMS_OK;
+  HIPCK(ctx, hipSetDevice(ctx->device));
+  int rc = ensure_ws2(ctx, sizeof(double2) * (size_t)gmres_wstride(n, maxit) * nb);
+  if (rc) return rc;
+  tbeg(ctx, "gmres");
+  rc = gmres_launch(ctx, (const double2 *)A_dev, (long long)n * n, n, nb, (const double2 *)b_dev,
+                    n, (double2 *)x_dev, n, maxit, tol > 0.0 ? tol : 1e-12,
+                    (double2 *)ctx->ws2, iters_dev, relres_dev);
+  tend(ctx);
+  return rc;
 }
 
 static int to_incident(fthms_ctx *ctx, const fthms_incident *inc, IncidentDev &d) {

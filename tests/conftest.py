@@ -24,3 +24,16 @@ def pytest_collection_modifyitems(config, items):
 @pytest.fixture(scope="session")
 def repo_root():
     return ROOT
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _torch_sees_the_gpu_first(request):
+    """GPU tests that hand torch tensors to the library need torch's HIP
+    runtime to initialise the device before the library's own runtime does
+    (the other order leaves torch without devices).  Session scope runs this
+    before any module fixture creates a library context."""
+    if any(it.get_closest_marker("gpu") is not None for it in request.session.items):
+        import torch
+        if torch.cuda.is_available():
+            torch.zeros(1, device="cuda")
+    yield

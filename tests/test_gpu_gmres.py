@@ -1,0 +1,122 @@
+"""GPU parity of the batched GMRES solver (the iterative alternative to LU
+the paper uses, Section 5 Geometries 5) against the GMRES oracle: iteration
+counts (the same Krylov method: equal up to one iteration where rounding
+decides a threshold crossing), solutions against the direct solve, and the
+failure report when the tolerance cannot be reached."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import closed as ocl
+from oracle import gmres as ogm
+from oracle import incident as oinc
+from oracle import nystrom as ony
+from workloads import CircularArc, ClosedKite, IncidentSpec
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def fth():
+    import paper_2507_05725_amd as m  # raises if the HIP library is missing
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(fth):
+    return fth.Context(0)
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
+
+
+CAVITY = (0.02 * math.pi, 1.98 * math.pi)
+
+
+@pytest.mark.parametrize("case", ["arc", "cavity", "patch"])
+def test_gmres_open_arcs(ctx, fth, case):
+    """Open arcs: a circular arc (N = 128), the nearly closed circular cavity
+    of Geometries 5 (N = 256, trapping) and one of its six patches (N = 64)."""
+    if case == "arc":
+        curve, n = CircularArc(1.0, -1.0, 1.4), 128
+    elif case == "cavity":
+        curve, n = CircularArc(1.0, *CAVITY), 256
+    else:
+        d = (CAVITY[1] - CAVITY[0]) / 6
+        curve, n = CircularArc(1.0, CAVITY[0] + 2 * d - 0.25 * d, CAVITY[0] + 3 * d + 0.25 * d), 64
+    spec = IncidentSpec("plane", theta=-math.pi)
+    ks = np.array([3.0, 9.5, 17.0])
+    say("gmres", case, n)
+    arc = ctx.arc_from_curve(curve, n)
+    rhs = ctx.rhs(arc, ks, spec)
+    x, it, rr = ctx.solve(arc, ks, rhs, fth.GMRES, 1e-12)
+    nd = ony.arc_nodes(curve, n)
+    for i, k in enumerate(ks):
+        A = ony.assemble(nd, k)
+        b = -oinc.incident(spec, k, nd["y"])
+        xo, ito, hist = ogm.gmres(A, b, tol=1e-12, maxit=min(n, 256))
+        assert abs(int(it[i]) - ito) <= 1, (k, it[i], ito)
+        assert rr[i] <= 1e-12
+        ref = np.linalg.solve(A, b)
+        assert rel(x[i], ref) < 1e-9, (k, rel(x[i], ref))
+
+
+def test_gmres_closed_patch(ctx, fth):
+    """The combined-field equation (second kind) converges in few
+    iterations; same count and solution as the oracle."""
+    curve, n = ClosedKite(1.0), 128
+    spec = IncidentSpec("point", z0=(0.05, 0.1), sigma=0.0)
+    ks = np.array([2.0, 7.5])
+    arc = ctx.closed_from_curve(curve, n)
+    rhs = ctx.rhs(arc, ks, spec)
+    x, it, rr = ctx.solve(arc, ks, rhs, fth.GMRES, 1e-12)
+    nd = ocl.nodes(curve, n)
+    for i, k in enumerate(ks):
+        A = ocl.assemble(nd, k)
+        b = -oinc.incident(spec, k, nd["y"])
+        _, ito, _ = ogm.gmres(A, b, tol=1e-12, maxit=n)
+        assert abs(int(it[i]) - ito) <= 1 and it[i] < 60
+        assert rel(x[i], np.linalg.solve(A, b)) < 1e-10
+
+
+def test_gmres_dev_raw_matrices(ctx, fth):
+    """The stage entry point on given matrices (ragged size, several
+    systems), including a zero right-hand side."""
+    import torch
+    rng = np.random.default_rng(5)
+    n, nb = 200, 5
+    A = np.stack([np.eye(n) * 2 + (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+                  / (2 * np.sqrt(n)) for _ in range(nb)])
+    b = rng.standard_normal((nb, n)) + 1j * rng.standard_normal((nb, n))
+    b[3] = 0.0
+    At = torch.from_numpy(np.ascontiguousarray(np.transpose(A, (0, 2, 1)))).to("cuda")  # column-major
+    bt = torch.from_numpy(b).to("cuda")
+    xt = torch.empty_like(bt)
+    it = torch.empty(nb, dtype=torch.int32, device="cuda")
+    rr = torch.empty(nb, dtype=torch.float64, device="cuda")
+    ctx.gmres_dev(At, bt, xt, it, rr, tol=1e-12, maxit=200)
+    torch.cuda.synchronize()
+    x, it, rr = xt.cpu().numpy(), it.cpu().numpy(), rr.cpu().numpy()
+    for s in range(nb):
+        if s == 3:
+            assert it[s] == 0 and np.all(x[s] == 0)
+            continue
+        _, ito, _ = ogm.gmres(A[s], b[s], tol=1e-12, maxit=200)
+        assert abs(int(it[s]) - ito) <= 1
+        assert rel(x[s], np.linalg.solve(A[s], b[s])) < 1e-11
+
+
+def test_gmres_reports_no_convergence(ctx, fth):
+    """An unreachable tolerance: FTHMS_ENOCONV from the host entry point."""
+    arc = ctx.arc_from_curve(CircularArc(1.0, -1.0, 1.4), 32)
+    rhs = ctx.rhs(arc, np.array([4.0]), IncidentSpec("plane"))
+    with pytest.raises(fth.FthmsError) as e:
+        ctx.solve(arc, np.array([4.0]), rhs, fth.GMRES, 1e-30)
+    assert e.value.code == -5
