@@ -267,6 +267,47 @@ def closed_obstacles(fth, ctx, reps=3, n=256):
     return rec
 
 
+def gmres_cavity(fth, ctx, n_full=256, n_patch=64, patches=6, nk=401, W=25.0):
+    """The circular cavity of the paper's Geometries 5 (the arc of the unit
+    circle over (0.02 pi, 1.98 pi), plane wave from theta = -pi), nk
+    frequencies on (0, W]: GMRES iterations (tol 1e-12) for the whole
+    trapping arc (n_full nodes) against its decomposition into `patches`
+    overlapping arcs (n_patch nodes each; quarter-part overlaps), and the
+    time of the whole-arc batch by GMRES and by LU."""
+    from workloads import CircularArc, IncidentSpec
+    a0, a1 = 0.02 * math.pi, 1.98 * math.pi
+    d = (a1 - a0) / patches
+    spec = IncidentSpec("plane", theta=-math.pi)
+    om = W * np.arange(1, nk + 1) / nk
+    rec = {"workload": "circular cavity (0.02 pi, 1.98 pi), plane wave theta = -pi, %d frequencies "
+                       "on (0, %g], GMRES tol 1e-12" % (nk, W)}
+
+    def run(curve, n, prec):
+        arc = ctx.arc_from_curve(curve, n)
+        rhs = ctx.rhs(arc, om, spec)
+        ctx.solve(arc, om[:8], rhs[:8], prec, 1e-12)  # warm-up
+        t0 = time.perf_counter()
+        _, it, rr = ctx.solve(arc, om, rhs, prec, 1e-12)
+        dt = time.perf_counter() - t0
+        arc.close()
+        return it, dt
+
+    it_full, t_gm = run(CircularArc(1.0, a0, a1), n_full, fth.GMRES)
+    _, t_lu = run(CircularArc(1.0, a0, a1), n_full, fth.FP64)
+    its = []
+    for j in range(patches):
+        c = CircularArc(1.0, max(a0, a0 + j * d - 0.25 * d), min(a1, a0 + (j + 1) * d + 0.25 * d))
+        its.append(run(c, n_patch, fth.GMRES)[0])
+    its = np.concatenate(its)
+    rec["whole_arc"] = {"n": n_full, "gmres_iters_mean": round(float(np.mean(it_full)), 1),
+                        "gmres_iters_max": int(np.max(it_full)),
+                        "gmres_batch_s": round(t_gm, 4), "lu_fp64_batch_s": round(t_lu, 4)}
+    rec["patches"] = {"count": patches, "n": n_patch,
+                      "gmres_iters_mean": round(float(np.mean(its)), 1),
+                      "gmres_iters_max": int(np.max(its))}
+    return rec
+
+
 def serving(fth, workers=8, count=32, seed=5):
     """Serving loop: exterior scattering requests (1-3 obstacles of 4 arcs,
     n 32..96, 48..128 frequencies, time-domain stop 1e-8 within 100 steps)
@@ -324,7 +365,7 @@ def main():
                     help="refinement stop: predicted relative error (the metric's 1e-10 "
                          "with a 10x margin); every solve's error is measured")
     ap.add_argument("--no-cavity", action="store_true",
-                    help="skip the kite cavity and closed-obstacle runs")
+                    help="skip the kite cavity, closed-obstacle and GMRES cavity runs")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving loop measurement (Poisson arrivals, p50/p99)")
     ap.add_argument("--no-uneven", action="store_true",
@@ -460,9 +501,11 @@ def main():
 
     cavity = None
     closed = None
+    gcav = None
     if not args.no_cavity:
         cavity = kite_cavity(fth, ctx)
         closed = closed_obstacles(fth, ctx)
+        gcav = gmres_cavity(fth, ctx)
 
     serve = None
     if not args.no_serving:
@@ -513,6 +556,7 @@ def main():
         "uneven_batch": uneven,
         "kite_cavity": cavity,
         "closed_obstacles": closed,
+        "gmres_cavity": gcav,
         "serving": serve,
         "cpu_baseline": base,
     }
