@@ -9,6 +9,7 @@ the frequency-domain FTH-MS hot path, written from the paper:
   closed patches, combined-field
   equation (Section 3.3) ................. ``oracle.closed``
   GMRES for the dense systems ............ ``oracle.gmres``
+  windowing and time recentering ......... ``oracle.windowed``
   incident fields ....................... ``oracle.incident``
   multiple-scattering recursion ......... ``oracle.ms``
   frequency-to-time transform ........... ``oracle.transform``
@@ -23,4 +24,4 @@ against closed forms, textbook identities, brute-force quadrature or
 library routines (see the pin tests under tests/).  None is "parity
 unpinned".
 """
-from . import closed, gmres, nystrom, incident, ms, panels, transform  # noqa: F401
+from . import closed, gmres, nystrom, incident, ms, panels, transform, windowed  # noqa: F401
