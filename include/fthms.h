@@ -184,6 +184,32 @@ int fthms_gmres_dev(fthms_ctx *ctx, int n, int nb, const fthms_c64 *A_dev,
                     const fthms_c64 *b_dev, fthms_c64 *x_dev, double tol, int maxit,
                     int *iters_dev, double *relres_dev);
 
+/* ---- windowing and time recentering (Section 2.1, eqs. windowing,
+ * Fourierk, TDsol; Algorithm 1 with Q windows) -----------------------------
+ *
+ * Time-domain incident field for windowed runs: a train of npulse Gaussian
+ * plane-wave pulses (u2 of Section 5 in the time domain), direction theta,
+ *   u(x, t) = sum_{p < npulse} f(t - p period - x.d),
+ *   f(tau) = sigma/(2 sqrt(pi)) exp(-i omega0 (tau - tau0) - sigma^2 (tau - tau0)^2 / 4). */
+typedef struct {
+  double theta, omega0, sigma, tau0, period;
+  int npulse;
+} fthms_pulse_train;
+
+/* Time traces u_M(x_p, t_n), t_n = n dt (n < nt), of the problem's M-step
+ * recursion run through the time domain with Q windows (s_q = 3/2 (q-1) H,
+ * the window function of Section 5): every step transforms each arc's
+ * boundary data about each window centre over the nk frequencies k (with
+ * quadrature weights w for the way back), solves with the factors of the
+ * first step, evaluates the fields and transforms them back shifted by
+ * s_q.  The data must fit inside sum_q window = 1, i.e. nt dt <= s_Q + H/2
+ * for signals that last to the end.  FP64 problems only; traces [nt][nobs]
+ * (host).  All frequencies and time series stay resident (FTHMS_ENOMEM if
+ * they do not fit the budget). */
+int fthms_problem_traces_windowed(fthms_problem *pb, int nk, const double *k, const double *w,
+                                  int nt, double dt, int Q, double H,
+                                  const fthms_pulse_train *inc, fthms_c64 *traces);
+
 /* ---- closed patches (Section 3.3, eqs. FDsolk-closed, FDBIEk-closed) -------
  *
  * A closed curve treated as one patch: its density solves the combined-field

@@ -47,6 +47,11 @@ class ProblemDesc(C.Structure):
                 ("obs_xy", C.POINTER(C.c_double)), ("group", C.POINTER(C.c_int))]
 
 
+class PulseTrain(C.Structure):
+    _fields_ = [("theta", C.c_double), ("omega0", C.c_double), ("sigma", C.c_double),
+                ("tau0", C.c_double), ("period", C.c_double), ("npulse", C.c_int)]
+
+
 class Request(C.Structure):
     _fields_ = [("narcs", C.c_int), ("n", C.c_int), ("xy", C.POINTER(C.c_double)),
                 ("dxy", C.POINTER(C.c_double)), ("interval", C.POINTER(C.c_double)),
@@ -82,6 +87,8 @@ _SIGS = {
     "fthms_tov_breaks": ([_i, _vp, _vp, _d, _vp, _vp], _i),
     "fthms_closed_create": ([_vp, _i, _vp, _vp, _vp, C.POINTER(_vp)], _i),
     "fthms_gmres_dev": ([_vp, _i, _i, _vp, _vp, _vp, _d, _i, _vp, _vp], _i),
+    "fthms_problem_traces_windowed": ([_vp, _i, _vp, _vp, _i, _d, _i, _d,
+                                       C.POINTER(PulseTrain), _vp], _i),
     "fthms_solve": ([_vp, _vp, _i, _vp, _vp, _vp, _i, _d, _vp, _vp], _i),
     "fthms_solve_dev": ([_vp, _vp, _i, _vp, _vp, _vp, _i, _d, _vp, _vp], _i),
     "fthms_rhs": ([_vp, _vp, _i, _vp, C.POINTER(Incident), _vp], _i),
@@ -435,6 +442,19 @@ class Problem:
                                                  stop_tol, _ptr(out), C.byref(steps)),
                        "problem_traces")
         return out, steps.value
+
+    def traces_windowed(self, k, w, dt, nt, Q, H, theta, omega0, sigma, tau0, npulse=1,
+                        period=0.0):
+        """Time traces of the recursion run through the time domain with Q
+        windows, for a pulse-train incident field; returns [nt][nobs]."""
+        k = np.ascontiguousarray(k, dtype=np.float64)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        out = np.empty((nt, self.obs.shape[0]), dtype=np.complex128)
+        inc = PulseTrain(theta, omega0, sigma, tau0, period, npulse)
+        self.ctx.check(_lib.fthms_problem_traces_windowed(self.h, k.size, _ptr(k), _ptr(w), nt,
+                                                          dt, Q, H, C.byref(inc), _ptr(out)),
+                       "problem_traces_windowed")
+        return out
 
     def run_dev(self, k, U, alpha=None):
         self.ctx.check(_lib.fthms_problem_run_dev(self.h, k.numel(), _dptr(k), _dptr(U),

@@ -1446,5 +1446,6 @@ int fthms_bessel_dev(fthms_ctx *ctx, int nz, const double *z_dev, double *j0_dev
 }  // extern "C"
 
 #include "problem.h"
+#include "windowed.h"
 #include "batch.h"
 #include "serve.h"

@@ -1,0 +1,268 @@
+// Windowing and time recentering of the multiple-scattering recursion
+// (Section 2.1, eqs. windowing, Fourierk, TDsol; Algorithm 1 with Q windows;
+// the window function of Section 5).
+//
+// Each step m works on boundary data g_{j,m}(y, t_n), t_n = n dt, at the
+// nodes of every arc (time-major [nt][n]).  For every arc j and window q:
+//   G(w_l) = sum_n dt P(t_n - s_q) g_j(t_n) exp(i w_l (t_n - s_q))      (eq. Fourierk)
+//   Psi(w_l) = A_j(w_l)^{-1} G(w_l)       (factors of the first step reused)
+//   V(w_l) at the other arcs' nodes and the observation points (near/far fields)
+//   v(t_n) += (1/2pi) sum_l w_l V(w_l) exp(-i w_l (t_n - s_q))           (eq. TDsol)
+// and after all arcs g_{k,m+1} = -chi_k sum_{j != k} v~_{j,k,m} (eqs.
+// criterion_int2, vtilde: the fields skip the masked overlap nodes), while
+// the observation fields accumulate into u_M.  Both transforms are the dense
+// frequency/time kernel of the single-window path: the forward one with the
+// roles of times and frequencies exchanged.  Window: s_q = 3/2 (q-1) H,
+// P(s) = eta(s/H; 1/2, 1) on [-H/2, H], 1 - eta(s/H + 3/2; 1/2, 1) on
+// (-H, -H/2), 0 elsewhere.  Signals are complex, frequencies positive.
+// The initial data come from a train of Gaussian plane-wave pulses given in
+// the time domain (u2 of Section 5 transformed back):
+//   u(x, t) = sum_p f(t - p T - x.d),
+//   f(tau) = sigma/(2 sqrt(pi)) exp(-i w0 (tau - tau0) - sigma^2 (tau - tau0)^2 / 4).
+#pragma once
+
+namespace fthms {
+
+struct PulseTrainDev {
+  double dx, dy, omega0, sigma, tau0, period;
+  int npulse;
+};
+
+// out[n][i] = -chi[i] u(y_i, n dt)   (chi == nullptr: 1)
+__global__ void pulse_train_kernel(PulseTrainDev in, const double2 *__restrict__ y,
+                                   const double *__restrict__ chi, int n, int nt, double dt,
+                                   double2 *__restrict__ out) {
+  const long long nn = (long long)n * nt;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nn;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n);
+    const double tn = (double)(e / n) * dt;
+    const double xd = y[i].x * in.dx + y[i].y * in.dy;
+    double ar = 0.0, ai = 0.0;
+    for (int p = 0; p < in.npulse; ++p) {
+      const double tau = tn - p * in.period - xd - in.tau0;
+      const double a = in.sigma / (2.0 * sqrt(kPi)) * exp(-0.25 * in.sigma * in.sigma * tau * tau);
+      double s, c;
+      sincos(-in.omega0 * tau, &s, &c);
+      ar += a * c;
+      ai += a * s;
+    }
+    const double sc = chi ? -chi[i] : -1.0;
+    out[e] = make_double2(sc * ar, sc * ai);
+  }
+}
+
+// P(s) of the windowing partition of unity (host)
+static double window_pou(double s, double H) {
+  if (s >= -0.5 * H && s <= H) return eta_window(s / H, 0.5, 1.0);
+  if (s > -H && s < -0.5 * H) return 1.0 - eta_window(s / H + 1.5, 0.5, 1.0);
+  return 0.0;
+}
+
+static int problem_windowed_impl(fthms_problem *pb, int nk, const double *k_dev,
+                                 const double *w_dev, const std::vector<double> &k_host,
+                                 double kmax, int nt, double dt, int Q, double H,
+                                 const PulseTrainDev &inc, double2 *traces) {
+  fthms_ctx *ctx = pb->ctx;
+  const int J = pb->narcs, P = pb->nobs;
+  int rc = problem_plan(pb, kmax);
+  if (rc) return rc;
+  int nmax = std::max(P, 1);
+  for (int j = 0; j < J; ++j) nmax = std::max(nmax, pb->arcs[j]->n);
+  // workspace: per arc factors, permutations, status, right-hand sides and
+  // densities for all frequencies, time series of data and cross fields;
+  // shared frequency and time buffers, window tables
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return r;
+  };
+  struct Ws {
+    size_t A, piv, swp, st, G, psi, g, cr;
+  };
+  std::vector<Ws> o(J);
+  for (int j = 0; j < J; ++j) {
+    const size_t n = pb->arcs[j]->n;
+    o[j].A = take(n * n * sizeof(double2) * nk);
+    o[j].piv = take(n * sizeof(int) * nk);
+    o[j].swp = take(kLuScratchBytes * nk);
+    o[j].st = take(sizeof(int) * nk);
+    o[j].G = take(n * sizeof(double2) * nk);
+    o[j].psi = take(n * sizeof(double2) * nk);
+    o[j].g = take(n * sizeof(double2) * nt);
+    o[j].cr = take(n * sizeof(double2) * nt);
+  }
+  const size_t oV = take((size_t)nmax * sizeof(double2) * nk);
+  const size_t oT = take((size_t)nmax * sizeof(double2) * nt);
+  const size_t oTq = take(sizeof(double) * (size_t)Q * nt);  // t_n - s_q
+  const size_t oWq = take(sizeof(double) * (size_t)Q * nt);  // 2pi dt P(t_n - s_q)
+  const size_t oNk = take(sizeof(double) * nk);              // -w_l
+  if (ctx->budget && off > ctx->budget)
+    return fail(ctx, FTHMS_ENOMEM, "windowed run: the factors and time series of all "
+                                   "frequencies do not fit the budget");
+  if ((rc = ensure_ws(ctx, off))) return rc;
+  char *base = (char *)ctx->ws;
+  auto at = [&](size_t o_) { return (void *)(base + o_); };
+  double2 *V = (double2 *)at(oV), *T = (double2 *)at(oT);
+  double *tq = (double *)at(oTq), *wq = (double *)at(oWq), *nkv = (double *)at(oNk);
+  {
+    std::vector<double> htq((size_t)Q * nt), hwq((size_t)Q * nt), hnk(nk);
+    for (int q = 0; q < Q; ++q)
+      for (int n = 0; n < nt; ++n) {
+        const double s = n * dt - 1.5 * H * q;
+        htq[(size_t)q * nt + n] = s;
+        hwq[(size_t)q * nt + n] = 2.0 * kPi * dt * window_pou(s, H);
+      }
+    for (int l = 0; l < nk; ++l) hnk[l] = -k_host[l];
+    HIPCK(ctx, hipMemcpy(tq, htq.data(), sizeof(double) * htq.size(), hipMemcpyHostToDevice));
+    HIPCK(ctx, hipMemcpy(wq, hwq.data(), sizeof(double) * hwq.size(), hipMemcpyHostToDevice));
+    HIPCK(ctx, hipMemcpy(nkv, hnk.data(), sizeof(double) * nk, hipMemcpyHostToDevice));
+  }
+  // factor every (arc, frequency) matrix once; initial data in time
+  for (int j = 0; j < J; ++j) {
+    const fthms_arc *a = pb->arcs[j];
+    const int n = a->n;
+    double2 *A = (double2 *)at(o[j].A);
+    tbeg(ctx, "assemble");
+    rc = assemble_launch(ctx, a, k_dev, nk, A, nullptr);
+    tend(ctx);
+    if (rc) return rc;
+    tbeg(ctx, "lu");
+    rc = launch_lu(ctx, false, A, n, (long long)n * n, (int *)at(o[j].piv), at(o[j].swp),
+                   (int *)at(o[j].st), nk);
+    tend(ctx);
+    if (rc) return rc;
+    const long long nn = (long long)nt * n;
+    pulse_train_kernel<<<grid1d(nn), 256, 0, ctx->stream>>>(
+        inc, a->d_y, J > 1 ? pb->d_chi[j] : nullptr, n, nt, dt, (double2 *)at(o[j].g));
+    if ((rc = check_launch(ctx, "pulse_train_kernel"))) return rc;
+  }
+  const long long ntr = (long long)nt * P;
+  if (ntr) zero_kernel<<<grid1d(ntr), 256, 0, ctx->stream>>>(traces, ntr);
+  auto to_time = [&](const double *tshift, int np, const double2 *Vf, double2 *out) -> int {
+    dim3 g((np + kFtTile - 1) / kFtTile, (nt + kFtTile - 1) / kFtTile);
+    freq_to_time_kernel<<<g, 256, 0, ctx->stream>>>(nk, k_dev, w_dev, np, Vf, nt, tshift, out);
+    return check_launch(ctx, "freq_to_time_kernel (window)");
+  };
+  for (int m = 0; m < pb->M; ++m) {
+    for (int k = 0; k < J; ++k) {
+      const long long nn = (long long)nt * pb->arcs[k]->n;
+      zero_kernel<<<grid1d(nn), 256, 0, ctx->stream>>>((double2 *)at(o[k].cr), nn);
+    }
+    for (int j = 0; j < J; ++j) {
+      const fthms_arc *a = pb->arcs[j];
+      const int n = a->n;
+      double2 *G = (double2 *)at(o[j].G), *psi = (double2 *)at(o[j].psi);
+      for (int q = 0; q < Q; ++q) {
+        // slow transform about s_q: sum over time samples with the window weights
+        tbeg(ctx, "window_transform");
+        {
+          dim3 g((n + kFtTile - 1) / kFtTile, (nk + kFtTile - 1) / kFtTile);
+          freq_to_time_kernel<<<g, 256, 0, ctx->stream>>>(
+              nt, tq + (size_t)q * nt, wq + (size_t)q * nt, n, (const double2 *)at(o[j].g), nk,
+              nkv, G);
+        }
+        tend(ctx);
+        if ((rc = check_launch(ctx, "freq_to_time_kernel (slow transform)"))) return rc;
+        tbeg(ctx, "solve");
+        lu_solve64_kernel<<<nk, kLuThreads, 0, ctx->stream>>>(
+            (double2 *)at(o[j].A), lu_perm(at(o[j].swp), nk), n, (long long)n * n, G, psi, n);
+        tend(ctx);
+        if ((rc = check_launch(ctx, "lu_solve64_kernel"))) return rc;
+        // fields at the other arcs' nodes, back to time with the shift
+        for (int k = 0; k < J && J > 1; ++k) {
+          if (k == j) continue;
+          const fthms_arc *b = pb->arcs[k];
+          const long long nv = (long long)nk * b->n;
+          zero_kernel<<<grid1d(nv), 256, 0, ctx->stream>>>(V, nv);
+          tbeg(ctx, "field");
+          rc = field_dev_impl(ctx, a, nk, k_dev, psi, n, b->n, b->d_y,
+                              pb->pair_plan[(size_t)j * J + k], V, b->n, 0);
+          tend(ctx);
+          if (rc) return rc;
+          tbeg(ctx, "freq_to_time");
+          rc = to_time(tq + (size_t)q * nt, b->n, V, T);
+          tend(ctx);
+          if (rc) return rc;
+          axpy_kernel<<<grid1d((long long)nt * b->n), 256, 0, ctx->stream>>>(
+              (double2 *)at(o[k].cr), T, (long long)nt * b->n);
+        }
+        if (P) {
+          const long long nv = (long long)nk * P;
+          zero_kernel<<<grid1d(nv), 256, 0, ctx->stream>>>(V, nv);
+          tbeg(ctx, "field");
+          rc = field_dev_impl(ctx, a, nk, k_dev, psi, n, P, pb->d_obs, pb->obs_plan[j], V, P, 0);
+          tend(ctx);
+          if (rc) return rc;
+          tbeg(ctx, "freq_to_time");
+          rc = to_time(tq + (size_t)q * nt, P, V, T);
+          tend(ctx);
+          if (rc) return rc;
+          axpy_kernel<<<grid1d(ntr), 256, 0, ctx->stream>>>(traces, T, ntr);
+        }
+      }
+    }
+    // next step's data: g_k = -chi_k * (masked sum of the other arcs' fields)
+    if (m + 1 < pb->M)
+      for (int k = 0; k < J; ++k) {
+        const int n = pb->arcs[k]->n;
+        const long long nn = (long long)nt * n;
+        chi_scale_kernel<<<grid1d(nn), 256, 0, ctx->stream>>>((const double2 *)at(o[k].cr),
+                                                              pb->d_chi[k], n, nn,
+                                                              (double2 *)at(o[k].g));
+      }
+    if ((rc = check_launch(ctx, "windowed step"))) return rc;
+  }
+  return FTHMS_OK;
+}
+
+}  // namespace fthms
+
+extern "C" {
+
+int fthms_problem_traces_windowed(fthms_problem *pb, int nk, const double *k, const double *w,
+                                  int nt, double dt, int Q, double H,
+                                  const fthms_pulse_train *inc, fthms_c64 *traces) {
+  if (!pb || nk < 1 || !k || !w || nt < 1 || !(dt > 0.0) || Q < 1 || !(H > 0.0) || !inc ||
+      !traces || inc->npulse < 1 || !(inc->sigma > 0.0))
+    return fail(pb ? pb->ctx : nullptr, FTHMS_EINVAL,
+                "bad argument to fthms_problem_traces_windowed");
+  fthms_ctx *ctx = pb->ctx;
+  if (pb->precision != FTHMS_FP64)
+    return fail(ctx, FTHMS_EINVAL, "windowed runs solve in FP64");
+  double kmax = 0.0;
+  for (int l = 0; l < nk; ++l) {
+    if (!(k[l] > 0.0) || !std::isfinite(k[l]) || !std::isfinite(w[l]))
+      return fail(ctx, FTHMS_EINVAL_DATA, "wavenumbers must be finite and > 0");
+    kmax = std::max(kmax, k[l]);
+  }
+  HIPCK(ctx, hipSetDevice(ctx->device));
+  Staging st(ctx);
+  double *dk, *dw;
+  double2 *du;
+  int rc;
+  const int P = std::max(pb->nobs, 1);
+  if ((rc = st.get(&dk, sizeof(double) * nk)) || (rc = st.get(&dw, sizeof(double) * nk)) ||
+      (rc = st.get(&du, sizeof(double2) * (size_t)nt * P)))
+    return rc;
+  HIPCK(ctx, hipMemcpyAsync(dk, k, sizeof(double) * nk, hipMemcpyHostToDevice, ctx->stream));
+  HIPCK(ctx, hipMemcpyAsync(dw, w, sizeof(double) * nk, hipMemcpyHostToDevice, ctx->stream));
+  PulseTrainDev d;
+  d.dx = std::cos(inc->theta);
+  d.dy = std::sin(inc->theta);
+  d.omega0 = inc->omega0;
+  d.sigma = inc->sigma;
+  d.tau0 = inc->tau0;
+  d.period = inc->period;
+  d.npulse = inc->npulse;
+  std::vector<double> kh(k, k + nk);
+  if ((rc = problem_windowed_impl(pb, nk, dk, dw, kh, kmax, nt, dt, Q, H, d, du))) return rc;
+  if (pb->nobs)
+    HIPCK(ctx, hipMemcpyAsync(traces, du, sizeof(double2) * (size_t)nt * pb->nobs,
+                              hipMemcpyDeviceToHost, ctx->stream));
+  HIPCK(ctx, hipStreamSynchronize(ctx->stream));
+  return FTHMS_OK;
+}
+
+}  // extern "C"
