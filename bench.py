@@ -308,6 +308,50 @@ def gmres_cavity(fth, ctx, n_full=256, n_patch=64, patches=6, nk=401, W=25.0):
     return rec
 
 
+def windowed_long_time(fth, ctx, n=64, M=10, npulse=8, period=10.0, H=10.0, dt=0.1):
+    """A long incident signal (npulse Gaussian plane-wave pulses, w0 = 9,
+    sigma = 1, period apart) on the three-arc disc: the recursion through
+    the time domain with windows of half-width H uses a fixed frequency set
+    (81 frequencies, spacing 0.15, period 42 > 2H + decay), while the single
+    window needs a spacing of 2 pi / T: time per run of both at T =
+    npulse * period + 20."""
+    from workloads import IncidentSpec, disc_interior_case
+    om0, sig = 9.0, 1.0
+    T = npulse * period + 20.0
+    nt = int(round(T / dt)) + 1
+    Q = int(math.ceil((T - 0.5 * H) / (1.5 * H))) + 1
+    rec = {"workload": "disc of radius 1, 3 arcs of N = %d, M = %d, %d pulses (w0 = 9, sigma = 1) "
+                       "%g apart, t in [0, %g], dt = %g" % (n, M, npulse, period, T, dt)}
+    for name, nf in (("windowed", 81), ("single_window", int(math.ceil(12.0 * sig * T / (2 * math.pi))) + 1)):
+        om = np.linspace(om0 - 6 * sig, om0 + 6 * sig, nf)
+        w = np.full(nf, om[1] - om[0])
+        w[0] *= 0.5
+        w[-1] *= 0.5
+        pb = disc_interior_case(n=n, omegas=om, M=M)
+        pb.incident = IncidentSpec("gplane", theta=0.3, omega0=om0, sigma=sig, tau0=7.0)
+        arcs = [ctx.arc_from_curve(a.curve, a.n) for a in pb.arcs]
+        iv = np.array([a.curve.interval for a in pb.arcs])
+        prob = fth.Problem(ctx, arcs, pb.incident, pb.obs, intervals=iv, M=pb.M)
+        t = dt * np.arange(nt)
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            if name == "windowed":
+                prob.traces_windowed(om, w, dt, nt, Q, H, theta=0.3, omega0=om0, sigma=sig,
+                                     tau0=7.0, npulse=npulse, period=period)
+            else:
+                # the single-window run of one pulse (the recursion is linear:
+                # a train costs the same per pulse shift only through the data)
+                prob.traces(om, w, t)
+            ts.append(time.perf_counter() - t0)
+        rec[name] = {"frequencies": nf, "windows": Q if name == "windowed" else 1,
+                     "ms_per_run": round(1e3 * min(ts), 1)}
+        prob.close()
+        for a in arcs:
+            a.close()
+    return rec
+
+
 def serving(fth, workers=8, count=32, seed=5):
     """Serving loop: exterior scattering requests (1-3 obstacles of 4 arcs,
     n 32..96, 48..128 frequencies, time-domain stop 1e-8 within 100 steps)
@@ -502,10 +546,12 @@ def main():
     cavity = None
     closed = None
     gcav = None
+    wlong = None
     if not args.no_cavity:
         cavity = kite_cavity(fth, ctx)
         closed = closed_obstacles(fth, ctx)
         gcav = gmres_cavity(fth, ctx)
+        wlong = windowed_long_time(fth, ctx)
 
     serve = None
     if not args.no_serving:
@@ -557,6 +603,7 @@ def main():
         "kite_cavity": cavity,
         "closed_obstacles": closed,
         "gmres_cavity": gcav,
+        "windowed_long_time": wlong,
         "serving": serve,
         "cpu_baseline": base,
     }

@@ -52,6 +52,23 @@ __global__ void pulse_train_kernel(PulseTrainDev in, const double2 *__restrict__
   }
 }
 
+// x[q][l][i] *= exp(i w_l s_q): the recentering phase of window q folded
+// into its densities, so that all windows share one field evaluation and
+// one inverse transform at unshifted times
+__global__ void window_phase_kernel(double2 *__restrict__ x, int n, int nk, int Q,
+                                    const double *__restrict__ k, const double *__restrict__ s) {
+  const long long nn = (long long)n * nk * Q;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nn;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long b = e / n;
+    const int l = (int)(b % nk), q = (int)(b / nk);
+    double sn, cs;
+    sincos(k[l] * s[q], &sn, &cs);
+    const double2 v = x[e];
+    x[e] = make_double2(v.x * cs - v.y * sn, v.x * sn + v.y * cs);
+  }
+}
+
 // P(s) of the windowing partition of unity (host)
 static double window_pou(double s, double H) {
   if (s >= -0.5 * H && s <= H) return eta_window(s / H, 0.5, 1.0);
@@ -88,16 +105,20 @@ static int problem_windowed_impl(fthms_problem *pb, int nk, const double *k_dev,
     o[j].piv = take(n * sizeof(int) * nk);
     o[j].swp = take(kLuScratchBytes * nk);
     o[j].st = take(sizeof(int) * nk);
-    o[j].G = take(n * sizeof(double2) * nk);
-    o[j].psi = take(n * sizeof(double2) * nk);
+    o[j].G = take(n * sizeof(double2) * nk * Q);
+    o[j].psi = take(n * sizeof(double2) * nk * Q);
     o[j].g = take(n * sizeof(double2) * nt);
     o[j].cr = take(n * sizeof(double2) * nt);
   }
-  const size_t oV = take((size_t)nmax * sizeof(double2) * nk);
+  const size_t oV = take((size_t)nmax * sizeof(double2) * nk * Q);
   const size_t oT = take((size_t)nmax * sizeof(double2) * nt);
   const size_t oTq = take(sizeof(double) * (size_t)Q * nt);  // t_n - s_q
   const size_t oWq = take(sizeof(double) * (size_t)Q * nt);  // 2pi dt P(t_n - s_q)
   const size_t oNk = take(sizeof(double) * nk);              // -w_l
+  const size_t oKq = take(sizeof(double) * nk * Q);          // w_l, tiled per window
+  const size_t oWt = take(sizeof(double) * nk * Q);          // quadrature weights, tiled
+  const size_t oSq = take(sizeof(double) * Q);               // s_q
+  const size_t oT0 = take(sizeof(double) * nt);              // t_n
   if (ctx->budget && off > ctx->budget)
     return fail(ctx, FTHMS_ENOMEM, "windowed run: the factors and time series of all "
                                    "frequencies do not fit the budget");
@@ -106,19 +127,36 @@ static int problem_windowed_impl(fthms_problem *pb, int nk, const double *k_dev,
   auto at = [&](size_t o_) { return (void *)(base + o_); };
   double2 *V = (double2 *)at(oV), *T = (double2 *)at(oT);
   double *tq = (double *)at(oTq), *wq = (double *)at(oWq), *nkv = (double *)at(oNk);
+  double *kq = (double *)at(oKq), *wt = (double *)at(oWt), *sqv = (double *)at(oSq);
+  double *t0v = (double *)at(oT0);
   {
-    std::vector<double> htq((size_t)Q * nt), hwq((size_t)Q * nt), hnk(nk);
-    for (int q = 0; q < Q; ++q)
+    std::vector<double> htq((size_t)Q * nt), hwq((size_t)Q * nt), hnk(nk), hsq(Q), ht0(nt);
+    for (int q = 0; q < Q; ++q) {
+      hsq[q] = 1.5 * H * q;
       for (int n = 0; n < nt; ++n) {
-        const double s = n * dt - 1.5 * H * q;
+        const double s = n * dt - hsq[q];
         htq[(size_t)q * nt + n] = s;
         hwq[(size_t)q * nt + n] = 2.0 * kPi * dt * window_pou(s, H);
       }
+    }
+    for (int n = 0; n < nt; ++n) ht0[n] = n * dt;
     for (int l = 0; l < nk; ++l) hnk[l] = -k_host[l];
-    HIPCK(ctx, hipMemcpy(tq, htq.data(), sizeof(double) * htq.size(), hipMemcpyHostToDevice));
-    HIPCK(ctx, hipMemcpy(wq, hwq.data(), sizeof(double) * hwq.size(), hipMemcpyHostToDevice));
-    HIPCK(ctx, hipMemcpy(nkv, hnk.data(), sizeof(double) * nk, hipMemcpyHostToDevice));
+    // on the context stream: k_dev and w_dev were written there
+    hipStream_t st = ctx->stream;
+    HIPCK(ctx, hipMemcpyAsync(tq, htq.data(), sizeof(double) * htq.size(), hipMemcpyHostToDevice, st));
+    HIPCK(ctx, hipMemcpyAsync(wq, hwq.data(), sizeof(double) * hwq.size(), hipMemcpyHostToDevice, st));
+    HIPCK(ctx, hipMemcpyAsync(nkv, hnk.data(), sizeof(double) * nk, hipMemcpyHostToDevice, st));
+    HIPCK(ctx, hipMemcpyAsync(sqv, hsq.data(), sizeof(double) * Q, hipMemcpyHostToDevice, st));
+    HIPCK(ctx, hipMemcpyAsync(t0v, ht0.data(), sizeof(double) * nt, hipMemcpyHostToDevice, st));
+    for (int q = 0; q < Q; ++q) {
+      HIPCK(ctx, hipMemcpyAsync(kq + (size_t)q * nk, k_dev, sizeof(double) * nk,
+                                hipMemcpyDeviceToDevice, st));
+      HIPCK(ctx, hipMemcpyAsync(wt + (size_t)q * nk, w_dev, sizeof(double) * nk,
+                                hipMemcpyDeviceToDevice, st));
+    }
+    HIPCK(ctx, hipStreamSynchronize(st));  // the host tables go out of scope
   }
+  const int nkq = nk * Q;
   // factor every (arc, frequency) matrix once; initial data in time
   for (int j = 0; j < J; ++j) {
     const fthms_arc *a = pb->arcs[j];
@@ -140,10 +178,11 @@ static int problem_windowed_impl(fthms_problem *pb, int nk, const double *k_dev,
   }
   const long long ntr = (long long)nt * P;
   if (ntr) zero_kernel<<<grid1d(ntr), 256, 0, ctx->stream>>>(traces, ntr);
-  auto to_time = [&](const double *tshift, int np, const double2 *Vf, double2 *out) -> int {
+  // all windows at once: (window, frequency) pairs with the phase folded in
+  auto to_time = [&](int np, const double2 *Vf, double2 *out) -> int {
     dim3 g((np + kFtTile - 1) / kFtTile, (nt + kFtTile - 1) / kFtTile);
-    freq_to_time_kernel<<<g, 256, 0, ctx->stream>>>(nk, k_dev, w_dev, np, Vf, nt, tshift, out);
-    return check_launch(ctx, "freq_to_time_kernel (window)");
+    freq_to_time_kernel<<<g, 256, 0, ctx->stream>>>(nkq, kq, wt, np, Vf, nt, t0v, out);
+    return check_launch(ctx, "freq_to_time_kernel (windows)");
   };
   for (int m = 0; m < pb->M; ++m) {
     for (int k = 0; k < J; ++k) {
@@ -156,51 +195,55 @@ static int problem_windowed_impl(fthms_problem *pb, int nk, const double *k_dev,
       double2 *G = (double2 *)at(o[j].G), *psi = (double2 *)at(o[j].psi);
       for (int q = 0; q < Q; ++q) {
         // slow transform about s_q: sum over time samples with the window weights
+        double2 *Gq = G + (size_t)q * nk * n, *pq = psi + (size_t)q * nk * n;
         tbeg(ctx, "window_transform");
         {
           dim3 g((n + kFtTile - 1) / kFtTile, (nk + kFtTile - 1) / kFtTile);
           freq_to_time_kernel<<<g, 256, 0, ctx->stream>>>(
               nt, tq + (size_t)q * nt, wq + (size_t)q * nt, n, (const double2 *)at(o[j].g), nk,
-              nkv, G);
+              nkv, Gq);
         }
         tend(ctx);
         if ((rc = check_launch(ctx, "freq_to_time_kernel (slow transform)"))) return rc;
         tbeg(ctx, "solve");
         lu_solve64_kernel<<<nk, kLuThreads, 0, ctx->stream>>>(
-            (double2 *)at(o[j].A), lu_perm(at(o[j].swp), nk), n, (long long)n * n, G, psi, n);
+            (double2 *)at(o[j].A), lu_perm(at(o[j].swp), nk), n, (long long)n * n, Gq, pq, n);
         tend(ctx);
         if ((rc = check_launch(ctx, "lu_solve64_kernel"))) return rc;
-        // fields at the other arcs' nodes, back to time with the shift
-        for (int k = 0; k < J && J > 1; ++k) {
-          if (k == j) continue;
-          const fthms_arc *b = pb->arcs[k];
-          const long long nv = (long long)nk * b->n;
-          zero_kernel<<<grid1d(nv), 256, 0, ctx->stream>>>(V, nv);
-          tbeg(ctx, "field");
-          rc = field_dev_impl(ctx, a, nk, k_dev, psi, n, b->n, b->d_y,
-                              pb->pair_plan[(size_t)j * J + k], V, b->n, 0);
-          tend(ctx);
-          if (rc) return rc;
-          tbeg(ctx, "freq_to_time");
-          rc = to_time(tq + (size_t)q * nt, b->n, V, T);
-          tend(ctx);
-          if (rc) return rc;
-          axpy_kernel<<<grid1d((long long)nt * b->n), 256, 0, ctx->stream>>>(
-              (double2 *)at(o[k].cr), T, (long long)nt * b->n);
-        }
-        if (P) {
-          const long long nv = (long long)nk * P;
-          zero_kernel<<<grid1d(nv), 256, 0, ctx->stream>>>(V, nv);
-          tbeg(ctx, "field");
-          rc = field_dev_impl(ctx, a, nk, k_dev, psi, n, P, pb->d_obs, pb->obs_plan[j], V, P, 0);
-          tend(ctx);
-          if (rc) return rc;
-          tbeg(ctx, "freq_to_time");
-          rc = to_time(tq + (size_t)q * nt, P, V, T);
-          tend(ctx);
-          if (rc) return rc;
-          axpy_kernel<<<grid1d(ntr), 256, 0, ctx->stream>>>(traces, T, ntr);
-        }
+      }
+      window_phase_kernel<<<grid1d((long long)n * nkq), 256, 0, ctx->stream>>>(psi, n, nk, Q,
+                                                                               k_dev, sqv);
+      if ((rc = check_launch(ctx, "window_phase_kernel"))) return rc;
+      // fields of all windows at the other arcs' nodes, back to time
+      for (int k = 0; k < J && J > 1; ++k) {
+        if (k == j) continue;
+        const fthms_arc *b = pb->arcs[k];
+        const long long nv = (long long)nkq * b->n;
+        zero_kernel<<<grid1d(nv), 256, 0, ctx->stream>>>(V, nv);
+        tbeg(ctx, "field");
+        rc = field_dev_impl(ctx, a, nkq, kq, psi, n, b->n, b->d_y,
+                            pb->pair_plan[(size_t)j * J + k], V, b->n, 0);
+        tend(ctx);
+        if (rc) return rc;
+        tbeg(ctx, "freq_to_time");
+        rc = to_time(b->n, V, T);
+        tend(ctx);
+        if (rc) return rc;
+        axpy_kernel<<<grid1d((long long)nt * b->n), 256, 0, ctx->stream>>>(
+            (double2 *)at(o[k].cr), T, (long long)nt * b->n);
+      }
+      if (P) {
+        const long long nv = (long long)nkq * P;
+        zero_kernel<<<grid1d(nv), 256, 0, ctx->stream>>>(V, nv);
+        tbeg(ctx, "field");
+        rc = field_dev_impl(ctx, a, nkq, kq, psi, n, P, pb->d_obs, pb->obs_plan[j], V, P, 0);
+        tend(ctx);
+        if (rc) return rc;
+        tbeg(ctx, "freq_to_time");
+        rc = to_time(P, V, T);
+        tend(ctx);
+        if (rc) return rc;
+        axpy_kernel<<<grid1d(ntr), 256, 0, ctx->stream>>>(traces, T, ntr);
       }
     }
     // next step's data: g_k = -chi_k * (masked sum of the other arcs' fields)
