@@ -418,8 +418,9 @@ def main():
                     help="run one plain 1 GiB device copy first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only (the solve path shards by frequency; "
-              "no multi-GPU run is part of this build)", file=sys.stderr)
+        print("bench.py measures one GPU only: the solve path would shard by frequency "
+              "(one all-reduce of the traces at the end), and only the one-GPU share "
+              "is implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch

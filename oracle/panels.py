@@ -215,19 +215,20 @@ def adaptive_gl_vec(f, a, b, breaks=(), tol=1e-14, order=16, max_rounds=200):
     raise RuntimeError("adaptive_gl_vec: no convergence")
 
 
-def log_table(arc, tol=1e-14):
+def log_table(arc, tol=1e-14, rows=None):
     """W_ij = int_{panel(j)} log|y_i - y(s)| l_j(s) ds for every node i of
     the arc and node j: adaptive Gauss-Legendre quadrature of the vector of
     Chebyshev moments int log|y_i - y(s)| T_m(s) ds, split at the target
-    when it lies on the panel, then l_j = sum_m C[m, j] T_m.  On the
+    when it lies on the panel, then l_j = sum_m C[m, j] T_m (``rows``: only
+    those rows; the others are NaN).  On the
     target's own panel the distances come from ``PanelArc.ydiff``: where the
     cosine maps cluster the nodes, plain subtraction of nearly equal points
     would lose ~1e-10 of the table."""
     nd = arc.nodes()
     N, n = nd["n"], arc.n
     C = _coef_matrix(arc.phi)
-    W = np.empty((N, N))
-    for i in range(N):
+    W = np.full((N, N), np.nan)
+    for i in (range(N) if rows is None else rows):
         yi = nd["y"][i]
         for p in range(arc.P):
 

@@ -90,6 +90,24 @@ def test_closed_ms_problem(ctx, fth, mixed):
     assert rel(A[0], np.concatenate(ref["alpha_tot"])) < TOL
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_closed_maximum_size(ctx, fth, prec):
+    """1024 nodes (the largest closed patch) at a high wavenumber."""
+    curve = ClosedKite(1.0)
+    spec = IncidentSpec("point", z0=(0.05, 0.1), sigma=0.0)
+    ks = np.array([60.0])
+    say("closed 1024 prec", prec)
+    arc = ctx.closed_from_curve(curve, 1024)
+    rhs = ctx.rhs(arc, ks, spec)
+    psi, _, _ = ctx.solve(arc, ks, rhs, prec)
+    nd = ocl.nodes(curve, 1024)
+    b = -oinc.incident(spec, ks[0], nd["y"])
+    ref = np.linalg.solve(ocl.assemble(nd, ks[0]), b)
+    assert rel(psi[0], ref) < TOL, rel(psi[0], ref)
+    z = np.array([[3.0, 0.0], [0.0, -3.0]])
+    assert rel(ctx.eval_field(arc, ks, psi, z)[0], -oinc.incident(spec, ks[0], z)) < 1e-9
+
+
 def test_closed_error_paths(ctx, fth):
     curve = ClosedEllipse(1.0, 0.6)
     arc = ctx.closed_from_curve(curve, 32)

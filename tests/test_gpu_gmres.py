@@ -113,6 +113,25 @@ def test_gmres_dev_raw_matrices(ctx, fth):
         assert rel(x[s], np.linalg.solve(A[s], b[s])) < 1e-11
 
 
+def test_gmres_maximum_size(ctx, fth):
+    """n = 1024 with the full 256-iteration budget."""
+    import torch
+    rng = np.random.default_rng(9)
+    n = 1024
+    A = np.eye(n) * 2 + (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / (3 * np.sqrt(n))
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    At = torch.from_numpy(np.ascontiguousarray(A.T)[None]).to("cuda")
+    bt = torch.from_numpy(b[None]).to("cuda")
+    xt = torch.empty_like(bt)
+    it = torch.empty(1, dtype=torch.int32, device="cuda")
+    rr = torch.empty(1, dtype=torch.float64, device="cuda")
+    ctx.gmres_dev(At, bt, xt, it, rr, tol=1e-12, maxit=256)
+    torch.cuda.synchronize()
+    _, ito, _ = ogm.gmres(A, b, tol=1e-12, maxit=256)
+    assert abs(int(it.item()) - ito) <= 1
+    assert rel(xt.cpu().numpy()[0], np.linalg.solve(A, b)) < 1e-11
+
+
 def test_gmres_reports_no_convergence(ctx, fth):
     """An unreachable tolerance: FTHMS_ENOCONV from the host entry point."""
     arc = ctx.arc_from_curve(CircularArc(1.0, -1.0, 1.4), 32)

@@ -14,7 +14,7 @@ from oracle import incident as oinc
 from oracle import ms as oms
 from oracle import nystrom as ony
 from oracle import panels as opn
-from workloads import CircularArc, EllipseArc, IncidentSpec, disc_interior_case
+from workloads import CircularArc, EllipseArc, IncidentSpec, Segment, disc_interior_case
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-10
@@ -115,6 +115,34 @@ def test_panel_ms_kite(ctx, fth):
     ref = oms.run_frequency(oms.Layout(pb), om[0])
     assert rel(U[0], ref["U"]) < TOL, rel(U[0], ref["U"])
     assert rel(A[0], np.concatenate(ref["alpha_tot"])) < TOL
+
+
+def test_panel_maximum_size(ctx, fth):
+    """3 x 341 = 1023 nodes (the largest panel arc).  The table on the
+    segment x(t) = (t, 0) against the closed form of the log integral
+    (sum_j W_ij (dt/ds)_j = (1+t)log(1+t) + (1-t)log(1-t) - 2; the oracle's
+    adaptive table is too slow at this size), and on an ellipse the field of
+    a solve against the single-panel arc of 1024 nodes (both converged for
+    this smooth problem)."""
+    say("panel arc 3 x 341: segment table")
+    br = (-1.0, -0.3, 0.4, 1.0)
+    seg = ctx.panel_arc_from_curve(Segment((-1.0, 0.0), (1.0, 0.0)), 341, br)
+    W, _ = seg.panel_table()
+    oarc = opn.PanelArc(Segment((-1.0, 0.0), (1.0, 0.0)), 341, br)
+    t = oarc.nodes()["t"]
+    dts = np.concatenate([oarc.t_of(p, oarc.s)[1] for p in range(oarc.P)])
+    ref = (1 + t) * np.log(1 + t) + (1 - t) * np.log(1 - t) - 2.0
+    assert np.max(np.abs(W @ dts - ref)) < 1e-11
+    say("panel arc 3 x 341: ellipse field")
+    curve = EllipseArc(1.3, 0.7, -0.4, 2.2)
+    arc = ctx.panel_arc_from_curve(curve, 341, (-1.0, -0.2, 0.5, 1.0))
+    spec = IncidentSpec("plane", theta=0.7)
+    ks = np.array([5.0, 40.0])
+    mu, _, _ = ctx.solve(arc, ks, ctx.rhs(arc, ks, spec), 1)
+    plain = ctx.arc_from_curve(curve, 1024)
+    al, _, _ = ctx.solve(plain, ks, ctx.rhs(plain, ks, spec), 0)
+    z = np.array([[0.0, 2.5], [-2.0, -1.5], [2.5, 0.3]])
+    assert rel(ctx.eval_field(arc, ks, mu, z), ctx.eval_field(plain, ks, al, z)) < 1e-9
 
 
 def test_panel_error_paths(ctx, fth):
