@@ -544,6 +544,26 @@ def main():
     if not args.no_uneven:
         uneven = uneven_batch(fth, ctx, torch, max(1, args.steps), args.tol)
 
+    # latency of one solve (N = 512, one wavenumber, inputs resident):
+    # assembly + LU + solve (+ refinement) on the device, host-timed with a
+    # synchronisation after each
+    single = {}
+    kk = k[NK // 2:NK // 2 + 1].contiguous()
+    rhs1 = torch.empty((1, N_ARC), dtype=torch.complex128, device=dev)
+    ctx.rhs_dev(arc, kk, case["incident"], rhs1)
+    x1 = torch.empty_like(rhs1)
+    for p, name in ((fth.FP64, "fp64"), (fth.FP32_REFINED, "refined")):
+        ls = []
+        for r in range(55):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.solve_dev(arc, kk, rhs1, x1, p, args.tol)
+            torch.cuda.synchronize()
+            if r >= 5:
+                ls.append(1e3 * (time.perf_counter() - t0))
+        single[name] = {"p50_ms": round(float(np.percentile(ls, 50)), 3),
+                        "p99_ms": round(float(np.percentile(ls, 99)), 3)}
+
     cavity = None
     closed = None
     gcav = None
@@ -595,6 +615,7 @@ def main():
         "max_rel_err_vs_oracle_sampled": oracle_err,
         "latency_ms_per_batch": {"p50": round(float(np.percentile(lat32, 50)), 3),
                                  "p99": round(float(np.percentile(lat32, 99)), 3)},
+        "latency_single_solve": single,
         "kernel_ms_per_step_refined": {n: round(v[0] / args.steps, 3)
                                        for n, v in r32["kt"].items()},
         "kernel_ms_per_step_fp64": {n: round(v[0] / args.steps, 3)
