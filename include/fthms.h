@@ -485,6 +485,9 @@ int fthms_server_create(int device, size_t hbm_budget, int workers,
                         fthms_server **out);
 /* Waits for running requests; queued ones are cancelled. */
 int fthms_server_destroy(fthms_server *server);
+/* Text of the last error on this server (NULL: of the last failed
+ * fthms_server_create on this thread); the pointer stays valid until the
+ * calling thread's next call of this function. */
 const char *fthms_server_error(const fthms_server *server);
 
 /* Queue a request; *ticket identifies it.  FTHMS_ENOMEM if its estimate

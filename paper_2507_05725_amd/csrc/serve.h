@@ -195,7 +195,12 @@ int fthms_server_destroy(fthms_server *sv) {
 }
 
 const char *fthms_server_error(const fthms_server *sv) {
-  return sv ? sv->err.c_str() : g_create_err.c_str();
+  if (!sv) return g_create_err.c_str();
+  // a copy per calling thread: workers and other callers may replace sv->err
+  static thread_local std::string copy;
+  std::lock_guard<std::mutex> lk(const_cast<fthms_server *>(sv)->mu);
+  copy = sv->err;
+  return copy.c_str();
 }
 
 int fthms_submit(fthms_server *sv, const fthms_request *r, uint64_t *ticket) {
