@@ -98,10 +98,18 @@ typedef struct {
 
 int fthms_abi_version(void);
 
+/* Passed as `hip_stream` to fthms_create: the context creates and owns a
+ * non-blocking stream of its own (default priority), unordered with every
+ * other stream; the caller orders its own work with fthms_sync. */
+#define FTHMS_OWN_STREAM ((void *)(intptr_t)-1)
+
 /* Create a context on HIP device `device`.  `hbm_budget_bytes` caps the
- * device memory the context may hold (0 = no cap).  `hip_stream` is a
- * hipStream_t to order _dev calls on, or NULL for a stream the context owns.
- * Fails with FTHMS_EDEVICE when no gfx950 device is usable. */
+ * device memory the context may hold (0 = no cap).  `hip_stream` is the
+ * hipStream_t that _dev calls are ordered on: NULL is HIP's null (default)
+ * stream, as everywhere in HIP -- the stream PyTorch uses by default, so
+ * _dev calls on torch tensors follow torch's earlier work on it without a
+ * synchronisation; FTHMS_OWN_STREAM asks for a private stream.  Fails with
+ * FTHMS_EDEVICE when no gfx950 device is usable. */
 int fthms_create(fthms_ctx **out, int device, size_t hbm_budget_bytes,
                  void *hip_stream);
 int fthms_destroy(fthms_ctx *ctx);

@@ -19,6 +19,9 @@ LIB_PATH = os.path.join(PKG, "libfthms.so")
 FP64 = 0
 FP32_REFINED = 1
 GMRES = 2
+# Context(stream=OWN_STREAM): the context creates a private stream
+OWN_STREAM = "own"
+_OWN_STREAM_HANDLE = (1 << 64) - 1  # FTHMS_OWN_STREAM, (void *)(intptr_t)-1
 INC_PLANE, INC_GPLANE, INC_POINT = 0, 1, 2
 
 _ERR = {0: "OK", -1: "EINVAL", -2: "EINVAL_DATA", -3: "ENOMEM",
@@ -202,9 +205,16 @@ def incident_struct(spec):
 
 class Context:
     def __init__(self, device=0, hbm_budget=0, stream=None):
+        """stream: a hipStream_t handle (an int), None for HIP's null stream
+        (torch's default stream), or OWN_STREAM for a private one."""
         h = C.c_void_p()
-        rc = _lib.fthms_create(C.byref(h), int(device), int(hbm_budget),
-                               None if stream is None else C.c_void_p(int(stream)))
+        if stream is None or (not isinstance(stream, str) and int(stream) == 0):
+            st = None
+        elif stream == OWN_STREAM:
+            st = C.c_void_p(_OWN_STREAM_HANDLE)
+        else:
+            st = C.c_void_p(int(stream))
+        rc = _lib.fthms_create(C.byref(h), int(device), int(hbm_budget), st)
         if rc:
             raise FthmsError(rc, _lib.fthms_last_error(None).decode())
         self.h = h

@@ -213,8 +213,8 @@ int fthms_create(fthms_ctx **out, int device, size_t hbm_budget_bytes, void *hip
     delete ctx;
     return fail(nullptr, FTHMS_EDEVICE, "hipSetDevice failed");
   }
-  if (hip_stream) {
-    ctx->stream = (hipStream_t)hip_stream;
+  if (hip_stream != FTHMS_OWN_STREAM) {
+    ctx->stream = (hipStream_t)hip_stream;  // NULL: the null stream
   } else {
     if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
       delete ctx;

@@ -115,7 +115,8 @@ int serve_run(fthms_ctx *ctx, fthms_server::Job &jb) {
 
 void serve_worker(fthms_server *sv) {
   fthms_ctx *ctx = nullptr;
-  const int rc0 = fthms_create(&ctx, sv->device, 0, nullptr);
+  // a private stream per worker, so that requests run side by side
+  const int rc0 = fthms_create(&ctx, sv->device, 0, FTHMS_OWN_STREAM);
   for (;;) {
     uint64_t id = 0;
     {

@@ -126,6 +126,45 @@ def test_lu_solve(env, n):
         assert np.linalg.norm(xs[b] - ref) / np.linalg.norm(ref) < 1e-12
 
 
+def test_dev_calls_follow_torch_default_stream(env):
+    """A context on torch's current stream (HIP's null stream; the binding
+    passes handle 0 as NULL) orders its _dev calls after torch's earlier work
+    on it: an LU enqueued right behind a slow product and the copy that fills
+    its input factors the whole input, with no synchronisation between.  A
+    private stream (OWN_STREAM) gives the same factors once the caller has
+    synchronised."""
+    fth, ctx, torch = env
+    n, nb = 512, 64
+    g = torch.Generator(device="cuda").manual_seed(3)
+    A0 = torch.randn((nb, n, n), dtype=torch.complex64, device="cuda", generator=g)
+    X = torch.randn((4096, 4096), dtype=torch.float32, device="cuda", generator=g)
+    piv = torch.empty((nb, n), dtype=torch.int32, device="cuda")
+    ref = A0.clone()
+    torch.cuda.synchronize()
+    ctx.lu_dev(ref, piv, precision=1)
+    torch.cuda.synchronize()
+    ref_piv = piv.clone()
+    say("lu behind torch work", n, nb)
+    for _ in range(3):
+        A = torch.empty_like(A0)
+        Y = X @ X  # keeps the stream busy for a while
+        A.copy_(A0)
+        ctx.lu_dev(A, piv, precision=1)
+        torch.cuda.synchronize()
+        assert torch.equal(A, ref) and torch.equal(piv, ref_piv)
+        del Y
+    own = fth.Context(0, stream=fth.OWN_STREAM)
+    try:
+        A = A0.clone()
+        piv2 = torch.empty_like(piv)
+        torch.cuda.synchronize()
+        own.lu_dev(A, piv2, precision=1)
+        own.sync()
+        assert torch.equal(A, ref) and torch.equal(piv2, ref_piv)
+    finally:
+        own.close()
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_batched_lu_split_batch_bitwise(env, prec):
     """Large batches are factored as two halves on two streams; every matrix
