@@ -460,7 +460,8 @@ constexpr int kStripW = 64;
 // occupancy target: FP64 strips are LDS-bound at 2 workgroups per CU, FP32
 // strips fit 4 (register budget 256 and 128 per lane)
 template <typename T>
-__global__ __launch_bounds__(kLuThreads, sizeof(T) == 8 ? 2 : 4) void lu_strip_kernel(
+__global__ __launch_bounds__(kLuThreads, sizeof(T) == 8 ? 2 : 3)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3, sizeof(T) == 8 ? 2 : 3))) void lu_strip_kernel(
     cplx_t<T> *Abase, int N, long long mstride, int k0, const int *swapbase,
     const cplx_t<T> *Linv, int batch, int nleft, int nright, const int *status,
     int only_failed) {
@@ -482,33 +483,64 @@ __global__ __launch_bounds__(kLuThreads, sizeof(T) == 8 ? 2 : 4) void lu_strip_k
   const int c0 = right ? k0 + nb + (s - nleft) * kStripW : s * kStripW;
   const int cw = min(kStripW, (right ? N : k0) - c0);
   // ---- row permutation as a gather (read every source, then write), 32
-  // columns at a time through LDS
+  // columns at a time.  No global access of this kernel sits under a bounds
+  // branch: an access under a divergent branch is followed by a wait for it,
+  // which serialises a whole loop of them on the memory latency.  Indices
+  // are clamped into range instead; a clamped pair entry (pair npair - 1,
+  // column cw - 1) copies exactly what that entry's own thread copies, so
+  // its store is a duplicate of the same value.
   const int npair = swp[0];
   for (int e = tid; e < 2 * npair; e += kLuThreads) spair[e] = swp[1 + e];
   __syncthreads();
-  T2 *tmpb = &sX[0][0];  // viewed as [32][kSwapMax + 2]
-  for (int half = 0; half < 2; ++half) {
-    const int cb0 = half * 32;
-    for (int e = tid; e < 32 * npair; e += kLuThreads) {
-      const int c = e & 31, j = e >> 5;
-      if (cb0 + c < cw) tmpb[c * (kSwapMax + 2) + j] = A[spair[2 * j + 1] + (long long)(c0 + cb0 + c) * N];
+  if (npair > 0) {
+    constexpr int kGi = 32 * kSwapMax / kLuThreads;  // entries per thread per half
+    const int nit = (32 * npair + kLuThreads - 1) / kLuThreads;
+    for (int half = 0; half < 2; ++half) {
+      const int cb0 = half * 32;
+      if (cb0 >= cw) break;
+      // real and imaginary parts in scalar arrays, every element set
+      // (entries past the last pair load duplicates of its row): both keep
+      // the arrays in registers
+      T gx[kGi], gy[kGi];
+      int dst[kGi];  // destination element within the matrix
+#pragma unroll
+      for (int it = 0; it < kGi; ++it) {
+        const int e = tid + it * kLuThreads;
+        const int c = min(cb0 + (e & 31), cw - 1), j = min(e >> 5, npair - 1);
+        const int col = (c0 + c) * N;
+        const T2 v = A[spair[2 * j + 1] + col];
+        gx[it] = v.x;
+        gy[it] = v.y;
+        dst[it] = spair[2 * j] + col;
+      }
+      __syncthreads();  // every source read before any row is overwritten
+#pragma unroll
+      for (int it = 0; it < kGi; ++it)
+        if (it < nit) A[dst[it]] = mk<T>(gx[it], gy[it]);  // uniform test
+      __syncthreads();
     }
-    __syncthreads();
-    for (int e = tid; e < 32 * npair; e += kLuThreads) {
-      const int c = e & 31, j = e >> 5;
-      if (cb0 + c < cw) A[spair[2 * j] + (long long)(c0 + cb0 + c) * N] = tmpb[c * (kSwapMax + 2) + j];
-    }
-    __syncthreads();
   }
   if (!right) return;
   // ---- U12 for this strip: X = L11^{-1} A12 on the matrix cores, with
   // the inverse from the panel kernel; A12 in LDS as the B operand, the
   // product kept in registers, then written over it (and to memory)
   const int lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
-  const int kpad = (nb + 3) & ~3;
-  for (int e = tid; e < kLuNB * kStripW; e += kLuThreads) {
-    const int r = e / kStripW, c = e % kStripW;
-    sX[r][c] = (r < nb && c < cw) ? A[(k0 + r) + (long long)(c0 + c) * N] : mk<T>(0, 0);
+  {
+    constexpr int kSi = kLuNB * kStripW / kLuThreads;
+    T gx[kSi], gy[kSi];
+#pragma unroll
+    for (int it = 0; it < kSi; ++it) {
+      const int e = tid + it * kLuThreads, r = e / kStripW, c = e % kStripW;
+      const T2 v = A[(k0 + min(r, nb - 1)) + (c0 + min(c, cw - 1)) * N];
+      gx[it] = v.x;
+      gy[it] = v.y;
+    }
+#pragma unroll
+    for (int it = 0; it < kSi; ++it) {
+      const int e = tid + it * kLuThreads, r = e / kStripW, c = e % kStripW;
+      const bool ok = r < nb && c < cw;
+      sX[r][c] = mk<T>(ok ? gx[it] : T(0), ok ? gy[it] : T(0));
+    }
   }
   __syncthreads();
   {
@@ -522,9 +554,19 @@ __global__ __launch_bounds__(kLuThreads, sizeof(T) == 8 ? 2 : 4) void lu_strip_k
         xi[cb][r] = 0;
       }
     const int arow = 16 * wave + li;
-#pragma unroll 1
-    for (int kk = 0; kk < kpad; kk += 4) {
-      const T2 fa = lv[arow + kLuNB * (kk + lk)];
+    // every fragment of this wave's rows of L11^{-1} (64 x 64, always in
+    // bounds) in flight at once
+    T2 fl[kLuNB / 4];
+#pragma unroll
+    for (int st = 0; st < kLuNB / 4; ++st) fl[st] = lv[arow + kLuNB * (4 * st + lk)];
+    __builtin_amdgcn_sched_barrier(0);
+    // all 16 steps even for a partial last block (nb < 64): there the
+    // inverse is zero outside the block and so are the staged rows >= nb,
+    // and a loop without an exit lets every load above stay in flight
+#pragma unroll
+    for (int st = 0; st < kLuNB / 4; ++st) {
+      const int kk = 4 * st;
+      const T2 fa = fl[st];
       const T ar = fa.x, ai = fa.y, nai = -fa.y;
       T br[4], bi[4];
 #pragma unroll
@@ -553,7 +595,7 @@ __global__ __launch_bounds__(kLuThreads, sizeof(T) == 8 ? 2 : 4) void lu_strip_k
         const int row = 16 * wave + Mma<T>::crow(lk, r), col = cb * 16 + li;
         const T2 v = mk<T>(xr[cb][r], xi[cb][r]);
         sX[row][col] = v;
-        if (row < nb && col < cw) A[(k0 + row) + (long long)(c0 + col) * N] = v;
+        if (row < nb && col < cw) A[(k0 + row) + (c0 + col) * N] = v;
       }
     __syncthreads();
   }
@@ -561,52 +603,65 @@ __global__ __launch_bounds__(kLuThreads, sizeof(T) == 8 ? 2 : 4) void lu_strip_k
   for (int r0 = k0 + nb; r0 < N; r0 += 64) {
     const int rw = r0 + 16 * wave;  // first row of this wave
     if (rw >= N) continue;
-    acc_t cr[4], ci[4];
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-      const int col = cb * 16 + li;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = rw + Mma<T>::crow(lk, r);
-        T2 v = mk<T>(0, 0);
-        if (row < N && col < cw) v = A[row + (long long)(c0 + col) * N];
-        cr[cb][r] = v.x;
-        ci[cb][r] = v.y;
-      }
-    }
-    // all L21 fragments of this tile in one round trip
-    const int arow = rw + li;
-    const T2 *ap = A + arow + (long long)k0 * N;
+    // C tile and L21 fragments in one round trip, indices clamped (no
+    // selects either: the compiler turns a select of a load back into a
+    // branch).  Clamped C entries (rows >= N, columns >= cw) only feed
+    // outputs that are never stored; clamped L21 columns (kc >= nb, in a
+    // partial last block) meet the zero rows >= nb of U12.  The products
+    // accumulate from zero and C is added at the end, so that the C loads
+    // have the whole product chain to arrive.
+    // Issue order: the L21 fragments (needed first, in step order), then C;
+    // memory returns count down in issue order, so step st waits for its
+    // own fragment only.  The scheduling barrier keeps the compiler from
+    // sinking the loads towards their uses.
+    const int arow = min(rw + li, N - 1) + k0 * N;
     T2 fa[kLuNB / 4];
 #pragma unroll
-    for (int st = 0; st < kLuNB / 4; ++st) {
-      const int kc = 4 * st + lk;
-      fa[st] = (arow < N && kc < nb) ? ap[(long long)kc * N] : mk<T>(0, 0);
+    for (int st = 0; st < kLuNB / 4; ++st) fa[st] = A[arow + min(4 * st + lk, nb - 1) * N];
+    const int ccl = c0 + min(li, cw - 1);  // clamped column of cb = 0
+    T cx[4][4], cy[4][4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      const int colc = min(ccl + cb * 16, c0 + cw - 1);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = min(rw + Mma<T>::crow(lk, r), N - 1);
+        const T2 v = A[row + colc * N];
+        cx[cb][r] = v.x;
+        cy[cb][r] = v.y;
+      }
     }
+    __builtin_amdgcn_sched_barrier(0);
+    acc_t cr[4], ci[4];
 #pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        cr[cb][r] = 0;
+        ci[cb][r] = 0;
+      }
+#pragma unroll
+    // all 16 steps (zero fragments and rows beyond a partial block)
     for (int st = 0; st < kLuNB / 4; ++st) {
-      const int kk = 4 * st;
-      if (kk < kpad) {
-        const T ar = -fa[st].x, ai = -fa[st].y, pai = fa[st].y;
-        T br[4], bi[4];
-        const int krow = kk + lk;
+      const T ar = -fa[st].x, ai = -fa[st].y, pai = fa[st].y;
+      T br[4], bi[4];
+      const int krow = 4 * st + lk;
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-          const T2 bv = sX[krow][cb * 16 + li];
-          br[cb] = bv.x;
-          bi[cb] = bv.y;
-        }
-        // C - A B:  re += (-Ar) Br + Ai Bi ;  im += (-Ar) Bi + (-Ai) Br
+      for (int cb = 0; cb < 4; ++cb) {
+        const T2 bv = sX[krow][cb * 16 + li];
+        br[cb] = bv.x;
+        bi[cb] = bv.y;
+      }
+      // C - A B:  re += (-Ar) Br + Ai Bi ;  im += (-Ar) Bi + (-Ai) Br
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-          cr[cb] = Mma<T>::run(ar, br[cb], cr[cb]);
-          ci[cb] = Mma<T>::run(ar, bi[cb], ci[cb]);
-        }
+      for (int cb = 0; cb < 4; ++cb) {
+        cr[cb] = Mma<T>::run(ar, br[cb], cr[cb]);
+        ci[cb] = Mma<T>::run(ar, bi[cb], ci[cb]);
+      }
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-          cr[cb] = Mma<T>::run(pai, bi[cb], cr[cb]);
-          ci[cb] = Mma<T>::run(ai, br[cb], ci[cb]);
-        }
+      for (int cb = 0; cb < 4; ++cb) {
+        cr[cb] = Mma<T>::run(pai, bi[cb], cr[cb]);
+        ci[cb] = Mma<T>::run(ai, br[cb], ci[cb]);
       }
     }
 #pragma unroll
@@ -615,7 +670,8 @@ __global__ __launch_bounds__(kLuThreads, sizeof(T) == 8 ? 2 : 4) void lu_strip_k
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = rw + Mma<T>::crow(lk, r);
-        if (row < N && col < cw) A[row + (long long)(c0 + col) * N] = mk<T>(cr[cb][r], ci[cb][r]);
+        if (row < N && col < cw)
+          A[row + (c0 + col) * N] = mk<T>(cx[cb][r] + cr[cb][r], cy[cb][r] + ci[cb][r]);
       }
     }
   }
