@@ -63,6 +63,14 @@ __global__ __launch_bounds__(kGmresThreads) void gmres_kernel(
   double2 *x = xbase + (long long)sys * xstride;
   double2 *V = work + (long long)sys * wstride;
   double2 *R = V + (long long)(maxit + 1) * N;
+  // this thread's rows tid + 256 q, clamped into the matrix
+  int rowc[kGmresRows];
+  double rmask[kGmresRows];  // 1 for a row of the matrix, 0 for a clamped one
+#pragma unroll
+  for (int q = 0; q < kGmresRows; ++q) {
+    rowc[q] = min(tid + q * kGmresThreads, N - 1);
+    rmask[q] = tid + q * kGmresThreads < N ? 1.0 : 0.0;
+  }
   // v_0 = b / |b|
   double2 w[kGmresRows];
   double2 p = make_double2(0.0, 0.0);
@@ -98,22 +106,41 @@ __global__ __launch_bounds__(kGmresThreads) void gmres_kernel(
     __syncthreads();
     for (int i = tid; i < N; i += kGmresThreads) sv[i] = V[(long long)j * N + i];
     __syncthreads();
-    // w = A v_j
+    // w = A v_j, four columns per batch with all their loads in flight.
+    // Rows are clamped into the matrix rather than tested (a load under a
+    // divergent test is waited for before the next one is issued); the
+    // clamped rows' sums are dropped after the sweep.
 #pragma unroll
     for (int q = 0; q < kGmresRows; ++q) w[q] = make_double2(0.0, 0.0);
-    for (int c = 0; c < N; ++c) {
-      const double2 vc = sv[c];
-      const double2 *ac = A + (long long)c * N;
+    int c = 0;
+    for (; c + 4 <= N; c += 4) {
+      double2 a[4][kGmresRows];
 #pragma unroll
-      for (int q = 0; q < kGmresRows; ++q) {
-        const int i = tid + q * kGmresThreads;
-        if (i < N) {
-          const double2 a = ac[i];
-          w[q].x += a.x * vc.x - a.y * vc.y;
-          w[q].y += a.x * vc.y + a.y * vc.x;
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < kGmresRows; ++q) a[u][q] = A[(long long)(c + u) * N + rowc[q]];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double2 vc = sv[c + u];
+#pragma unroll
+        for (int q = 0; q < kGmresRows; ++q) {
+          w[q].x += a[u][q].x * vc.x - a[u][q].y * vc.y;
+          w[q].y += a[u][q].x * vc.y + a[u][q].y * vc.x;
         }
       }
     }
+    for (; c < N; ++c) {
+      const double2 vc = sv[c];
+#pragma unroll
+      for (int q = 0; q < kGmresRows; ++q) {
+        const double2 a = A[(long long)c * N + rowc[q]];
+        w[q].x += a.x * vc.x - a.y * vc.y;
+        w[q].y += a.x * vc.y + a.y * vc.x;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kGmresRows; ++q)
+      if (tid + q * kGmresThreads >= N) w[q] = make_double2(0.0, 0.0);
     // modified Gram-Schmidt: h_i = <v_i, w>, w -= h_i v_i
     for (int i2 = 0; i2 <= j; ++i2) {
       const double2 *vi = V + (long long)i2 * N;
@@ -121,8 +148,10 @@ __global__ __launch_bounds__(kGmresThreads) void gmres_kernel(
       double2 vr[kGmresRows];
 #pragma unroll
       for (int q = 0; q < kGmresRows; ++q) {
-        const int i = tid + q * kGmresThreads;
-        vr[q] = i < N ? vi[i] : make_double2(0.0, 0.0);
+        // clamped rows are zeroed by a multiply (a select of a load would
+        // be turned back into a branch); basis entries are finite
+        const double2 v = vi[rowc[q]];
+        vr[q] = make_double2(v.x * rmask[q], v.y * rmask[q]);
         // conj(v) w
         s.x += vr[q].x * w[q].x + vr[q].y * w[q].y;
         s.y += vr[q].x * w[q].y - vr[q].y * w[q].x;

@@ -279,25 +279,42 @@ __global__ __launch_bounds__(kLuThreads) void lu_panel_kernel(cplx_t<T> *Abase, 
       }
       __syncthreads();
     }
-    // lower rows of the panel: load and apply every earlier panel at once
+    // lower rows of the panel: load and apply every earlier panel at once.
+    // All loads are issued before any value is converted (a conversion
+    // right after each load, or a load under a bounds test, would wait for
+    // it); out-of-range entries are clamped loads zeroed by a multiply.
     double2 v[R][kLuPW];
+    {
+      T2 raw[R][kLuPW];
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int row = p0 + tid + kLuThreads * q;
+      for (int q = 0; q < R; ++q) {
+        const int rowc = min(p0 + tid + kLuThreads * q, N - 1);
 #pragma unroll
-      for (int c = 0; c < kLuPW; ++c)
-        v[q][c] = (row < N && c < pw) ? to_d2(A[row + (long long)(p0 + c) * N])
-                                      : make_double2(0.0, 0.0);
-    }
-    // earlier L columns, 8 at a time (independent read-only loads)
-    for (int j0 = 0; j0 < lead; j0 += kLuPW) {
-      T2 lv[R][kLuPW];
+        for (int c = 0; c < kLuPW; ++c) raw[q][c] = A[rowc + (long long)(p0 + min(c, pw - 1)) * N];
+      }
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         const int row = p0 + tid + kLuThreads * q;
 #pragma unroll
-        for (int t = 0; t < kLuPW; ++t)
-          lv[q][t] = row < N ? A[row + (long long)(k0 + j0 + t) * N] : mk<T>(0, 0);
+        for (int c = 0; c < kLuPW; ++c) {
+          const double m = (row < N && c < pw) ? 1.0 : 0.0;
+          const double2 d = to_d2(raw[q][c]);
+          v[q][c] = make_double2(d.x * m, d.y * m);
+        }
+      }
+    }
+    // earlier L columns, 8 at a time (independent read-only loads)
+    // (rows past N: clamped loads zeroed by a multiply, as above)
+    double rmask[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) rmask[q] = p0 + tid + kLuThreads * q < N ? 1.0 : 0.0;
+    for (int j0 = 0; j0 < lead; j0 += kLuPW) {
+      T2 lv[R][kLuPW];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int rowc = min(p0 + tid + kLuThreads * q, N - 1);
+#pragma unroll
+        for (int t = 0; t < kLuPW; ++t) lv[q][t] = A[rowc + (long long)(k0 + j0 + t) * N];
       }
 #pragma unroll
       for (int t = 0; t < kLuPW; ++t) {
@@ -308,7 +325,8 @@ __global__ __launch_bounds__(kLuThreads) void lu_panel_kernel(cplx_t<T> *Abase, 
         for (int c = 0; c < kLuPW; ++c) u[c] = sm.big.a.ut[j0 + t][c];
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-          const double2 l = to_d2(lv[q][t]);
+          const double2 ld = to_d2(lv[q][t]);
+          const double2 l = make_double2(ld.x * rmask[q], ld.y * rmask[q]);
 #pragma unroll
           for (int c = 0; c < kLuPW; ++c) v[q][c] = cfms(v[q][c], l, u[c]);
         }
@@ -378,10 +396,23 @@ __global__ __launch_bounds__(kLuThreads) void lu_panel_kernel(cplx_t<T> *Abase, 
     // the panel's row swaps for the other block columns, as a gather
     const int wl = p0 - k0, wr = k0 + nb - p0 - pw;
     const int npr = sm.npr;
-    for (int e = tid; e < (wl + wr) * npr; e += kLuThreads) {
-      const int ce = e / npr, j = e % npr;
-      const int col = ce < wl ? k0 + ce : p0 + pw + (ce - wl);
-      sm.big.gat[ce][j] = to_d2(A[sm.pr_src[j] + (long long)col * N]);
+    if ((wl + wr) * npr > 0) {
+      // at most 56 columns x 16 rows: four entries per thread, loads first
+      constexpr int kGi = (kLuNB * 2 * kLuPW + kLuThreads - 1) / kLuThreads;
+      const int tot = (wl + wr) * npr;
+      T2 raw[kGi];
+#pragma unroll
+      for (int it = 0; it < kGi; ++it) {
+        const int e = min(tid + it * kLuThreads, tot - 1);
+        const int ce = e / npr, j = e % npr;
+        const int col = ce < wl ? k0 + ce : p0 + pw + (ce - wl);
+        raw[it] = A[sm.pr_src[j] + (long long)col * N];
+      }
+#pragma unroll
+      for (int it = 0; it < kGi; ++it) {
+        const int e = tid + it * kLuThreads;
+        if (e < tot) sm.big.gat[e / npr][e % npr] = to_d2(raw[it]);
+      }
     }
     __syncthreads();
     for (int e = tid; e < (wl + wr) * npr; e += kLuThreads) {
