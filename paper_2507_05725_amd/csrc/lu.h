@@ -1,5 +1,5 @@
 // Batched dense complex LU with partial pivoting, triangular solves and
-// FP64 iterative refinement; one 256-thread workgroup per matrix.
+// FP64 iterative refinement.
 //
 // The solve of the first-kind open-arc system (Section 3.2, eq.
 // FDBIEk-interior; the paper states the subproblems are solved by direct
@@ -8,19 +8,22 @@
 //
 // Right-looking blocked LU, two kernels per block of NB = 64 columns:
 //
-//   lu_panel_kernel  (one workgroup per matrix)  factors the m x 64 block
-//     in inner panels of PW = 8 columns held in registers (FP64 partial
-//     pivoting: pivot = largest |re| + |im|, first index on ties), with the
-//     in-block triangular solves and updates in FP64 on the VALU, and
-//     writes the block's net row permutation as (destination, source) pairs;
+//   the panel  factors the m x 64 block with partial pivoting (pivot =
+//     largest |re| + |im|, first index on ties) and writes L11^{-1} and the
+//     block's net row permutation as (destination, source) pairs: either
+//     lu_panel_reg_kernel (panel.h; the whole block in registers, one
+//     1024-thread workgroup per matrix, used whenever the block fits) or
+//     lu_panel_kernel (one 256-thread workgroup per matrix, inner panels of
+//     PW = 8 columns in registers, in-block solves and updates in FP64 on
+//     the VALU);
 //   lu_strip_kernel  (one workgroup per 64-column strip of one matrix,
 //     XCD-aware: all strips of a matrix land on the same XCD and share its
-//     L2) applies the permutation to its columns as a gather, solves
-//     U12 = L11^{-1} A12 for its 64 columns into LDS (FP64 arithmetic), and
-//     updates the strip below, A22 -= L21 U12, on the matrix cores: complex
-//     products as four real 16x16x4 MFMA chains (f64 for the FP64 form, f32
-//     with f32 accumulation for the refined form), U12 as the LDS-resident
-//     B operand, L21 fragments streamed from memory.
+//     L2) applies the permutation to its columns as a gather, forms
+//     U12 = L11^{-1} A12 for its 64 columns on the matrix cores into LDS, and
+//     updates the strip below, A22 -= L21 U12: complex products as four real
+//     16x16x4 MFMA chains (f64 for the FP64 form, f32 with f32 accumulation
+//     for the refined form), U12 as the LDS-resident B operand, the L21
+//     fragments and the C tile of each 64-row tile loaded in one round trip.
 #pragma once
 
 #include "common.h"
