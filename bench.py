@@ -629,8 +629,8 @@ def main():
     if not args.no_cpu_baseline:
         idx = np.linspace(0, NK - 1, 64).astype(int)
         rows = a32[idx].cpu().numpy()
-        single, oracle_err = cpu_single_leg(case, k_np[idx], rows)
-        base = dict(pool_base, single_core=single)
+        one_core, oracle_err = cpu_single_leg(case, k_np[idx], rows)
+        base = dict(pool_base, single_core=one_core)
 
     lat32 = np.array(r32["lat"]) * 1000.0
     line = {
