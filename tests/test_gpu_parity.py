@@ -68,6 +68,26 @@ def test_plain_segment_case_full(ctx, fth, prec):
         assert np.all(iters >= 1), iters
 
 
+def test_refined_fallback_to_fp64(ctx, fth):
+    """A refinement tolerance no solve can reach sends every refined solve
+    through its iteration cap to the FP64 redo (iters = -1): the redo
+    factors the same FP64 matrix with the FP64 kernels, so it matches the
+    FP64 form and the oracle."""
+    case = plain_segment_case()
+    k = case["k"][::8]
+    say("refined fallback nk", k.size)
+    arc = ctx.arc_from_curve(case["curve"], case["n"])
+    rhs = ctx.rhs(arc, k, case["incident"])
+    a64, it64, _ = ctx.solve(arc, k, rhs, fth.FP64)
+    a32, it32, _ = ctx.solve(arc, k, rhs, fth.FP32_REFINED, 1e-300)
+    assert np.all(it64 == 0), it64
+    assert np.all(it32 == -1), it32
+    assert rel(a32, a64) < 1e-13, rel(a32, a64)
+    for i, kk in enumerate(k):
+        _, a_ref = oracle_solve(case["curve"], case["n"], kk, case["incident"])
+        assert rel(a32[i], a_ref) < TOL, (i, kk, rel(a32[i], a_ref))
+
+
 @pytest.mark.parametrize("n", [2, 3, 7, 31, 33, 64, 65, 100, 257])
 def test_ragged_sizes(ctx, fth, n):
     curves = [CircularArc(1.3, 0.2, 2.4), EllipseArc(1.2, 0.5, -0.4, 1.9),
