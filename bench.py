@@ -528,6 +528,21 @@ def main():
                             "rhs", "field", "freq_to_time")}
         results[p] = dict(total=total, lat=lat, kt=kt)
 
+    # the same refined steps with every batched LU on one stream, so that the
+    # strip kernel runs with no other kernel beside it (its own efficiency;
+    # the headline keeps the faster two-stream form)
+    os.environ["FTHMS_LU_SPLIT"] = "0"
+    step(fth.FP32_REFINED)
+    torch.cuda.synchronize()
+    ctx.timing_reset()
+    ctx.timing(True)
+    for _ in range(args.steps):
+        step(fth.FP32_REFINED)
+    torch.cuda.synchronize()
+    ctx.timing(False)
+    kt_iso = {name: ctx.timing_read(name) for name in ("lu", "lu_strip")}
+    del os.environ["FTHMS_LU_SPLIT"]
+
     # refinement steps taken, on a sample of 512 wavenumbers
     ks = k[:: NK // 512].contiguous()
     rhs_s = torch.empty((ks.numel(), N_ARC), dtype=torch.complex128, device=dev)
@@ -585,6 +600,17 @@ def main():
                       "FP32 MFMA)",
             "avg_launch_ms": strip["avg_launch_ms"],
             "alg_gflop_per_launch": strip["alg_gflop_per_launch"]}
+
+    ms_iso, n_iso = kt_iso["lu_strip"]
+    avg_iso = ms_iso / max(n_iso, 1)
+    fl_iso = strip_f * NK * nsteps / max(n_iso, 1)
+    ach_iso = fl_iso / (avg_iso / 1e3) / 1e12 if n_iso else 0.0
+    roof_iso = {"achieved": round(ach_iso, 3), "peak": PEAK["fp32_mfma_tflops"],
+                "unit": "TFLOP/s", "frac": round(ach_iso / PEAK["fp32_mfma_tflops"], 4),
+                "avg_launch_ms": round(avg_iso, 4),
+                "alg_gflop_per_launch": round(fl_iso / 1e9, 3),
+                "lu_ms_per_step": round(kt_iso["lu"][0] / nsteps, 3),
+                "kernel": strip_name + ", every LU on one stream (nothing beside it)"}
 
     uneven = None
     if not args.no_uneven:
@@ -668,6 +694,7 @@ def main():
         "kernel_ms_per_step_fp64": {n: round(v[0] / args.steps, 3)
                                     for n, v in r64["kt"].items()},
         "roofline": roof,
+        "roofline_isolated": roof_iso,
         "uneven_batch": uneven,
         "kite_cavity": cavity,
         "closed_obstacles": closed,

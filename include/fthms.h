@@ -263,6 +263,9 @@ int fthms_arc_panel_table(const fthms_arc *arc, double *W, double *w);
  * FP64, -1 for a solve redone in FP64); relres[nk] (optional) the last
  * relative correction |delta|/|alpha|.  FTHMS_ESINGULAR if a pivot is
  * exactly zero (alpha is then not meaningful for that k).
+ * Batches of at least 256 matrices are factored as two half batches on two
+ * streams (same results as one); FTHMS_LU_SPLIT=0 in the environment keeps
+ * them on one stream.
  * precision FTHMS_GMRES solves each assembled system with GMRES in FP64
  * instead (x0 = 0, modified Gram-Schmidt Arnoldi, Givens rotations, no
  * restart; the iterative solver the paper names beside direct ones, §5

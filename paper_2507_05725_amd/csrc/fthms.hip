@@ -763,12 +763,19 @@ static void lu_step(fthms_ctx *ctx, hipStream_t st, cplx_t<T> *A, int N, long lo
 // kernel of the other.
 constexpr int kLuSplitMin = 256;
 
+// FTHMS_LU_SPLIT=0 in the environment keeps every batched LU on one stream
+// (a kernel then runs with nothing beside it, e.g. to time it alone).
+static bool lu_split_allowed() {
+  const char *e = getenv("FTHMS_LU_SPLIT");
+  return !(e && e[0] == '0' && e[1] == '\0');
+}
+
 template <typename T, int R>
 static void lu_blocks(fthms_ctx *ctx, cplx_t<T> *A, int N, long long ms, int *piv, void *scr,
                       int *status, int count, int only_failed, const LuOpts &o) {
   int *swp = (int *)scr;
   cplx_t<T> *linv = (cplx_t<T> *)((char *)scr + sizeof(int) * kSwapStride * (size_t)count);
-  if (only_failed || count < kLuSplitMin || !o.split) {
+  if (only_failed || count < kLuSplitMin || !o.split || !lu_split_allowed()) {
     for (int k0 = 0; k0 < N; k0 += kLuNB)
       lu_step<T, R>(ctx, ctx->stream, A, N, ms, k0, piv, swp, linv, status, count, only_failed,
                     o);

@@ -187,6 +187,17 @@ def test_batched_lu_split_batch_bitwise(env, prec):
     A1 = A.clone()
     piv = torch.empty((nb, n), dtype=torch.int32, device="cuda")
     ctx.lu_dev(A, piv, precision=prec)
+    # the same batch with the two-stream split switched off
+    import os
+    A2 = A1.clone()
+    piv2 = torch.empty_like(piv)
+    os.environ["FTHMS_LU_SPLIT"] = "0"
+    try:
+        ctx.lu_dev(A2, piv2, precision=prec)
+    finally:
+        del os.environ["FTHMS_LU_SPLIT"]
+    torch.cuda.synchronize()
+    assert torch.equal(A2, A) and torch.equal(piv2, piv)
     piv1 = torch.empty((1, n), dtype=torch.int32, device="cuda")
     for b in (0, 1, 150, 151, 152, 153, 299, 300):
         one = A1[b:b + 1].clone()
