@@ -141,7 +141,20 @@ def cpu_pool_leg(case, k_all, budget_s=12.0):
     return {"value": nsol / dt, "unit": "solves/s", "cores": workers, "kind": "oracle",
             "sample": "%d of the %d wavenumbers, evenly spaced, over %d worker processes "
                       "(assembly + LU solve + 256-point field per solve, numpy/scipy FP64, "
-                      "BLAS on one thread each)" % (nsol, len(k_all), workers)}
+                      "BLAS on one thread each)" % (nsol, len(k_all), workers),
+            "cpu_model": cpu_model()}
+
+
+def cpu_model():
+    """The host CPU's model name (Linux), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def cpu_single_leg(case, k_sample, alpha_gpu_rows, budget_s=12.0):
