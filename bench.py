@@ -58,13 +58,14 @@ def lu_block_flops(n, nb=64):
     return panel, strip
 
 
-def source_digest():
+def source_digest(path=None):
     """sha256 of the code of csrc/lu.h (line comments and blank lines
     dropped), so that only a change to the kernels voids the recorded
     traffic."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "paper_2507_05725_amd", "csrc", "lu.h")
+    if path is None:
+        path = os.path.join(ROOT, "paper_2507_05725_amd", "csrc", "lu.h")
     with open(path) as f:
         lines = [re.sub(r"//.*", "", ln).rstrip() for ln in f]
     code = "\n".join(ln for ln in lines if ln.strip())
