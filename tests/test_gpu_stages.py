@@ -77,9 +77,11 @@ def _lu_reconstruct(LU, piv):
     return L @ U, P
 
 
-@pytest.mark.parametrize("n", [1, 5, 8, 9, 16, 64, 65, 130, 300, 512])
+@pytest.mark.parametrize("n", [1, 5, 8, 9, 16, 64, 65, 130, 300, 512, 777, 1024])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_batched_lu(env, n, prec):
+    # n > 512 (FP32) and n > 256 (FP64) take the LDS panel kernel for their
+    # first blocks, the register panel for the rest
     fth, ctx, torch = env
     rng = np.random.default_rng(n)
     nb = 3
