@@ -72,10 +72,11 @@ def source_digest(path=None):
     return hashlib.sha256(code.encode()).hexdigest()
 
 
-def recorded_traffic(kernel):
+def recorded_traffic(kernel, per_launch=None):
     """HBM bytes per launch of `kernel` from the committed counter summary,
-    or None when the summary is absent or the kernel source has changed
-    since the counters were taken."""
+    or None when the summary is absent, the kernel source has changed since
+    the counters were taken, or (per_launch given) its launches covered a
+    different number of matrices."""
     path = os.path.join(ROOT, "profiles", "lu_strip_f512_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -88,6 +89,8 @@ def recorded_traffic(kernel):
     if rec.get("kernel") != kernel or rec.get("lu.h code sha256") != source_digest():
         return None
     try:
+        if per_launch is not None and int(rec["matrices per launch"]) != per_launch:
+            return None
         return float(rec["hbm bytes per launch"])
     except (KeyError, ValueError):
         return None
@@ -605,7 +608,10 @@ def main():
     k64 = lu_kernels(r64, PEAK["fp64_mfma_tflops"])
     strip = k32["lu_strip_kernel"]
     strip_name = "lu_strip_kernel<float>"
-    traffic = recorded_traffic(strip_name)
+    # matrices per strip launch in the timed steps (N / 64 block steps per LU)
+    n_strip = r32["kt"]["lu_strip"][1]
+    per_launch = round(NK * nsteps * (N_ARC // 64) / n_strip) if n_strip else None
+    traffic = recorded_traffic(strip_name, per_launch)
     roof = {"bound": "mfma", "achieved": strip["achieved_tflops"],
             "peak": PEAK["fp32_mfma_tflops"], "unit": "TFLOP/s",
             "frac": strip["frac_of_mfma_peak"],
@@ -613,7 +619,8 @@ def main():
             "kernel": strip_name + " (block triangular solve + trailing update, "
                       "FP32 MFMA)",
             "avg_launch_ms": strip["avg_launch_ms"],
-            "alg_gflop_per_launch": strip["alg_gflop_per_launch"]}
+            "alg_gflop_per_launch": strip["alg_gflop_per_launch"],
+            "matrices_per_launch": per_launch}
 
     ms_iso, n_iso = kt_iso["lu_strip"]
     avg_iso = ms_iso / max(n_iso, 1)

@@ -411,7 +411,7 @@ int fthms_problem_traces(fthms_problem *pb, int nk, const double *k,
  * that are assembled, factored and solved together; the whole batch runs as
  * one HIP graph, captured at the first run and replayed afterwards.  The
  * batch copies its tables to the device and owns a workspace for its largest
- * group (groups are cut to fit 16 GiB or half the context's free budget;
+ * group (groups are cut to fit 32 GiB or half the context's free budget;
  * FTHMS_ENOMEM if one matrix does not fit).  The arcs must outlive the batch.
  * Densities are packed: solve i occupies alpha[off_i, off_i + n_i) with
  * off_i = n_0 + ... + n_{i-1}.  precision and tol as in fthms_solve. */

@@ -228,10 +228,10 @@ int fthms_batch_create(fthms_ctx *ctx, int nb, const fthms_arc *const *arcs, con
   }
   const bool fp32 = precision == FTHMS_FP32_REFINED;
   // buckets by n (largest first), each cut so that its workspace stays
-  // within 16 GiB (or the context's remaining budget)
+  // within kChunkBytes (or half the context's remaining budget)
   std::map<int, std::vector<int>, std::greater<int>> byn;
   for (int i = 0; i < nb; ++i) byn[arcs[i]->n].push_back(i);
-  size_t cap = (size_t)16 << 30;
+  size_t cap = kChunkBytes;
   if (ctx->budget) cap = std::min(cap, ctx->budget > ctx->held ? (ctx->budget - ctx->held) / 2 : 0);
   size_t need = 0;
   for (auto &kv : byn) {

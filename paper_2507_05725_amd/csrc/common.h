@@ -11,6 +11,11 @@ namespace fthms {
 constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr double kEulerGamma = 0.57721566490153286060651209008240243;
 
+// Device memory one batched call keeps in flight for its matrices and their
+// workspace (less under a context budget): 32 GiB of the 288 GB HBM, which
+// holds the 4096 N = 512 matrices of a refined batch (about 26 GB) at once.
+constexpr size_t kChunkBytes = (size_t)32 << 30;
+
 template <typename T> struct cplx;
 template <> struct cplx<double> { using type = double2; };
 template <> struct cplx<float> { using type = float2; };

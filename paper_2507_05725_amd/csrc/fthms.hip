@@ -860,7 +860,7 @@ static size_t per_matrix_bytes(int N, bool fp32) {
 
 static int solve_ws(fthms_ctx *ctx, int N, bool fp32, int nk, SolveWs &w) {
   const size_t per = per_matrix_bytes(N, fp32);
-  size_t cap = (size_t)16 << 30;  // at most 16 GiB of matrices in flight
+  size_t cap = kChunkBytes;
   if (ctx->budget) {
     const size_t avail = ctx->budget > ctx->held ? ctx->budget - ctx->held + ctx->ws_bytes : 0;
     cap = std::min(cap, avail);
@@ -954,7 +954,7 @@ static int gmres_solve_impl(fthms_ctx *ctx, const fthms_arc *arc, int nk, const 
   const int maxit = std::min(N, kGmresMaxIt);
   const size_t per = sizeof(double2) * ((size_t)N * N + (size_t)gmres_wstride(N, maxit)) +
                      sizeof(int) + sizeof(double) + 1024;
-  size_t cap = (size_t)16 << 30;
+  size_t cap = kChunkBytes;
   if (ctx->budget) {
     const size_t avail = ctx->budget > ctx->held ? ctx->budget - ctx->held + ctx->ws_bytes : 0;
     cap = std::min(cap, avail);

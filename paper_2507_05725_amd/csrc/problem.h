@@ -408,7 +408,7 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
            kLuScratchBytes + 4 * n * sizeof(double2) + sizeof(int) + sizeof(double) + 2048;
     nsum += (int)n;
   }
-  size_t cap = (size_t)16 << 30;
+  size_t cap = kChunkBytes;
   if (ctx->budget) {
     const size_t avail = ctx->budget > ctx->held ? ctx->budget - ctx->held + ctx->ws_bytes : 0;
     cap = std::min(cap, avail);
