@@ -51,13 +51,6 @@ template <int CTRL> __device__ __forceinline__ double dpp_v(double x) {
   const int lo = dpp_i<CTRL>((int)(b & 0xffffffffLL)), hi = dpp_i<CTRL>((int)(b >> 32));
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-template <typename T>
-__device__ __forceinline__ void argmax_merge(T &best, int &brow, T ob, int orow) {
-  // branch-free: bitwise operators on the comparison masks
-  const bool take = (ob > best) | ((ob == best) & (orow < brow));
-  best = take ? ob : best;
-  brow = take ? orow : brow;
-}
 template <typename T> __device__ __forceinline__ void swap_pair16(T &a, T &b);
 template <> __device__ __forceinline__ void swap_pair16<int>(int &a, int &b) {
   const auto r = __builtin_amdgcn_permlane16_swap(a, a, false, false);
@@ -99,20 +92,31 @@ template <> __device__ __forceinline__ void swap_pair32<double>(double &a, doubl
   b = __longlong_as_double(((long long)hi2 << 32) | (unsigned int)lo2);
 }
 // Wave-wide argmax of (best, brow): largest value, smallest row on ties;
-// every lane ends with the result.
+// every lane ends with the result.  Two reductions: the wave's largest
+// value, then the smallest row among the lanes holding it (each lane's brow
+// is already its smallest row reaching its best, so this is the smallest
+// row of the wave reaching the maximum).  Values are never NaN here.
 template <typename T> __device__ __forceinline__ void wave_argmax(T &best, int &brow) {
-  argmax_merge(best, brow, dpp_v<0xB1>(best), dpp_i<0xB1>(brow));    // lane ^ 1
-  argmax_merge(best, brow, dpp_v<0x4E>(best), dpp_i<0x4E>(brow));    // lane ^ 2
-  argmax_merge(best, brow, dpp_v<0x141>(best), dpp_i<0x141>(brow));  // mirror in 8
-  argmax_merge(best, brow, dpp_v<0x140>(best), dpp_i<0x140>(brow));  // mirror in 16
-  T b2;
-  int r2;
-  swap_pair16<T>(best, b2);
-  swap_pair16<int>(brow, r2);
-  argmax_merge(best, brow, b2, r2);
-  swap_pair32<T>(best, b2);
-  swap_pair32<int>(brow, r2);
-  argmax_merge(best, brow, b2, r2);
+  T m = best, m2;
+  m = fmax(m, dpp_v<0xB1>(m));   // lane ^ 1
+  m = fmax(m, dpp_v<0x4E>(m));   // lane ^ 2
+  m = fmax(m, dpp_v<0x141>(m));  // mirror in 8
+  m = fmax(m, dpp_v<0x140>(m));  // mirror in 16
+  swap_pair16<T>(m, m2);
+  m = fmax(m, m2);
+  swap_pair32<T>(m, m2);
+  m = fmax(m, m2);
+  int r = best == m ? brow : 0x7fffffff, r2;
+  r = min(r, dpp_i<0xB1>(r));
+  r = min(r, dpp_i<0x4E>(r));
+  r = min(r, dpp_i<0x141>(r));
+  r = min(r, dpp_i<0x140>(r));
+  swap_pair16<int>(r, r2);
+  r = min(r, r2);
+  swap_pair32<int>(r, r2);
+  r = min(r, r2);
+  best = m;
+  brow = r;
 }
 
 template <typename T> __device__ __forceinline__ cplx_t<T> tmul(cplx_t<T> a, cplx_t<T> b) {
