@@ -167,7 +167,7 @@ __device__ __forceinline__ cplx_t<T> row_value(const cplx_t<T> (&a)[RL][4], int 
 }
 
 // One column c = 4 cw + J of the block.  used: bit i set if row lane + 64 i
-// has been chosen as a pivot.  rowat/pos (wave 0): row at each position,
+// has been chosen as a pivot or lies past the block.  rowat/pos (wave 0): row at each position,
 // position of each row.
 template <typename T, int RL, int J>
 __device__ __forceinline__ void panel_reg_column(cplx_t<T> (&a)[RL][4], int &used,
@@ -187,7 +187,7 @@ __device__ __forceinline__ void panel_reg_column(cplx_t<T> (&a)[RL][4], int &use
     int brow = 0x7fffffff;
 #pragma unroll
     for (int i = 0; i < RL; ++i) {
-      const bool ok = ((used >> i) & 1) == 0 && lane < m - 64 * i;
+      const bool ok = ((used >> i) & 1) == 0;
       double mag = fabs((double)a[i][J].x) + fabs((double)a[i][J].y);
       mag = mag == mag ? mag : -0.5;
       const bool take = ok & (mag > best);
@@ -208,7 +208,7 @@ __device__ __forceinline__ void panel_reg_column(cplx_t<T> (&a)[RL][4], int &use
     const T2 inv = nz ? from_d2<T>(trcp<double>(to_d2(u[J]))) : mk<T>(T(0), T(0));
 #pragma unroll
     for (int i = 0; i < RL; ++i) {
-      const bool below = ((used >> i) & 1) == 0 && lane < m - 64 * i;
+      const bool below = ((used >> i) & 1) == 0;
       const T2 l = below ? tmul<T>(a[i][J], inv) : mk<T>(T(0), T(0));
       if (below) a[i][J] = l;
       sm.lbuf[b][lane + 64 * i] = l;
@@ -267,16 +267,24 @@ __global__ __launch_bounds__(kPrThreads) void lu_panel_reg_kernel(
   const int m = N - k0, nb = min(kLuNB, m);
   // this wave's first column, row k0 (a scalar base; lanes add row offsets)
   T2 *colp = A + k0 + (long long)(k0 + 4 * w) * N;
+  // The block, loaded with row and column indices clamped into it: rows past
+  // the block are marked used below (never pivots, zero multipliers, never
+  // stored) and columns past a partial block are never factored or stored,
+  // so their values do not matter; no per-slot mask is needed here.
+  const T2 *blk = A + k0 + (long long)k0 * N;
   T2 a[RL][4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int col = 4 * w + j;
+    const long long coff = (long long)min(4 * w + j, nb - 1) * N;
 #pragma unroll
-    for (int i = 0; i < RL; ++i)
-      a[i][j] = (lane < m - 64 * i && col < nb) ? colp[lane + 64 * i + (long long)j * N]
-                                                : mk<T>(T(0), T(0));
+    for (int i = 0; i < RL; ++i) a[i][j] = blk[min(lane + 64 * i, m - 1) + coff];
   }
+  // used: bit i set if row lane + 64 i is a pivot already or lies past the
+  // block (rows >= m are marked from the start, so that one bit test
+  // excludes both and no per-slot row mask stays live across the loop)
   int used = 0, rowat[RL], pos[RL];
+#pragma unroll
+  for (int i = 0; i < RL; ++i) used |= lane < m - 64 * i ? 0 : 1 << i;
 #pragma unroll
   for (int i = 0; i < RL; ++i) rowat[i] = pos[i] = lane + 64 * i;
   if (tid == 0) sm.zero_pivot = 0x7fffffff;
@@ -315,9 +323,12 @@ __global__ __launch_bounds__(kPrThreads) void lu_panel_reg_kernel(
   if (tid < nb) piv[k0 + tid] = k0 + sm.ipiv[tid];
   // store every row at its final position; stage L11 (strictly lower part)
   // transposed, by final position
+  // this lane's rows in the block: slots i < nslot (written in a form of its
+  // own, so that the compiler does not keep masks from the top of the kernel)
+  const int nslot = (m - lane + 63) >> 6;
 #pragma unroll
   for (int i = 0; i < RL; ++i) {
-    if (lane < m - 64 * i) {
+    if (i < nslot) {
       const int fp = sm.posv[lane + 64 * i];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
