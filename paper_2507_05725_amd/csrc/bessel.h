@@ -76,7 +76,8 @@ FTHMS_HD void bessel_asym(double z, double &j0, double &y0) {
     Q = Q * w + c.q[k];
   }
   Q *= iz;
-  const double s = sin(z), co = cos(z);
+  double s, co;
+  sincos(z, &s, &co);
   const double r2 = 0.70710678118654752440084436210484904;
   const double cm = (co + s) * r2, sm = (s - co) * r2;
   const double f = sqrt((2.0 / kPi) * iz);
@@ -190,7 +191,8 @@ FTHMS_HD void bessel_asym1(double z, double &j1, double &y1) {
     Q = Q * w + c.q[k];
   }
   Q *= iz;
-  const double s = sin(z), co = cos(z);
+  double s, co;
+  sincos(z, &s, &co);
   const double r2 = 0.70710678118654752440084436210484904;
   const double cm = (s - co) * r2, sm = -(s + co) * r2;
   const double f = sqrt((2.0 / kPi) * iz);
