@@ -701,14 +701,14 @@ struct LuOpts {
 };
 
 // Panel of the block at k0: register-resident kernel when the block fits
-// (m = N - k0 <= 512 in FP32, <= 256 in FP64), else the LDS/global kernel.
+// (m = N - k0 <= 512 in FP32, <= 320 in FP64), else the LDS/global kernel.
 template <typename T, int R>
 static void launch_panel(hipStream_t st, cplx_t<T> *A, int N, long long ms, int k0, int *piv,
                          int *swp, cplx_t<T> *linv, int *status, int count, int only_failed,
                          bool reg_panel) {
   const int m = N - k0;
   const int rl = (m + 63) / 64;
-  const int rl_max = !reg_panel ? 0 : sizeof(T) == 4 ? 8 : 4;
+  const int rl_max = !reg_panel ? 0 : sizeof(T) == 4 ? 8 : 5;
 #define FTHMS_PANEL_REG(RL)                                                            \
   lu_panel_reg_kernel<T, RL><<<count, kPrThreads, 0, st>>>(A, N, ms, k0, piv, swp, linv, \
                                                            status, only_failed)
@@ -720,9 +720,12 @@ static void launch_panel(hipStream_t st, cplx_t<T> *A, int N, long long ms, int 
       case 4: FTHMS_PANEL_REG(4); return;
       default: break;
     }
+    if (rl == 5) {
+      FTHMS_PANEL_REG(5);
+      return;
+    }
     if constexpr (sizeof(T) == 4) {
       switch (rl) {
-        case 5: FTHMS_PANEL_REG(5); return;
         case 6: FTHMS_PANEL_REG(6); return;
         case 7: FTHMS_PANEL_REG(7); return;
         default: FTHMS_PANEL_REG(8); return;

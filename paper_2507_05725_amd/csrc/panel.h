@@ -25,7 +25,7 @@
 //
 // Arithmetic is in the storage precision T.  Register budget: RL x 4
 // complex values of T per lane; the launch bound of 1024 threads leaves 128
-// VGPRs per lane, so FP32 blocks up to m = 512 and FP64 blocks up to m = 256
+// VGPRs per lane, so FP32 blocks up to m = 512 and FP64 blocks up to m = 320
 // take this path (larger ones use lu_panel_kernel).
 #pragma once
 
