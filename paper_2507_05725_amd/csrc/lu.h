@@ -720,24 +720,23 @@ __device__ __forceinline__ double2 ld2(const cplx_t<T> *p) {
 }
 
 // acc -= sum_{c < n} col[c * stride] * y[c]: column sweep of one row with
-// the next batch of 8 loads in flight while the current one is used
+// the next batch of 8 loads in flight while the current one is used (n >= 1).
+// The loads take their column clamped to n - 1 instead of a test per load:
+// such tests are loop-invariant masks the compiler keeps (and spills) across
+// the sweep; the values past n are never accumulated.
 template <typename P>
 __device__ __forceinline__ double2 row_sweep(double2 acc, const P *col, long long stride,
                                              const double2 *y, int n) {
   constexpr int B = 8;
   P cur[B], nxt[B];
 #pragma unroll
-  for (int u = 0; u < B; ++u)
-    if (u < n) nxt[u] = col[(long long)u * stride];
+  for (int u = 0; u < B; ++u) nxt[u] = col[(long long)min(u, n - 1) * stride];
 #pragma unroll 1
   for (int c0 = 0; c0 < n; c0 += B) {
 #pragma unroll
     for (int u = 0; u < B; ++u) cur[u] = nxt[u];
-    if (c0 + B < n) {
 #pragma unroll
-      for (int u = 0; u < B; ++u)
-        if (c0 + B + u < n) nxt[u] = col[(long long)(c0 + B + u) * stride];
-    }
+    for (int u = 0; u < B; ++u) nxt[u] = col[(long long)min(c0 + B + u, n - 1) * stride];
 #pragma unroll
     for (int u = 0; u < B; ++u)
       if (c0 + u < n) acc = cfms(acc, to_d2(cur[u]), y[c0 + u]);

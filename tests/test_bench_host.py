@@ -28,6 +28,14 @@ def test_source_digest_ignores_comments_only(tmp_path):
     assert bench.source_digest(str(a)) != bench.source_digest(str(c))
 
 
+def test_source_digest_stops_at_the_triangular_solves(tmp_path):
+    a = tmp_path / "a.h"
+    b = tmp_path / "b.h"
+    a.write_text("int strip(int x) { return x; }\n" + bench.SOLVE_MARK + "\nint solve() { return 1; }\n")
+    b.write_text("int strip(int x) { return x; }\n" + bench.SOLVE_MARK + "\nint solve() { return 2; }\n")
+    assert bench.source_digest(str(a)) == bench.source_digest(str(b))
+
+
 def test_recorded_traffic_matches_the_current_kernel_or_is_absent():
     v = bench.recorded_traffic("lu_strip_kernel<float>")
     assert v is None or v > 1e8
