@@ -168,10 +168,14 @@ __global__ __launch_bounds__(kFieldThreads) void field_near_kernel(
 constexpr int kFtTile = 64;
 constexpr int kFtChunk = 16;
 
+// Frequencies [z lsplit, (z + 1) lsplit) for blockIdx.z = z: with part ==
+// nullptr (one split) the block writes u directly, otherwise its unscaled
+// partial sum to part[z][n][p], summed by freq_to_time_sum_kernel (a fixed
+// order, so the result does not depend on scheduling).
 __global__ __launch_bounds__(256) void freq_to_time_kernel(
     int nk, const double *__restrict__ om, const double *__restrict__ w, int np,
     const double2 *__restrict__ U, int nt, const double *__restrict__ t,
-    double2 *__restrict__ u) {
+    double2 *__restrict__ u, int lsplit, double2 *__restrict__ part) {
   __shared__ double2 sE[kFtTile][kFtChunk + 1];
   __shared__ double2 sU[kFtChunk][kFtTile];
   const int n0 = blockIdx.y * kFtTile, p0 = blockIdx.x * kFtTile;
@@ -181,11 +185,12 @@ __global__ __launch_bounds__(256) void freq_to_time_kernel(
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[a][c] = make_double2(0.0, 0.0);
-  for (int l0 = 0; l0 < nk; l0 += kFtChunk) {
+  const int lb = blockIdx.z * lsplit, le = min(nk, lb + lsplit);
+  for (int l0 = lb; l0 < le; l0 += kFtChunk) {
     for (int e = threadIdx.x; e < kFtTile * kFtChunk; e += 256) {
       const int nn = e / kFtChunk, ll = e % kFtChunk;
       double2 v = make_double2(0.0, 0.0);
-      if (n0 + nn < nt && l0 + ll < nk) {
+      if (n0 + nn < nt && l0 + ll < le) {
         double s, c;
         sincos(om[l0 + ll] * t[n0 + nn], &s, &c);
         const double ww = w[l0 + ll];
@@ -195,7 +200,7 @@ __global__ __launch_bounds__(256) void freq_to_time_kernel(
     }
     for (int e = threadIdx.x; e < kFtTile * kFtChunk; e += 256) {
       const int ll = e / kFtTile, pp = e % kFtTile;
-      sU[ll][pp] = (l0 + ll < nk && p0 + pp < np) ? U[(long long)(l0 + ll) * np + p0 + pp]
+      sU[ll][pp] = (l0 + ll < le && p0 + pp < np) ? U[(long long)(l0 + ll) * np + p0 + pp]
                                                   : make_double2(0.0, 0.0);
     }
     __syncthreads();
@@ -214,13 +219,35 @@ __global__ __launch_bounds__(256) void freq_to_time_kernel(
     __syncthreads();
   }
   const double s = 1.0 / (2.0 * kPi);
+  double2 *pz = part ? part + (long long)blockIdx.z * nt * np : nullptr;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int n = n0 + ty + 16 * a, p = p0 + tx + 16 * c;
-      if (n < nt && p < np) u[(long long)n * np + p] = make_double2(s * acc[a][c].x, s * acc[a][c].y);
+      if (n < nt && p < np) {
+        if (pz)
+          pz[(long long)n * np + p] = acc[a][c];
+        else
+          u[(long long)n * np + p] = make_double2(s * acc[a][c].x, s * acc[a][c].y);
+      }
     }
+}
+
+// u[i] = (1/2pi) sum_z part[z][i], z in order.
+__global__ __launch_bounds__(256) void freq_to_time_sum_kernel(int nsplit, long long nn,
+                                                               const double2 *__restrict__ part,
+                                                               double2 *__restrict__ u) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nn) return;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int z = 0; z < nsplit; ++z) {
+    const double2 v = part[(long long)z * nn + i];
+    acc.x += v.x;
+    acc.y += v.y;
+  }
+  const double s = 1.0 / (2.0 * kPi);
+  u[i] = make_double2(s * acc.x, s * acc.y);
 }
 
 // Device copy of a near-target quadrature plan (built on the host by

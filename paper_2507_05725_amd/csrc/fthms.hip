@@ -39,6 +39,9 @@ struct fthms_ctx {
   void *ws = nullptr;
   size_t ws_bytes = 0;
   void *ws2 = nullptr;
+  // partial sums of the split frequency-to-time transform (optional)
+  void *ft = nullptr;
+  size_t ft_bytes = 0;
   size_t ws2_bytes = 0;
   // kernel timing with HIP events on `stream` (off while a graph is captured)
   bool timing = false;
@@ -134,6 +137,27 @@ static int ensure_ws2(fthms_ctx *ctx, size_t bytes) {
   if (rc) return rc;
   ctx->ws2_bytes = bytes;
   return FTHMS_OK;
+}
+
+// Scratch for the split transform if it can be had (budget, memory);
+// false leaves the transform unsplit, and no error is recorded.
+static bool try_ft_scratch(fthms_ctx *ctx, size_t bytes) {
+  if (ctx->ft_bytes >= bytes) return true;
+  if (ctx->budget && ctx->held - std::min(ctx->held, ctx->ft_bytes) + bytes > ctx->budget)
+    return false;
+  (void)hipStreamSynchronize(ctx->stream);
+  dev_free(ctx, ctx->ft, ctx->ft_bytes);
+  ctx->ft = nullptr;
+  ctx->ft_bytes = 0;
+  void *p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  ctx->ft = p;
+  ctx->ft_bytes = bytes;
+  ctx->held += bytes;
+  return true;
 }
 
 static void tbeg(fthms_ctx *ctx, const char *name, hipStream_t st = nullptr) {
@@ -240,6 +264,7 @@ int fthms_destroy(fthms_ctx *ctx) {
   timing_collect(ctx);
   dev_free(ctx, ctx->ws, ctx->ws_bytes);
   dev_free(ctx, ctx->ws2, ctx->ws2_bytes);
+  dev_free(ctx, ctx->ft, ctx->ft_bytes);
   if (ctx->aux) {
     (void)hipStreamSynchronize(ctx->aux);
     (void)hipStreamDestroy(ctx->aux);
@@ -1327,6 +1352,35 @@ int fthms_eval_field(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double 
   return rc;
 }
 
+// u[n][p] = (1/2pi) sum_l w_l U[l][p] exp(-i om_l t_n) on the context's stream.
+// When the (time, point) tiles alone give few workgroups, the frequency sum
+// is split over blockIdx.z (about 512 workgroups in all) into partial sums
+// that a second kernel adds in a fixed order.
+static int launch_freq_to_time(fthms_ctx *ctx, int nk, const double *om, const double *w, int np,
+                               const double2 *U, int nt, const double *t, double2 *u) {
+  if (np == 0 || nt == 0) return FTHMS_OK;
+  const int gx = (np + kFtTile - 1) / kFtTile, gy = (nt + kFtTile - 1) / kFtTile;
+  const int tiles = gx * gy;
+  const int nchunk = std::max(1, (nk + kFtChunk - 1) / kFtChunk);
+  int S = tiles >= 256 ? 1 : std::min(nchunk, (512 + tiles - 1) / tiles);
+  int lsplit = ((nchunk + S - 1) / S) * kFtChunk;
+  S = std::max(1, (nk + lsplit - 1) / lsplit);
+  const long long nn = (long long)nt * np;
+  if (S > 1 && !try_ft_scratch(ctx, sizeof(double2) * (size_t)S * (size_t)nn)) S = 1;
+  if (S == 1) {
+    freq_to_time_kernel<<<dim3(gx, gy, 1), 256, 0, ctx->stream>>>(nk, om, w, np, U, nt, t, u,
+                                                                  std::max(nk, 1), nullptr);
+    return check_launch(ctx, "freq_to_time_kernel");
+  }
+  double2 *part = (double2 *)ctx->ft;
+  freq_to_time_kernel<<<dim3(gx, gy, S), 256, 0, ctx->stream>>>(nk, om, w, np, U, nt, t, u, lsplit,
+                                                                 part);
+  int rc = check_launch(ctx, "freq_to_time_kernel");
+  if (rc) return rc;
+  freq_to_time_sum_kernel<<<(unsigned)((nn + 255) / 256), 256, 0, ctx->stream>>>(S, nn, part, u);
+  return check_launch(ctx, "freq_to_time_sum_kernel");
+}
+
 int fthms_freq_to_time_dev(fthms_ctx *ctx, int nk, const double *omega_dev, const double *w_dev,
                            int np, const fthms_c64 *U_dev, int nt, const double *t_dev,
                            fthms_c64 *u_dev) {
@@ -1334,13 +1388,11 @@ int fthms_freq_to_time_dev(fthms_ctx *ctx, int nk, const double *omega_dev, cons
     return fail(ctx, FTHMS_EINVAL, "bad argument to fthms_freq_to_time_dev");
   if (np == 0 || nt == 0) return FTHMS_OK;
   HIPCK(ctx, hipSetDevice(ctx->device));
-  dim3 g((np + kFtTile - 1) / kFtTile, (nt + kFtTile - 1) / kFtTile);
   tbeg(ctx, "freq_to_time");
-  freq_to_time_kernel<<<g, 256, 0, ctx->stream>>>(nk, omega_dev, w_dev, np,
-                                                   (const double2 *)U_dev, nt, t_dev,
-                                                   (double2 *)u_dev);
+  const int rc = launch_freq_to_time(ctx, nk, omega_dev, w_dev, np, (const double2 *)U_dev, nt,
+                                     t_dev, (double2 *)u_dev);
   tend(ctx);
-  return check_launch(ctx, "freq_to_time_kernel");
+  return rc;
 }
 
 int fthms_freq_to_time(fthms_ctx *ctx, int nk, const double *omega, const double *w, int np,

@@ -512,9 +512,7 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
                               P, 1)))
         return r;
     }
-    dim3 g((P + kFtTile - 1) / kFtTile, (tr->nt + kFtTile - 1) / kFtTile);
-    freq_to_time_kernel<<<g, 256, 0, ctx->stream>>>(c, kc, tr->w, P, Ustep, tr->nt, tr->t, du);
-    if ((r = check_launch(ctx, "freq_to_time_kernel"))) return r;
+    if ((r = launch_freq_to_time(ctx, c, kc, tr->w, P, Ustep, tr->nt, tr->t, du))) return r;
     const long long nn = (long long)tr->nt * P;
     if (first)
       HIPCK(ctx, hipMemcpyAsync(tr->traces, du, sizeof(double2) * nn, hipMemcpyDeviceToDevice,

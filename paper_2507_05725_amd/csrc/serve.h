@@ -110,6 +110,9 @@ int serve_run(fthms_ctx *ctx, fthms_server::Job &jb) {
   dev_free(ctx, ctx->ws2, ctx->ws2_bytes);
   ctx->ws2 = nullptr;
   ctx->ws2_bytes = 0;
+  dev_free(ctx, ctx->ft, ctx->ft_bytes);
+  ctx->ft = nullptr;
+  ctx->ft_bytes = 0;
   return rc;
 }
 

@@ -180,9 +180,7 @@ static int problem_windowed_impl(fthms_problem *pb, int nk, const double *k_dev,
   if (ntr) zero_kernel<<<grid1d(ntr), 256, 0, ctx->stream>>>(traces, ntr);
   // all windows at once: (window, frequency) pairs with the phase folded in
   auto to_time = [&](int np, const double2 *Vf, double2 *out) -> int {
-    dim3 g((np + kFtTile - 1) / kFtTile, (nt + kFtTile - 1) / kFtTile);
-    freq_to_time_kernel<<<g, 256, 0, ctx->stream>>>(nkq, kq, wt, np, Vf, nt, t0v, out);
-    return check_launch(ctx, "freq_to_time_kernel (windows)");
+    return launch_freq_to_time(ctx, nkq, kq, wt, np, Vf, nt, t0v, out);
   };
   for (int m = 0; m < pb->M; ++m) {
     for (int k = 0; k < J; ++k) {
@@ -197,14 +195,10 @@ static int problem_windowed_impl(fthms_problem *pb, int nk, const double *k_dev,
         // slow transform about s_q: sum over time samples with the window weights
         double2 *Gq = G + (size_t)q * nk * n, *pq = psi + (size_t)q * nk * n;
         tbeg(ctx, "window_transform");
-        {
-          dim3 g((n + kFtTile - 1) / kFtTile, (nk + kFtTile - 1) / kFtTile);
-          freq_to_time_kernel<<<g, 256, 0, ctx->stream>>>(
-              nt, tq + (size_t)q * nt, wq + (size_t)q * nt, n, (const double2 *)at(o[j].g), nk,
-              nkv, Gq);
-        }
+        rc = launch_freq_to_time(ctx, nt, tq + (size_t)q * nt, wq + (size_t)q * nt, n,
+                                 (const double2 *)at(o[j].g), nk, nkv, Gq);
         tend(ctx);
-        if ((rc = check_launch(ctx, "freq_to_time_kernel (slow transform)"))) return rc;
+        if (rc) return rc;
         tbeg(ctx, "solve");
         lu_solve64_kernel<<<nk, kLuThreads, 0, ctx->stream>>>(
             (double2 *)at(o[j].A), lu_perm(at(o[j].swp), nk), n, (long long)n * n, Gq, pq, n);
