@@ -25,14 +25,18 @@ constexpr int kFieldThreads = 256;
 
 // One block: up to 256 targets for one wavenumber; nodes and density in LDS.
 // Composite-panel arcs pass their Fejer weights: U(z) = sum_j w_j Phi_k(z,
-// y_j) mu_j; otherwise the weight is pi/N.
+// y_j) mu_j; otherwise the weight is pi/N.  With fewer targets than threads
+// (split = 2, 4 or 8) each target's node sum is shared by `split` threads
+// (nodes j = s, s + split, ...), whose partial sums are added in LDS in a
+// fixed order; split = 1 is one thread per target.
 __global__ __launch_bounds__(kFieldThreads) void field_far_kernel(
     const double2 *__restrict__ ynodes, int N, const double *__restrict__ wnode,
     const double *__restrict__ kvec, const double2 *__restrict__ alpha, long long astride,
     const double2 *__restrict__ pts, int np, const unsigned char *__restrict__ cls,
-    double2 *__restrict__ U, long long ustride, int accumulate) {
+    double2 *__restrict__ U, long long ustride, int accumulate, int split) {
   __shared__ double2 sy[1024];
   __shared__ double2 sa[1024];
+  __shared__ double2 red[kFieldThreads];
   const int b = blockIdx.y;
   for (int j = threadIdx.x; j < N; j += kFieldThreads) {
     sy[j] = ynodes[j];
@@ -41,21 +45,34 @@ __global__ __launch_bounds__(kFieldThreads) void field_far_kernel(
     sa[j] = a;
   }
   __syncthreads();
-  const int p = blockIdx.x * kFieldThreads + threadIdx.x;
-  if (p >= np) return;
-  if (cls && cls[p] != 1) return;
+  const int tpb = kFieldThreads / split;  // targets per block
+  const int pl = threadIdx.x % tpb, sl = threadIdx.x / tpb;
+  const int p = blockIdx.x * tpb + pl;
+  const bool active = p < np && (!cls || cls[p] == 1);
   const double k = kvec[b];
-  const double2 z = pts[p];
   double accr = 0.0, acci = 0.0;
-  for (int j = 0; j < N; ++j) {
-    const double dx = z.x - sy[j].x, dy = z.y - sy[j].y;
-    double j0v, y0v;
-    bessel_j0_y0(k * sqrt(dx * dx + dy * dy), j0v, y0v);
-    const double2 a = sa[j];
-    // (i J0 - Y0) * a
-    accr += -y0v * a.x - j0v * a.y;
-    acci += j0v * a.x - y0v * a.y;
+  if (active) {
+    const double2 z = pts[p];
+    for (int j = sl; j < N; j += split) {
+      const double dx = z.x - sy[j].x, dy = z.y - sy[j].y;
+      double j0v, y0v;
+      bessel_j0_y0(k * sqrt(dx * dx + dy * dy), j0v, y0v);
+      const double2 a = sa[j];
+      // (i J0 - Y0) * a
+      accr += -y0v * a.x - j0v * a.y;
+      acci += j0v * a.x - y0v * a.y;
+    }
   }
+  if (split > 1) {
+    red[threadIdx.x] = make_double2(accr, acci);
+    __syncthreads();
+    if (sl != 0) return;
+    for (int q = 1; q < split; ++q) {
+      accr += red[pl + q * tpb].x;
+      acci += red[pl + q * tpb].y;
+    }
+  }
+  if (!active) return;
   const double s = wnode ? 0.25 : kPi / (4.0 * N);
   double2 *u = U + (long long)b * ustride + p;
   if (accumulate) {
@@ -64,6 +81,14 @@ __global__ __launch_bounds__(kFieldThreads) void field_far_kernel(
   } else {
     *u = make_double2(s * accr, s * acci);
   }
+}
+
+// Threads per target for field_far_kernel: 1 for 256 targets or more, else
+// up to 8 so that a block's threads all have work.
+inline int field_far_split(int np) {
+  int split = 1;
+  while (split < 8 && np * split * 2 <= kFieldThreads) split *= 2;
+  return split;
 }
 
 // Chebyshev coefficients of the density interpolant for each wavenumber,
