@@ -117,6 +117,26 @@ __global__ __launch_bounds__(kFieldThreads) void cheb_coeff_kernel(
   }
 }
 
+// Clenshaw helpers of field_near_kernel: read a[m], ..., a[m-7] (m >= 7) and
+// take the eight recurrence steps that use them.
+__device__ __forceinline__ void clenshaw_read8(const double2 *a, int m, double2 *c) {
+#pragma unroll
+  for (int u = 0; u < 8; ++u) c[u] = a[m - u];
+}
+
+__device__ __forceinline__ void clenshaw_steps8(const double2 *c, double c2, double &b1r,
+                                                double &b1i, double &b2r, double &b2i) {
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const double nr = fma(c2, b1r, c[u].x - b2r);
+    const double ni = fma(c2, b1i, c[u].y - b2i);
+    b2r = b1r;
+    b2i = b1i;
+    b1r = nr;
+    b1i = ni;
+  }
+}
+
 // Near targets: one block per (target, wavenumber).
 //   U(z) = sum_q w_q (i/4) H0(k |z - x_q|) alpha_N(c_q),
 //   alpha_N(c) = sum_m a_m T_m(c) by Clenshaw's recurrence, c_q = cos(phi_q),
@@ -141,10 +161,31 @@ __global__ __launch_bounds__(kFieldThreads) void field_near_kernel(
   for (int q = q0 + threadIdx.x; q < q1; q += kFieldThreads) {
     const double c = cq[q], c2 = 2.0 * c;
     const double2 *a = pq ? sa + pq[q] * nper : sa;
+    // Clenshaw: b_m = a_m + 2c b_{m+1} - b_{m+2}, written fma(2c, b_{m+1},
+    // a_m - b_{m+2}) so one operation per step waits on b_{m+1}; the
+    // coefficients are read from LDS eight at a time into two alternating
+    // buffers, the next eight issued before the steps of the current ones.
     double b1r = 0.0, b1i = 0.0, b2r = 0.0, b2i = 0.0;
-    for (int m = nper - 1; m >= 1; --m) {
-      const double nr = a[m].x + c2 * b1r - b2r;
-      const double ni = a[m].y + c2 * b1i - b2i;
+    int m = nper - 1;
+    if (m >= 8) {
+      double2 ca[8], cb[8];
+      clenshaw_read8(a, m, ca);
+      for (;;) {
+        clenshaw_read8(a, max(m - 8, 7), cb);
+        __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the steps
+        clenshaw_steps8(ca, c2, b1r, b1i, b2r, b2i);
+        m -= 8;
+        if (m < 8) break;
+        clenshaw_read8(a, max(m - 8, 7), ca);
+        __builtin_amdgcn_sched_barrier(0);
+        clenshaw_steps8(cb, c2, b1r, b1i, b2r, b2i);
+        m -= 8;
+        if (m < 8) break;
+      }
+    }
+    for (; m >= 1; --m) {
+      const double nr = fma(c2, b1r, a[m].x - b2r);
+      const double ni = fma(c2, b1i, a[m].y - b2i);
       b2r = b1r;
       b2i = b1i;
       b1r = nr;
