@@ -53,11 +53,17 @@ __global__ __launch_bounds__(kFieldThreads) void field_far_kernel(
   double accr = 0.0, acci = 0.0;
   if (active) {
     const double2 z = pts[p];
+    // node j + split is read from LDS (index clamped) before node j's Hankel
+    // evaluation, which hides the read
+    double2 yn = sy[min(sl, N - 1)], an = sa[min(sl, N - 1)];
     for (int j = sl; j < N; j += split) {
-      const double dx = z.x - sy[j].x, dy = z.y - sy[j].y;
+      const double2 yj = yn, a = an;
+      const int jn = min(j + split, N - 1);
+      yn = sy[jn];
+      an = sa[jn];
+      const double dx = z.x - yj.x, dy = z.y - yj.y;
       double j0v, y0v;
       bessel_j0_y0(k * sqrt(dx * dx + dy * dy), j0v, y0v);
-      const double2 a = sa[j];
       // (i J0 - Y0) * a
       accr += -y0v * a.x - j0v * a.y;
       acci += j0v * a.x - y0v * a.y;
@@ -158,9 +164,23 @@ __global__ __launch_bounds__(kFieldThreads) void field_near_kernel(
   const double k = kvec[b];
   const int q0 = qoff[t], q1 = qoff[t + 1];
   double accr = 0.0, acci = 0.0;
+  // the next quadrature point's data is read one point ahead (index clamped
+  // to the target's last point; every near target has at least one point), so
+  // its global loads overlap this point's sums
+  const int qlast = q1 - 1;
+  int qn = min(q0 + (int)threadIdx.x, qlast);
+  double cn = cq[qn], wn = wq[qn];
+  double2 xn = xq[qn];
+  int pn = pq ? pq[qn] : 0;
   for (int q = q0 + threadIdx.x; q < q1; q += kFieldThreads) {
-    const double c = cq[q], c2 = 2.0 * c;
-    const double2 *a = pq ? sa + pq[q] * nper : sa;
+    const double c = cn, c2 = 2.0 * c, wcur = wn;
+    const double2 x = xn;
+    const double2 *a = sa + pn * nper;
+    qn = min(q + kFieldThreads, qlast);
+    cn = cq[qn];
+    wn = wq[qn];
+    xn = xq[qn];
+    if (pq) pn = pq[qn];
     // Clenshaw: b_m = a_m + 2c b_{m+1} - b_{m+2}, written fma(2c, b_{m+1},
     // a_m - b_{m+2}) so one operation per step waits on b_{m+1}; the
     // coefficients are read from LDS eight at a time into two alternating
@@ -193,11 +213,10 @@ __global__ __launch_bounds__(kFieldThreads) void field_near_kernel(
     }
     const double dr = a[0].x + c * b1r - b2r;
     const double di = a[0].y + c * b1i - b2i;
-    const double2 x = xq[q];
     const double dx = z.x - x.x, dy = z.y - x.y;
     double j0v, y0v;
     bessel_j0_y0(k * sqrt(dx * dx + dy * dy), j0v, y0v);
-    const double w = 0.25 * wq[q];
+    const double w = 0.25 * wcur;
     // (i/4)(J0 + i Y0) * d = w (-Y0 + i J0) * d
     accr += w * (-y0v * dr - j0v * di);
     acci += w * (j0v * dr - y0v * di);
