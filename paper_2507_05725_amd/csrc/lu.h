@@ -782,16 +782,66 @@ __global__ __launch_bounds__(64) void perm_from_piv_kernel(const int *pivbase, i
     if (lane + 64 * q < N) perm[lane + 64 * q] = v[q];
 }
 
-// y := U^{-1} L^{-1} P y for the factors in LU (column-major, ld = N), P
-// given as the gather perm.  Each 64 x 64 diagonal block is staged in LDS
-// (D, element (r, c) at D[r][(c + r) & 63] so that column reads are
-// bank-conflict free) with one coalesced load, and wave 0 substitutes with
-// the solution values passed between lanes by readlane; the off-diagonal
-// block columns are applied by all threads with batched loads.
+// Diagonal-block solve on wave 0: y[jb, jb + nb) := L11^{-1} y (forward,
+// unit lower) or U11^{-1} y (backward).  Lane i holds row jb + i; column c
+// of the block is one coalesced load from the factors, issued eight columns
+// ahead of its step.  Lanes past nb read row jb + nb - 1 instead: their
+// values are never broadcast or stored.  Steps past the block are switched
+// off per lane (column index clamped for the lane read), not by a branch.
 template <typename T>
-__device__ void lu_solve_lds(const cplx_t<T> *LU, const int *perm, double2 *y, int N,
-                             cplx_t<T> (*D)[64]) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+__device__ __forceinline__ void diag_block_solve(const cplx_t<T> *LU, int N, int jb, int nb,
+                                                 bool fwd, double2 *y) {
+  constexpr int B = 8;
+  const int lane = threadIdx.x & 63;
+  const cplx_t<T> *rowp = LU + (jb + min(lane, nb - 1)) + (long long)jb * N;
+  double2 yi = lane < nb ? y[jb + lane] : make_double2(0.0, 0.0);
+  cplx_t<T> cur[B], nxt[B];
+  if (fwd) {
+#pragma unroll
+    for (int u = 0; u < B; ++u) nxt[u] = rowp[(long long)min(u, nb - 1) * N];
+#pragma unroll 1
+    for (int c0 = 0; c0 < nb - 1; c0 += B) {
+#pragma unroll
+      for (int u = 0; u < B; ++u) cur[u] = nxt[u];
+#pragma unroll
+      for (int u = 0; u < B; ++u) nxt[u] = rowp[(long long)min(c0 + B + u, nb - 1) * N];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int c = c0 + u;
+        const double2 yc = rdlane2(yi, min(c, 63));
+        if (lane > c && c < nb - 1) yi = cfms(yi, to_d2(cur[u]), yc);
+      }
+    }
+  } else {
+    const double2 dinv = lane < nb ? crcp(to_d2(rowp[(long long)lane * N])) : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < B; ++u) nxt[u] = rowp[(long long)max(nb - 1 - u, 0) * N];
+#pragma unroll 1
+    for (int c0 = nb - 1; c0 >= 0; c0 -= B) {
+#pragma unroll
+      for (int u = 0; u < B; ++u) cur[u] = nxt[u];
+#pragma unroll
+      for (int u = 0; u < B; ++u) nxt[u] = rowp[(long long)max(c0 - B - u, 0) * N];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int c = c0 - u;
+        if (lane == c) yi = cmul(yi, dinv);
+        const double2 yc = rdlane2(yi, max(c, 0));
+        if (lane < c) yi = cfms(yi, to_d2(cur[u]), yc);
+      }
+    }
+  }
+  if (lane < nb) y[jb + lane] = yi;
+}
+
+// y := (P A)^{-1} y = U^{-1} L^{-1} P y for the factors LU (column-major,
+// stride N) and the gather permutation perm; y is in LDS.  Per 64-column
+// block: the diagonal block on wave 0, then the rows below (forward) or above
+// (backward) swept by the whole workgroup.
+template <typename T>
+__device__ __forceinline__ void lu_solve_lds(const cplx_t<T> *LU, const int *perm, double2 *y,
+                                             int N) {
+  const int tid = threadIdx.x, wave = tid >> 6;
   {
     // y := P y as a gather, four rows per thread (kMaxN = 4 x 256)
     static_assert(kMaxN == 4 * kLuThreads, "gather assumes four rows per thread");
@@ -805,34 +855,13 @@ __device__ void lu_solve_lds(const cplx_t<T> *LU, const int *perm, double2 *y, i
     if (i2 < N) y[i2] = g2;
     if (i3 < N) y[i3] = g3;
   }
+  __syncthreads();
   const int nblk = (N + 63) / 64;
   for (int bi = 0; bi < 2 * nblk; ++bi) {
     const bool fwd = bi < nblk;
     const int jb = (fwd ? bi : 2 * nblk - 1 - bi) * 64;
     const int nb = min(64, N - jb);
-    for (int e = tid; e < 64 * 64; e += kLuThreads) {
-      const int r = e & 63, c = e >> 6;
-      D[r][(c + r) & 63] = (r < nb && c < nb) ? LU[(jb + r) + (long long)(jb + c) * N] : mk<T>(0, 0);
-    }
-    __syncthreads();
-    if (wave == 0) {
-      double2 yi = lane < nb ? y[jb + lane] : make_double2(0.0, 0.0);
-      if (fwd) {
-        for (int c = 0; c < nb - 1; ++c) {
-          const double2 yc = rdlane2(yi, c);
-          if (lane > c) yi = cfms(yi, to_d2(D[lane][(c + lane) & 63]), yc);
-        }
-      } else {
-        const double2 dinv =
-            lane < nb ? crcp(to_d2(D[lane][(2 * lane) & 63])) : make_double2(0.0, 0.0);
-        for (int c = nb - 1; c >= 0; --c) {
-          if (lane == c) yi = cmul(yi, dinv);
-          const double2 yc = rdlane2(yi, c);
-          if (lane < c) yi = cfms(yi, to_d2(D[lane][(c + lane) & 63]), yc);
-        }
-      }
-      if (lane < nb) y[jb + lane] = yi;
-    }
+    if (wave == 0) diag_block_solve<T>(LU, N, jb, nb, fwd, y);
     __syncthreads();
     // rows below (forward) or above (backward) the block
     const int r0 = fwd ? jb + nb : 0, r1 = fwd ? N : jb;
@@ -847,12 +876,11 @@ __global__ __launch_bounds__(kLuThreads, 2) void lu_solve64_kernel(
     const double2 *LUbase, const int *permbase, int N, long long mstride,
     const double2 *b, double2 *x, long long vstride) {
   __shared__ double2 y[kMaxN];
-  __shared__ double2 D[64][64];
   const double2 *LU = LUbase + (long long)blockIdx.x * mstride;
   const int *piv = permbase + (long long)blockIdx.x * kMaxN;
   for (int i = threadIdx.x; i < N; i += kLuThreads) y[i] = b[(long long)blockIdx.x * vstride + i];
   __syncthreads();
-  lu_solve_lds<double>(LU, piv, y, N, D);
+  lu_solve_lds<double>(LU, piv, y, N);
   for (int i = threadIdx.x; i < N; i += kLuThreads) x[(long long)blockIdx.x * vstride + i] = y[i];
 }
 
@@ -879,11 +907,10 @@ __global__ __launch_bounds__(kLuThreads, 3) void refine_kernel(
     const float2 *LUbase, const int *permbase, const double2 *A64base, int N,
     long long mstride, const double2 *b, double2 *x, long long vstride, double tol,
     int max_iter, int *status, double *relres) {
-  // dynamic LDS: x and r, N complex128 each (sized at launch), so that
-  // three workgroups fit on a CU at N = 512
+  // dynamic LDS: x and r, N complex128 each (sized at launch; 16 KB at
+  // N = 512), the only LDS of the kernel, so registers set its occupancy
   extern __shared__ double2 refine_dyn[];
   double2 *xs = refine_dyn, *rs = refine_dyn + N;
-  __shared__ float2 D[64][64];
   __shared__ double red[4];
   const long long mb = (long long)blockIdx.x;
   const float2 *LU = LUbase + mb * mstride;
@@ -897,7 +924,7 @@ __global__ __launch_bounds__(kLuThreads, 3) void refine_kernel(
   }
   for (int i = tid; i < N; i += kLuThreads) xs[i] = bb[i];
   __syncthreads();
-  lu_solve_lds<float>(LU, piv, xs, N, D);
+  lu_solve_lds<float>(LU, piv, xs, N);
   // the initial solve counts as the first correction (from x = 0), so the
   // contraction can be estimated, and the loop stopped, after one step
   double x0n = 0.0;
@@ -908,7 +935,7 @@ __global__ __launch_bounds__(kLuThreads, 3) void refine_kernel(
     // r = b - A x  (each thread owns rows; column sweep, coalesced)
     for (int r = tid; r < N; r += kLuThreads) rs[r] = row_sweep(bb[r], A + r, N, xs, N);
     __syncthreads();
-    lu_solve_lds<float>(LU, piv, rs, N, D);
+    lu_solve_lds<float>(LU, piv, rs, N);
     double dn = 0.0, xn = 0.0;
     for (int i = tid; i < N; i += kLuThreads) {
       const double2 xi = cadd(xs[i], rs[i]);
@@ -942,14 +969,13 @@ __global__ __launch_bounds__(kLuThreads, 2) void solve_failed64_kernel(
     const double2 *LUbase, const int *permbase, int N, long long mstride, const double2 *b,
     double2 *x, long long vstride, const int *status) {
   __shared__ double2 y[kMaxN];
-  __shared__ double2 D[64][64];
   const long long mb = blockIdx.x;
   if (status[mb] >= 0) return;
   const double2 *LU = LUbase + mb * mstride;
   const int *piv = permbase + mb * kMaxN;
   for (int i = threadIdx.x; i < N; i += kLuThreads) y[i] = b[mb * vstride + i];
   __syncthreads();
-  lu_solve_lds<double>(LU, piv, y, N, D);
+  lu_solve_lds<double>(LU, piv, y, N);
   for (int i = threadIdx.x; i < N; i += kLuThreads) x[mb * vstride + i] = y[i];
 }
 
