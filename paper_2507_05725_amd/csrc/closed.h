@@ -84,15 +84,19 @@ __global__ __launch_bounds__(256) void cfie_assemble_kernel(
 }
 
 // (D - i eta S)[Psi] at targets by the trapezoid rule: one block per 256
-// targets and wavenumber; nodes, tangents and density in LDS.
+// threads and wavenumber; nodes, tangents and density in LDS.
 //   kernel = (k/4)(q/r)(-Y1 + i J1) + (eta |x'_j| / 4)(J0 + i Y0),
 //   q = x2'_j (z1 - y1_j) - x1'_j (z2 - y2_j).
+// With fewer targets than threads each target's node sum is shared by
+// `split` threads (2, 4 or 8; nodes j = s, s + split, ...) whose partial sums
+// are added in LDS in a fixed order; split = 1 is one thread per target.
 __global__ __launch_bounds__(256) void closed_field_kernel(
     const double2 *__restrict__ ynodes, const double2 *__restrict__ dy, int N,
     const double *__restrict__ kvec, const double2 *__restrict__ psi, long long pstride,
     const double2 *__restrict__ pts, int np, const unsigned char *__restrict__ cls,
-    double2 *__restrict__ U, long long ustride, int accumulate) {
+    double2 *__restrict__ U, long long ustride, int accumulate, int split) {
   __shared__ double2 sy[1024], sd[1024], sp[1024];
+  __shared__ double2 red[256];
   const int b = blockIdx.y;
   for (int j = threadIdx.x; j < N; j += 256) {
     sy[j] = ynodes[j];
@@ -100,25 +104,38 @@ __global__ __launch_bounds__(256) void closed_field_kernel(
     sp[j] = psi[(long long)b * pstride + j];
   }
   __syncthreads();
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p >= np) return;
-  if (cls && cls[p] != 1) return;
+  const int tpb = 256 / split;  // targets per block
+  const int pl = threadIdx.x % tpb, sl = threadIdx.x / tpb;
+  const int p = blockIdx.x * tpb + pl;
+  const bool active = p < np && (!cls || cls[p] == 1);
   const double k = kvec[b], eta = k;
-  const double2 z = pts[p];
   double accr = 0.0, acci = 0.0;
-  for (int j = 0; j < N; ++j) {
-    const double ex = z.x - sy[j].x, ey = z.y - sy[j].y;
-    const double r = sqrt(ex * ex + ey * ey);
-    const double q = sd[j].y * ex - sd[j].x * ey;
-    const double s = sqrt(sd[j].x * sd[j].x + sd[j].y * sd[j].y);
-    double j0, y0, j1, y1;
-    bessel_01(k * r, j0, y0, j1, y1);
-    const double a = 0.25 * k * q / r, c = 0.25 * eta * s;
-    const double kr = -a * y1 + c * j0, ki = a * j1 + c * y0;
-    const double2 w = sp[j];
-    accr += kr * w.x - ki * w.y;
-    acci += kr * w.y + ki * w.x;
+  if (active) {
+    const double2 z = pts[p];
+    for (int j = sl; j < N; j += split) {
+      const double ex = z.x - sy[j].x, ey = z.y - sy[j].y;
+      const double r = sqrt(ex * ex + ey * ey);
+      const double q = sd[j].y * ex - sd[j].x * ey;
+      const double s = sqrt(sd[j].x * sd[j].x + sd[j].y * sd[j].y);
+      double j0, y0, j1, y1;
+      bessel_01(k * r, j0, y0, j1, y1);
+      const double a = 0.25 * k * q / r, c = 0.25 * eta * s;
+      const double kr = -a * y1 + c * j0, ki = a * j1 + c * y0;
+      const double2 w = sp[j];
+      accr += kr * w.x - ki * w.y;
+      acci += kr * w.y + ki * w.x;
+    }
   }
+  if (split > 1) {
+    red[threadIdx.x] = make_double2(accr, acci);
+    __syncthreads();
+    if (sl != 0) return;
+    for (int t = 1; t < split; ++t) {
+      accr += red[pl + t * tpb].x;
+      acci += red[pl + t * tpb].y;
+    }
+  }
+  if (!active) return;
   const double h = 2.0 * kPi / N;
   double2 *u = U + (long long)b * ustride + p;
   if (accumulate) {

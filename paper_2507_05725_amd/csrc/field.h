@@ -89,9 +89,9 @@ __global__ __launch_bounds__(kFieldThreads) void field_far_kernel(
   }
 }
 
-// Threads per target for field_far_kernel: 1 for 256 targets or more, else
-// up to 8 so that a block's threads all have work.
-inline int field_far_split(int np) {
+// Threads per target for field_far_kernel and closed_field_kernel: 1 for
+// 256 targets or more, else up to 8 so that a block's threads all have work.
+inline int field_target_split(int np) {
   int split = 1;
   while (split < 8 && np * split * 2 <= kFieldThreads) split *= 2;
   return split;

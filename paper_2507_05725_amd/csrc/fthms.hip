@@ -1260,13 +1260,12 @@ int field_dev_impl(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double *k
                    const double2 *alpha, long long astride, int np, const double2 *pts_dev,
                    const NearPlan &plan, double2 *U, long long ustride, int accumulate) {
   if (nk == 0 || np == 0) return FTHMS_OK;
-  const int split = field_far_split(np), tpb = kFieldThreads / split;
-  dim3 g((np + kFieldThreads - 1) / kFieldThreads, nk);
+  const int split = field_target_split(np), tpb = kFieldThreads / split;
   dim3 gf((np + tpb - 1) / tpb, nk);
   if (arc->closed) {
-    closed_field_kernel<<<g, 256, 0, ctx->stream>>>(arc->d_y, arc->d_dy, arc->n, k_dev, alpha,
-                                                   astride, pts_dev, np, plan.d_cls, U, ustride,
-                                                   accumulate);
+    closed_field_kernel<<<gf, kFieldThreads, 0, ctx->stream>>>(
+        arc->d_y, arc->d_dy, arc->n, k_dev, alpha, astride, pts_dev, np, plan.d_cls, U, ustride,
+        accumulate, split);
     return check_launch(ctx, "closed_field_kernel");
   }
   field_far_kernel<<<gf, kFieldThreads, 0, ctx->stream>>>(arc->d_y, arc->n, arc->d_w, k_dev,
