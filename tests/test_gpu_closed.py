@@ -127,3 +127,25 @@ def test_closed_error_paths(ctx, fth):
     with pytest.raises(fth.FthmsError):
         fth.Problem(ctx, [arc, other], IncidentSpec("plane"), np.array([[5.0, 5.0]]),
                     intervals=np.array([[0, 2 * np.pi]] * 2), M=2, groups=[0, 0])
+
+
+@pytest.mark.parametrize("npts", [1, 33, 100, 200, 256, 300])
+def test_closed_field_target_counts(ctx, fth, npts):
+    """(D - i eta S) Psi at target counts that take every thread-per-target
+    split (8, 4, 2 threads below 256 targets, one from 256 up, a ragged
+    second block at 300) against the oracle's trapezoid sum."""
+    curve = ClosedKite(1.0)
+    n = 128
+    arc = ctx.closed_from_curve(curve, n)
+    rng = np.random.default_rng(200 + npts)
+    ks = np.array([3.0, 17.0])
+    psi = rng.standard_normal((2, n)) + 1j * rng.standard_normal((2, n))
+    ang = rng.uniform(0.0, 2.0 * math.pi, npts)
+    rad = rng.uniform(3.0, 4.0, npts)
+    z = np.stack([rad * np.cos(ang), rad * np.sin(ang)], -1)
+    say("closed field targets", npts)
+    U = ctx.eval_field(arc, ks, psi, z)
+    nd = ocl.nodes(curve, n)
+    for i, k in enumerate(ks):
+        Uref = ocl.field(k, z, nd, psi[i])
+        assert rel(U[i], Uref) < 1e-12, (npts, k, rel(U[i], Uref))

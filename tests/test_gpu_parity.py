@@ -313,3 +313,26 @@ def test_error_paths(ctx, fth):
     with pytest.raises(fth.FthmsError) as e:
         small.solve(arc2, np.linspace(1, 5, 64), np.ones((64, 64), dtype=complex), 0)
     assert e.value.code == -3
+
+
+@pytest.mark.parametrize("npts", [1, 33, 100, 200, 256, 300])
+def test_far_field_target_counts(ctx, fth, npts):
+    """Far-field sums at target counts that take every thread-per-target
+    split (8, 4, 2 threads below 256 targets, one from 256 up, a ragged
+    second block at 300) against the oracle's Gauss-Chebyshev sum."""
+    curve = CircularArc(1.0, -1.0, 1.0)
+    n = 96
+    arc = ctx.arc_from_curve(curve, n)
+    rng = np.random.default_rng(100 + npts)
+    k = np.array([4.0, 23.0])
+    alpha = rng.standard_normal((2, n)) + 1j * rng.standard_normal((2, n))
+    ang = rng.uniform(0.0, 2.0 * math.pi, npts)
+    rad = rng.uniform(2.5, 3.5, npts)
+    pts = np.stack([rad * np.cos(ang), rad * np.sin(ang)], -1)
+    say("far field targets", npts)
+    U = ctx.eval_field(arc, k, alpha, pts)
+    y = ony.arc_nodes(curve, n)["y"]
+    for i, kk in enumerate(k):
+        ref = ony.field_far(kk, pts, y, alpha[i])
+        err = np.linalg.norm(U[i] - ref) / np.linalg.norm(ref)
+        assert err < 1e-12, (npts, kk, err)
