@@ -785,26 +785,35 @@ __global__ __launch_bounds__(64) void perm_from_piv_kernel(const int *pivbase, i
 // Diagonal-block solve on wave 0: y[jb, jb + nb) := L11^{-1} y (forward,
 // unit lower) or U11^{-1} y (backward).  Lane i holds row jb + i; column c
 // of the block is one coalesced load from the factors, issued eight columns
-// ahead of its step.  Lanes past nb read row jb + nb - 1 instead: their
-// values are never broadcast or stored.  Steps past the block are switched
-// off per lane (column index clamped for the lane read), not by a branch.
+// ahead of its step.  A lane whose entry of column c is not used (rows
+// c and above going forward, c and below going backward, rows past nb) loads
+// the address of the nearest row that is, so the column costs only the cache
+// lines of the triangle it contributes; such values are never applied.  Steps
+// past the block are switched off per lane (column index clamped for the
+// lane read), not by a branch.
 template <typename T>
 __device__ __forceinline__ void diag_block_solve(const cplx_t<T> *LU, int N, int jb, int nb,
                                                  bool fwd, double2 *y) {
   constexpr int B = 8;
   const int lane = threadIdx.x & 63;
-  const cplx_t<T> *rowp = LU + (jb + min(lane, nb - 1)) + (long long)jb * N;
+  const int rl = min(lane, nb - 1);
+  const cplx_t<T> *blk = LU + jb + (long long)jb * N;
   double2 yi = lane < nb ? y[jb + lane] : make_double2(0.0, 0.0);
   cplx_t<T> cur[B], nxt[B];
   if (fwd) {
+    // column c (clamped to the block), row max(lane, c + 1) clamped to the block
+    auto ld = [&](int c) {
+      const int cc = min(c, nb - 1);
+      return blk[max(rl, min(cc + 1, nb - 1)) + (long long)cc * N];
+    };
 #pragma unroll
-    for (int u = 0; u < B; ++u) nxt[u] = rowp[(long long)min(u, nb - 1) * N];
+    for (int u = 0; u < B; ++u) nxt[u] = ld(u);
 #pragma unroll 1
     for (int c0 = 0; c0 < nb - 1; c0 += B) {
 #pragma unroll
       for (int u = 0; u < B; ++u) cur[u] = nxt[u];
 #pragma unroll
-      for (int u = 0; u < B; ++u) nxt[u] = rowp[(long long)min(c0 + B + u, nb - 1) * N];
+      for (int u = 0; u < B; ++u) nxt[u] = ld(c0 + B + u);
 #pragma unroll
       for (int u = 0; u < B; ++u) {
         const int c = c0 + u;
@@ -813,15 +822,21 @@ __device__ __forceinline__ void diag_block_solve(const cplx_t<T> *LU, int N, int
       }
     }
   } else {
-    const double2 dinv = lane < nb ? crcp(to_d2(rowp[(long long)lane * N])) : make_double2(0.0, 0.0);
+    // column c (clamped at 0), row min(lane, c - 1) clamped at 0
+    auto ld = [&](int c) {
+      const int cc = max(c, 0);
+      return blk[min(rl, max(cc - 1, 0)) + (long long)cc * N];
+    };
+    const double2 dinv =
+        lane < nb ? crcp(to_d2(blk[rl + (long long)rl * N])) : make_double2(0.0, 0.0);
 #pragma unroll
-    for (int u = 0; u < B; ++u) nxt[u] = rowp[(long long)max(nb - 1 - u, 0) * N];
+    for (int u = 0; u < B; ++u) nxt[u] = ld(nb - 1 - u);
 #pragma unroll 1
     for (int c0 = nb - 1; c0 >= 0; c0 -= B) {
 #pragma unroll
       for (int u = 0; u < B; ++u) cur[u] = nxt[u];
 #pragma unroll
-      for (int u = 0; u < B; ++u) nxt[u] = rowp[(long long)max(c0 - B - u, 0) * N];
+      for (int u = 0; u < B; ++u) nxt[u] = ld(c0 - B - u);
 #pragma unroll
       for (int u = 0; u < B; ++u) {
         const int c = c0 - u;
