@@ -335,6 +335,24 @@ int fthms_lu_solve_dev(fthms_ctx *ctx, int n, int nb, const fthms_c64 *LU_dev,
                        const int *piv_dev, const fthms_c64 *b_dev,
                        fthms_c64 *x_dev);
 
+/* The refinement stage of the FTHMS_FP32_REFINED solve (the direct solve of
+ * Section 3.2, eq. FDBIEk-interior, factored in FP32 and corrected in FP64),
+ * on caller-given matrices: A[nb] n x n complex128 (column-major, read
+ * only), LU32[nb] its complex64 factors and piv[nb][n] the pivots, both as
+ * fthms_lu_dev(FTHMS_FP32_REFINED) writes them, b[nb][n] right-hand sides
+ * (device pointers, context stream).  x0 = LU32^{-1} P b, then repeatedly
+ * r = b - A x in FP64, d = LU32^{-1} P r, x += d, until the predicted
+ * relative error |d_k| (|d_k| / |d_{k-1}|) falls below tol (> 0), at most
+ * max_iter (1..100) steps.  x[nb][n] receives the result; iters[nb]
+ * (optional) the steps taken, or -1 when the corrections stopped
+ * contracting or the cap was hit -- there is no FP64 redo here, x then
+ * holds the last iterate; relres[nb] (optional) the last |d| / |x|.
+ * b and x must not alias. */
+int fthms_lu_refine_dev(fthms_ctx *ctx, int n, int nb, const fthms_c64 *A_dev,
+                        const void *LU32_dev, const int *piv_dev, const fthms_c64 *b_dev,
+                        fthms_c64 *x_dev, double tol, int max_iter, int *iters_dev,
+                        double *relres_dev);
+
 /* Device Bessel functions used by the kernels: J0(z) and Y0(z) for nz
  * arguments z > 0 (FP64). */
 int fthms_bessel_dev(fthms_ctx *ctx, int nz, const double *z_dev,

@@ -103,6 +103,7 @@ _SIGS = {
     "fthms_assemble_dev": ([_vp, _vp, _i, _vp, _vp], _i),
     "fthms_lu_dev": ([_vp, _i, _i, _i, _vp, _vp, _vp], _i),
     "fthms_lu_solve_dev": ([_vp, _i, _i, _vp, _vp, _vp, _vp], _i),
+    "fthms_lu_refine_dev": ([_vp, _i, _i, _vp, _vp, _vp, _vp, _vp, _d, _i, _vp, _vp], _i),
     "fthms_bessel_dev": ([_vp, _i, _vp, _vp, _vp], _i),
     "fthms_problem_create": ([_vp, C.POINTER(ProblemDesc), C.POINTER(_vp)], _i),
     "fthms_problem_destroy": ([_vp], _i),
@@ -352,6 +353,13 @@ class Context:
         nb, n = LU.shape[0], LU.shape[-1]
         self.check(_lib.fthms_lu_solve_dev(self.h, n, nb, _dptr(LU), _dptr(piv), _dptr(b),
                                            _dptr(x)), "lu_solve_dev")
+
+    def lu_refine_dev(self, A, LU32, piv, b, x, tol=1e-12, max_iter=10, iters=None,
+                      relres=None):
+        nb, n = A.shape[0], A.shape[-1]
+        self.check(_lib.fthms_lu_refine_dev(self.h, n, nb, _dptr(A), _dptr(LU32), _dptr(piv),
+                                            _dptr(b), _dptr(x), tol, int(max_iter),
+                                            _dptr(iters), _dptr(relres)), "lu_refine_dev")
 
     def bessel_dev(self, z, j0, y0):
         self.check(_lib.fthms_bessel_dev(self.h, z.numel(), _dptr(z), _dptr(j0), _dptr(y0)),

@@ -1497,6 +1497,36 @@ int fthms_lu_solve_dev(fthms_ctx *ctx, int n, int nb, const fthms_c64 *LU_dev, c
   return check_launch(ctx, "lu_solve64_kernel");
 }
 
+int fthms_lu_refine_dev(fthms_ctx *ctx, int n, int nb, const fthms_c64 *A_dev,
+                        const void *LU32_dev, const int *piv_dev, const fthms_c64 *b_dev,
+                        fthms_c64 *x_dev, double tol, int max_iter, int *iters_dev,
+                        double *relres_dev) {
+  if (!ctx || n < 1 || n > kMaxN || nb < 0 || max_iter < 1 || max_iter > 100 ||
+      !(tol > 0.0) ||
+      (nb > 0 && (!A_dev || !LU32_dev || !piv_dev || !b_dev || !x_dev)))
+    return fail(ctx, FTHMS_EINVAL, "bad argument to fthms_lu_refine_dev");
+  if (nb == 0) return FTHMS_OK;
+  HIPCK(ctx, hipSetDevice(ctx->device));
+  // scratch: gather permutations [nb][kMaxN], then the status words [nb]
+  const size_t perm_bytes = sizeof(int) * kMaxN * (size_t)nb;
+  int rc = ensure_ws2(ctx, perm_bytes + sizeof(int) * (size_t)nb + 256);
+  if (rc) return rc;
+  int *perm = (int *)ctx->ws2;
+  int *status = (int *)((char *)ctx->ws2 + perm_bytes);
+  HIPCK(ctx, hipMemsetAsync(status, 0, sizeof(int) * (size_t)nb, ctx->stream));
+  tbeg(ctx, "solve");
+  launch_perm(ctx->stream, piv_dev, n, perm, nullptr, nb, 0);
+  refine_kernel<<<nb, kLuThreads, 2 * n * sizeof(double2), ctx->stream>>>(
+      (const float2 *)LU32_dev, perm, (const double2 *)A_dev, n, (long long)n * n,
+      (const double2 *)b_dev, (double2 *)x_dev, n, tol, max_iter, status, relres_dev);
+  tend(ctx);
+  if ((rc = check_launch(ctx, "refine_kernel"))) return rc;
+  if (iters_dev)
+    HIPCK(ctx, hipMemcpyAsync(iters_dev, status, sizeof(int) * (size_t)nb,
+                              hipMemcpyDeviceToDevice, ctx->stream));
+  return FTHMS_OK;
+}
+
 int fthms_bessel_dev(fthms_ctx *ctx, int nz, const double *z_dev, double *j0_dev, double *y0_dev) {
   if (!ctx || nz < 0 || (nz > 0 && (!z_dev || !j0_dev || !y0_dev)))
     return fail(ctx, FTHMS_EINVAL, "bad argument to fthms_bessel_dev");

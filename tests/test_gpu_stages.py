@@ -207,3 +207,72 @@ def test_batched_lu_split_batch_bitwise(env, prec):
         torch.cuda.synchronize()
         assert torch.equal(one[0], A[b]), b
         assert torch.equal(piv1[0], piv[b]), b
+
+
+@pytest.mark.parametrize("n", [7, 65, 300, 512, 1024])
+def test_refined_solve_with_row_interchanges(env, n):
+    """The refined solve (FP32 factors with pivoting, FP64 residuals) on
+    random complex matrices, whose partial pivoting moves rows in every
+    block: the gather of the permutation inside the refinement kernel and the
+    FP32 substitutions after real swaps.  Every solve must converge by
+    refinement alone (no FP64 redo) to the oracle's direct solve."""
+    fth, ctx, torch = env
+    rng = np.random.default_rng(500 + n)
+    nb = 3
+    M = rng.standard_normal((nb, n, n)) + 1j * rng.standard_normal((nb, n, n))
+    bvec = rng.standard_normal((nb, n)) + 1j * rng.standard_normal((nb, n))
+    say("lu_refine n", n)
+    Acm = np.ascontiguousarray(M.transpose(0, 2, 1))
+    A64 = torch.tensor(Acm, dtype=torch.complex128, device="cuda")
+    LU32 = torch.tensor(Acm, dtype=torch.complex64, device="cuda")
+    piv = torch.empty((nb, n), dtype=torch.int32, device="cuda")
+    info = torch.empty(nb, dtype=torch.int32, device="cuda")
+    ctx.lu_dev(LU32, piv, info, precision=1)
+    bt = torch.tensor(bvec, device="cuda")
+    x = torch.empty_like(bt)
+    iters = torch.empty(nb, dtype=torch.int32, device="cuda")
+    relres = torch.empty(nb, dtype=torch.float64, device="cuda")
+    ctx.lu_refine_dev(A64, LU32, piv, bt, x, tol=1e-12, max_iter=10, iters=iters,
+                      relres=relres)
+    torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0)
+    pv = piv.cpu().numpy()
+    it = iters.cpu().numpy()
+    xs = x.cpu().numpy()
+    # the input is untouched (it is the FP64 residual's matrix)
+    assert torch.equal(A64.cpu(), torch.tensor(Acm))
+    for b in range(nb):
+        if n > 1:
+            assert np.any(pv[b] != np.arange(n)), "test matrix did not pivot"
+        assert it[b] >= 1, (n, b, it[b])
+        ref = ony.solve(M[b], bvec[b])
+        err = np.linalg.norm(xs[b] - ref) / np.linalg.norm(ref)
+        assert err < 1e-10, (n, b, err, it[b])
+
+
+def test_refined_solve_reports_cap(env):
+    """With a cap of one step and an unreachable tolerance the refinement
+    reports -1 (not converged) and still returns its last iterate."""
+    fth, ctx, torch = env
+    n, nb = 200, 2
+    rng = np.random.default_rng(77)
+    M = rng.standard_normal((nb, n, n)) + 1j * rng.standard_normal((nb, n, n))
+    bvec = rng.standard_normal((nb, n)) + 1j * rng.standard_normal((nb, n))
+    Acm = np.ascontiguousarray(M.transpose(0, 2, 1))
+    A64 = torch.tensor(Acm, dtype=torch.complex128, device="cuda")
+    LU32 = torch.tensor(Acm, dtype=torch.complex64, device="cuda")
+    piv = torch.empty((nb, n), dtype=torch.int32, device="cuda")
+    ctx.lu_dev(LU32, piv, precision=1)
+    bt = torch.tensor(bvec, device="cuda")
+    x = torch.empty_like(bt)
+    iters = torch.empty(nb, dtype=torch.int32, device="cuda")
+    say("lu_refine cap", n)
+    ctx.lu_refine_dev(A64, LU32, piv, bt, x, tol=1e-30, max_iter=1, iters=iters)
+    torch.cuda.synchronize()
+    assert np.all(iters.cpu().numpy() == -1)
+    xs = x.cpu().numpy()
+    for b in range(nb):
+        ref = ony.solve(M[b], bvec[b])
+        assert np.linalg.norm(xs[b] - ref) / np.linalg.norm(ref) < 1e-6
+    with pytest.raises(fth.FthmsError):
+        ctx.lu_refine_dev(A64, LU32, piv, bt, x, tol=1e-12, max_iter=0)
