@@ -23,6 +23,7 @@ import json
 import math
 import os
 import sys
+import subprocess
 import time
 
 import numpy as np
@@ -126,18 +127,28 @@ def _oracle_job(case, kk):
     return (float(kk), case["curve"], case["incident"], case["obs"])
 
 
+# Worker processes of the all-cores CPU baseline: one GPU's share of the host
+# (16 cores) however many cores the host shows, so that the baseline neither
+# oversubscribes a shared host nor depends on its size.
+CPU_SHARE = 16
+
+
 def cpu_pool_leg(case, k_all, budget_s=12.0):
-    """The oracle on every host core: a pool of worker processes, each solving
-    whole wavenumbers with BLAS on one thread, over about budget_s of work on
-    evenly spaced wavenumbers across the band.  Run before anything touches
-    the GPU, so the workers start from a process with no device state."""
+    """The oracle on the GPU's share of the host cores (min(CPU_SHARE, cores
+    this process may run on) worker processes, each solving whole wavenumbers
+    with BLAS on one thread), over about budget_s of work on evenly spaced
+    wavenumbers across the band.  Run before anything touches the GPU, so the
+    workers start from a process with no device state.  The record names the
+    cap, the host's core count and its CPU model."""
     import multiprocessing as mp
     from concurrent.futures import ProcessPoolExecutor
     t0 = time.perf_counter()
     for kk in (k_all[0], k_all[-1]):
         _oracle_solve(_oracle_job(case, kk))
     rate = 2.0 / (time.perf_counter() - t0)  # one core, for sizing the sample
-    workers = max(1, min(16, os.cpu_count() or 1))
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (
+        os.cpu_count() or 1)
+    workers = max(1, min(CPU_SHARE, avail))
     nsol = min(len(k_all), workers * max(1, int(rate * budget_s)))
     args = [_oracle_job(case, kk) for kk in k_all[np.linspace(0, len(k_all) - 1, nsol).astype(int)]]
     # an executor, not multiprocessing.Pool: a worker that dies raises here
@@ -152,11 +163,20 @@ def cpu_pool_leg(case, k_all, budget_s=12.0):
             "sample": "%d of the %d wavenumbers, evenly spaced, over %d worker processes "
                       "(assembly + LU solve + 256-point field per solve, numpy/scipy FP64, "
                       "BLAS on one thread each)" % (nsol, len(k_all), workers),
+            "worker_cap": CPU_SHARE,
+            "host_nproc": os.cpu_count(), "host_cores_available": avail,
             "cpu_model": cpu_model()}
 
 
 def cpu_model():
-    """The host CPU's model name (Linux), or None."""
+    """The host CPU's model name (lscpu, else /proc/cpuinfo), or None."""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.strip().startswith("Model name"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:

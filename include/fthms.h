@@ -133,7 +133,10 @@ int fthms_timing_read(fthms_ctx *ctx, const char *name, double *total_ms,
 /* ---- discretisation ---------------------------------------------------- */
 
 /* First-kind Chebyshev nodes t_i = cos((2i - 1) pi / (2n)), i = 1..n
- * (n >= 2), written to t_out[n] in that order (t decreasing). */
+ * (n >= 2), written to t_out[n] in that order (t decreasing): the
+ * collocation points of the endpoint-weighted density discretisation
+ * (Section 4.3, eq. singularity: psi |x'| = alpha / sqrt(1 - t^2), alpha
+ * expanded in Chebyshev polynomials). */
 int fthms_cheb_nodes(int n, double *t_out);
 
 /* Register one arc from samples at the Chebyshev nodes: xy[n][2] = x(t_i),
@@ -250,8 +253,10 @@ int fthms_arc_panel_table(const fthms_arc *arc, double *W, double *w);
 
 /* ---- the per-(arc, k) solve --------------------------------------------- */
 
-/* For each of nk wavenumbers k[i] > 0: assemble the Nystrom matrix of
- * V_Gamma on `arc`, factor it (LU with partial pivoting) and solve
+/* The open-arc first-kind equation V_Gamma[psi] = G (Section 3.2, eq.
+ * FDBIEk-interior; Phi_k of Section 2.1; discretised per Section 4.3, eq.
+ * singularity).  For each of nk wavenumbers k[i] > 0: assemble the Nystrom
+ * matrix of V_Gamma on `arc`, factor it (LU with partial pivoting) and solve
  * A alpha = rhs[i].  rhs, alpha: [nk][n].  precision FTHMS_FP64 factors in
  * complex FP64; FTHMS_FP32_REFINED factors in complex FP32 (MFMA trailing
  * updates, pivots chosen on FP64 magnitudes) and refines with FP64
@@ -290,7 +295,7 @@ int fthms_rhs_dev(fthms_ctx *ctx, const fthms_arc *arc, int nk,
                   fthms_c64 *rhs_dev);
 
 /* Single-layer potential U(z_p) = S_Gamma[psi](z_p) of the density alpha
- * at np points xy[np][2]: U[nk][np].  Points farther than ten node spacings
+ * at np points xy[np][2] (Section 3.2, eq. FDsolk-interior): U[nk][np].  Points farther than ten node spacings
  * from every node use the Gauss-Chebyshev rule; nearer points use a graded
  * composite Gauss-Legendre rule on the Chebyshev interpolant of alpha.  The
  * _dev form copies the points and wavenumbers to the host to plan the near
@@ -302,7 +307,10 @@ int fthms_eval_field_dev(fthms_ctx *ctx, const fthms_arc *arc, int nk,
                          const double *k_dev, const fthms_c64 *alpha_dev,
                          int np, const double *xy_dev, fthms_c64 *U_dev);
 
-/* u(x_p, t_n) = (1/2pi) sum_l w[l] U[l][p] exp(-i omega[l] t_n):
+/* The inverse Fourier transform of Section 2.1 (eq. backwardFT, applied
+ * as in eq. TDsol-interior with one window) by a quadrature over the given
+ * frequencies:
+ * u(x_p, t_n) = (1/2pi) sum_l w[l] U[l][p] exp(-i omega[l] t_n):
  * U[nk][np] -> u[nt][np]. */
 int fthms_freq_to_time(fthms_ctx *ctx, int nk, const double *omega,
                        const double *w, int np, const fthms_c64 *U, int nt,
@@ -394,8 +402,11 @@ int fthms_problem_create(fthms_ctx *ctx, const fthms_problem_desc *desc,
                          fthms_problem **out);
 int fthms_problem_destroy(fthms_problem *pb);
 
-/* Run the recursion at nk wavenumbers and evaluate u_M = sum_m sum_j v_{j,m}
- * at the observation points: U[nk][nobs] (optional).  alpha_tot (optional)
+/* Run the multiple-scattering recursion (Section 3.1, Definition
+ * inductive_int, eqs. criterion_int1, criterion_int2 and vtilde; the loop of
+ * Algorithm 1 taken per frequency) at nk wavenumbers and evaluate
+ * u_M = sum_m sum_j v_{j,m} (eq. mult-scatt-int) at the observation points:
+ * U[nk][nobs] (optional).  alpha_tot (optional)
  * receives sum_m alpha_{j,m} as [nk][sum_j n_j] in arc order.  The _dev form
  * takes device pointers; it copies k to the host (to size the near-target
  * rules) and then enqueues everything on the context's stream. */
