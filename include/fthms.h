@@ -361,6 +361,20 @@ int fthms_lu_refine_dev(fthms_ctx *ctx, int n, int nb, const fthms_c64 *A_dev,
                         fthms_c64 *x_dev, double tol, int max_iter, int *iters_dev,
                         double *relres_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * solve as fthms_lu_solve_dev, with its scratch (the gather permutations)
+ * in a fixed device array of the library instead of the context's
+ * workspace.  The array holds 4096 matrices of up to 1024 rows (16 MiB per
+ * device, held until the process ends); nb > 4096 fails with FTHMS_EINVAL.
+ * No device or host memory is allocated and no timing events are recorded.
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (other streams, other threads, other contexts) race and must
+ * be ordered by the caller. */
+int fthms_lu_solve_noalloc_dev(fthms_ctx *ctx, int n, int nb, const fthms_c64 *LU_dev,
+                               const int *piv_dev, const fthms_c64 *b_dev,
+                               fthms_c64 *x_dev);
+
 /* Device Bessel functions used by the kernels: J0(z) and Y0(z) for nz
  * arguments z > 0 (FP64). */
 int fthms_bessel_dev(fthms_ctx *ctx, int nz, const double *z_dev,

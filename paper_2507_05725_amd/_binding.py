@@ -103,6 +103,7 @@ _SIGS = {
     "fthms_assemble_dev": ([_vp, _vp, _i, _vp, _vp], _i),
     "fthms_lu_dev": ([_vp, _i, _i, _i, _vp, _vp, _vp], _i),
     "fthms_lu_solve_dev": ([_vp, _i, _i, _vp, _vp, _vp, _vp], _i),
+    "fthms_lu_solve_noalloc_dev": ([_vp, _i, _i, _vp, _vp, _vp, _vp], _i),
     "fthms_lu_refine_dev": ([_vp, _i, _i, _vp, _vp, _vp, _vp, _vp, _d, _i, _vp, _vp], _i),
     "fthms_bessel_dev": ([_vp, _i, _vp, _vp, _vp], _i),
     "fthms_problem_create": ([_vp, C.POINTER(ProblemDesc), C.POINTER(_vp)], _i),
@@ -353,6 +354,11 @@ class Context:
         nb, n = LU.shape[0], LU.shape[-1]
         self.check(_lib.fthms_lu_solve_dev(self.h, n, nb, _dptr(LU), _dptr(piv), _dptr(b),
                                            _dptr(x)), "lu_solve_dev")
+
+    def lu_solve_noalloc_dev(self, LU, piv, b, x):
+        nb, n = LU.shape[0], LU.shape[-1]
+        self.check(_lib.fthms_lu_solve_noalloc_dev(self.h, n, nb, _dptr(LU), _dptr(piv),
+                                                   _dptr(b), _dptr(x)), "lu_solve_noalloc_dev")
 
     def lu_refine_dev(self, A, LU32, piv, b, x, tol=1e-12, max_iter=10, iters=None,
                       relres=None):

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <map>
 #include <new>
 #include <string>
@@ -83,6 +84,18 @@ struct fthms_arc {
 };
 
 static thread_local std::string g_create_err;
+
+// ---- fixed device scratch for the allocation-free entry point ------------
+// The gather permutations of fthms_lu_solve_noalloc_dev live in this array:
+// kNoAllocMatrices slots of kMaxN ints (16 MiB), one copy per device for the
+// life of the process.  Host code never uses the array's name as an address:
+// fthms_create looks up each device's copy with hipGetSymbolAddress (with
+// that device current) and keeps the pointer in g_scratch_ptr.
+constexpr int kNoAllocMatrices = 4096;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) int scratch[(size_t)kNoAllocMatrices * kMaxN];
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
 
 static int fail(fthms_ctx *ctx, int code, const std::string &msg) {
   if (ctx) ctx->err = msg;
@@ -236,6 +249,24 @@ int fthms_create(fthms_ctx **out, int device, size_t hbm_budget_bytes, void *hip
   if (hipSetDevice(device) != hipSuccess) {
     delete ctx;
     return fail(nullptr, FTHMS_EDEVICE, "hipSetDevice failed");
+  }
+  if (device >= kMaxDevices) {
+    delete ctx;
+    return fail(nullptr, FTHMS_EINVAL, "device index beyond the library's device table");
+  }
+  {
+    // this device's copy of the fixed scratch array, looked up once
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+      void *p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p) {
+        delete ctx;
+        return fail(nullptr, FTHMS_EDEVICE,
+                    std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      }
+      g_scratch_ptr[device] = p;
+    }
   }
   if (hip_stream != FTHMS_OWN_STREAM) {
     ctx->stream = (hipStream_t)hip_stream;  // NULL: the null stream
@@ -1495,6 +1526,33 @@ int fthms_lu_solve_dev(fthms_ctx *ctx, int n, int nb, const fthms_c64 *LU_dev, c
                                                         (double2 *)x_dev, n);
   tend(ctx);
   return check_launch(ctx, "lu_solve64_kernel");
+}
+
+int fthms_lu_solve_noalloc_dev(fthms_ctx *ctx, int n, int nb, const fthms_c64 *LU_dev,
+                               const int *piv_dev, const fthms_c64 *b_dev, fthms_c64 *x_dev) {
+  if (!ctx || n < 1 || n > kMaxN || nb < 0 ||
+      (nb > 0 && (!LU_dev || !piv_dev || !b_dev || !x_dev)))
+    return fail(ctx, FTHMS_EINVAL, "bad argument to fthms_lu_solve_noalloc_dev");
+  if (nb > kNoAllocMatrices)
+    return fail(ctx, FTHMS_EINVAL,
+                "fthms_lu_solve_noalloc_dev: nb = " + std::to_string(nb) +
+                    " exceeds the fixed scratch of " + std::to_string(kNoAllocMatrices) +
+                    " matrices");
+  if (nb == 0) return FTHMS_OK;
+  HIPCK(ctx, hipSetDevice(ctx->device));
+  int *perm = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    perm = (int *)g_scratch_ptr[ctx->device];
+  }
+  if (!perm) return fail(ctx, FTHMS_EDEVICE, "fixed scratch not set up for this device");
+  // every entry the solve reads is written by the permutation kernel first,
+  // so nothing needs clearing; no timing events either (they allocate)
+  launch_perm(ctx->stream, piv_dev, n, perm, nullptr, nb, 0);
+  lu_solve64_kernel<<<nb, kLuThreads, 0, ctx->stream>>>((const double2 *)LU_dev, perm, n,
+                                                        (long long)n * n, (const double2 *)b_dev,
+                                                        (double2 *)x_dev, n);
+  return check_launch(ctx, "lu_solve64_kernel (no-alloc)");
 }
 
 int fthms_lu_refine_dev(fthms_ctx *ctx, int n, int nb, const fthms_c64 *A_dev,
