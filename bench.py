@@ -266,7 +266,8 @@ def uneven_batch(fth, ctx, torch, steps, tol):
 
 def kite_cavity(fth, ctx, reps=3, n_per=86):
     """The kite cavity (4 arcs, 512 frequencies up to 80, M = 6, 64 interior
-    points, 2001 time samples) with single-panel arcs of N = 256 and with
+    points, 2001 time samples) with single-panel arcs of N = 256 (FP64 and the
+    refined form, whose fields are compared with the FP64 ones) and with
     composite-panel arcs (each arc cut at the ends of its truncated overlap,
     three panels of n_per nodes): set-up time (tables, plans) and warm time
     per run (all frequencies, all steps, fields and the time transform)."""
@@ -279,14 +280,18 @@ def kite_cavity(fth, ctx, reps=3, n_per=86):
     iv = np.array([a.curve.interval for a in pb.arcs])
     rec = {"workload": "kite cavity, 4 arcs (120 deg, 30 deg overlaps), 512 frequencies on (0, 80], "
                        "M = 6, 64 interior points, 2001 time samples"}
-    for name in ("single_panel", "panels"):
+    U64 = None
+    for name in ("single_panel", "single_panel_refined", "panels"):
         t0 = time.perf_counter()
         if name == "panels":
             brs = fth.tov_breaks(iv, None, pb.period)
             arcs = [ctx.panel_arc_from_curve(a.curve, n_per, b) for a, b in zip(pb.arcs, brs)]
         else:
             arcs = [ctx.arc_from_curve(a.curve, a.n) for a in pb.arcs]
-        prob = fth.Problem(ctx, arcs, pb.incident, pb.obs, intervals=iv, M=pb.M)
+        refined = name.endswith("_refined")
+        prob = fth.Problem(ctx, arcs, pb.incident, pb.obs, intervals=iv, M=pb.M,
+                           precision=fth.FP32_REFINED if refined else fth.FP64,
+                           tol=1e-11 if refined else 0.0)
         U = prob.run(om)
         ctx.freq_to_time(om, w, U, pb.times)
         setup = time.perf_counter() - t0
@@ -299,6 +304,11 @@ def kite_cavity(fth, ctx, reps=3, n_per=86):
         rec[name] = {"n_per_arc": arcs[0].n, "first_run_with_setup_s": round(setup, 3),
                      "ms_per_run": round(1e3 * min(ts), 2),
                      "solves_per_s": round(len(arcs) * om.size * pb.M / min(ts), 1)}
+        if name == "single_panel":
+            U64 = U
+        elif refined:
+            rec[name]["max_rel_err_fields_vs_fp64"] = float(max(
+                np.linalg.norm(U[i] - U64[i]) / np.linalg.norm(U64[i]) for i in range(om.size)))
         prob.close()
         for a in arcs:
             a.close()

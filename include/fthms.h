@@ -214,7 +214,8 @@ typedef struct {
  * quadrature weights w for the way back), solves with the factors of the
  * first step, evaluates the fields and transforms them back shifted by
  * s_q.  The data must fit inside sum_q window = 1, i.e. nt dt <= s_Q + H/2
- * for signals that last to the end.  FP64 problems only; traces [nt][nobs]
+ * for signals that last to the end.  Either precision (the refined form
+ * keeps each matrix's FP32 factors for every window and step); traces [nt][nobs]
  * (host).  All frequencies and time series stay resident (FTHMS_ENOMEM if
  * they do not fit the budget). */
 int fthms_problem_traces_windowed(fthms_problem *pb, int nk, const double *k, const double *w,
@@ -393,7 +394,10 @@ int fthms_bessel_dev(fthms_ctx *ctx, int nz, const double *z_dev,
  * `period` (arc j's local t = -1 maps to interval[2j]); they decide overlap
  * membership.  c0, c1 are the POU constants of eq. POU1 (the paper uses
  * 1/3, 2/3); the window distances are chords.  M >= 1 multiple-scattering
- * steps.  Multi-arc problems run in FTHMS_FP64.  narcs == 1 is allowed and
+ * steps.  precision FTHMS_FP64 or FTHMS_FP32_REFINED (FP32 factors kept
+ * for all M steps and refined to tol at every solve; a matrix whose
+ * refinement fails is refactored in FP64 once and solved with those
+ * factors from then on).  narcs == 1 is allowed and
  * runs the plain sound-soft single-arc problem (G = -U^inc, no recursion,
  * either precision).  The field u_M is evaluated at nobs observation
  * points obs_xy[nobs][2] (copied at creation). */

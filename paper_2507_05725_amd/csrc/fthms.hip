@@ -890,12 +890,20 @@ static int launch_lu(fthms_ctx *ctx, bool fp32, void *A, int N, long long ms, in
   return check_launch(ctx, "lu kernels");
 }
 
-// FP64 redo of refined solves with negative status: factor A64 in place and
-// solve.
+// FP64 redo of refined solves: factor A64 in place for the matrices the
+// redo mode selects (kRedoFailed: status < 0 after a first solve; kRedoLate:
+// refinement failed at a later solve) and solve every matrix whose status
+// is negative with its FP64 factors (those redone now and, at later solves,
+// those redone before).
 static int launch_fallback(fthms_ctx *ctx, double2 *A, int N, long long ms, int *piv, void *swp,
-                           const double2 *b, double2 *x, int *status, int count) {
-  int rc = launch_lu(ctx, false, A, N, ms, piv, swp, status, count, 1);
+                           const double2 *b, double2 *x, int *status, int count,
+                           int mode = kRedoFailed) {
+  int rc = launch_lu(ctx, false, A, N, ms, piv, swp, status, count, mode);
   if (rc) return rc;
+  if (mode == kRedoLate) {
+    late_redo_done_kernel<<<(count + 255) / 256, 256, 0, ctx->stream>>>(status, count);
+    if ((rc = check_launch(ctx, "late_redo_done_kernel"))) return rc;
+  }
   solve_failed64_kernel<<<count, kLuThreads, 0, ctx->stream>>>(A, lu_perm(swp, count), N, ms, b,
                                                                x, N, status);
   return check_launch(ctx, "solve_failed64_kernel");

@@ -88,6 +88,30 @@ constexpr int kLuNB = 64;
 constexpr int kLuPW = 8;
 
 constexpr int kMaxN = 1024;
+
+// Status words of a batched factorisation and what a redo pass factors.
+// After the FP32 LU: 0, or -2 for an exactly zero pivot.  A refined solve
+// writes its step count (>= 1) or, when it does not converge, -1 on the
+// first solve with fresh factors and kStatusLateFail on a later solve with
+// factors kept from earlier (multiple-scattering steps).  A redo pass
+// (FP64 LU of A64 in place) then sets -1: the matrix is solved with FP64
+// factors from then on.  Redo modes: kRedoNone factors every matrix,
+// kRedoFailed those with status < 0 (first solves), kRedoLate those with
+// status kStatusLateFail (later solves; the others, still FP32 or already
+// FP64, are left alone).
+constexpr int kStatusLateFail = -3;
+constexpr int kRedoNone = 0, kRedoFailed = 1, kRedoLate = 2;
+__device__ __forceinline__ bool redo_skips(int mode, const int *status, long long mb) {
+  if (mode == kRedoFailed) return status[mb] >= 0;
+  if (mode == kRedoLate) return status[mb] != kStatusLateFail;
+  return false;
+}
+// status written by a panel at block 0 (k0 == 0): zero pivot, or the mode's
+// "factored" value (a late redo keeps its marker until the whole
+// factorisation is done, so that every block step still selects it)
+__device__ __forceinline__ int panel_status(int mode, bool zero) {
+  return zero ? -2 : mode == kRedoFailed ? -1 : mode == kRedoLate ? kStatusLateFail : 0;
+}
 constexpr int kSwapMax = 2 * kLuNB;          // pairs per block
 constexpr int kSwapStride = 1 + 2 * kSwapMax;  // ints per matrix
 
@@ -252,7 +276,7 @@ __global__ __launch_bounds__(kLuThreads) void lu_panel_kernel(cplx_t<T> *Abase, 
   typedef cplx_t<T> T2;
   __shared__ LuSmem sm;
   const long long mb = blockIdx.x;
-  if (only_failed && status[mb] >= 0) return;
+  if (redo_skips(only_failed, status, mb)) return;
   T2 *A = Abase + mb * mstride;
   int *piv = pivbase + mb * N;
   int *swp = swapbase + mb * kSwapStride;
@@ -479,9 +503,9 @@ __global__ __launch_bounds__(kLuThreads) void lu_panel_kernel(cplx_t<T> *Abase, 
   __syncthreads();
   if (tid == 0) {
     swp[0] = sm.count;
-    // status: 0 ok, -2 exact zero pivot; a redo (only_failed) stays negative
-    // (-1: redone in FP64) so that its solve is redone too
-    if (k0 == 0) status[mb] = sm.zero_pivot ? -2 : (only_failed ? -1 : 0);
+    // status: 0 ok, -2 exact zero pivot; a redo stays negative (-1: redone
+    // in FP64) so that its solve is redone too
+    if (k0 == 0) status[mb] = panel_status(only_failed, sm.zero_pivot != 0);
     else if (sm.zero_pivot) status[mb] = -2;
   }
 }
@@ -508,7 +532,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3, sizeof(T) == 8 ? 2 : 
   const int ns = nleft + nright;
   const int mat = xcd + 8 * (idx / ns), s = idx % ns;
   if (mat >= batch) return;
-  if (only_failed && status[mat] >= 0) return;
+  if (redo_skips(only_failed, status, mat)) return;
   T2 *A = Abase + (long long)mat * mstride;
   const int *swp = swapbase + (long long)mat * kSwapStride;
   const int tid = threadIdx.x;
@@ -753,7 +777,7 @@ template <int S>
 __global__ __launch_bounds__(64) void perm_from_piv_kernel(const int *pivbase, int N, int *permbase,
                                                            const int *status, int only_failed) {
   const long long mb = blockIdx.x;
-  if (only_failed && status[mb] >= 0) return;
+  if (redo_skips(only_failed, status, mb)) return;
   const int *piv = pivbase + mb * N;
   int *perm = permbase + mb * kMaxN;
   const int lane = threadIdx.x;
@@ -921,7 +945,7 @@ __device__ double block_sum(double v, double *red) {
 __global__ __launch_bounds__(kLuThreads, 3) void refine_kernel(
     const float2 *LUbase, const int *permbase, const double2 *A64base, int N,
     long long mstride, const double2 *b, double2 *x, long long vstride, double tol,
-    int max_iter, int *status, double *relres) {
+    int max_iter, int *status, double *relres, int later = 0) {
   // dynamic LDS: x and r, N complex128 each (sized at launch; 16 KB at
   // N = 512), the only LDS of the kernel, so registers set its occupancy
   extern __shared__ double2 refine_dyn[];
@@ -937,6 +961,8 @@ __global__ __launch_bounds__(kLuThreads, 3) void refine_kernel(
     for (int i = tid; i < N; i += kLuThreads) x[mb * vstride + i] = make_double2(0.0, 0.0);
     return;
   }
+  // a later solve of a matrix already redone in FP64: its FP64 solve follows
+  if (later && status && status[mb] < 0) return;
   for (int i = tid; i < N; i += kLuThreads) xs[i] = bb[i];
   __syncthreads();
   lu_solve_lds<float>(LU, piv, xs, N);
@@ -973,9 +999,16 @@ __global__ __launch_bounds__(kLuThreads, 3) void refine_kernel(
   }
   for (int i = tid; i < N; i += kLuThreads) x[mb * vstride + i] = xs[i];
   if (tid == 0) {
-    if (status) status[mb] = done ? (it > 0 ? it : 1) : -1;
+    if (status) status[mb] = done ? (it > 0 ? it : 1) : (later ? kStatusLateFail : -1);
     if (relres) relres[mb] = last;
   }
+}
+
+// After a late redo: the matrices factored in FP64 (status
+// kStatusLateFail) are solved with FP64 factors from now on (-1).
+__global__ void late_redo_done_kernel(int *status, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count && status[i] == kStatusLateFail) status[i] = -1;
 }
 
 // Solve for the matrices whose status is negative (FP64 redo after a

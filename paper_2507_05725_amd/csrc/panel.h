@@ -256,7 +256,7 @@ __global__ __launch_bounds__(kPrThreads) void lu_panel_reg_kernel(
   typedef cplx_t<T> T2;
   __shared__ PanelRegSmem<T, RL> sm;
   const long long mb = blockIdx.x;
-  if (only_failed && status[mb] >= 0) return;
+  if (redo_skips(only_failed, status, mb)) return;
   T2 *A = Abase + mb * mstride;
   int *piv = pivbase + mb * N;
   int *swp = swapbase + mb * kSwapStride;
@@ -361,7 +361,7 @@ __global__ __launch_bounds__(kPrThreads) void lu_panel_reg_kernel(
     // status: 0 ok, -2 exact zero pivot; a redo (only_failed) stays negative
     // (-1: redone in FP64) so that its solve is redone too
     const bool zero = sm.zero_pivot != 0x7fffffff;
-    if (k0 == 0) status[mb] = zero ? -2 : (only_failed ? -1 : 0);
+    if (k0 == 0) status[mb] = panel_status(only_failed, zero);
     else if (zero) status[mb] = -2;
   }
 }

@@ -237,8 +237,6 @@ int fthms_problem_create(fthms_ctx *ctx, const fthms_problem_desc *d, fthms_prob
   if (d->M < 1) return fail(ctx, FTHMS_EINVAL, "M must be >= 1");
   if (d->precision != FTHMS_FP64 && d->precision != FTHMS_FP32_REFINED)
     return fail(ctx, FTHMS_EINVAL, "unknown precision");
-  if (d->narcs > 1 && d->precision != FTHMS_FP64)
-    return fail(ctx, FTHMS_EINVAL, "multi-arc problems run in FP64");
   if (d->narcs > 1 && (!d->interval || !(d->period > 0.0) || !(d->c0 > 0.0) ||
                        !(d->c0 < 0.5) || !(d->c1 > 0.5) || !(d->c1 < 1.0)))
     return fail(ctx, FTHMS_EINVAL, "multi-arc problems need intervals, period > 0, "
@@ -475,7 +473,15 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
       nrm = (double *)(base + o[(size_t)10 * J + 2]);
     }
   }
-  auto solve_arc = [&](int j, int c) -> int {
+  // later: a solve after the first with the same factors (the FP32 factors
+  // of every arc are kept for all M steps; a matrix whose refinement fails
+  // is refactored in FP64 once and solved with those factors afterwards).
+  // FTHMS_REFINE_LATE_MAXIT=<n> in the environment caps the refinement
+  // steps of later solves (a test hook: 0 makes every later refinement fail,
+  // which exercises the late FP64 redo)
+  int late_maxit = 10;
+  if (const char *e = getenv("FTHMS_REFINE_LATE_MAXIT")) late_maxit = std::max(0, atoi(e));
+  auto solve_arc = [&](int j, int c, bool later = false) -> int {
     const int n = pb->arcs[j]->n;
     const long long ms = (long long)n * n;
     if (!fp32) {
@@ -487,14 +493,14 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
     }
     tbeg(ctx, "solve");
     refine_kernel<<<c, kLuThreads, 2 * n * sizeof(double2), ctx->stream>>>(
-        w[j].A32, lu_perm(w[j].swp, c), w[j].A64, n, ms, w[j].b, w[j].al, n, pb->tol, 10,
-        w[j].status, w[j].relres);
+        w[j].A32, lu_perm(w[j].swp, c), w[j].A64, n, ms, w[j].b, w[j].al, n, pb->tol,
+        later ? late_maxit : 10, w[j].status, w[j].relres, later ? 1 : 0);
     tend(ctx);
     int r = check_launch(ctx, "refine_kernel");
     if (r) return r;
     tbeg(ctx, "fallback");
     r = launch_fallback(ctx, w[j].A64, n, ms, w[j].piv, w[j].swp, w[j].b, w[j].al, w[j].status,
-                        c);
+                        c, later ? kRedoLate : kRedoFailed);
     tend(ctx);
     return r;
   };
@@ -579,7 +585,7 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
         const long long nn = (long long)n * c;
         chi_scale_kernel<<<grid1d(nn), 256, 0, ctx->stream>>>(w[j].cr, pb->d_chi[j], n, nn, w[j].b);
         if ((rc = check_launch(ctx, "chi_scale_kernel"))) return rc;
-        if ((rc = solve_arc(j, c))) return rc;
+        if ((rc = solve_arc(j, c, true))) return rc;
         axpy_kernel<<<grid1d(nn), 256, 0, ctx->stream>>>(w[j].tot, w[j].al, nn);
         if ((rc = check_launch(ctx, "axpy_kernel"))) return rc;
       }

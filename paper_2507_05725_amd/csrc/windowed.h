@@ -95,13 +95,17 @@ static int problem_windowed_impl(fthms_problem *pb, int nk, const double *k_dev,
     off += (bytes + 255) & ~(size_t)255;
     return r;
   };
+  // refined form: FP64 matrices kept for the residuals beside FP32 factors
+  const bool fp32 = pb->precision == FTHMS_FP32_REFINED;
   struct Ws {
-    size_t A, piv, swp, st, G, psi, g, cr;
+    size_t A, A32, piv, swp, st, rr, G, psi, g, cr;
   };
   std::vector<Ws> o(J);
   for (int j = 0; j < J; ++j) {
     const size_t n = pb->arcs[j]->n;
     o[j].A = take(n * n * sizeof(double2) * nk);
+    o[j].A32 = fp32 ? take(n * n * sizeof(float2) * nk) : 0;
+    o[j].rr = take(sizeof(double) * nk);
     o[j].piv = take(n * sizeof(int) * nk);
     o[j].swp = take(kLuScratchBytes * nk);
     o[j].st = take(sizeof(int) * nk);
@@ -162,13 +166,14 @@ static int problem_windowed_impl(fthms_problem *pb, int nk, const double *k_dev,
     const fthms_arc *a = pb->arcs[j];
     const int n = a->n;
     double2 *A = (double2 *)at(o[j].A);
+    float2 *A32 = fp32 ? (float2 *)at(o[j].A32) : nullptr;
     tbeg(ctx, "assemble");
-    rc = assemble_launch(ctx, a, k_dev, nk, A, nullptr);
+    rc = assemble_launch(ctx, a, k_dev, nk, A, A32);
     tend(ctx);
     if (rc) return rc;
     tbeg(ctx, "lu");
-    rc = launch_lu(ctx, false, A, n, (long long)n * n, (int *)at(o[j].piv), at(o[j].swp),
-                   (int *)at(o[j].st), nk);
+    rc = launch_lu(ctx, fp32, fp32 ? (void *)A32 : (void *)A, n, (long long)n * n,
+                   (int *)at(o[j].piv), at(o[j].swp), (int *)at(o[j].st), nk);
     tend(ctx);
     if (rc) return rc;
     const long long nn = (long long)nt * n;
@@ -199,11 +204,30 @@ static int problem_windowed_impl(fthms_problem *pb, int nk, const double *k_dev,
                                  (const double2 *)at(o[j].g), nk, nkv, Gq);
         tend(ctx);
         if (rc) return rc;
-        tbeg(ctx, "solve");
-        lu_solve64_kernel<<<nk, kLuThreads, 0, ctx->stream>>>(
-            (double2 *)at(o[j].A), lu_perm(at(o[j].swp), nk), n, (long long)n * n, Gq, pq, n);
-        tend(ctx);
-        if ((rc = check_launch(ctx, "lu_solve64_kernel"))) return rc;
+        if (!fp32) {
+          tbeg(ctx, "solve");
+          lu_solve64_kernel<<<nk, kLuThreads, 0, ctx->stream>>>(
+              (double2 *)at(o[j].A), lu_perm(at(o[j].swp), nk), n, (long long)n * n, Gq, pq, n);
+          tend(ctx);
+          if ((rc = check_launch(ctx, "lu_solve64_kernel"))) return rc;
+        } else {
+          // the first solve of each matrix uses fresh factors; every later
+          // one (other windows, later steps) reuses them
+          const bool later = m > 0 || q > 0;
+          tbeg(ctx, "solve");
+          refine_kernel<<<nk, kLuThreads, 2 * n * sizeof(double2), ctx->stream>>>(
+              (const float2 *)at(o[j].A32), lu_perm(at(o[j].swp), nk), (const double2 *)at(o[j].A),
+              n, (long long)n * n, Gq, pq, n, pb->tol, 10, (int *)at(o[j].st),
+              (double *)at(o[j].rr), later ? 1 : 0);
+          tend(ctx);
+          if ((rc = check_launch(ctx, "refine_kernel"))) return rc;
+          tbeg(ctx, "fallback");
+          rc = launch_fallback(ctx, (double2 *)at(o[j].A), n, (long long)n * n,
+                               (int *)at(o[j].piv), at(o[j].swp), Gq, pq, (int *)at(o[j].st), nk,
+                               later ? kRedoLate : kRedoFailed);
+          tend(ctx);
+          if (rc) return rc;
+        }
       }
       window_phase_kernel<<<grid1d((long long)n * nkq), 256, 0, ctx->stream>>>(psi, n, nk, Q,
                                                                                k_dev, sqv);
@@ -266,8 +290,6 @@ int fthms_problem_traces_windowed(fthms_problem *pb, int nk, const double *k, co
     return fail(pb ? pb->ctx : nullptr, FTHMS_EINVAL,
                 "bad argument to fthms_problem_traces_windowed");
   fthms_ctx *ctx = pb->ctx;
-  if (pb->precision != FTHMS_FP64)
-    return fail(ctx, FTHMS_EINVAL, "windowed runs solve in FP64");
   double kmax = 0.0;
   for (int l = 0; l < nk; ++l) {
     if (!(k[l] > 0.0) || !std::isfinite(k[l]) || !std::isfinite(w[l]))

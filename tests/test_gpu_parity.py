@@ -336,3 +336,96 @@ def test_far_field_target_counts(ctx, fth, npts):
         ref = ony.field_far(kk, pts, y, alpha[i])
         err = np.linalg.norm(U[i] - ref) / np.linalg.norm(ref)
         assert err < 1e-12, (npts, kk, err)
+
+
+def test_ms_refined_matches_oracle(ctx, fth):
+    """The refined form inside the multiple-scattering recursion (FP32
+    factors kept for all M steps, refined at every solve): the small kite
+    and the two-obstacle exterior problem against the oracle's recursion."""
+    from workloads import two_obstacle_case
+    pb = small_kite_case(n=40, omegas=(3.0, 7.5, 12.25), M=3, nobs=8)
+    say("ms small kite refined")
+    arcs = [ctx.arc_from_curve(a.curve, a.n) for a in pb.arcs]
+    iv = np.array([a.curve.interval for a in pb.arcs])
+    prob = fth.Problem(ctx, arcs, pb.incident, pb.obs, intervals=iv, M=pb.M,
+                       precision=fth.FP32_REFINED, tol=1e-12)
+    U, A = prob.run(np.asarray(pb.omegas, dtype=float), want_alpha=True)
+    lay = oms.Layout(pb)
+    for i, kk in enumerate(pb.omegas):
+        ref = oms.run_frequency(lay, kk)
+        assert rel(U[i], ref["U"]) < TOL, (kk, rel(U[i], ref["U"]))
+        assert rel(A[i], np.concatenate(ref["alpha_tot"])) < TOL
+    pb = two_obstacle_case(n=20, omegas=np.array([7.25]), M=5)
+    pb.incident = IncidentSpec("gplane", theta=0.4, omega0=7.5, sigma=1.5, tau0=3.0)
+    say("ms two obstacles refined")
+    arcs = [ctx.arc_from_curve(a.curve, a.n) for a in pb.arcs]
+    iv = np.array([a.curve.interval for a in pb.arcs])
+    prob = fth.Problem(ctx, arcs, pb.incident, pb.obs, intervals=iv, M=pb.M,
+                       groups=[a.group for a in pb.arcs], precision=fth.FP32_REFINED,
+                       tol=1e-12)
+    U, A = prob.run(np.asarray(pb.omegas, dtype=float), want_alpha=True)
+    ref = oms.run_frequency(oms.Layout(pb), pb.omegas[0])
+    assert rel(U[0], ref["U"]) < TOL, rel(U[0], ref["U"])
+    assert rel(A[0], np.concatenate(ref["alpha_tot"])) < TOL
+
+
+def test_ms_kite_cavity_refined(ctx, fth):
+    """The kite cavity at full size in the refined form: sampled frequencies
+    against the oracle's recursion, every frequency against the GPU's FP64
+    run, and the time traces against the FP64 run's traces."""
+    pb = kite_cavity_case()
+    say("ms kite cavity refined", len(pb.omegas), "frequencies")
+    arcs = [ctx.arc_from_curve(a.curve, a.n) for a in pb.arcs]
+    iv = np.array([a.curve.interval for a in pb.arcs])
+    om = np.asarray(pb.omegas, dtype=float)
+    p64 = fth.Problem(ctx, arcs, pb.incident, pb.obs, intervals=iv, M=pb.M)
+    p32 = fth.Problem(ctx, arcs, pb.incident, pb.obs, intervals=iv, M=pb.M,
+                      precision=fth.FP32_REFINED, tol=1e-12)
+    U64, A64 = p64.run(om, want_alpha=True)
+    U32, A32 = p32.run(om, want_alpha=True)
+    err_a = max(rel(A32[i], A64[i]) for i in range(om.size))
+    err_u = max(rel(U32[i], U64[i]) for i in range(om.size))
+    say("kite cavity refined vs FP64: densities %.2e, fields %.2e" % (err_a, err_u))
+    assert err_a < TOL and err_u < TOL
+    lay = oms.Layout(pb)
+    for i in (0, int(np.argmin(np.abs(om - 20.0)))):
+        ref = oms.run_frequency(lay, om[i])
+        assert rel(U32[i], ref["U"]) < TOL, (om[i], rel(U32[i], ref["U"]))
+        assert rel(A32[i], np.concatenate(ref["alpha_tot"])) < TOL, om[i]
+    w = otr.trapezoid_weights(om)
+    u64 = ctx.freq_to_time(om, w, U64, pb.times)
+    u32 = ctx.freq_to_time(om, w, U32, pb.times)
+    assert rel(u32, u64) < TOL
+
+
+def test_ms_refined_fp64_redo_paths(ctx, fth):
+    """Refinement failures inside the recursion: with an unreachable
+    tolerance every first solve is redone in FP64 and the matrices stay in
+    FP64 (bit-identical to the FP64 problem); with the later solves' step
+    cap at zero (a test hook) every later solve fails and is redone once in
+    FP64, which must still agree with the oracle."""
+    import os
+    pb = small_kite_case(n=40, omegas=(3.0, 7.5, 12.25), M=4, nobs=8)
+    arcs = [ctx.arc_from_curve(a.curve, a.n) for a in pb.arcs]
+    iv = np.array([a.curve.interval for a in pb.arcs])
+    om = np.asarray(pb.omegas, dtype=float)
+    p64 = fth.Problem(ctx, arcs, pb.incident, pb.obs, intervals=iv, M=pb.M)
+    U64, A64 = p64.run(om, want_alpha=True)
+    say("ms refined, every solve redone")
+    pall = fth.Problem(ctx, arcs, pb.incident, pb.obs, intervals=iv, M=pb.M,
+                       precision=fth.FP32_REFINED, tol=1e-30)
+    Ua, Aa = pall.run(om, want_alpha=True)
+    assert np.array_equal(Ua, U64) and np.array_equal(Aa, A64)
+    say("ms refined, later solves redone")
+    plate = fth.Problem(ctx, arcs, pb.incident, pb.obs, intervals=iv, M=pb.M,
+                        precision=fth.FP32_REFINED, tol=1e-12)
+    os.environ["FTHMS_REFINE_LATE_MAXIT"] = "0"
+    try:
+        Ul, Al = plate.run(om, want_alpha=True)
+    finally:
+        del os.environ["FTHMS_REFINE_LATE_MAXIT"]
+    lay = oms.Layout(pb)
+    for i, kk in enumerate(om):
+        ref = oms.run_frequency(lay, kk)
+        assert rel(Ul[i], ref["U"]) < TOL, (kk, rel(Ul[i], ref["U"]))
+        assert rel(Al[i], np.concatenate(ref["alpha_tot"])) < TOL

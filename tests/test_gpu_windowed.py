@@ -65,3 +65,17 @@ def test_windowed_agrees_with_single_window_traces(ctx, fth):
     uw = prob.traces_windowed(om, w, 0.1, 151, 2, 10.0, theta=0.3, omega0=9.0, sigma=1.0,
                               tau0=7.0)
     assert rel(uw, uf) < 1e-3
+
+
+def test_windowed_refined_matches_oracle(ctx, fth):
+    """The windowed recursion in the refined form (FP32 factors reused by
+    every window and step) against the oracle."""
+    pb, _, om, w, arcs = _setup(ctx, fth, 16, 41, 2)
+    iv = np.array([a.curve.interval for a in pb.arcs])
+    prob = fth.Problem(ctx, arcs, pb.incident, pb.obs, intervals=iv, M=pb.M,
+                       precision=fth.FP32_REFINED, tol=1e-12)
+    inc = dict(theta=0.3, omega0=9.0, sigma=1.0, tau0=7.0, npulse=3, period=4.0)
+    say("windowed refined, Q 5")
+    u = prob.traces_windowed(om, w, 0.1, 201, 5, 6.0, **inc)
+    ref = ow.run_windowed(oms.Layout(pb), om, w, 0.1, 201, 5, 6.0, inc)
+    assert rel(u, ref) < TOL, rel(u, ref)
