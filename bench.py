@@ -448,49 +448,101 @@ def windowed_long_time(fth, ctx, n=64, M=10, npulse=8, period=10.0, H=10.0, dt=0
     return rec
 
 
-def serving(fth, workers=8, count=32, seed=5):
-    """Serving loop: exterior scattering requests (1-3 obstacles of 4 arcs,
-    n 32..96, 48..128 frequencies, time-domain stop 1e-8 within 100 steps)
+# Serving request sizes drawn up to these caps (the workload allows n and J up
+# to 1024): the saturated rate, the 2 x 200 Poisson requests and the burst
+# then fit about two minutes.
+N_CAP = (64, 128)
+J_CAP = (128, 256)
+
+
+def _wait_ok(srv, fth, ticket):
+    """(traces, steps, latency) of a served request, or None if it failed."""
+    try:
+        return srv.wait(ticket)
+    except fth.FthmsError:
+        return None
+
+
+def serving(fth, workers=8, burst=64, count=200, seed=5):
+    """Serving loop on requests drawn from the serving workload's
+    distributions (workloads.serving_c5_requests: 1-12 closed obstacles, n
+    per obstacle U{64..128} (raised so that the other obstacles lie 5 node
+    spacings away), 128..256 frequencies (raised so that the frequency grid's
+    period covers twice the time window) on (0, 2 w0], w0 in [5, 40], Gaussian plane wave, 32 points,
+    time-domain stop 1e-8 decided on the device, at most 100 steps),
     submitted to a server with `workers` concurrent slots.  The saturated
-    rate comes from a burst of `count` requests; then `count` requests arrive
+    rate comes from a burst of `burst` requests; then `count` requests arrive
     as a Poisson stream at 0.5 and 0.8 of that rate, and the latency from
-    arrival to traces in host memory is reported (p50/p99)."""
-    from workloads import serving_requests
-    reqs = [fth.request_from_workload(r) for r in serving_requests(seed=seed, count=3 * count)]
+    arrival to traces in host memory is reported (p50/p99), with the steps
+    each request took and which rule ended it."""
+    from workloads import serving_c5_requests
+    gen = serving_c5_requests(seed=seed, count=workers + burst + 2 * count,
+                              n_range=N_CAP, nk_range=J_CAP)
+    reqs = [fth.request_from_workload(r) for r in gen]
     solves = lambda q, steps: len(q["xy"]) * len(q["k"]) * steps
     srv = fth.Server(0, workers=workers)
     # warm up (first touches of the device and of every worker)
     for t in [srv.submit(q) for q in reqs[:workers]]:
         srv.wait(t)
-    burst = reqs[:count]
+    reqs = reqs[workers:]
+    sl = slice(0, burst)
     t0 = time.perf_counter()
-    tickets = [srv.submit(q) for q in burst]
-    res = [srv.wait(t) for t in tickets]
+    tickets = [srv.submit(q) for q in reqs[sl]]
+    res = [_wait_ok(srv, fth, t) for t in tickets]
     dt = time.perf_counter() - t0
-    sat = count / dt
-    rec = {"workload": "exterior requests, 1-3 obstacles x 4 arcs (ellipses or kites), n 32..96, "
-                       "48..128 frequencies on (0, 2 w0], w0 in [3, 8], Gaussian plane wave, 32 "
-                       "points, stop 1e-8 (at most 100 steps); seed %d" % seed,
-           "workers": workers, "saturated_requests_per_s": round(sat, 2),
-           "saturated_solves_per_s": round(sum(solves(q, r[1]) for q, r in zip(burst, res)) / dt, 1),
-           "mean_steps": round(float(np.mean([r[1] for r in res])), 2), "poisson": []}
+    failed = sum(r is None for r in res)
+    sat = (burst - failed) / dt
+    all_steps = [r[1] for r in res if r is not None]
+    rec = {"workload": "exterior requests drawn from the serving distributions: 1-12 closed "
+                       "obstacles (ellipses with semi-axes U[0.2,1] or kites x U[0.3,1], >= 0.5 "
+                       "apart), each one combined-field patch of n nodes, n ~ U{64..128} raised "
+                       "so other obstacles lie 5 node spacings away, J ~ U{128..256} frequencies "
+                       "on (0, 2 w0] raised so the grid period covers twice the window, "
+                       "w0 ~ U[5,40], "
+                       "Gaussian plane wave, 32 points, t in [0, tau0 + 10] step 0.05, stop 1e-8 "
+                       "decided on the device (at most 100 steps), FP64; seed %d" % seed,
+           "caps": "n <= 128 per obstacle and J <= 256 drawn before the raises (the workload "
+                   "allows 1024 and 1024)",
+           "workers": workers, "burst_requests": burst,
+           "saturated_requests_per_s": round(sat, 2),
+           "saturated_solves_per_s": round(sum(solves(q, r[1]) for q, r in
+                                               zip(reqs[sl], res) if r is not None) / dt, 1),
+           "poisson": []}
     rng = np.random.default_rng(seed + 1)
-    for frac, sl in ((0.5, slice(count, 2 * count)), (0.8, slice(2 * count, 3 * count))):
+    off = burst
+    for frac in (0.5, 0.8):
         lam = frac * sat
         gaps = rng.exponential(1.0 / lam, count)
+        batch = reqs[off:off + count]
+        off += count
         start = time.perf_counter()
         due = start + np.cumsum(gaps)
         tickets = []
-        for q, tdue in zip(reqs[sl], due):
+        for q, tdue in zip(batch, due):
             now = time.perf_counter()
             if tdue > now:
                 time.sleep(tdue - now)
             tickets.append(srv.submit(q))
-        lat = np.array([srv.wait(t)[2] for t in tickets])
+        out = [_wait_ok(srv, fth, t) for t in tickets]
+        wall = time.perf_counter() - start
+        failed += sum(o is None for o in out)
+        batch = [q for q, o in zip(batch, out) if o is not None]
+        out = [o for o in out if o is not None]
+        lat = np.array([o[2] for o in out])
+        steps = [o[1] for o in out]
+        all_steps += steps
         rec["poisson"].append({"rate_fraction": frac, "lambda_per_s": round(lam, 3),
                                "requests": count,
                                "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
-                               "p99_latency_s": round(float(np.percentile(lat, 99)), 4)})
+                               "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+                               "max_latency_s": round(float(lat.max()), 4),
+                               "solves_per_s": round(sum(solves(q, o[1]) for q, o in
+                                                         zip(batch, out)) / wall, 1)})
+    st = np.array(all_steps)
+    rec["failed_requests"] = failed
+    rec["ms_steps"] = {"mean": round(float(st.mean()), 2), "p50": int(np.percentile(st, 50)),
+                       "max": int(st.max()), "ended_by_stop_rule": int(np.sum(st < 100)),
+                       "ended_by_cap": int(np.sum(st >= 100)), "requests": int(st.size)}
     srv.close()
     return rec
 

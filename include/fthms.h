@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define FTHMS_ABI_VERSION 1
+#define FTHMS_ABI_VERSION 2
 
 enum {
   FTHMS_OK = 0,
@@ -498,12 +498,18 @@ int fthms_batch_buckets(const fthms_batch *batch, int *ngroups, int *n,
 
 /* A request: one multiple-scattering problem answered with its time traces
  * (the arguments of fthms_problem_create + fthms_problem_traces in one
- * self-contained record; everything is copied at submission).  narcs arcs of
- * n nodes each: xy, dxy [narcs][n][2] samples of x(t), x'(t) at
- * fthms_cheb_nodes(n); interval [narcs][2] and group [narcs] (NULL: one
- * curve) as in fthms_problem_desc; k, w [nk] frequencies and quadrature
- * weights; obs_xy [nobs][2]; t [nt]; at most max_steps steps with the
- * time-domain stop tolerance stop_tol.  Solves run in FP64. */
+ * self-contained record; everything is copied at submission).  narcs
+ * patches of n nodes each.  closed == 0: open arcs, xy, dxy [narcs][n][2]
+ * samples of x(t), x'(t) at fthms_cheb_nodes(n), interval [narcs][2] and
+ * group [narcs] (NULL: one curve) as in fthms_problem_desc.  closed == 1:
+ * every patch is a closed obstacle solved as one combined-field patch
+ * (Section 3.3, the paper's treatment of closed curves), xy, dxy, ddxy
+ * [narcs][n][2] samples of x, x', x'' at tau_j = 2 pi j / n (n even) as in
+ * fthms_closed_create; interval and group are ignored.  k, w [nk]
+ * frequencies and quadrature weights; obs_xy [nobs][2]; t [nt]; at most
+ * max_steps steps with the time-domain stop tolerance stop_tol (decided on
+ * the device); precision FTHMS_FP64 or FTHMS_FP32_REFINED (refined to
+ * 1e-12). */
 typedef struct {
   int narcs;
   int n;
@@ -522,6 +528,9 @@ typedef struct {
   const double *t;
   int max_steps;
   double stop_tol;
+  int closed;
+  const double *ddxy;
+  int precision;
 } fthms_request;
 
 enum {

@@ -62,7 +62,8 @@ class Request(C.Structure):
                 ("k", C.POINTER(C.c_double)), ("w", C.POINTER(C.c_double)),
                 ("incident", Incident), ("nobs", C.c_int), ("obs_xy", C.POINTER(C.c_double)),
                 ("nt", C.c_int), ("t", C.POINTER(C.c_double)), ("max_steps", C.c_int),
-                ("stop_tol", C.c_double)]
+                ("stop_tol", C.c_double), ("closed", C.c_int),
+                ("ddxy", C.POINTER(C.c_double)), ("precision", C.c_int)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -581,10 +582,16 @@ class Server:
         raise FthmsError(rc, "%s: %s" % (what, _lib.fthms_server_error(self.h).decode()))
 
     def submit(self, req):
+        closed = bool(req.get("closed", False))
+        nob = len(req["xy"])
         keep = dict(xy=np.ascontiguousarray(req["xy"], dtype=np.float64),
                     dxy=np.ascontiguousarray(req["dxy"], dtype=np.float64),
-                    iv=np.ascontiguousarray(req["interval"], dtype=np.float64),
-                    grp=np.ascontiguousarray(req["group"], dtype=np.int32),
+                    ddxy=(np.ascontiguousarray(req["ddxy"], dtype=np.float64) if closed
+                          else None),
+                    iv=np.ascontiguousarray(req["interval"] if not closed
+                                            else np.zeros((nob, 2)), dtype=np.float64),
+                    grp=np.ascontiguousarray(req["group"] if not closed
+                                             else np.arange(nob), dtype=np.int32),
                     k=np.ascontiguousarray(req["k"], dtype=np.float64),
                     w=np.ascontiguousarray(req["w"], dtype=np.float64),
                     obs=np.ascontiguousarray(req["obs"], dtype=np.float64),
@@ -600,6 +607,10 @@ class Server:
         r.nt, r.t = keep["t"].size, _dp(keep["t"])
         r.max_steps = int(req.get("max_steps", 100))
         r.stop_tol = float(req.get("stop_tol", 1e-8))
+        r.closed = 1 if closed else 0
+        if closed:
+            r.ddxy = _dp(keep["ddxy"])
+        r.precision = int(req.get("precision", FP64))
         ticket = C.c_uint64()
         rc = _lib.fthms_submit(self.h, C.byref(r), C.byref(ticket))
         if rc:
@@ -658,11 +669,20 @@ def request_from_workload(req):
     ends)."""
     arcs = req["arcs"]
     n = arcs[0].n
-    t = cheb_nodes(n)
     om = np.asarray(req["omegas"], dtype=np.float64)
     w = np.full(om.size, om[1] - om[0] if om.size > 1 else 1.0)
     w[0] *= 0.5
     w[-1] *= 0.5
+    if req.get("closed", False):
+        # every obstacle one closed patch: samples at tau_j = 2 pi j / n
+        tau = 2.0 * np.pi * np.arange(n) / n
+        return dict(closed=True, xy=np.stack([a.curve.x(tau) for a in arcs]),
+                    dxy=np.stack([a.curve.dx(tau) for a in arcs]),
+                    ddxy=np.stack([a.curve.ddx(tau) for a in arcs]), k=om, w=w,
+                    incident=req["incident"], obs=req["obs"], t=req["times"],
+                    max_steps=req["max_steps"], stop_tol=req["stop_tol"],
+                    precision=req.get("precision", FP64))
+    t = cheb_nodes(n)
     return dict(xy=np.stack([a.curve.x(t) for a in arcs]),
                 dxy=np.stack([a.curve.dx(t) for a in arcs]),
                 interval=np.array([a.curve.interval for a in arcs]),

@@ -146,4 +146,68 @@ __global__ __launch_bounds__(256) void closed_field_kernel(
   }
 }
 
+// Stored cross operators of closed patches (multiple scattering between
+// obstacles, each one combined-field patch): for every wavenumber b the
+// matrix T[b] (S x S, row-major, S = total node count) with
+//   T[b][i][l] = h_l kernel(y_i, y_l),  kernel as in closed_field_kernel,
+// for nodes i and l on different patches, and 0 within a patch, so that
+// the field of every other patch at the nodes of patch j is
+// sum_l T[b][i][l] psi_l -- the trapezoid rule of closed_field_kernel with
+// each target's terms stored once and applied at every step.
+// pid[S]: patch of each node; hs[S]: its trapezoid weight 2 pi / N.
+__global__ __launch_bounds__(256) void closed_cross_build_kernel(
+    const double2 *__restrict__ y, const double2 *__restrict__ dy,
+    const int *__restrict__ pid, const double *__restrict__ hs, int S,
+    const double *__restrict__ kvec, double2 *__restrict__ T) {
+  const int b = blockIdx.y;
+  const long long e = blockIdx.x * 256LL + threadIdx.x;
+  if (e >= (long long)S * S) return;
+  const int i = (int)(e / S), l = (int)(e % S);
+  double2 v = make_double2(0.0, 0.0);
+  if (pid[i] != pid[l]) {
+    const double k = kvec[b], eta = k;
+    const double2 z = y[i], yl = y[l], d = dy[l];
+    const double ex = z.x - yl.x, ey = z.y - yl.y;
+    const double r = sqrt(ex * ex + ey * ey);
+    const double q = d.y * ex - d.x * ey;
+    const double sp = sqrt(d.x * d.x + d.y * d.y);
+    double j0, y0, j1, y1;
+    bessel_01(k * r, j0, y0, j1, y1);
+    const double a = 0.25 * k * q / r, c = 0.25 * eta * sp;
+    const double h = hs[l];
+    v = make_double2(h * (-a * y1 + c * j0), h * (a * j1 + c * y0));
+  }
+  T[(long long)b * S * S + e] = v;
+}
+
+// out[b][i] = sum_l T[b][i][l] x[b][l] (complex, FP64): one block per 16
+// rows of one wavenumber, 16 threads per row striding over the columns
+// (coalesced), partial sums reduced with lane shuffles; x in LDS.
+constexpr int kCrossMaxS = 4096;  // nodes of all patches (x in LDS: 64 KB)
+__global__ __launch_bounds__(256) void cross_apply_kernel(const double2 *__restrict__ T, int S,
+                                                         const double2 *__restrict__ x,
+                                                         double2 *__restrict__ out) {
+  __shared__ double2 sx[kCrossMaxS];
+  const int b = blockIdx.y;
+  const double2 *xb = x + (long long)b * S;
+  for (int l = threadIdx.x; l < S; l += 256) sx[l] = xb[l];
+  __syncthreads();
+  const int row = blockIdx.x * 16 + (threadIdx.x >> 4), c0 = threadIdx.x & 15;
+  double ar = 0.0, ai = 0.0;
+  if (row < S) {
+    const double2 *Tr = T + ((long long)b * S + row) * S;
+    for (int l = c0; l < S; l += 16) {
+      const double2 t = Tr[l], v = sx[l];
+      ar += t.x * v.x - t.y * v.y;
+      ai += t.x * v.y + t.y * v.x;
+    }
+  }
+#pragma unroll
+  for (int off = 8; off >= 1; off >>= 1) {
+    ar += __shfl_xor(ar, off, 16);
+    ai += __shfl_xor(ai, off, 16);
+  }
+  if (row < S && c0 == 0) out[(long long)b * S + row] = make_double2(ar, ai);
+}
+
 }  // namespace fthms

@@ -33,8 +33,14 @@ struct fthms_ctx {
   // forked from and joined back into `stream` inside each call
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_lead = nullptr, ev_join = nullptr;
+  // per-step events and a small pinned host buffer (device-decided stop rule)
+  hipEvent_t ev_step[2] = {nullptr, nullptr};
+  int *pinned = nullptr;
   size_t budget = 0;
   size_t held = 0;
+  // serving workers allocate stream-ordered (hipMallocAsync / hipFreeAsync),
+  // so that one request's frees do not wait for the other workers' kernels
+  bool async_alloc = false;
   std::string err;
   // solve workspace and a second scratch area (both grown on demand)
   void *ws = nullptr;
@@ -116,14 +122,22 @@ static int dev_alloc(fthms_ctx *ctx, void **p, size_t bytes) {
     return fail(ctx, FTHMS_ENOMEM,
                 "device memory budget exceeded (" + std::to_string(ctx->held + bytes) +
                     " > " + std::to_string(ctx->budget) + " bytes)");
-  HIPCK(ctx, hipMalloc(p, bytes ? bytes : 1));
+  if (ctx->async_alloc) {
+    // stream-ordered: no device-wide synchronisation; the memory is ready
+    // once this context's stream has reached the allocation
+    HIPCK(ctx, hipMallocAsync(p, bytes ? bytes : 1, ctx->stream));
+    HIPCK(ctx, hipStreamSynchronize(ctx->stream));
+  } else {
+    HIPCK(ctx, hipMalloc(p, bytes ? bytes : 1));
+  }
   ctx->held += bytes;
   return FTHMS_OK;
 }
 
 static void dev_free(fthms_ctx *ctx, void *p, size_t bytes) {
   if (p) {
-    (void)hipFree(p);
+    if (ctx->async_alloc) (void)hipFreeAsync(p, ctx->stream);
+    else (void)hipFree(p);
     ctx->held -= std::min(ctx->held, bytes);
   }
 }
@@ -137,6 +151,13 @@ static int ensure_ws(fthms_ctx *ctx, size_t bytes) {
   int rc = dev_alloc(ctx, &ctx->ws, bytes);
   if (rc) return rc;
   ctx->ws_bytes = bytes;
+  return FTHMS_OK;
+}
+
+// The context's pinned host buffer (16 ints, allocated on first use).
+static int ctx_pinned(fthms_ctx *ctx, int **out) {
+  if (!ctx->pinned) HIPCK(ctx, hipHostMalloc((void **)&ctx->pinned, 16 * sizeof(int)));
+  *out = ctx->pinned;
   return FTHMS_OK;
 }
 
@@ -280,7 +301,9 @@ int fthms_create(fthms_ctx **out, int device, size_t hbm_budget_bytes, void *hip
   if (hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ev_lead, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_step[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_step[1], hipEventDisableTiming) != hipSuccess) {
     fthms_destroy(ctx);
     return fail(nullptr, FTHMS_EDEVICE, "hipStreamCreate/hipEventCreate failed");
   }
@@ -303,6 +326,9 @@ int fthms_destroy(fthms_ctx *ctx) {
   if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
   if (ctx->ev_lead) (void)hipEventDestroy(ctx->ev_lead);
   if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+  for (auto &e : ctx->ev_step)
+    if (e) (void)hipEventDestroy(e);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return FTHMS_OK;

@@ -43,6 +43,33 @@ __global__ void axpy_kernel(double2 *y, const double2 *x, long long nn) {
     y[e] = make_double2(y[e].x + x[e].x, y[e].y + x[e].y);
 }
 
+// dst[b][i] = src[b][off + i], b < nb, i < n (the inverse of place_kernel)
+__global__ void take_kernel(const double2 *src, long long sstride, long long off, int n, int nb,
+                            double2 *dst) {
+  const long long nn = (long long)n * nb;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nn;
+       e += (long long)gridDim.x * blockDim.x)
+    dst[e] = src[(e / n) * sstride + off + e % n];
+}
+
+// y += x unless the run has stopped (gate[0] != 0: the step at which the
+// time-domain stop rule held)
+__global__ void axpy_gated_kernel(double2 *y, const double2 *x, long long nn, const int *gate) {
+  if (gate[0] != 0) return;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nn;
+       e += (long long)gridDim.x * blockDim.x)
+    y[e] = make_double2(y[e].x + x[e].x, y[e].y + x[e].y);
+}
+
+// The stop rule on the device: after step `step`, gate[0] = step if the
+// step's change |du| (nrm[0] = |du|^2) is at most tol |u| (nrm[1] = |u|^2)
+// and no earlier step stopped the run.
+__global__ void stop_check_kernel(const double *nrm, double tol, int step, int *gate) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && gate[0] == 0 &&
+      sqrt(nrm[0]) <= tol * sqrt(nrm[1]))
+    gate[0] = step;
+}
+
 // dst[b][off + i] = src[b][i], b < nb, i < n
 __global__ void place_kernel(const double2 *src, int n, int nb, double2 *dst, long long dstride,
                              long long off) {
@@ -411,6 +438,15 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
     const size_t avail = ctx->budget > ctx->held ? ctx->budget - ctx->held + ctx->ws_bytes : 0;
     cap = std::min(cap, avail);
   }
+  // Problems made only of closed patches (obstacles of an exterior problem,
+  // each one patch) store every pair's cross operator once per wavenumber
+  // (S x S, S = all nodes) when all wavenumbers fit with it, and apply it at
+  // every step instead of evaluating the fields again.
+  bool use_ops = J > 1 && nsum <= kCrossMaxS;
+  for (int j = 0; j < J; ++j) use_ops = use_ops && pb->arcs[j]->closed;
+  const size_t op_per = (size_t)nsum * nsum * sizeof(double2) + 2 * (size_t)nsum * sizeof(double2);
+  if (use_ops && (size_t)nk * (per + op_per) + (size_t)(4 * nsum + 64) * 16 > cap) use_ops = false;
+  if (use_ops) per += op_per;
   int C = (int)std::min<size_t>((size_t)nk, cap / per);
   C = std::min(C, 4096);
   if (C < 1) return fail(ctx, FTHMS_ENOMEM, "no room for one wavenumber");
@@ -428,8 +464,11 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
     double2 *b, *al, *cr, *tot;
   };
   std::vector<ArcWs> w(J);
+  std::vector<size_t> ops_off;
+  double2 *Tops = nullptr, *xcat = nullptr, *ycat = nullptr;
   double2 *Ustep = nullptr, *du = nullptr;
   double *nrm = nullptr;
+  int *gate = nullptr;
   {
     size_t off = 0;
     std::vector<size_t> o((size_t)J * 10);
@@ -448,10 +487,20 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
       for (int v = 0; v < 4; ++v) o[10 * j + 5 + v] = take(n * sizeof(double2) * C);
       o[10 * j + 9] = take(kLuScratchBytes * C);
     }
+    // stored cross operators: T [C][S][S], gathered densities and fields
+    // [C][S], node tables [S]
+    const size_t oT = use_ops ? take(sizeof(double2) * (size_t)C * nsum * nsum) : 0;
+    const size_t oX = use_ops ? take(sizeof(double2) * (size_t)C * nsum) : 0;
+    const size_t oY = use_ops ? take(sizeof(double2) * (size_t)C * nsum) : 0;
+    const size_t oNy = use_ops ? take(sizeof(double2) * (size_t)nsum) : 0;
+    const size_t oNd = use_ops ? take(sizeof(double2) * (size_t)nsum) : 0;
+    const size_t oNp = use_ops ? take(sizeof(int) * (size_t)nsum) : 0;
+    const size_t oNh = use_ops ? take(sizeof(double) * (size_t)nsum) : 0;
+    ops_off = {oT, oX, oY, oNy, oNd, oNp, oNh};
     if (tr) {
       o.push_back(take(sizeof(double2) * (size_t)C * std::max(1, pb->nobs)));   // U of a step
       o.push_back(take(sizeof(double2) * (size_t)tr->nt * std::max(1, pb->nobs)));  // its trace
-      o.push_back(take(sizeof(double2)));                                            // two norms
+      o.push_back(take(sizeof(double2) + 2 * sizeof(int)));  // two norms, then the gate
     }
     if ((rc = ensure_ws(ctx, off))) return rc;
     char *base = (char *)ctx->ws;
@@ -467,15 +516,57 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
       w[j].tot = (double2 *)(base + o[10 * j + 8]);
       w[j].swp = (void *)(base + o[10 * j + 9]);
     }
+    if (use_ops) {
+      Tops = (double2 *)(base + ops_off[0]);
+      xcat = (double2 *)(base + ops_off[1]);
+      ycat = (double2 *)(base + ops_off[2]);
+      // node tables of all patches, concatenated in arc order
+      std::vector<double2> hy(nsum), hd(nsum);
+      std::vector<int> hp(nsum);
+      std::vector<double> hh(nsum);
+      int q = 0;
+      for (int j = 0; j < J; ++j) {
+        const fthms_arc *a = pb->arcs[j];
+        for (int i = 0; i < a->n; ++i, ++q) {
+          hy[q] = make_double2(a->xy[2 * i], a->xy[2 * i + 1]);
+          hd[q] = make_double2(a->dxy[2 * i], a->dxy[2 * i + 1]);
+          hp[q] = j;
+          hh[q] = 2.0 * kPi / a->n;
+        }
+      }
+      HIPCK(ctx, hipMemcpy(base + ops_off[3], hy.data(), sizeof(double2) * nsum,
+                           hipMemcpyHostToDevice));
+      HIPCK(ctx, hipMemcpy(base + ops_off[4], hd.data(), sizeof(double2) * nsum,
+                           hipMemcpyHostToDevice));
+      HIPCK(ctx, hipMemcpy(base + ops_off[5], hp.data(), sizeof(int) * nsum,
+                           hipMemcpyHostToDevice));
+      HIPCK(ctx, hipMemcpy(base + ops_off[6], hh.data(), sizeof(double) * nsum,
+                           hipMemcpyHostToDevice));
+      // every target must be a few node spacings from the other patches (the
+      // trapezoid rule of the stored operators, as for the field kernel)
+      for (int j = 0; j < J; ++j)
+        for (int k = 0; k < J; ++k) {
+          if (k == j) continue;
+          const fthms_arc *ak = pb->arcs[k], *aj = pb->arcs[j];
+          for (int i = 0; i < aj->n; ++i)
+            for (int l = 0; l < ak->n; ++l)
+              if (!(std::hypot(aj->xy[2 * i] - ak->xy[2 * l],
+                               aj->xy[2 * i + 1] - ak->xy[2 * l + 1]) >= 5.0 * ak->hmax))
+                return fail(ctx, FTHMS_EINVAL_DATA,
+                            "target closer than 5 node spacings to a closed patch "
+                            "(trapezoid rule only)");
+        }
+    }
     if (tr) {
       Ustep = (double2 *)(base + o[(size_t)10 * J]);
       du = (double2 *)(base + o[(size_t)10 * J + 1]);
       nrm = (double *)(base + o[(size_t)10 * J + 2]);
+      gate = (int *)(nrm + 2);
     }
   }
   // later: a solve after the first with the same factors (the FP32 factors
   // of every arc are kept for all M steps; a matrix whose refinement fails
-  // is refactored in FP64 once and solved with those factors afterwards).
+  // is refactored in FP64 once and solved with those factors afterwards)
   // FTHMS_REFINE_LATE_MAXIT=<n> in the environment caps the refinement
   // steps of later solves (a test hook: 0 makes every later refinement fail,
   // which exercises the late FP64 redo)
@@ -504,10 +595,12 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
     tend(ctx);
     return r;
   };
-  // fold the densities of the step just solved into the traces; returns 1
-  // once the step's change is below the stop tolerance
-  auto trace_step = [&](int c, const double *kc, bool first, int &stop) -> int {
-    stop = 0;
+  // fold the densities of step `step` into the traces.  With a stop
+  // tolerance the rule is decided on the device: every accumulation of a
+  // step after the one that met it is skipped (gate), so the host may run
+  // ahead of the decision and reads it one step late.
+  const bool gated = tr && tr->stop_tol > 0.0;
+  auto trace_step = [&](int c, const double *kc, int step) -> int {
     const int P = pb->nobs;
     if (P == 0 || tr->nt == 0) return FTHMS_OK;
     zero_kernel<<<grid1d((long long)c * P), 256, 0, ctx->stream>>>(Ustep, (long long)c * P);
@@ -520,22 +613,38 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
     }
     if ((r = launch_freq_to_time(ctx, c, kc, tr->w, P, Ustep, tr->nt, tr->t, du))) return r;
     const long long nn = (long long)tr->nt * P;
-    if (first)
+    if (step == 1)
       HIPCK(ctx, hipMemcpyAsync(tr->traces, du, sizeof(double2) * nn, hipMemcpyDeviceToDevice,
                                 ctx->stream));
+    else if (gated)
+      axpy_gated_kernel<<<grid1d(nn), 256, 0, ctx->stream>>>(tr->traces, du, nn, gate);
     else
       axpy_kernel<<<grid1d(nn), 256, 0, ctx->stream>>>(tr->traces, du, nn);
-    if (tr->stop_tol <= 0.0) return FTHMS_OK;
+    if (!gated) return check_launch(ctx, "axpy_kernel");
     zero_kernel<<<1, 256, 0, ctx->stream>>>((double2 *)nrm, 1);
     const int nb = (int)std::min<long long>(1024, (nn + 255) / 256);
     norm2_kernel<<<nb, 256, 0, ctx->stream>>>(du, nn, nrm);
     norm2_kernel<<<nb, 256, 0, ctx->stream>>>(tr->traces, nn, nrm + 1);
-    if ((r = check_launch(ctx, "norm2_kernel"))) return r;
-    double h[2];
-    HIPCK(ctx, hipMemcpyAsync(h, nrm, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCK(ctx, hipStreamSynchronize(ctx->stream));
-    stop = std::sqrt(h[0]) <= tr->stop_tol * std::sqrt(h[1]) ? 1 : 0;
+    stop_check_kernel<<<1, 64, 0, ctx->stream>>>(nrm, tr->stop_tol, step, gate);
+    return check_launch(ctx, "stop_check_kernel");
+  };
+  // the host's view of the gate: copied to pinned memory after each step,
+  // read one step later (so the device never waits for the host)
+  int *hgate = nullptr;
+  if (gated) {
+    if ((rc = ctx_pinned(ctx, &hgate))) return rc;
+    hgate[0] = hgate[1] = 0;
+    HIPCK(ctx, hipMemsetAsync(gate, 0, 2 * sizeof(int), ctx->stream));
+  }
+  auto publish_gate = [&](int slot) -> int {
+    HIPCK(ctx, hipMemcpyAsync(hgate + slot, gate, sizeof(int), hipMemcpyDeviceToHost,
+                              ctx->stream));
+    HIPCK(ctx, hipEventRecord(ctx->ev_step[slot], ctx->stream));
     return FTHMS_OK;
+  };
+  auto read_gate = [&](int slot) -> int {
+    HIPCK(ctx, hipEventSynchronize(ctx->ev_step[slot]));
+    return hgate[slot];
   };
   long long aoff = 0;
   for (int f0 = 0; f0 < nk; f0 += C) {
@@ -563,22 +672,56 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
       HIPCK(ctx, hipMemcpyAsync(w[j].tot, w[j].al, sizeof(double2) * n * c,
                                 hipMemcpyDeviceToDevice, ctx->stream));
     }
-    int steps = 1, stop = 0;
-    if (tr && (rc = trace_step(c, kc, true, stop))) return rc;
-    for (int m = 1; m < pb->M && !stop; ++m) {
-      for (int j = 0; j < J; ++j) {
-        const long long nn = (long long)pb->arcs[j]->n * c;
-        zero_kernel<<<grid1d(nn), 256, 0, ctx->stream>>>(w[j].cr, nn);
-      }
+    if (use_ops && pb->M > 1) {
       tbeg(ctx, "field_cross");
-      for (int j = 0; j < J; ++j)
-        for (int k = 0; k < J; ++k) {
-          if (k == j) continue;
-          const fthms_arc *ak = pb->arcs[k], *aj = pb->arcs[j];
-          if ((rc = field_dev_impl(ctx, ak, c, kc, w[k].al, ak->n, aj->n, aj->d_y,
-                                   pb->pair_plan[(size_t)k * J + j], w[j].cr, aj->n, 1)))
-            return rc;
+      const long long ss = (long long)nsum * nsum;
+      dim3 gb((unsigned)((ss + 255) / 256), c);
+      closed_cross_build_kernel<<<gb, 256, 0, ctx->stream>>>(
+          (const double2 *)((char *)ctx->ws + ops_off[3]),
+          (const double2 *)((char *)ctx->ws + ops_off[4]), (const int *)((char *)ctx->ws + ops_off[5]),
+          (const double *)((char *)ctx->ws + ops_off[6]), nsum, kc, Tops);
+      tend(ctx);
+      if ((rc = check_launch(ctx, "closed_cross_build_kernel"))) return rc;
+    }
+    int steps = 1, stop = 0;
+    if (tr && (rc = trace_step(c, kc, 1))) return rc;
+    if (gated && (rc = publish_gate(0))) return rc;
+    for (int m = 1; m < pb->M && !stop; ++m) {
+      tbeg(ctx, "field_cross");
+      if (use_ops) {
+        // the stored operators: gather every patch's densities, one product
+        // per wavenumber, scatter the fields to the patches
+        long long off = 0;
+        for (int j = 0; j < J; ++j) {
+          const int n = pb->arcs[j]->n;
+          place_kernel<<<grid1d((long long)n * c), 256, 0, ctx->stream>>>(w[j].al, n, c, xcat,
+                                                                          nsum, off);
+          off += n;
         }
+        dim3 ga((nsum + 15) / 16, c);
+        cross_apply_kernel<<<ga, 256, 0, ctx->stream>>>(Tops, nsum, xcat, ycat);
+        off = 0;
+        for (int j = 0; j < J; ++j) {
+          const int n = pb->arcs[j]->n;
+          take_kernel<<<grid1d((long long)n * c), 256, 0, ctx->stream>>>(ycat, nsum, off, n, c,
+                                                                         w[j].cr);
+          off += n;
+        }
+        if ((rc = check_launch(ctx, "cross_apply_kernel"))) return rc;
+      } else {
+        for (int j = 0; j < J; ++j) {
+          const long long nn = (long long)pb->arcs[j]->n * c;
+          zero_kernel<<<grid1d(nn), 256, 0, ctx->stream>>>(w[j].cr, nn);
+        }
+        for (int j = 0; j < J; ++j)
+          for (int k = 0; k < J; ++k) {
+            if (k == j) continue;
+            const fthms_arc *ak = pb->arcs[k], *aj = pb->arcs[j];
+            if ((rc = field_dev_impl(ctx, ak, c, kc, w[k].al, ak->n, aj->n, aj->d_y,
+                                     pb->pair_plan[(size_t)k * J + j], w[j].cr, aj->n, 1)))
+              return rc;
+          }
+      }
       tend(ctx);
       for (int j = 0; j < J; ++j) {
         const int n = pb->arcs[j]->n;
@@ -586,11 +729,25 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
         chi_scale_kernel<<<grid1d(nn), 256, 0, ctx->stream>>>(w[j].cr, pb->d_chi[j], n, nn, w[j].b);
         if ((rc = check_launch(ctx, "chi_scale_kernel"))) return rc;
         if ((rc = solve_arc(j, c, true))) return rc;
-        axpy_kernel<<<grid1d(nn), 256, 0, ctx->stream>>>(w[j].tot, w[j].al, nn);
+        if (gated)
+          axpy_gated_kernel<<<grid1d(nn), 256, 0, ctx->stream>>>(w[j].tot, w[j].al, nn, gate);
+        else
+          axpy_kernel<<<grid1d(nn), 256, 0, ctx->stream>>>(w[j].tot, w[j].al, nn);
         if ((rc = check_launch(ctx, "axpy_kernel"))) return rc;
       }
       steps = m + 1;
-      if (tr && (rc = trace_step(c, kc, false, stop))) return rc;
+      if (tr && (rc = trace_step(c, kc, m + 1))) return rc;
+      if (gated) {
+        // step m + 1 is enqueued; the decision after step m is read now
+        if ((rc = publish_gate(m & 1))) return rc;
+        stop = read_gate((m - 1) & 1) != 0;
+      }
+    }
+    if (gated) {
+      HIPCK(ctx, hipStreamSynchronize(ctx->stream));
+      int g = 0;
+      HIPCK(ctx, hipMemcpy(&g, gate, sizeof(int), hipMemcpyDeviceToHost));
+      if (g) steps = g;
     }
     if (tr && tr->steps) *tr->steps = steps;
     if (pb->nobs > 0 && U) {

@@ -24,8 +24,9 @@ struct fthms_server {
   struct Job {
     // copy of the request
     int narcs = 0, n = 0, nk = 0, nobs = 0, nt = 0, max_steps = 1;
+    int closed = 0, precision = FTHMS_FP64;
     double period = 0.0, stop_tol = 0.0;
-    std::vector<double> xy, dxy, interval, k, w, obs, t;
+    std::vector<double> xy, dxy, ddxy, interval, k, w, obs, t;
     std::vector<int> group;
     fthms_incident inc{};
     // bookkeeping
@@ -60,9 +61,17 @@ namespace {
 // vectors and scratch, plus traces.
 size_t request_bytes(const fthms_request *r) {
   const size_t n = (size_t)r->n;
-  const size_t per = n * n * sizeof(double2) + n * sizeof(int) + kLuScratchBytes +
-                     4 * n * sizeof(double2) + sizeof(int) + sizeof(double) + 2048;
-  return per * (size_t)r->narcs * (size_t)r->nk +
+  const size_t per = n * n * sizeof(double2) +
+                     (r->precision == FTHMS_FP32_REFINED ? n * n * sizeof(float2) : 0) +
+                     n * sizeof(int) + kLuScratchBytes + 4 * n * sizeof(double2) + sizeof(int) +
+                     sizeof(double) + 2048;
+  // closed obstacles: the stored cross operators of all patches ([S][S] per
+  // frequency, S = narcs n) when they fit beside the rest
+  const size_t S = n * (size_t)r->narcs;
+  const size_t ops = (r->closed && r->narcs > 1 && S <= (size_t)kCrossMaxS)
+                         ? (S * S + 2 * S) * sizeof(double2) * (size_t)r->nk
+                         : 0;
+  return per * (size_t)r->narcs * (size_t)r->nk + ops +
          2 * sizeof(double2) * (size_t)std::max(1, r->nt) * std::max(1, r->nobs) +
          sizeof(double2) * (size_t)r->nk * std::max(1, r->nobs) + ((size_t)64 << 20);
 }
@@ -73,8 +82,11 @@ int serve_run(fthms_ctx *ctx, fthms_server::Job &jb) {
   std::vector<fthms_arc *> arcs(J, nullptr);
   int rc = FTHMS_OK;
   for (int j = 0; j < J && rc == FTHMS_OK; ++j)
-    rc = fthms_arc_create(ctx, n, jb.xy.data() + (size_t)2 * n * j,
-                          jb.dxy.data() + (size_t)2 * n * j, &arcs[j]);
+    rc = jb.closed ? fthms_closed_create(ctx, n, jb.xy.data() + (size_t)2 * n * j,
+                                         jb.dxy.data() + (size_t)2 * n * j,
+                                         jb.ddxy.data() + (size_t)2 * n * j, &arcs[j])
+                   : fthms_arc_create(ctx, n, jb.xy.data() + (size_t)2 * n * j,
+                                      jb.dxy.data() + (size_t)2 * n * j, &arcs[j]);
   fthms_problem *pb = nullptr;
   if (rc == FTHMS_OK) {
     fthms_problem_desc d{};
@@ -85,8 +97,8 @@ int serve_run(fthms_ctx *ctx, fthms_server::Job &jb) {
     d.c0 = 1.0 / 3.0;
     d.c1 = 2.0 / 3.0;
     d.M = jb.max_steps;
-    d.precision = FTHMS_FP64;
-    d.tol = 0.0;
+    d.precision = jb.precision;
+    d.tol = 1e-12;
     d.incident = jb.inc;
     d.nobs = jb.nobs;
     d.obs_xy = jb.obs.data();
@@ -120,6 +132,7 @@ void serve_worker(fthms_server *sv) {
   fthms_ctx *ctx = nullptr;
   // a private stream per worker, so that requests run side by side
   const int rc0 = fthms_create(&ctx, sv->device, 0, FTHMS_OWN_STREAM);
+  if (ctx) ctx->async_alloc = true;
   for (;;) {
     uint64_t id = 0;
     {
@@ -178,6 +191,14 @@ int fthms_server_create(int device, size_t hbm_budget, int workers, fthms_server
   if (!sv) return fail(nullptr, FTHMS_ENOMEM, "host allocation failed");
   sv->device = device;
   sv->budget = hbm_budget ? hbm_budget : freeb / 10 * 9;
+  // the workers allocate from the device's stream-ordered pool: keep freed
+  // blocks in the pool for the next request instead of returning them at
+  // every synchronisation
+  hipMemPool_t pool = nullptr;
+  if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess && pool) {
+    uint64_t thr = (uint64_t)sv->budget;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
   sv->nworkers = workers;
   for (int i = 0; i < workers; ++i) sv->workers.emplace_back(serve_worker, sv);
   *out = sv;
@@ -214,9 +235,11 @@ int fthms_submit(fthms_server *sv, const fthms_request *r, uint64_t *ticket) {
     sv->err = m;
     return code;
   };
-  if (r->narcs < 1 || r->n < 2 || r->n > kMaxN || !r->xy || !r->dxy || !r->interval ||
-      !(r->period > 0.0) || r->nk < 1 || !r->k || !r->w || r->nobs < 1 || !r->obs_xy ||
-      r->nt < 1 || !r->t || r->max_steps < 1)
+  if (r->narcs < 1 || r->n < 2 || r->n > kMaxN || !r->xy || !r->dxy ||
+      (!r->closed && (!r->interval || !(r->period > 0.0))) ||
+      (r->closed && (!r->ddxy || (r->n & 1))) || (r->closed != 0 && r->closed != 1) ||
+      (r->precision != FTHMS_FP64 && r->precision != FTHMS_FP32_REFINED) || r->nk < 1 ||
+      !r->k || !r->w || r->nobs < 1 || !r->obs_xy || r->nt < 1 || !r->t || r->max_steps < 1)
     return bad(FTHMS_EINVAL, "incomplete request");
   fthms_server::Job jb;
   jb.narcs = r->narcs;
@@ -225,20 +248,36 @@ int fthms_submit(fthms_server *sv, const fthms_request *r, uint64_t *ticket) {
   jb.nobs = r->nobs;
   jb.nt = r->nt;
   jb.max_steps = r->max_steps;
-  jb.period = r->period;
   jb.stop_tol = r->stop_tol;
+  jb.closed = r->closed;
+  jb.precision = r->precision;
   const size_t pts = (size_t)2 * r->n * r->narcs;
   jb.xy.assign(r->xy, r->xy + pts);
   jb.dxy.assign(r->dxy, r->dxy + pts);
-  jb.interval.assign(r->interval, r->interval + 2 * (size_t)r->narcs);
-  jb.group.assign(r->narcs, 0);
-  if (r->group) jb.group.assign(r->group, r->group + r->narcs);
+  if (r->closed) {
+    // every obstacle alone in its group; intervals are not used
+    jb.ddxy.assign(r->ddxy, r->ddxy + pts);
+    jb.period = 2.0 * kPi;
+    jb.interval.resize(2 * (size_t)r->narcs);
+    jb.group.resize(r->narcs);
+    for (int j = 0; j < r->narcs; ++j) {
+      jb.interval[2 * j] = 0.0;
+      jb.interval[2 * j + 1] = 2.0 * kPi;
+      jb.group[j] = j;
+    }
+  } else {
+    jb.period = r->period;
+    jb.interval.assign(r->interval, r->interval + 2 * (size_t)r->narcs);
+    jb.group.assign(r->narcs, 0);
+    if (r->group) jb.group.assign(r->group, r->group + r->narcs);
+  }
   jb.k.assign(r->k, r->k + r->nk);
   jb.w.assign(r->w, r->w + r->nk);
   jb.obs.assign(r->obs_xy, r->obs_xy + 2 * (size_t)r->nobs);
   jb.t.assign(r->t, r->t + r->nt);
   jb.inc = r->incident;
-  if (!finite_all(jb.xy.data(), jb.xy.size()) || !finite_all(jb.k.data(), jb.k.size()) ||
+  if (!finite_all(jb.xy.data(), jb.xy.size()) || !finite_all(jb.dxy.data(), jb.dxy.size()) ||
+      !finite_all(jb.ddxy.data(), jb.ddxy.size()) || !finite_all(jb.k.data(), jb.k.size()) ||
       !finite_all(jb.w.data(), jb.w.size()) || !finite_all(jb.t.data(), jb.t.size()))
     return bad(FTHMS_EINVAL_DATA, "non-finite request data");
   for (double v : jb.k)

@@ -53,4 +53,4 @@ def test_host_only_calls(lib):
     assert np.max(np.abs(t - ref)) < 2e-16
     assert lib.fthms_cheb_nodes(1, t.ctypes.data_as(ctypes.c_void_p)) == -1
     lib.fthms_abi_version.restype = ctypes.c_int
-    assert lib.fthms_abi_version() == 1
+    assert lib.fthms_abi_version() == 2

@@ -17,7 +17,7 @@ from .curves import (Curve, Segment, CircularArc, KiteArc, EllipseArc,
                      ClosedKite)
 from .configs import (plain_segment_case, kite_cavity_case, uneven_batch_case,
                       fixed512_case, small_kite_case, disc_interior_case,
-                      two_obstacle_case, two_arc_exterior_case, serving_requests, IncidentSpec, ArcSpec, MSProblem,
+                      two_obstacle_case, two_arc_exterior_case, serving_requests, serving_c5_requests, IncidentSpec, ArcSpec, MSProblem,
                       closed_obstacles_case)
 
 __all__ = [
@@ -26,5 +26,5 @@ __all__ = [
     "closed_obstacles_case",
     "plain_segment_case", "kite_cavity_case", "uneven_batch_case",
     "fixed512_case", "small_kite_case", "disc_interior_case",
-    "two_obstacle_case", "two_arc_exterior_case", "serving_requests", "IncidentSpec", "ArcSpec", "MSProblem",
+    "two_obstacle_case", "two_arc_exterior_case", "serving_requests", "serving_c5_requests", "IncidentSpec", "ArcSpec", "MSProblem",
 ]

@@ -13,7 +13,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .curves import (Curve, Segment, CircularArc, KiteArc, EllipseArc,
-                     SineArc, kite_point)
+                     SineArc, kite_point, ClosedEllipse, ClosedKite)
 
 
 @dataclass
@@ -337,3 +337,106 @@ def serving_requests(seed=5, count=32, max_obstacles=3, n_range=(32, 96),
                         max_steps=max_steps, stop_tol=stop_tol, n=n, obstacles=nob,
                         name="request%d" % q))
     return out
+
+
+def _perimeter(curve, m=2048):
+    """Length of a closed curve by the trapezoid rule on m points (periodic:
+    spectrally accurate)."""
+    tau = 2.0 * np.pi * np.arange(m) / m
+    d = curve.dx(tau)
+    return float(np.sum(np.hypot(d[:, 0], d[:, 1])) * 2.0 * np.pi / m)
+
+
+# largest distance of the unit kite (cos t + 0.65 cos 2t - 0.65, 1.5 sin t)
+# from its centre (the origin), for bounding circles
+_KITE_RADIUS = float(np.max(np.hypot(np.cos(np.linspace(0, 2 * np.pi, 20001))
+                                     + 0.65 * np.cos(2 * np.linspace(0, 2 * np.pi, 20001)) - 0.65,
+                                     1.5 * np.sin(np.linspace(0, 2 * np.pi, 20001)))))
+
+
+def _max_speed(curve, m=4096):
+    """max |x'(tau)| of a closed curve (dense sampling)."""
+    tau = 2.0 * np.pi * np.arange(m) / m
+    d = curve.dx(tau)
+    return float(np.max(np.hypot(d[:, 0], d[:, 1])))
+
+
+def serving_c5_requests(seed=5, count=200, max_obstacles=12, n_range=(64, 256),
+                        nk_range=(128, 512), omega0_range=(5.0, 40.0), nobs=32, dt=0.05,
+                        max_steps=100, stop_tol=1e-8, sep=0.5, precision=0):
+    """Exterior scattering requests with the serving workload's
+    distributions, each obstacle one closed patch (the paper's treatment of
+    closed curves):
+
+    * 1..max_obstacles obstacles, each an ellipse (probability 1/2; semi-axes
+      U[0.2, 1], random rotation) or a kite scaled by U[0.3, 1] (random
+      rotation); centres rejection-sampled in a square growing with the count
+      so that the boundary-to-boundary distance (bounding circles) is at
+      least ``sep``;
+    * n nodes per obstacle ~ U{n_range}, raised where needed so that the
+      largest node spacing (2 pi max |x'| / n) is at most sep / 5.25: the
+      other obstacles then lie at least 5 node spacings away (the closed
+      patches' far rule); rounded up to even;
+    * J ~ U{nk_range} frequencies omega_l = 2 omega0 l / J, omega0 ~
+      U[omega0_range], J raised where needed so that the grid's period
+      2 pi / (2 omega0 / J) covers twice the time window (no wrap-around of
+      late multiple-scattering arrivals into the traces);
+    * a Gaussian plane wave, sigma = 0.2 omega0, random direction,
+      tau0 = R_cluster + 12 / sigma; nobs points on the circle of radius
+      R_cluster + 1 about the cluster centre; t = 0 .. tau0 + 10 in steps of
+      dt; the time-domain stop rule at stop_tol within max_steps steps."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(count):
+        nob = int(rng.integers(1, max_obstacles + 1))
+        box = 1.5 + 1.2 * math.sqrt(nob)
+        shapes, centres, radii = [], [], []
+        while len(shapes) < nob:
+            if rng.random() < 0.5:
+                ea, eb = rng.uniform(0.2, 1.0), rng.uniform(0.2, 1.0)
+                rot = rng.uniform(0.0, math.pi)
+                rad = max(ea, eb)
+                mk = ("ellipse", ea, eb, rot)
+            else:
+                sc = rng.uniform(0.3, 1.0)
+                rot = rng.uniform(0.0, 2.0 * math.pi)
+                rad = _KITE_RADIUS * sc
+                mk = ("kite", sc, rot)
+            c = rng.uniform(-box, box, 2)
+            if all(math.hypot(*(c - c2)) - rad - r2 >= sep for c2, r2 in zip(centres, radii)):
+                shapes.append(mk)
+                centres.append(c)
+                radii.append(rad)
+        curves = []
+        for shp, c in zip(shapes, centres):
+            if shp[0] == "ellipse":
+                curves.append(ClosedEllipse(shp[1], shp[2], center=tuple(c), rot=shp[3]))
+            else:
+                curves.append(ClosedKite(shp[1], center=tuple(c), rot=shp[2]))
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        n = max(n, max(int(math.ceil(5.25 * 2.0 * math.pi * _max_speed(cv) / sep))
+                       for cv in curves))
+        n = min(1024, n + (n & 1))
+        arcs = [ArcSpec(cv, n, g) for g, cv in enumerate(curves)]
+        cc = np.mean(centres, axis=0)
+        rcl = max(math.hypot(*(c - cc)) + r for c, r in zip(centres, radii))
+        omega0 = rng.uniform(*omega0_range)
+        sigma = 0.2 * omega0
+        tau0 = rcl + 12.0 / sigma
+        t_end = tau0 + 10.0
+        nk = int(rng.integers(nk_range[0], nk_range[1] + 1))
+        nk = max(nk, int(math.ceil(2.0 * omega0 * t_end / math.pi)))
+        p = 2.0 * np.pi * np.arange(nobs) / nobs
+        obs = np.stack([cc[0] + (rcl + 1.0) * np.cos(p), cc[1] + (rcl + 1.0) * np.sin(p)],
+                       axis=-1)
+        om = 2.0 * omega0 * np.arange(1, nk + 1) / nk
+        # period of the frequency grid covers twice the time window
+        assert 2.0 * np.pi / (om[1] - om[0]) >= 2.0 * t_end - 1e-9
+        out.append(dict(arcs=arcs, closed=True, precision=precision,
+                        incident=IncidentSpec("gplane", theta=rng.uniform(0.0, 2.0 * math.pi),
+                                              omega0=omega0, sigma=sigma, tau0=tau0),
+                        omegas=om, obs=obs, times=dt * np.arange(int(t_end / dt) + 1),
+                        max_steps=max_steps, stop_tol=stop_tol, n=n, obstacles=nob,
+                        name="c5request%d" % q))
+    return out
+
