@@ -222,6 +222,57 @@ int fthms_problem_traces_windowed(fthms_problem *pb, int nk, const double *k, co
                                   int nt, double dt, int Q, double H,
                                   const fthms_pulse_train *inc, fthms_c64 *traces);
 
+/* ---- high-frequency transforms of real signals (Section 4.1, eqs. ft_appr,
+ * backwardFT1, int1, int2; the frequency set of Section 5) ------------------
+ *
+ * The frequency set: Clenshaw-Curtis points (ncc per interval, shared ends
+ * once) on the graded intervals (mu_j, mu_{j+1}), mu_j = wc (j/P)^p,
+ * j = 1..P-1 (mu_P = wc), then the uniform grid wc + l (W - wc)/L,
+ * l = 0..L; sorted, each point once.  Requires 0 < wc < W, P >= 2, p >= 1,
+ * 3 <= ncc <= 64, L >= 8. */
+typedef struct {
+  double wc, W, p;
+  int P, ncc, L;
+} fthms_hf_grid;
+
+/* The set's frequencies (omega may be NULL: *nk receives the count). */
+int fthms_hf_frequencies(const fthms_hf_grid *grid, double *omega, int *nk);
+
+/* Inverse transform of a real signal from its samples on the set,
+ * g(t) ~ (1/2pi) int_{-W}^{W} G e^{-iwt} dw = (1/pi) Re [int_0^{wc} + int_{wc}^{W}]
+ * (G(-w) = conj G(w)): the part near 0 by Filon-Clenshaw-Curtis on the
+ * graded intervals (the logarithmic singularity of 2D fields at w = 0; the
+ * piece (0, mu_1) is left out), the rest by a least-squares Fourier
+ * continuation of the uniform samples (period 2 (W - wc), modes |k| <= L/4)
+ * integrated term by term.  U[nk][np] complex samples (device), times
+ * t_n = t0 + n dt, u[nt][np] real (device).  The weights are built on the
+ * host per call. */
+int fthms_hf_to_time_dev(fthms_ctx *ctx, const fthms_hf_grid *grid, int np,
+                         const fthms_c64 *U_dev, double t0, double dt, int nt, double *u_dev);
+int fthms_hf_to_time(fthms_ctx *ctx, const fthms_hf_grid *grid, int np, const fthms_c64 *U,
+                     double t0, double dt, int nt, double *u);
+
+/* The real pulse incident field of Section 5: u3 (eq. planewave,
+ * u3 = -sin(4 l) exp(-1.6 (l - 3)^2), l = t - 2 - x.d, d = (cos theta,
+ * sin theta)) repeated npulse times, period apart (u4 of eq. multi: 5
+ * pulses, 10 apart). */
+typedef struct {
+  double theta, period;
+  int npulse;
+} fthms_pulse3;
+
+/* Real time traces u_M(x_p, t_n), t_n = n dt (n < nt), of the problem's
+ * M-step recursion run through the time domain with Q windows (as
+ * fthms_problem_traces_windowed) for the real pulse field inc: the slow
+ * transforms are taken at the frequency set of `grid` and the way back is
+ * the high-frequency transform of real signals above, at the shifted times
+ * t_n - s_q.  traces[nt][nobs] (host, real).  Either precision; all
+ * frequencies and time series stay resident (FTHMS_ENOMEM if they do not
+ * fit the budget).  The transform weights are built on the host. */
+int fthms_problem_traces_windowed_real(fthms_problem *pb, const fthms_hf_grid *grid, int nt,
+                                       double dt, int Q, double H, const fthms_pulse3 *inc,
+                                       double *traces);
+
 /* ---- closed patches (Section 3.3, eqs. FDsolk-closed, FDBIEk-closed) -------
  *
  * A closed curve treated as one patch: its density solves the combined-field

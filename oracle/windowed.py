@@ -95,3 +95,48 @@ def run_windowed(layout, omegas, weights, dt, nt, Q, H, inc):
                 u += back @ Vo
         g = [-layout.chi[k][None, :] * cross[k] for k in range(J)]
     return u
+
+
+def run_windowed_real(layout, fs, dt, nt, Q, H, inc):
+    """Traces u_M(x_p, t_n) (real), t_n = n dt (n < nt), of the windowed
+    recursion for the real pulse field u4 of Section 5 (eq. multi; inc =
+    dict(theta, npulse, period)) on the frequency set fs of
+    ``oracle.hftransform``: the slow transforms of eq. Fourierk are taken at
+    the frequencies of fs (positive; real data have G(-w) = conj G(w)), and
+    the way back is the real-signal transform of Section 4.1 (Filon-Clenshaw-
+    Curtis near 0, Fourier continuation on [w_c, W]) at the shifted times
+    t - s_q of eq. TDsol."""
+    from . import hftransform as hf
+    p, J = layout.p, layout.J
+    om = np.asarray(fs.omega, dtype=float)
+    t = dt * np.arange(nt)
+    sq = 1.5 * H * np.arange(Q)
+    nodes = layout.nodes
+    F = [[lu_factor(layout.assemble(j, k)) for k in om] for j in range(J)]
+    npulse, period = inc.get("npulse", 5), inc.get("period", 10.0)
+    g = [-layout.chi[j][None, :] * hf.u4(nodes[j]["y"], t, inc["theta"], npulse, period)
+         for j in range(J)]
+    back = [hf.transform_weights(fs, t - sq[q]) / math.pi for q in range(Q)]
+    u = np.zeros((nt, p.obs.shape[0]))
+    for m in range(p.M):
+        cross = [np.zeros((nt, nodes[k]["n"])) for k in range(J)]
+        for j in range(J):
+            for q in range(Q):
+                win = dt * pou(t - sq[q], H)
+                E = np.exp(1j * np.outer(om, t - sq[q]))
+                G = E @ (win[:, None] * g[j])                     # [nk][n_j]
+                psi = [lu_solve(F[j][l], G[l]) for l in range(om.size)]
+                for k in range(J):
+                    if k == j:
+                        continue
+                    msk = layout.mask[j][k]
+                    tgt = nodes[k]["y"][msk]
+                    if tgt.shape[0] == 0:
+                        continue
+                    V = np.array([layout.field(j, om[l], tgt, psi[l]) for l in range(om.size)])
+                    cross[k][:, msk] += np.real(back[q] @ V)
+                Vo = np.array([layout.field(j, om[l], p.obs, psi[l]) for l in range(om.size)])
+                u += np.real(back[q] @ Vo)
+        g = [-layout.chi[k][None, :] * cross[k] for k in range(J)]
+    return u
+

@@ -10,7 +10,8 @@ _NAMES = ("FP64", "FP32_REFINED", "GMRES", "INC_PLANE", "INC_GPLANE", "INC_POINT
           "Arc", "Batch", "Context", "FthmsError", "Problem", "Server", "cheb_nodes",
           "JOB_QUEUED", "JOB_RUNNING", "JOB_DONE", "JOB_FAILED", "JOB_CANCELLED",
           "incident_struct", "lib", "EXPORTED", "request_from_workload", "panel_nodes", "tov_breaks",
-          "COV_NONE", "COV_BOTH", "COV_LEFT", "COV_RIGHT", "OWN_STREAM")
+          "COV_NONE", "COV_BOTH", "COV_LEFT", "COV_RIGHT", "OWN_STREAM", "hf_grid",
+          "hf_frequencies")
 
 __all__ = list(_NAMES)
 

@@ -55,6 +55,15 @@ class PulseTrain(C.Structure):
                 ("tau0", C.c_double), ("period", C.c_double), ("npulse", C.c_int)]
 
 
+class HfGrid(C.Structure):
+    _fields_ = [("wc", C.c_double), ("W", C.c_double), ("p", C.c_double), ("P", C.c_int),
+                ("ncc", C.c_int), ("L", C.c_int)]
+
+
+class Pulse3(C.Structure):
+    _fields_ = [("theta", C.c_double), ("period", C.c_double), ("npulse", C.c_int)]
+
+
 class Request(C.Structure):
     _fields_ = [("narcs", C.c_int), ("n", C.c_int), ("xy", C.POINTER(C.c_double)),
                 ("dxy", C.POINTER(C.c_double)), ("interval", C.POINTER(C.c_double)),
@@ -107,6 +116,11 @@ _SIGS = {
     "fthms_lu_solve_noalloc_dev": ([_vp, _i, _i, _vp, _vp, _vp, _vp], _i),
     "fthms_lu_refine_dev": ([_vp, _i, _i, _vp, _vp, _vp, _vp, _vp, _d, _i, _vp, _vp], _i),
     "fthms_bessel_dev": ([_vp, _i, _vp, _vp, _vp], _i),
+    "fthms_problem_traces_windowed_real": ([_vp, C.POINTER(HfGrid), _i, _d, _i, _d,
+                                            C.POINTER(Pulse3), _vp], _i),
+    "fthms_hf_frequencies": ([C.POINTER(HfGrid), _vp, C.POINTER(_i)], _i),
+    "fthms_hf_to_time_dev": ([_vp, C.POINTER(HfGrid), _i, _vp, _d, _d, _i, _vp], _i),
+    "fthms_hf_to_time": ([_vp, C.POINTER(HfGrid), _i, _vp, _d, _d, _i, _vp], _i),
     "fthms_problem_create": ([_vp, C.POINTER(ProblemDesc), C.POINTER(_vp)], _i),
     "fthms_problem_destroy": ([_vp], _i),
     "fthms_problem_run": ([_vp, _i, _vp, _vp, _vp], _i),
@@ -155,6 +169,23 @@ def _dptr(t):
         return None
     assert t.is_cuda and t.is_contiguous()
     return C.c_void_p(t.data_ptr())
+
+
+def hf_grid(wc, W, P, p, ncc, L):
+    g = HfGrid()
+    g.wc, g.W, g.p, g.P, g.ncc, g.L = float(wc), float(W), float(p), int(P), int(ncc), int(L)
+    return g
+
+
+def hf_frequencies(grid):
+    """The frequency set of fthms_hf_grid `grid` (see hf_grid)."""
+    nk = C.c_int()
+    rc = _lib.fthms_hf_frequencies(C.byref(grid), None, C.byref(nk))
+    if rc:
+        raise FthmsError(rc, "bad high-frequency grid")
+    om = np.empty(nk.value)
+    _lib.fthms_hf_frequencies(C.byref(grid), _ptr(om), C.byref(nk))
+    return om
 
 
 def cheb_nodes(n):
@@ -335,6 +366,14 @@ class Context:
                                                _dptr(out)), "freq_to_time_dev")
 
 
+    def hf_to_time(self, grid, U, t0, dt, nt):
+        """Real signal u[nt][np] from complex samples U[nk][np] on the set."""
+        U = np.ascontiguousarray(U, dtype=np.complex128)
+        u = np.empty((nt, U.shape[1]))
+        self.check(_lib.fthms_hf_to_time(self.h, C.byref(grid), U.shape[1], _ptr(U), float(t0),
+                                         float(dt), int(nt), _ptr(u)), "hf_to_time")
+        return u
+
     # ---- single stages (torch tensors on the device) ----------------------
     def assemble_dev(self, arc, k, A):
         self.check(_lib.fthms_assemble_dev(self.h, arc.h, k.numel(), _dptr(k), _dptr(A)),
@@ -480,6 +519,17 @@ class Problem:
                                                           dt, Q, H, C.byref(inc), _ptr(out)),
                        "problem_traces_windowed")
         return out
+
+    def traces_windowed_real(self, grid, dt, nt, Q, H, theta, npulse=5, period=10.0):
+        """Real traces [nt][nobs] of the windowed recursion for the pulses u3
+        (u4 for 5 pulses 10 apart) on the frequency set of `grid`."""
+        inc = Pulse3()
+        inc.theta, inc.period, inc.npulse = float(theta), float(period), int(npulse)
+        u = np.empty((nt, self.obs.shape[0]))
+        self.ctx.check(_lib.fthms_problem_traces_windowed_real(
+            self.h, C.byref(grid), int(nt), float(dt), int(Q), float(H), C.byref(inc), _ptr(u)),
+            "problem_traces_windowed_real")
+        return u
 
     def run_dev(self, k, U, alpha=None):
         self.ctx.check(_lib.fthms_problem_run_dev(self.h, k.numel(), _dptr(k), _dptr(U),

@@ -22,6 +22,7 @@
 #include "panels.h"
 #include "closed.h"
 #include "gmres.h"
+#include "hftransform.h"
 
 using namespace fthms;
 
@@ -1616,6 +1617,83 @@ int fthms_lu_refine_dev(fthms_ctx *ctx, int n, int nb, const fthms_c64 *A_dev,
   if (iters_dev)
     HIPCK(ctx, hipMemcpyAsync(iters_dev, status, sizeof(int) * (size_t)nb,
                               hipMemcpyDeviceToDevice, ctx->stream));
+  return FTHMS_OK;
+}
+
+static bool hf_set_from(const fthms_hf_grid *g, HfSet &s) {
+  if (!g) return false;
+  s.wc = g->wc;
+  s.W = g->W;
+  s.p = g->p;
+  s.P = g->P;
+  s.ncc = g->ncc;
+  s.L = g->L;
+  return hf_set_build(s);
+}
+
+int fthms_hf_frequencies(const fthms_hf_grid *g, double *omega, int *nk) {
+  HfSet s;
+  if (!nk || !hf_set_from(g, s)) return FTHMS_EINVAL;
+  *nk = (int)s.omega.size();
+  if (omega) std::copy(s.omega.begin(), s.omega.end(), omega);
+  return FTHMS_OK;
+}
+
+int fthms_hf_to_time_dev(fthms_ctx *ctx, const fthms_hf_grid *g, int np, const fthms_c64 *U_dev,
+                         double t0, double dt, int nt, double *u_dev) {
+  HfSet s;
+  if (!ctx || !hf_set_from(g, s) || np < 0 || nt < 0 || !std::isfinite(t0) ||
+      !std::isfinite(dt) || (np > 0 && nt > 0 && (!U_dev || !u_dev)))
+    return fail(ctx, FTHMS_EINVAL, "bad argument to fthms_hf_to_time_dev");
+  if (np == 0 || nt == 0) return FTHMS_OK;
+  HIPCK(ctx, hipSetDevice(ctx->device));
+  const int nk = (int)s.omega.size();
+  HfFc fc;
+  hf_fc_factor(fc, s.L, s.W - s.wc, s.wc);
+  std::vector<double> t(nt);
+  for (int n = 0; n < nt; ++n) t[n] = t0 + n * dt;
+  std::vector<zd> Wt((size_t)nt * nk);
+  hf_weight_rows(s, fc, t.data(), nt, Wt.data());
+  Staging st(ctx);
+  double2 *dW;
+  int rc;
+  if ((rc = st.get(&dW, sizeof(double2) * Wt.size()))) return rc;
+  HIPCK(ctx, hipMemcpyAsync(dW, Wt.data(), sizeof(double2) * Wt.size(), hipMemcpyHostToDevice,
+                            ctx->stream));
+  dim3 g2((np + 63) / 64, (nt + 63) / 64);
+  tbeg(ctx, "freq_to_time");
+  hf_apply_kernel<true><<<g2, 256, 0, ctx->stream>>>(dW, nt, nk, (const double2 *)U_dev, np,
+                                                      u_dev, 0);
+  tend(ctx);
+  rc = check_launch(ctx, "hf_apply_kernel");
+  // the host weights are freed on return: wait for the copy
+  HIPCK(ctx, hipStreamSynchronize(ctx->stream));
+  return rc;
+}
+
+int fthms_hf_to_time(fthms_ctx *ctx, const fthms_hf_grid *g, int np, const fthms_c64 *U,
+                     double t0, double dt, int nt, double *u) {
+  int nk = 0;
+  if (!ctx || fthms_hf_frequencies(g, nullptr, &nk) != FTHMS_OK || np < 0 || nt < 0 ||
+      (np > 0 && nt > 0 && (!U || !u)))
+    return fail(ctx, FTHMS_EINVAL, "bad argument to fthms_hf_to_time");
+  if (np == 0 || nt == 0) return FTHMS_OK;
+  if (!finite_all((const double *)U, (size_t)2 * nk * np))
+    return fail(ctx, FTHMS_EINVAL_DATA, "non-finite samples");
+  HIPCK(ctx, hipSetDevice(ctx->device));
+  Staging st(ctx);
+  double2 *dU;
+  double *du;
+  int rc;
+  if ((rc = st.get(&dU, sizeof(double2) * (size_t)nk * np)) ||
+      (rc = st.get(&du, sizeof(double) * (size_t)nt * np)))
+    return rc;
+  HIPCK(ctx, hipMemcpyAsync(dU, U, sizeof(double2) * (size_t)nk * np, hipMemcpyHostToDevice,
+                            ctx->stream));
+  if ((rc = fthms_hf_to_time_dev(ctx, g, np, (const fthms_c64 *)dU, t0, dt, nt, du))) return rc;
+  HIPCK(ctx, hipMemcpyAsync(u, du, sizeof(double) * (size_t)nt * np, hipMemcpyDeviceToHost,
+                            ctx->stream));
+  HIPCK(ctx, hipStreamSynchronize(ctx->stream));
   return FTHMS_OK;
 }
 

@@ -26,6 +26,9 @@ namespace fthms {
 struct PulseTrainDev {
   double dx, dy, omega0, sigma, tau0, period;
   int npulse;
+  // 1: the real pulses u3 of Section 5 (eq. planewave, t_lag = 2) instead,
+  // u(x, t) = sum_p u3(x, t - p period) (eq. multi)
+  int real_u3 = 0;
 };
 
 // out[n][i] = -chi[i] u(y_i, n dt)   (chi == nullptr: 1)
@@ -39,6 +42,15 @@ __global__ void pulse_train_kernel(PulseTrainDev in, const double2 *__restrict__
     const double tn = (double)(e / n) * dt;
     const double xd = y[i].x * in.dx + y[i].y * in.dy;
     double ar = 0.0, ai = 0.0;
+    if (in.real_u3) {
+      for (int p = 0; p < in.npulse; ++p) {
+        const double l = tn - p * in.period - 2.0 - xd;
+        ar += -sin(4.0 * l) * exp(-1.6 * (l - 3.0) * (l - 3.0));
+      }
+      const double sc = chi ? -chi[i] : -1.0;
+      out[e] = make_double2(sc * ar, 0.0);
+      continue;
+    }
     for (int p = 0; p < in.npulse; ++p) {
       const double tau = tn - p * in.period - xd - in.tau0;
       const double a = in.sigma / (2.0 * sqrt(kPi)) * exp(-0.25 * in.sigma * in.sigma * tau * tau);
@@ -76,10 +88,14 @@ static double window_pou(double s, double H) {
   return 0.0;
 }
 
+// hfW (real signals, optional): the high-frequency transform's weights
+// [nt][Q nk] at the shifted times t_n - s_q (column q nk + l), used for the
+// way back instead of the trapezoid sum with the recentering phase.
 static int problem_windowed_impl(fthms_problem *pb, int nk, const double *k_dev,
                                  const double *w_dev, const std::vector<double> &k_host,
                                  double kmax, int nt, double dt, int Q, double H,
-                                 const PulseTrainDev &inc, double2 *traces) {
+                                 const PulseTrainDev &inc, double2 *traces,
+                                 const double2 *hfW = nullptr) {
   fthms_ctx *ctx = pb->ctx;
   const int J = pb->narcs, P = pb->nobs;
   int rc = problem_plan(pb, kmax);
@@ -185,6 +201,11 @@ static int problem_windowed_impl(fthms_problem *pb, int nk, const double *k_dev,
   if (ntr) zero_kernel<<<grid1d(ntr), 256, 0, ctx->stream>>>(traces, ntr);
   // all windows at once: (window, frequency) pairs with the phase folded in
   auto to_time = [&](int np, const double2 *Vf, double2 *out) -> int {
+    if (hfW) {
+      dim3 g2((np + 63) / 64, (nt + 63) / 64);
+      hf_apply_kernel<false><<<g2, 256, 0, ctx->stream>>>(hfW, nt, nkq, Vf, np, out, 0);
+      return check_launch(ctx, "hf_apply_kernel");
+    }
     return launch_freq_to_time(ctx, nkq, kq, wt, np, Vf, nt, t0v, out);
   };
   for (int m = 0; m < pb->M; ++m) {
@@ -229,9 +250,11 @@ static int problem_windowed_impl(fthms_problem *pb, int nk, const double *k_dev,
           if (rc) return rc;
         }
       }
-      window_phase_kernel<<<grid1d((long long)n * nkq), 256, 0, ctx->stream>>>(psi, n, nk, Q,
-                                                                               k_dev, sqv);
-      if ((rc = check_launch(ctx, "window_phase_kernel"))) return rc;
+      if (!hfW) {
+        window_phase_kernel<<<grid1d((long long)n * nkq), 256, 0, ctx->stream>>>(psi, n, nk, Q,
+                                                                                 k_dev, sqv);
+        if ((rc = check_launch(ctx, "window_phase_kernel"))) return rc;
+      }
       // fields of all windows at the other arcs' nodes, back to time
       for (int k = 0; k < J && J > 1; ++k) {
         if (k == j) continue;
@@ -320,6 +343,71 @@ int fthms_problem_traces_windowed(fthms_problem *pb, int nk, const double *k, co
   if (pb->nobs)
     HIPCK(ctx, hipMemcpyAsync(traces, du, sizeof(double2) * (size_t)nt * pb->nobs,
                               hipMemcpyDeviceToHost, ctx->stream));
+  HIPCK(ctx, hipStreamSynchronize(ctx->stream));
+  return FTHMS_OK;
+}
+
+int fthms_problem_traces_windowed_real(fthms_problem *pb, const fthms_hf_grid *grid, int nt,
+                                       double dt, int Q, double H, const fthms_pulse3 *inc,
+                                       double *traces) {
+  HfSet hs;
+  if (!pb || !hf_set_from(grid, hs) || nt < 1 || !(dt > 0.0) || Q < 1 || !(H > 0.0) || !inc ||
+      !traces || inc->npulse < 1 || !std::isfinite(inc->theta) || !std::isfinite(inc->period))
+    return fail(pb ? pb->ctx : nullptr, FTHMS_EINVAL,
+                "bad argument to fthms_problem_traces_windowed_real");
+  fthms_ctx *ctx = pb->ctx;
+  const int nk = (int)hs.omega.size();
+  HIPCK(ctx, hipSetDevice(ctx->device));
+  // the transform's weights at the shifted times t_n - s_q, one row per
+  // distinct time (the shifts are usually whole numbers of steps)
+  HfFc fc;
+  hf_fc_factor(fc, hs.L, hs.W - hs.wc, hs.wc);
+  std::vector<zd> Wall((size_t)nt * Q * nk);
+  std::map<long long, std::vector<zd>> rows;
+  std::vector<zd> row(nk);
+  for (int q = 0; q < Q; ++q)
+    for (int n = 0; n < nt; ++n) {
+      const double tt = n * dt - 1.5 * H * q;
+      const long long key = std::llround(tt * 1e9);
+      auto it = rows.find(key);
+      if (it == rows.end()) {
+        hf_weight_rows(hs, fc, &tt, 1, row.data());
+        it = rows.emplace(key, row).first;
+      }
+      std::copy(it->second.begin(), it->second.end(),
+                Wall.begin() + (size_t)n * Q * nk + (size_t)q * nk);
+    }
+  Staging st(ctx);
+  double *dk, *dw;
+  double2 *du, *dW;
+  int rc;
+  const int P = std::max(pb->nobs, 1);
+  if ((rc = st.get(&dk, sizeof(double) * nk)) || (rc = st.get(&dw, sizeof(double) * nk)) ||
+      (rc = st.get(&du, sizeof(double2) * (size_t)nt * P)) ||
+      (rc = st.get(&dW, sizeof(double2) * Wall.size())))
+    return rc;
+  std::vector<double> zeros(nk, 0.0);
+  HIPCK(ctx, hipMemcpyAsync(dk, hs.omega.data(), sizeof(double) * nk, hipMemcpyHostToDevice,
+                            ctx->stream));
+  HIPCK(ctx, hipMemcpyAsync(dw, zeros.data(), sizeof(double) * nk, hipMemcpyHostToDevice,
+                            ctx->stream));
+  HIPCK(ctx, hipMemcpyAsync(dW, Wall.data(), sizeof(double2) * Wall.size(), hipMemcpyHostToDevice,
+                            ctx->stream));
+  PulseTrainDev d{};
+  d.dx = std::cos(inc->theta);
+  d.dy = std::sin(inc->theta);
+  d.period = inc->period;
+  d.npulse = inc->npulse;
+  d.real_u3 = 1;
+  if ((rc = problem_windowed_impl(pb, nk, dk, dw, hs.omega, hs.W, nt, dt, Q, H, d, du, dW)))
+    return rc;
+  if (pb->nobs) {
+    std::vector<double2> h((size_t)nt * pb->nobs);
+    HIPCK(ctx, hipMemcpyAsync(h.data(), du, sizeof(double2) * h.size(), hipMemcpyDeviceToHost,
+                              ctx->stream));
+    HIPCK(ctx, hipStreamSynchronize(ctx->stream));
+    for (size_t e = 0; e < h.size(); ++e) traces[e] = h[e].x;
+  }
   HIPCK(ctx, hipStreamSynchronize(ctx->stream));
   return FTHMS_OK;
 }

@@ -79,3 +79,32 @@ def test_windowed_refined_matches_oracle(ctx, fth):
     u = prob.traces_windowed(om, w, 0.1, 201, 5, 6.0, **inc)
     ref = ow.run_windowed(oms.Layout(pb), om, w, 0.1, 201, 5, 6.0, inc)
     assert rel(u, ref) < TOL, rel(u, ref)
+
+
+def test_windowed_real_pulses_match_oracle(ctx, fth):
+    """Real pulses (u3 of Section 5, eq. planewave, two of them: eq. multi)
+    through the windowed recursion, slow transforms on the frequency set of
+    Section 5 and the high-frequency transform of real signals on the way
+    back (Section 4.1), against the oracle.  The grid resolves the data: the
+    continuation's modes reach time content pi K / (W - w_c) = 25 (K = L/4),
+    beyond the window half-width, the travel times and the slowly decaying
+    response of the open arcs (the least-squares fit of the windows'
+    spectra leaves residuals ~1e-12).  On a grid too coarse for the data the
+    least-squares continuation is ill-conditioned and two correct
+    implementations differ at that condition times the rounding (1e-8 at
+    (1, 6, 4, 6, 7, 80), fit residual 3e-5).  Arcs of 16 nodes: the library
+    takes the geometry of near targets from the node interpolant, exact to
+    rounding from about 16 Chebyshev nodes on these half circles."""
+    from oracle import hftransform as hf
+    grid = (1.0, 4.0, 4, 6.0, 7, 96)
+    fs = hf.FreqSet(*grid)
+    pb = disc_interior_case(n=16, omegas=fs.omega, M=2)
+    arcs = [ctx.arc_from_curve(a.curve, a.n) for a in pb.arcs]
+    iv = np.array([a.curve.interval for a in pb.arcs])
+    prob = fth.Problem(ctx, arcs, pb.incident, pb.obs, intervals=iv, M=pb.M)
+    say("windowed real pulses,", fs.omega.size, "frequencies")
+    u = prob.traces_windowed_real(fth.hf_grid(*grid), 0.1, 101, 2, 6.0, theta=0.3, npulse=2,
+                                  period=6.0)
+    ref = ow.run_windowed_real(oms.Layout(pb), fs, 0.1, 101, 2, 6.0,
+                               dict(theta=0.3, npulse=2, period=6.0))
+    assert rel(u, ref) < TOL, rel(u, ref)
