@@ -43,20 +43,33 @@ def lu_flops(n):
     return 8.0 / 3.0 * n ** 3
 
 
-def lu_block_flops(n, nb=64):
+def lu_block_flops(n, nb=64, sym=False):
     """Algorithmic real flops of one complex LU split by kernel: the panel
     kernel factors each (n-k0) x 64 column block, 4(m b^2 - b^3/3) flops; the
     strip kernel applies the block's triangular solve to the columns on its
     right (4 b^2 r) and the trailing update (8 b r^2), r = n - k0 - b.  The
-    two sums add up to (8/3) n^3 up to O(n^2) terms."""
+    two sums add up to (8/3) n^3 up to O(n^2) terms.
+    sym: the symmetric form -- the strip kernel scales the block's L21 rows
+    into U12 (6 b r) and updates the r(r+1)/2 entries on and below the
+    diagonal (8 b each); the sums then add up to (4/3) n^3 + O(n^2 b)."""
     panel = strip = 0.0
     for k0 in range(0, n, nb):
         b = min(nb, n - k0)
         m = n - k0
         r = m - b
         panel += 4.0 * (m * b * b - b ** 3 / 3.0)
-        strip += 4.0 * b * b * r + 8.0 * b * r * r
+        if sym:
+            strip += 6.0 * b * r + 4.0 * b * r * (r + 1)
+        else:
+            strip += 4.0 * b * b * r + 8.0 * b * r * r
     return panel, strip
+
+
+def lu_sym_used(n):
+    """The refined form factors the complex symmetric single-panel arc
+    matrices in the symmetric form up to n = 512 (FTHMS_LU_SYM=0 turns it
+    off)."""
+    return n <= 512 and os.environ.get("FTHMS_LU_SYM", "1") != "0"
 
 
 SOLVE_MARK = "// triangular solves on a vector held in LDS"
@@ -671,12 +684,15 @@ def main():
     ms_step = 1000.0 * r32["total"] / args.steps
     value = NK * args.steps / r32["total"]
     fp64_value = NK * args.steps / r64["total"]
-    panel_f, strip_f = lu_block_flops(N_ARC)
+    sym32 = lu_sym_used(N_ARC)
+    fl32 = lu_block_flops(N_ARC, sym=sym32)
+    fl64 = lu_block_flops(N_ARC)
+    panel_f, strip_f = fl32
     nsteps = args.steps
 
-    def lu_kernels(r, peak):
+    def lu_kernels(r, peak, fls):
         out = {}
-        for name, fl in (("lu_panel", panel_f), ("lu_strip", strip_f)):
+        for name, fl in (("lu_panel", fls[0]), ("lu_strip", fls[1])):
             ms, n = r["kt"][name]
             avg = ms / max(n, 1)
             flops_launch = fl * NK * nsteps / max(n, 1)
@@ -686,26 +702,34 @@ def main():
                                      "achieved_tflops": round(ach, 3),
                                      "frac_of_mfma_peak": round(ach / peak, 4)}
         ms, n = r["kt"]["lu"]
-        ach = lu_flops(N_ARC) * NK * nsteps / (ms / 1e3) / 1e12 if n else 0.0
+        ach = (fls[0] + fls[1]) * NK * nsteps / (ms / 1e3) / 1e12 if n else 0.0
         out["whole_lu"] = {"ms_per_step": round(ms / nsteps, 3),
+                           "alg_gflop_per_lu": round((fls[0] + fls[1]) / 1e9, 4),
                            "achieved_tflops": round(ach, 3),
                            "frac_of_mfma_peak": round(ach / peak, 4)}
         return out
 
-    k32 = lu_kernels(r32, PEAK["fp32_mfma_tflops"])
-    k64 = lu_kernels(r64, PEAK["fp64_mfma_tflops"])
+    k32 = lu_kernels(r32, PEAK["fp32_mfma_tflops"], fl32)
+    k64 = lu_kernels(r64, PEAK["fp64_mfma_tflops"], fl64)
+    k32["form"] = "symmetric (no row interchanges, lower-triangle updates)" if sym32 else \
+        "partial pivoting"
+    k64["form"] = "partial pivoting"
     strip = k32["lu_strip_kernel"]
-    strip_name = "lu_strip_kernel<float>"
-    # matrices per strip launch in the timed steps (N / 64 block steps per LU)
+    strip_name = "lu_strip_kernel<float, true>" if sym32 else "lu_strip_kernel<float, false>"
+    # matrices per strip launch in the timed steps: every block step launches
+    # strips in the pivoting form, only those with columns on the block's
+    # right in the symmetric form
     n_strip = r32["kt"]["lu_strip"][1]
-    per_launch = round(NK * nsteps * (N_ARC // 64) / n_strip) if n_strip else None
+    blocks = [k0 for k0 in range(0, N_ARC, 64) if N_ARC - k0 - 64 > 0 or (not sym32 and k0 > 0)]
+    per_launch = round(NK * nsteps * len(blocks) / n_strip) if n_strip else None
     traffic = recorded_traffic(strip_name, per_launch)
     roof = {"bound": "mfma", "achieved": strip["achieved_tflops"],
             "peak": PEAK["fp32_mfma_tflops"], "unit": "TFLOP/s",
             "frac": strip["frac_of_mfma_peak"],
             "traffic": traffic,
-            "kernel": strip_name + " (block triangular solve + trailing update, "
-                      "FP32 MFMA)",
+            "kernel": strip_name + (" (U12 from the block's L21 rows + lower-triangle "
+                                    "trailing update, FP32 MFMA)" if sym32 else
+                                    " (block triangular solve + trailing update, FP32 MFMA)"),
             "avg_launch_ms": strip["avg_launch_ms"],
             "alg_gflop_per_launch": strip["alg_gflop_per_launch"],
             "matrices_per_launch": per_launch}

@@ -70,7 +70,7 @@ enum {
   FTHMS_ECANCELLED = -8   /* served request was cancelled                */
 };
 
-enum { FTHMS_FP64 = 0, FTHMS_FP32_REFINED = 1, FTHMS_GMRES = 2 };
+enum { FTHMS_FP64 = 0, FTHMS_FP32_REFINED = 1, FTHMS_GMRES = 2, FTHMS_FP32_SYM = 3 };
 
 enum { FTHMS_INC_PLANE = 0, FTHMS_INC_GPLANE = 1, FTHMS_INC_POINT = 2 };
 
@@ -385,7 +385,16 @@ int fthms_assemble_dev(fthms_ctx *ctx, const fthms_arc *arc, int nk,
  * FTHMS_FP32_REFINED: A is complex64 (interleaved float re, im), factored
  * with FP32 MFMA updates and FP64 pivoting.  piv[nb][n] receives 0-based
  * pivot rows in LAPACK order (row i was swapped with piv[i]); info[nb]
- * (optional) 0, or -2 for an exactly zero pivot. */
+ * (optional) 0, or -2 for an exactly zero pivot.
+ * FTHMS_FP32_SYM (this stage only; the solves take it by themselves for
+ * the complex symmetric matrices of single-panel arcs, n <= 512): A is
+ * complex64 and complex symmetric (A = A^T, read from its lower triangle
+ * and diagonal blocks), n <= 512, factored without row interchanges, the
+ * trailing updates on and below the diagonal only.  The factors take the
+ * same form as FTHMS_FP32_REFINED's (unit lower L, U above, piv[i] = i);
+ * info is -2 where partial pivoting would have interchanged rows at some
+ * column (a row below the diagonal with larger |re| + |im| in the reduced
+ * matrix) or a pivot is exactly zero: those factors are not to be used. */
 int fthms_lu_dev(fthms_ctx *ctx, int n, int nb, int precision, void *A_dev,
                  int *piv_dev, int *info_dev);
 

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(PKG, "libfthms.so")
 FP64 = 0
 FP32_REFINED = 1
 GMRES = 2
+FP32_SYM = 3  # fthms_lu_dev only: complex symmetric matrices, no row interchanges
 # Context(stream=OWN_STREAM): the context creates a private stream
 OWN_STREAM = "own"
 _OWN_STREAM_HANDLE = (1 << 64) - 1  # FTHMS_OWN_STREAM, (void *)(intptr_t)-1

@@ -117,8 +117,12 @@ static int batch_factor(fthms_batch *bt, const fthms_batch::Bucket &bk, const Bu
   int rc = check_launch(ctx, "assemble_kernel (batch)");
   if (rc) return rc;
   tbeg(ctx, "lu");
+  // single-panel arc matrices are complex symmetric: the symmetric form
+  // wherever it applies (refined, n <= 512)
+  LuOpts o = bk.opts;
+  o.sym = true;
   rc = launch_lu(ctx, fp32, fp32 ? (void *)w.A32 : (void *)w.A64, n, ms, w.piv, w.scr, w.status, c,
-                 0, bk.opts);
+                 0, o);
   tend(ctx);
   return rc;
 }
@@ -399,8 +403,11 @@ int fthms_batch_tune(fthms_batch *bt, int reps) {
         LuOpts o;
         o.split = s == 0;
         o.reg_panel = r == 0;
+        o.sym = true;
         if (!o.split && bk.count < kLuSplitMin) continue;  // same launches as split
         if (!o.reg_panel && bk.n > (fp32 ? 512 : 256)) continue;
+        // the symmetric form always takes the register panel
+        if (!o.reg_panel && lu_sym_fits(fp32, bk.n)) continue;
         cand.push_back(o);
       }
     float best = 1e30f;

@@ -781,10 +781,50 @@ static void launch_perm(hipStream_t st, const int *piv, int N, int *perm, const 
 struct LuOpts {
   bool split = true;      // two half batches on two streams (large batches)
   bool reg_panel = true;  // register-resident panel where the block fits
+  // complex symmetric matrices: the symmetric form (no row interchanges,
+  // checked against partial pivoting; lu.h), FP32 with N <= 512 only -- the
+  // refined solve redoes a flagged matrix in FP64 from its FP64 copy
+  bool sym = false;
 };
+
+// The symmetric form applies: FP32 factors (an FP64 copy stays for the
+// redo) and every block within the register panel.  FTHMS_LU_SYM=0 in the
+// environment turns it off (every matrix then takes the pivoting form).
+static bool lu_sym_fits(bool fp32, int N) {
+  static const bool allowed = [] {
+    const char *e = getenv("FTHMS_LU_SYM");
+    return !(e && e[0] == '0' && e[1] == '\0');
+  }();
+  return allowed && fp32 && N <= 512;
+}
+
+// Arc matrices that are complex symmetric: the single-panel scheme's
+// (A_ij = A_ji exactly, the assembly writes each pair once and mirrors it);
+// composite-panel and closed-patch matrices are not.
+static bool arc_symmetric(const fthms_arc *arc) { return !arc->closed && !arc->d_w; }
 
 // Panel of the block at k0: register-resident kernel when the block fits
 // (m = N - k0 <= 512 in FP32, <= 320 in FP64), else the LDS/global kernel.
+// Symmetric form (FP32, m <= 512): the register panel without row interchanges.
+static void launch_panel_sym(hipStream_t st, float2 *A, int N, long long ms, int k0, int *piv,
+                             int *swp, float2 *linv, int *status, int count) {
+  const int rl = (N - k0 + 63) / 64;
+#define FTHMS_PANEL_SYM(RL)                                                         \
+  lu_panel_reg_kernel<float, RL, false><<<count, kPrThreads, 0, st>>>(A, N, ms, k0, piv, swp, \
+                                                                      linv, status, 0)
+  switch (rl) {
+    case 1: FTHMS_PANEL_SYM(1); break;
+    case 2: FTHMS_PANEL_SYM(2); break;
+    case 3: FTHMS_PANEL_SYM(3); break;
+    case 4: FTHMS_PANEL_SYM(4); break;
+    case 5: FTHMS_PANEL_SYM(5); break;
+    case 6: FTHMS_PANEL_SYM(6); break;
+    case 7: FTHMS_PANEL_SYM(7); break;
+    default: FTHMS_PANEL_SYM(8); break;
+  }
+#undef FTHMS_PANEL_SYM
+}
+
 template <typename T, int R>
 static void launch_panel(hipStream_t st, cplx_t<T> *A, int N, long long ms, int k0, int *piv,
                          int *swp, cplx_t<T> *linv, int *status, int count, int only_failed,
@@ -828,17 +868,37 @@ static void lu_step(fthms_ctx *ctx, hipStream_t st, cplx_t<T> *A, int N, long lo
   // per-kernel timing ranges, except in the redo pass (timed as a whole)
   const bool tk = !only_failed;
   const int nb = std::min(kLuNB, N - k0);
+  bool sym = false;
+  if constexpr (sizeof(T) == 4) sym = o.sym && !only_failed && lu_sym_fits(true, N);
   if (tk) tbeg(ctx, "lu_panel", st);
-  launch_panel<T, R>(st, A, N, ms, k0, piv, swp, linv, status, count, only_failed,
-                     o.reg_panel);
+  if constexpr (sizeof(T) == 4) {
+    if (sym) launch_panel_sym(st, A, N, ms, k0, piv, swp, linv, status, count);
+    else
+      launch_panel<T, R>(st, A, N, ms, k0, piv, swp, linv, status, count, only_failed,
+                         o.reg_panel);
+  } else {
+    launch_panel<T, R>(st, A, N, ms, k0, piv, swp, linv, status, count, only_failed,
+                       o.reg_panel);
+  }
   if (tk) tend(ctx);
-  const int nleft = (k0 + kStripW - 1) / kStripW;
+  // the symmetric form has no row interchanges: strips left of the block
+  // have nothing to do
+  const int nleft = sym ? 0 : (k0 + kStripW - 1) / kStripW;
   const int nright = (N - k0 - nb + kStripW - 1) / kStripW;
   if (nleft + nright > 0) {
     const long long blocks = 8LL * ((count + 7) / 8) * (nleft + nright);
     if (tk) tbeg(ctx, "lu_strip", st);
-    lu_strip_kernel<T><<<(unsigned)blocks, kLuThreads, 0, st>>>(
-        A, N, ms, k0, swp, linv, count, nleft, nright, status, only_failed);
+    bool done = false;
+    if constexpr (sizeof(T) == 4) {
+      if (sym) {
+        lu_strip_kernel<T, true><<<(unsigned)blocks, kLuThreads, 0, st>>>(
+            A, N, ms, k0, swp, linv, count, nleft, nright, status, only_failed);
+        done = true;
+      }
+    }
+    if (!done)
+      lu_strip_kernel<T, false><<<(unsigned)blocks, kLuThreads, 0, st>>>(
+          A, N, ms, k0, swp, linv, count, nleft, nright, status, only_failed);
     if (tk) tend(ctx);
   }
 }
@@ -1109,8 +1169,10 @@ static int solve_dev_impl(fthms_ctx *ctx, const fthms_arc *arc, int nk, const do
     tend(ctx);
     if (rc) return rc;
     tbeg(ctx, "lu");
+    LuOpts lo;
+    lo.sym = arc_symmetric(arc);
     rc = launch_lu(ctx, fp32, fp32 ? (void *)w.A32 : (void *)w.A64, N, ms, w.piv, w.swp, w.status,
-                   c);
+                   c, 0, lo);
     tend(ctx);
     if (rc) return rc;
     if (!fp32) {
@@ -1526,17 +1588,21 @@ int fthms_lu_dev(fthms_ctx *ctx, int n, int nb, int precision, void *A_dev, int 
                  int *info_dev) {
   if (!ctx || n < 1 || n > kMaxN || nb < 0 || (nb > 0 && (!A_dev || !piv_dev)))
     return fail(ctx, FTHMS_EINVAL, "bad argument to fthms_lu_dev");
-  if (precision != FTHMS_FP64 && precision != FTHMS_FP32_REFINED)
+  if (precision != FTHMS_FP64 && precision != FTHMS_FP32_REFINED && precision != FTHMS_FP32_SYM)
     return fail(ctx, FTHMS_EINVAL, "unknown precision");
+  if (precision == FTHMS_FP32_SYM && !lu_sym_fits(true, n))
+    return fail(ctx, FTHMS_EINVAL, "the symmetric form takes n <= 512");
   if (nb == 0) return FTHMS_OK;
   HIPCK(ctx, hipSetDevice(ctx->device));
   int rc = ensure_ws2(ctx, (kLuScratchBytes + sizeof(int)) * (size_t)nb + 256);
   if (rc) return rc;
   void *swp = ctx->ws2;
   int *status = (int *)((char *)ctx->ws2 + kLuScratchBytes * (size_t)nb);
+  LuOpts lo;
+  lo.sym = precision == FTHMS_FP32_SYM;
   tbeg(ctx, "lu");
-  rc = launch_lu(ctx, precision == FTHMS_FP32_REFINED, A_dev, n, (long long)n * n, piv_dev, swp,
-                 status, nb);
+  rc = launch_lu(ctx, precision != FTHMS_FP64, A_dev, n, (long long)n * n, piv_dev, swp, status,
+                 nb, 0, lo);
   tend(ctx);
   if (rc == FTHMS_OK && info_dev)
     HIPCK(ctx, hipMemcpyAsync(info_dev, status, sizeof(int) * nb, hipMemcpyDeviceToDevice,

@@ -517,7 +517,18 @@ constexpr int kStripW = 64;
 // U12 = L11^{-1} A12 and the update A22 -= L21 U12 down the whole strip.
 // occupancy target: FP64 strips are LDS-bound at 2 workgroups per CU, FP32
 // strips fit 4 (register budget 256 and 128 per lane)
-template <typename T>
+//
+// SYM: the symmetric form (complex symmetric A = A^T factored without row
+// interchanges, the panel kernel checking that partial pivoting would have
+// made none).  The reduced matrix stays symmetric, so that U12 = D1 L21^T
+// (D1 the diagonal of U11) comes from the block's own L21 rows of the strip's
+// columns, with no product and no row permutation, and only the tiles on and
+// below the diagonal are updated: A22 -= L21 U12 for rows >= the strip's
+// first column.  U12 is still stored, so that the factors take the usual LU
+// form (unit lower L, upper U, identity permutation) for the solves; the
+// part of the matrix strictly above the diagonal blocks is otherwise never
+// read again and is left stale.
+template <typename T, bool SYM = false>
 __global__ __launch_bounds__(kLuThreads, sizeof(T) == 8 ? 2 : 3)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3, sizeof(T) == 8 ? 2 : 3))) void lu_strip_kernel(
     cplx_t<T> *Abase, int N, long long mstride, int k0, const int *swapbase,
@@ -547,9 +558,9 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3, sizeof(T) == 8 ? 2 : 
   // are clamped into range instead; a clamped pair entry (pair npair - 1,
   // column cw - 1) copies exactly what that entry's own thread copies, so
   // its store is a duplicate of the same value.
-  const int npair = swp[0];
+  const int npair = SYM ? 0 : swp[0];
   for (int e = tid; e < 2 * npair; e += kLuThreads) spair[e] = swp[1 + e];
-  __syncthreads();
+  if (!SYM) __syncthreads();
   if (npair > 0) {
     constexpr int kGi = 32 * kSwapMax / kLuThreads;  // entries per thread per half
     const int nit = (32 * npair + kLuThreads - 1) / kLuThreads;
@@ -583,7 +594,29 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3, sizeof(T) == 8 ? 2 : 
   // the inverse from the panel kernel; A12 in LDS as the B operand, the
   // product kept in registers, then written over it (and to memory)
   const int lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
-  {
+  if constexpr (SYM) {
+    // U12[r][c] = d_r L(c0 + c, k0 + r): the panel's rows c0.. of its
+    // columns, contiguous in c for each r; stored (the U part of the
+    // factors) and kept in LDS as the update's B operand
+    constexpr int kSi = kLuNB * kStripW / kLuThreads;
+    T2 lv[kSi], dv[kSi];
+#pragma unroll
+    for (int it = 0; it < kSi; ++it) {
+      const int e = tid + it * kLuThreads, r = min(e / kStripW, nb - 1), c = e % kStripW;
+      lv[it] = A[(c0 + min(c, cw - 1)) + (long long)(k0 + r) * N];
+      dv[it] = A[(k0 + r) + (long long)(k0 + r) * N];
+    }
+#pragma unroll
+    for (int it = 0; it < kSi; ++it) {
+      const int e = tid + it * kLuThreads, r = e / kStripW, c = e % kStripW;
+      const bool ok = r < nb && c < cw;
+      const T2 d = dv[it], l = lv[it];
+      const T2 v = ok ? mk<T>(d.x * l.x - d.y * l.y, d.x * l.y + d.y * l.x) : mk<T>(T(0), T(0));
+      sX[r][c] = v;
+      if (ok) A[(k0 + r) + (long long)(c0 + c) * N] = v;
+    }
+    __syncthreads();
+  } else {
     constexpr int kSi = kLuNB * kStripW / kLuThreads;
     T gx[kSi], gy[kSi];
 #pragma unroll
@@ -599,9 +632,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3, sizeof(T) == 8 ? 2 : 
       const bool ok = r < nb && c < cw;
       sX[r][c] = mk<T>(ok ? gx[it] : T(0), ok ? gy[it] : T(0));
     }
-  }
-  __syncthreads();
-  {
+    __syncthreads();
     const T2 *lv = Linv + (long long)mat * (kLuNB * kLuNB);
     acc_t xr[4], xi[4];
 #pragma unroll
@@ -658,7 +689,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3, sizeof(T) == 8 ? 2 : 
     __syncthreads();
   }
   // ---- A22 -= L21 U12 down the strip: each wave owns 16 rows x 64 columns
-  for (int r0 = k0 + nb; r0 < N; r0 += 64) {
+  // (the symmetric form: from the strip's diagonal tile down)
+  for (int r0 = SYM ? c0 : k0 + nb; r0 < N; r0 += 64) {
     const int rw = r0 + 16 * wave;  // first row of this wave
     if (rw >= N) continue;
     // C tile and L21 fragments in one round trip, indices clamped (no

@@ -169,10 +169,11 @@ __device__ __forceinline__ cplx_t<T> row_value(const cplx_t<T> (&a)[RL][4], int 
 // One column c = 4 cw + J of the block.  used: bit i set if row lane + 64 i
 // has been chosen as a pivot or lies past the block.  rowat/pos (wave 0): row at each position,
 // position of each row.
-template <typename T, int RL, int J>
+template <typename T, int RL, int J, bool PIV>
 __device__ __forceinline__ void panel_reg_column(cplx_t<T> (&a)[RL][4], int &used,
                                                  int (&rowat)[RL], int (&pos)[RL], int w, int cw,
-                                                 int m, int &zero_col, PanelRegSmem<T, RL> &sm) {
+                                                 int m, int &zero_col, int &would_pivot,
+                                                 PanelRegSmem<T, RL> &sm) {
   typedef cplx_t<T> T2;
   const int lane = threadIdx.x & 63;
   const int c = 4 * cw + J, b = c & 1;
@@ -180,29 +181,46 @@ __device__ __forceinline__ void panel_reg_column(cplx_t<T> (&a)[RL][4], int &use
   if (w == cw) {
     // the owner's work is the critical path: raise its issue priority
     __builtin_amdgcn_s_setprio(2);
-    // pivot search in column J over the rows not yet chosen, with the
-    // magnitudes |re| + |im| formed in FP64 whatever the storage precision;
-    // a NaN entry ranks below every number so that a row is always found
+    // magnitudes |re| + |im| are formed in FP64 whatever the storage
+    // precision
     double best = -1.0;
-    int brow = 0x7fffffff;
+    if constexpr (PIV) {
+      // pivot search in column J over the rows not yet chosen; a NaN entry
+      // ranks below every number so that a row is always found
+      int brow = 0x7fffffff;
 #pragma unroll
-    for (int i = 0; i < RL; ++i) {
-      const bool ok = ((used >> i) & 1) == 0;
-      double mag = fabs((double)a[i][J].x) + fabs((double)a[i][J].y);
-      mag = mag == mag ? mag : -0.5;
-      const bool take = ok & (mag > best);
-      best = take ? mag : best;
-      brow = take ? lane + 64 * i : brow;
+      for (int i = 0; i < RL; ++i) {
+        const bool ok = ((used >> i) & 1) == 0;
+        double mag = fabs((double)a[i][J].x) + fabs((double)a[i][J].y);
+        mag = mag == mag ? mag : -0.5;
+        const bool take = ok & (mag > best);
+        best = take ? mag : best;
+        brow = take ? lane + 64 * i : brow;
+      }
+      wave_argmax<double>(best, brow);
+      p = __builtin_amdgcn_readfirstlane(brow);
+    } else {
+      p = c;
     }
-    wave_argmax<double>(best, brow);
-    p = __builtin_amdgcn_readfirstlane(brow);
     used |= lane == (p & 63) ? 1 << (p >> 6) : 0;
-    if (lane == 0) sm.pinfo[b] = p;
+    if (PIV && lane == 0) sm.pinfo[b] = p;
     T2 u[4];
     u[0] = row_value<T, RL, 0>(a, p);
     u[1] = row_value<T, RL, 1>(a, p);
     u[2] = row_value<T, RL, 2>(a, p);
     u[3] = row_value<T, RL, 3>(a, p);
+    if constexpr (!PIV) {
+      // the diagonal is the pivot; partial pivoting would have taken another
+      // row if one below is strictly larger (ties keep the first index):
+      // flag that, lane by lane, with no reduction on the critical path
+      best = fabs((double)u[J].x) + fabs((double)u[J].y);
+#pragma unroll
+      for (int i = 0; i < RL; ++i) {
+        const bool ok = ((used >> i) & 1) == 0;
+        const double mag = fabs((double)a[i][J].x) + fabs((double)a[i][J].y);
+        would_pivot |= (ok & (mag > best)) ? 1 : 0;
+      }
+    }
     const bool nz = best > 0.0;
     // pivot reciprocal in FP64, rounded once to the storage precision
     const T2 inv = nz ? from_d2<T>(trcp<double>(to_d2(u[J]))) : mk<T>(T(0), T(0));
@@ -221,7 +239,8 @@ __device__ __forceinline__ void panel_reg_column(cplx_t<T> (&a)[RL][4], int &use
   }
   __syncthreads();
   if (w != cw) {
-    p = __builtin_amdgcn_readfirstlane(sm.pinfo[b]);
+    if constexpr (PIV) p = __builtin_amdgcn_readfirstlane(sm.pinfo[b]);
+    else p = c;
     used |= lane == (p & 63) ? 1 << (p >> 6) : 0;
     if (w > cw) {
       T2 u[4];
@@ -237,7 +256,7 @@ __device__ __forceinline__ void panel_reg_column(cplx_t<T> (&a)[RL][4], int &use
       }
     }
   }
-  if (w == 0) {
+  if (PIV && w == 0) {
     // bookkeeping: row p moves to position c, the row there to p's position
     const int r = iget<RL>(pos, p);
     const int x = __builtin_amdgcn_readlane(rowat[0], c);
@@ -249,7 +268,12 @@ __device__ __forceinline__ void panel_reg_column(cplx_t<T> (&a)[RL][4], int &use
   }
 }
 
-template <typename T, int RL>
+// PIV = false: the symmetric form of the batched LU (lu.h) -- no row
+// interchanges (the diagonal is every column's pivot), no permutation and no
+// L11^{-1}; a column where partial pivoting would have chosen another row
+// makes the status -2 like a zero pivot, so that the caller solves that
+// matrix with a pivoting factorisation instead.
+template <typename T, int RL, bool PIV = true>
 __global__ __launch_bounds__(kPrThreads) void lu_panel_reg_kernel(
     cplx_t<T> *Abase, int N, long long mstride, int k0, int *pivbase, int *swapbase,
     cplx_t<T> *Linv, int *status, int only_failed) {
@@ -288,15 +312,41 @@ __global__ __launch_bounds__(kPrThreads) void lu_panel_reg_kernel(
 #pragma unroll
   for (int i = 0; i < RL; ++i) rowat[i] = pos[i] = lane + 64 * i;
   if (tid == 0) sm.zero_pivot = 0x7fffffff;
-  int zero_col = 0;
+  int zero_col = 0, would_pivot = 0;
   __syncthreads();
   // the column loop touches no global memory, so its barriers wait on LDS only
   for (int cw = 0; 4 * cw < nb; ++cw) {
     // nb is a multiple of 4 except in a last, partial block
-    panel_reg_column<T, RL, 0>(a, used, rowat, pos, w, cw, m, zero_col, sm);
-    if (4 * cw + 1 < nb) panel_reg_column<T, RL, 1>(a, used, rowat, pos, w, cw, m, zero_col, sm);
-    if (4 * cw + 2 < nb) panel_reg_column<T, RL, 2>(a, used, rowat, pos, w, cw, m, zero_col, sm);
-    if (4 * cw + 3 < nb) panel_reg_column<T, RL, 3>(a, used, rowat, pos, w, cw, m, zero_col, sm);
+    panel_reg_column<T, RL, 0, PIV>(a, used, rowat, pos, w, cw, m, zero_col, would_pivot, sm);
+    if (4 * cw + 1 < nb)
+      panel_reg_column<T, RL, 1, PIV>(a, used, rowat, pos, w, cw, m, zero_col, would_pivot, sm);
+    if (4 * cw + 2 < nb)
+      panel_reg_column<T, RL, 2, PIV>(a, used, rowat, pos, w, cw, m, zero_col, would_pivot, sm);
+    if (4 * cw + 3 < nb)
+      panel_reg_column<T, RL, 3, PIV>(a, used, rowat, pos, w, cw, m, zero_col, would_pivot, sm);
+  }
+  if constexpr (!PIV) {
+    // rows stay where they are; a flagged column counts as a zero pivot
+    const bool flag = __builtin_amdgcn_ballot_w64(would_pivot != 0) != 0;
+    if (lane == 0 && (flag || zero_col)) atomicMin(&sm.zero_pivot, 1);
+    __syncthreads();
+    if (tid < nb) piv[k0 + tid] = k0 + tid;
+    const int nslot = (m - lane + 63) >> 6;
+#pragma unroll
+    for (int i = 0; i < RL; ++i) {
+      if (i < nslot) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (4 * w + j < nb) colp[lane + 64 * i + (long long)j * N] = a[i][j];
+      }
+    }
+    if (tid == 0) {
+      swp[0] = 0;
+      const bool bad = sm.zero_pivot != 0x7fffffff;
+      if (k0 == 0) status[mb] = panel_status(only_failed, bad);
+      else if (bad) status[mb] = -2;
+    }
+    return;
   }
   // wave 0 publishes the final positions and the block's net permutation
   // (pairs "new row dst = old row src"; at most 2 x 64 rows move)

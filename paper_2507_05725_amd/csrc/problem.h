@@ -658,8 +658,10 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
       tend(ctx);
       if (rc) return rc;
       tbeg(ctx, "lu");
+      LuOpts lo;
+      lo.sym = arc_symmetric(a);
       rc = launch_lu(ctx, fp32, fp32 ? (void *)w[j].A32 : (void *)w[j].A64, n, (long long)n * n,
-                     w[j].piv, w[j].swp, w[j].status, c);
+                     w[j].piv, w[j].swp, w[j].status, c, 0, lo);
       tend(ctx);
       if (rc) return rc;
       tbeg(ctx, "rhs");

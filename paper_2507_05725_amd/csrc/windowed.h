@@ -188,8 +188,10 @@ static int problem_windowed_impl(fthms_problem *pb, int nk, const double *k_dev,
     tend(ctx);
     if (rc) return rc;
     tbeg(ctx, "lu");
+    LuOpts lo;
+    lo.sym = arc_symmetric(a);
     rc = launch_lu(ctx, fp32, fp32 ? (void *)A32 : (void *)A, n, (long long)n * n,
-                   (int *)at(o[j].piv), at(o[j].swp), (int *)at(o[j].st), nk);
+                   (int *)at(o[j].piv), at(o[j].swp), (int *)at(o[j].st), nk, 0, lo);
     tend(ctx);
     if (rc) return rc;
     const long long nn = (long long)nt * n;

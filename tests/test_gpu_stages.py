@@ -250,6 +250,104 @@ def test_refined_solve_with_row_interchanges(env, n):
         assert err < 1e-10, (n, b, err, it[b])
 
 
+def _symmetric_dominant(rng, nb, n):
+    """Complex symmetric matrices whose columns are dominated by their
+    diagonal (|re| + |im| of the diagonal above the column sum of the rest),
+    so that partial pivoting makes no interchange at any step."""
+    R = rng.standard_normal((nb, n, n)) + 1j * rng.standard_normal((nb, n, n))
+    S = 0.5 * (R + R.transpose(0, 2, 1))
+    return S + (2.0 * n) * (1 + 1j) * np.eye(n)
+
+
+def _pp_swaps(M):
+    """Row interchanges of partial pivoting (largest |re| + |im|, first row on
+    ties) in FP64, plain right-looking elimination."""
+    A = M.astype(np.complex128).copy()
+    n = A.shape[0]
+    swaps = 0
+    for c in range(n):
+        mag = np.abs(A[c:, c].real) + np.abs(A[c:, c].imag)
+        p = c + int(np.argmax(mag))
+        if mag[p - c] > mag[0]:
+            swaps += 1
+            A[[c, p]] = A[[p, c]]
+        A[c + 1:, c] /= A[c, c]
+        A[c + 1:, c + 1:] -= np.outer(A[c + 1:, c], A[c, c + 1:])
+    return swaps
+
+
+@pytest.mark.parametrize("n", [1, 5, 64, 65, 130, 300, 512])
+def test_symmetric_lu(env, n):
+    """The symmetric form (complex symmetric A, no row interchanges, updates
+    on and below the diagonal only) on matrices that partial pivoting would
+    not permute: identity pivots, info 0, factors with the FP32 backward
+    error of an LU, and the refined solve with those factors converging by
+    refinement alone to the oracle's direct solve."""
+    fth, ctx, torch = env
+    rng = np.random.default_rng(700 + n)
+    nb = 3
+    M = _symmetric_dominant(rng, nb, n)
+    assert all(_pp_swaps(M[b]) == 0 for b in range(nb))
+    bvec = rng.standard_normal((nb, n)) + 1j * rng.standard_normal((nb, n))
+    say("symmetric lu n", n)
+    Acm = np.ascontiguousarray(M.transpose(0, 2, 1))
+    LU32 = torch.tensor(Acm, dtype=torch.complex64, device="cuda")
+    A64 = torch.tensor(Acm, dtype=torch.complex128, device="cuda")
+    piv = torch.empty((nb, n), dtype=torch.int32, device="cuda")
+    info = torch.empty(nb, dtype=torch.int32, device="cuda")
+    ctx.lu_dev(LU32, piv, info, precision=fth.FP32_SYM)
+    bt = torch.tensor(bvec, device="cuda")
+    x = torch.empty_like(bt)
+    iters = torch.empty(nb, dtype=torch.int32, device="cuda")
+    ctx.lu_refine_dev(A64, LU32, piv, bt, x, tol=1e-12, max_iter=10, iters=iters)
+    torch.cuda.synchronize()
+    assert np.all(info.cpu().numpy() == 0)
+    assert np.array_equal(piv.cpu().numpy(), np.tile(np.arange(n), (nb, 1)))
+    LUs = LU32.cpu().numpy().astype(np.complex128).transpose(0, 2, 1)
+    it = iters.cpu().numpy()
+    xs = x.cpu().numpy()
+    for b in range(nb):
+        L = np.tril(LUs[b], -1) + np.eye(n)
+        U = np.triu(LUs[b])
+        err = np.linalg.norm(L @ U - M[b]) / np.linalg.norm(M[b])
+        ref = np.linalg.norm(np.abs(L) @ np.abs(U)) / np.linalg.norm(M[b])
+        assert err < 8.0 * np.sqrt(n) * 2.0 ** -24 * ref, (n, b, err)
+        assert it[b] >= 1, (n, b, it[b])
+        sol = ony.solve(M[b], bvec[b])
+        assert np.linalg.norm(xs[b] - sol) / np.linalg.norm(sol) < 1e-10
+
+
+@pytest.mark.parametrize("n", [65, 300, 512])
+def test_symmetric_lu_flags_pivoting(env, n):
+    """The symmetric form refuses what partial pivoting would permute: a
+    random complex symmetric matrix (interchanges from the first column on)
+    and a dominant one with one small diagonal entry late in the matrix (an
+    interchange at that column only) get info -2; the dominant ones beside
+    them in the batch get 0.  Sizes beyond 512 are refused."""
+    fth, ctx, torch = env
+    rng = np.random.default_rng(900 + n)
+    M = _symmetric_dominant(rng, 4, n)
+    R = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    M[1] = 0.5 * (R + R.T)
+    k = n - 40
+    M[3][k, k] = 1e-3
+    expect = [0, -2, 0, -2]
+    for b in range(4):
+        assert (_pp_swaps(M[b]) > 0) == (expect[b] == -2)
+    say("symmetric lu flags n", n)
+    LU32 = torch.tensor(np.ascontiguousarray(M.transpose(0, 2, 1)), dtype=torch.complex64,
+                        device="cuda")
+    piv = torch.empty((4, n), dtype=torch.int32, device="cuda")
+    info = torch.empty(4, dtype=torch.int32, device="cuda")
+    ctx.lu_dev(LU32, piv, info, precision=fth.FP32_SYM)
+    torch.cuda.synchronize()
+    assert list(info.cpu().numpy()) == expect
+    big = torch.zeros((1, 513, 513), dtype=torch.complex64, device="cuda")
+    p2 = torch.empty((1, 513), dtype=torch.int32, device="cuda")
+    with pytest.raises(fth.FthmsError):
+        ctx.lu_dev(big, p2, precision=fth.FP32_SYM)
+
+
 def test_refined_solve_reports_cap(env):
     """With a cap of one step and an unreachable tolerance the refinement
     reports -1 (not converged) and still returns its last iterate."""
