@@ -24,6 +24,14 @@
 //   A_ij = J0(z)(G_ij - w_j c) - (w_j/4) Y0hat(z) + i (w_j/4) J0(z),
 //   c = (gamma + log(k/2)) / (2pi);
 // A is then no longer symmetric, but J0 and Y0hat of a node pair are.
+//
+// Large arguments (z >= 4, where the Bessel routines produce Y0 itself):
+// since (2/pi)(log(z/2) + gamma) = (2/pi)(log(k/2) + gamma) + (2/pi) log r,
+// the same entries are
+//   A_ij = J0(z) Gl_ij - hq Y0(z) + i hq J0(z),   Gl_ij = G_ij + log(r_ij)/(2N)
+// (hq = pi/(4N); composite panels: Gl_ij = G_ij + w_j log(r_ij)/(2pi) and
+// w_j/4 for hq), with the frequency-independent table Gl stored after G:
+// no logarithm per entry and frequency.
 #pragma once
 
 #include "bessel.h"
@@ -36,6 +44,7 @@ namespace fthms {
 // column weights (WCOL) the mirror reuses the pair's Bessel values with its
 // own table entry and weight).  With ylist / Glist (uneven batches) matrix b
 // takes its own arc's nodes and table; otherwise every matrix uses y0 / G0.
+// G0 / Glist[b]: the arc's tables G and Gl, n x n each, one after the other.
 template <bool W32, bool WCOL>
 __global__ __launch_bounds__(256) void assemble_kernel(
     const double2 *__restrict__ y0, const double *__restrict__ G0, int N,
@@ -43,9 +52,11 @@ __global__ __launch_bounds__(256) void assemble_kernel(
     float2 *__restrict__ A32, long long mstride, const double2 *const *ylist,
     const double *const *Glist, const double *__restrict__ wcol) {
   __shared__ double2 tile[32][33];
+  __shared__ unsigned char large[32][33];
   const int b = blockIdx.y;
   const double2 *__restrict__ y = ylist ? ylist[b] : y0;
   const double *__restrict__ G = Glist ? Glist[b] : G0;
+  const double *__restrict__ Gl = G + (long long)N * N;
   const double k = kvec[b];
   const int t = blockIdx.x;
   int J = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
@@ -62,24 +73,35 @@ __global__ __launch_bounds__(256) void assemble_kernel(
   double2 yi = make_double2(0.0, 0.0);
   if (i < N) yi = y[i];
   if (WCOL) {
-    // tile holds (J0, Y0hat) of each pair; both writes form their own value
+    // tile holds (J0, Y) of each pair -- Y0hat with G below z = 4 (and on
+    // the diagonal), Y0 with Gl above -- and `large` which one; both writes
+    // form their own value
     const double c = (kEulerGamma + log(0.5 * k)) / (2.0 * kPi);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int j = j0 + ty + 8 * q;
       double2 jy = make_double2(1.0, 0.0);
+      bool big = false;
       if (i < N && j < N) {
+        double z = 0.0;
         if (i != j) {
           const double2 yj = y[j];
           const double dx = yi.x - yj.x, dy = yi.y - yj.y;
-          bessel_j0_y0hat(k * sqrt(dx * dx + dy * dy), jy.x, jy.y);
+          z = k * sqrt(dx * dx + dy * dy);
         }
-        const double g = G[i + (long long)j * N], w = wcol[j];
-        const double2 v = make_double2(jy.x * (g - w * c) - 0.25 * w * jy.y, 0.25 * w * jy.x);
-        A[i + (long long)j * N] = v;
-        if (W32) Af[i + (long long)j * N] = make_float2((float)v.x, (float)v.y);
+        big = z >= kBesselSeriesTo;
+        const long long e = i + (long long)j * N;
+        const double *tab = big ? Gl : G;  // one load from either table
+        const double g = tab[e], w = wcol[j];
+        if (big) bessel_modphase(z, jy.x, jy.y);
+        else if (i != j) bessel_series(z, jy.x, jy.y);
+        const double cc = big ? 0.0 : w * c;
+        const double2 v = make_double2(jy.x * (g - cc) - 0.25 * w * jy.y, 0.25 * w * jy.x);
+        A[e] = v;
+        if (W32) Af[e] = make_float2((float)v.x, (float)v.y);
       }
       tile[ty + 8 * q][tx] = jy;
+      large[ty + 8 * q][tx] = big;
     }
     if (I != J) {
       __syncthreads();
@@ -88,10 +110,14 @@ __global__ __launch_bounds__(256) void assemble_kernel(
         const int row = j0 + tx, col = i0 + ty + 8 * q;
         if (row < N && col < N) {
           const double2 jy = tile[tx][ty + 8 * q];
-          const double g = G[row + (long long)col * N], w = wcol[col];
-          const double2 v = make_double2(jy.x * (g - w * c) - 0.25 * w * jy.y, 0.25 * w * jy.x);
-          A[row + (long long)col * N] = v;
-          if (W32) Af[row + (long long)col * N] = make_float2((float)v.x, (float)v.y);
+          const bool big = large[tx][ty + 8 * q];
+          const long long e = row + (long long)col * N;
+          const double *tab = big ? Gl : G;
+          const double g = tab[e], w = wcol[col];
+          const double cc = big ? 0.0 : w * c;
+          const double2 v = make_double2(jy.x * (g - cc) - 0.25 * w * jy.y, 0.25 * w * jy.x);
+          A[e] = v;
+          if (W32) Af[e] = make_float2((float)v.x, (float)v.y);
         }
       }
     }
@@ -102,19 +128,23 @@ __global__ __launch_bounds__(256) void assemble_kernel(
     const int j = j0 + ty + 8 * q;
     double2 v = make_double2(0.0, 0.0);
     if (i < N && j < N) {
-      const double g = G[i + (long long)j * N];
+      const long long e = i + (long long)j * N;
       if (i == j) {
-        v = make_double2(g - ck, hq);
+        v = make_double2(G[e] - ck, hq);
       } else {
         const double2 yj = y[j];
         const double dx = yi.x - yj.x, dy = yi.y - yj.y;
         const double z = k * sqrt(dx * dx + dy * dy);
-        double j0v, yh;
-        bessel_j0_y0hat(z, j0v, yh);
-        v = make_double2(j0v * (g - ck) - hq * yh, hq * j0v);
+        const bool big = z >= kBesselSeriesTo;
+        const double *tab = big ? Gl : G;  // one load from either table
+        const double g = tab[e];
+        double j0v, yv;
+        if (big) bessel_modphase(z, j0v, yv);
+        else bessel_series(z, j0v, yv);
+        v = make_double2(j0v * (g - (big ? 0.0 : ck)) - hq * yv, hq * j0v);
       }
-      A[i + (long long)j * N] = v;
-      if (W32) Af[i + (long long)j * N] = make_float2((float)v.x, (float)v.y);
+      A[e] = v;
+      if (W32) Af[e] = make_float2((float)v.x, (float)v.y);
     }
     tile[ty + 8 * q][tx] = v;
   }

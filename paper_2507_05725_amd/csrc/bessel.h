@@ -2,22 +2,25 @@
 // fundamental solution Phi_k(r) = (i/4) H0^(1)(k r) = (i/4)(J0 + i Y0),
 // written from published mathematics (no vendor math library internals):
 //
-//   z < 1e-6     two terms of the ascending series (DLMF 10.8.1, 10.8.2)
-//   z < 16.5     Miller's backward recurrence J_{n-1} = (2n/z) J_n - J_{n+1}
-//                from a fixed start (32 steps below z = 8, 48 above),
-//                normalised by J0 + 2 sum_k J_{2k} = 1 (DLMF 10.12.4), with
-//                the Neumann series  Y0 = (2/pi)(log(z/2) + gamma) J0
-//                - (4/pi) sum_k (-1)^k J_{2k} / k  (DLMF 10.23.2 family)
-//   z >= 16.5    Hankel's asymptotic expansion (DLMF 10.17.3, 10.17.4) with
-//                14 terms in each of P and Q.
+//   z < 4        the ascending series in u = z^2/4 (DLMF 10.8.1, 10.8.2),
+//                17 terms, for J0 and for the regular part Y0hat below
+//   z >= 4       the modulus-phase form of Hankel's expansion (DLMF 10.17.3,
+//                10.17.4) with the exact modulus functions P(z), Q(z) in
+//                place of their divergent series: polynomial fits in
+//                (4/z)^2 on [4, 8) and in (8/z)^2 beyond (bessel_fit.h,
+//                written by bessel_fit.py), phase by sin/cos of z.
 //
 // Besides J0 and Y0 the routines expose the regular part
 //   Y0hat(z) = Y0(z) - (2/pi)(log(z/2) + gamma) J0(z),
 // an entire function of z^2 that the Nystrom assembly needs near the
 // diagonal without cancellation.  Host-compiled copies of these routines
 // are checked against mpmath over the full argument range of the workloads.
+//
+// Order one (the double-layer kernel of closed curves) keeps Miller's
+// backward recurrence below z = 16.5 and Hankel's series above (bessel_01).
 #pragma once
 
+#include "bessel_fit.h"
 #include "common.h"
 
 namespace fthms {
@@ -39,28 +42,6 @@ constexpr HankelAsymCoef make_hankel_asym_coef() {
     c.q[k] = ((k & 1) ? -1.0 : 1.0) * a[2 * k + 1];
   }
   return c;
-}
-
-// J0 and Y0hat by backward recurrence from n = NS (compile-time, unrolled).
-template <int NS>
-FTHMS_HD void bessel_miller(double z, double &j0, double &y0hat) {
-  const double rz = 2.0 / z;
-  double jp1 = 0.0, jn = 1.0e-250, even = 0.0, neu = 0.0;
-#pragma unroll
-  for (int n = NS; n >= 1; --n) {
-    const double jm1 = ((double)n * rz) * jn - jp1;
-    jp1 = jn;
-    jn = jm1;  // jn now holds J_{n-1} (unnormalised)
-    const int m = n - 1;
-    if (m > 0 && (m & 1) == 0) {
-      const int k = m >> 1;
-      even += jn;
-      neu += (((k & 1) ? -1.0 : 1.0) / (double)k) * jn;
-    }
-  }
-  const double inv = 1.0 / (jn + 2.0 * even);
-  j0 = jn * inv;
-  y0hat = -(4.0 / kPi) * neu * inv;
 }
 
 // J0 and Y0 from Hankel's expansion, phase via sin/cos of z itself:
@@ -92,31 +73,76 @@ FTHMS_HD double bessel_logpart(double z) {
   return (2.0 / kPi) * (log(0.5 * z) + kEulerGamma);
 }
 
+// Region boundaries of the order-zero routines.
+constexpr double kBesselSeriesTo = 4.0, kBesselMidTo = 8.0;
+
+// J0 and Y0hat for z < 4 by the ascending series.
+FTHMS_HD void bessel_series(double z, double &j0, double &y0hat) {
+  const double u = 0.25 * z * z;
+  double a = kSeriesJ[16], b = kSeriesY[16];
+#pragma unroll
+  for (int k = 15; k >= 0; --k) {
+    a = a * u + kSeriesJ[k];
+    b = b * u + kSeriesY[k];
+  }
+  j0 = a;
+  y0hat = b;
+}
+
+// J0 and Y0 for z >= 4 from the fitted modulus functions; the phase
+// z - pi/4 through sin/cos of z itself:
+// cos(z - pi/4) = (cos z + sin z)/sqrt2, sin(z - pi/4) = (sin z - cos z)/sqrt2.
+FTHMS_HD void bessel_modphase(double z, double &j0, double &y0) {
+  const double iz = 1.0 / z;
+  double P, Qz;
+  if (z < kBesselMidTo) {
+    const double x = (16.0 * iz * iz - kPQMidC) * (1.0 / kPQMidH);
+    P = kPQMidP[14];
+    Qz = kPQMidQ[14];
+#pragma unroll
+    for (int k = 13; k >= 0; --k) {
+      P = P * x + kPQMidP[k];
+      Qz = Qz * x + kPQMidQ[k];
+    }
+  } else {
+    const double w = 64.0 * iz * iz;
+    P = kPQBigP[12];
+    Qz = kPQBigQ[12];
+#pragma unroll
+    for (int k = 11; k >= 0; --k) {
+      P = P * w + kPQBigP[k];
+      Qz = Qz * w + kPQBigQ[k];
+    }
+  }
+  const double Q = Qz * iz;
+  double s, co;
+  sincos(z, &s, &co);
+  const double r2 = 0.70710678118654752440084436210484904;
+  const double cm = (co + s) * r2, sm = (s - co) * r2;
+  const double f = sqrt((2.0 / kPi) * iz);
+  j0 = f * (P * cm - Q * sm);
+  y0 = f * (P * sm + Q * cm);
+}
+
 // J0(z) and Y0hat(z), z >= 0.
 FTHMS_HD void bessel_j0_y0hat(double z, double &j0, double &yh) {
-  if (z < 1.0e-6) {
-    const double q = 0.25 * z * z;
-    j0 = 1.0 - q;
-    yh = (2.0 / kPi) * q;
-  } else if (z < 8.0) {
-    bessel_miller<32>(z, j0, yh);
-  } else if (z < kBesselAsymFrom) {
-    bessel_miller<48>(z, j0, yh);
+  if (z < kBesselSeriesTo) {
+    bessel_series(z, j0, yh);
   } else {
     double y0;
-    bessel_asym(z, j0, y0);
+    bessel_modphase(z, j0, y0);
     yh = y0 - bessel_logpart(z) * j0;
   }
 }
 
 // J0(z) and Y0(z), z > 0.
 FTHMS_HD void bessel_j0_y0(double z, double &j0, double &y0) {
-  if (z < kBesselAsymFrom) {
+  if (z < kBesselSeriesTo) {
     double yh;
-    bessel_j0_y0hat(z, j0, yh);
+    bessel_series(z, j0, yh);
     y0 = yh + bessel_logpart(z) * j0;
   } else {
-    bessel_asym(z, j0, y0);
+    bessel_modphase(z, j0, y0);
   }
 }
 

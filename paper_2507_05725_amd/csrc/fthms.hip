@@ -79,6 +79,9 @@ struct fthms_arc {
   std::vector<int> kinds;
   double hmax = 0.0;
   double2 *d_y = nullptr;
+  // [2][n][n]: the frequency-independent log table G of the assembly, then
+  // Gl = G + c_j log r_ij off the diagonal (c_j = 1/(2n); w_j/(2 pi) on
+  // composite panels), the table of the large-argument form (assemble.h)
   double *d_G = nullptr;
   double *d_cos = nullptr;  // [nper][nper] cos(m theta_j), row j
   double *d_w = nullptr;    // composite-panel arcs: Fejer weights
@@ -91,6 +94,28 @@ struct fthms_arc {
 };
 
 static thread_local std::string g_create_err;
+
+// G followed by Gl = G + c_j log r_ij (i != j) for an arc with nodes xy[n][2]:
+// c_j = 1/(2n) on a single-panel arc, w_j/(2 pi) with column weights w.
+static std::vector<double> with_log_shift(const std::vector<double> &G, const double *xy, int n,
+                                          const double *w) {
+  const size_t nn = (size_t)n * n;
+  std::vector<double> out(2 * nn);
+  std::copy(G.begin(), G.end(), out.begin());
+  for (int j = 0; j < n; ++j) {
+    const double c = w ? w[j] / (2.0 * kPi) : 0.5 / n;
+    for (int i = 0; i < n; ++i) {
+      const size_t e = (size_t)i + (size_t)j * n;
+      double v = G[e];
+      if (i != j) {
+        const double dx = xy[2 * i] - xy[2 * j], dy = xy[2 * i + 1] - xy[2 * j + 1];
+        v += c * std::log(std::sqrt(dx * dx + dy * dy));
+      }
+      out[nn + e] = v;
+    }
+  }
+  return out;
+}
 
 // ---- fixed device scratch for the allocation-free entry point ------------
 // The gather permutations of fthms_lu_solve_noalloc_dev live in this array:
@@ -465,16 +490,16 @@ int fthms_arc_create(fthms_ctx *ctx, int n, const double *xy, const double *dxy,
   for (int j = 0; j < n; ++j)
     for (int m = 0; m < n; ++m) cosT[(size_t)j * n + m] = std::cos(m * arc->theta[j]);
   int rc;
-  arc->bytes = sizeof(double2) * n + sizeof(double) * (size_t)n * n * 2;
+  arc->bytes = sizeof(double2) * n + sizeof(double) * (size_t)n * n * 3;
   if ((rc = dev_alloc(ctx, (void **)&arc->d_y, sizeof(double2) * n)) ||
-      (rc = dev_alloc(ctx, (void **)&arc->d_G, sizeof(double) * (size_t)n * n)) ||
+      (rc = dev_alloc(ctx, (void **)&arc->d_G, sizeof(double) * (size_t)n * n * 2)) ||
       (rc = dev_alloc(ctx, (void **)&arc->d_cos, sizeof(double) * (size_t)n * n))) {
     fthms_arc_destroy(arc);
     return rc;
   }
+  const std::vector<double> G2 = with_log_shift(G, xy, n, nullptr);
   HIPCK(ctx, hipMemcpy(arc->d_y, xy, sizeof(double2) * n, hipMemcpyHostToDevice));
-  HIPCK(ctx, hipMemcpy(arc->d_G, G.data(), sizeof(double) * (size_t)n * n,
-                       hipMemcpyHostToDevice));
+  HIPCK(ctx, hipMemcpy(arc->d_G, G2.data(), sizeof(double) * G2.size(), hipMemcpyHostToDevice));
   HIPCK(ctx, hipMemcpy(arc->d_cos, cosT.data(), sizeof(double) * (size_t)n * n,
                        hipMemcpyHostToDevice));
   *out = arc;
@@ -582,16 +607,18 @@ int fthms_arc_create_panels(fthms_ctx *ctx, int npan, const double *breaks, cons
   for (int j = 0; j < n_per; ++j)
     for (int m = 0; m < n_per; ++m) cosT[(size_t)j * n_per + m] = std::cos(m * arc->theta[j]);
   int rc;
-  arc->bytes = sizeof(double2) * n + sizeof(double) * ((size_t)n * n + (size_t)n_per * n_per + n);
+  arc->bytes =
+      sizeof(double2) * n + sizeof(double) * (2 * (size_t)n * n + (size_t)n_per * n_per + n);
+  const std::vector<double> G2 = with_log_shift(G, arc->xy.data(), n, arc->w.data());
   if ((rc = dev_alloc(ctx, (void **)&arc->d_y, sizeof(double2) * n)) ||
-      (rc = dev_alloc(ctx, (void **)&arc->d_G, sizeof(double) * (size_t)n * n)) ||
+      (rc = dev_alloc(ctx, (void **)&arc->d_G, sizeof(double) * G2.size())) ||
       (rc = dev_alloc(ctx, (void **)&arc->d_cos, sizeof(double) * (size_t)n_per * n_per)) ||
       (rc = dev_alloc(ctx, (void **)&arc->d_w, sizeof(double) * n))) {
     fthms_arc_destroy(arc);
     return rc;
   }
   if (hipMemcpy(arc->d_y, xy, sizeof(double2) * n, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(arc->d_G, G.data(), sizeof(double) * (size_t)n * n, hipMemcpyHostToDevice) !=
+      hipMemcpy(arc->d_G, G2.data(), sizeof(double) * G2.size(), hipMemcpyHostToDevice) !=
           hipSuccess ||
       hipMemcpy(arc->d_cos, cosT.data(), sizeof(double) * (size_t)n_per * n_per,
                 hipMemcpyHostToDevice) != hipSuccess ||
@@ -725,7 +752,7 @@ int fthms_arc_destroy(fthms_arc *arc) {
   fthms_ctx *ctx = arc->ctx;
   if (ctx) {
     dev_free(ctx, arc->d_y, sizeof(double2) * arc->n);
-    dev_free(ctx, arc->d_G, sizeof(double) * (size_t)arc->n * arc->n);
+    dev_free(ctx, arc->d_G, sizeof(double) * (size_t)arc->n * arc->n * 2);
     dev_free(ctx, arc->d_cos, sizeof(double) * (size_t)arc->nper * arc->nper);
     dev_free(ctx, arc->d_w, sizeof(double) * arc->n);
     dev_free(ctx, arc->d_dy, sizeof(double2) * arc->n);
