@@ -266,9 +266,13 @@ typedef struct {
  * fthms_problem_traces_windowed) for the real pulse field inc: the slow
  * transforms are taken at the frequency set of `grid` and the way back is
  * the high-frequency transform of real signals above, at the shifted times
- * t_n - s_q.  traces[nt][nobs] (host, real).  Either precision; all
- * frequencies and time series stay resident (FTHMS_ENOMEM if they do not
- * fit the budget).  The transform weights are built on the host. */
+ * t_n - s_q.  traces[nt][nobs] (host, real).  The recursion itself runs on
+ * the time mesh of Section 5, which covers [0, s_Q + H] (the last window's
+ * whole support): max(nt, ceil((s_Q + H)/dt) + 1) samples; the traces are
+ * the first nt, meaningful up to s_Q + H/2 where the windows sum to one.
+ * Either precision; all frequencies and time series stay resident
+ * (FTHMS_ENOMEM if they do not fit the budget).  The transform weights are
+ * built on the host. */
 int fthms_problem_traces_windowed_real(fthms_problem *pb, const fthms_hf_grid *grid, int nt,
                                        double dt, int Q, double H, const fthms_pulse3 *inc,
                                        double *traces);

@@ -60,9 +60,21 @@ def pulse_train(x, t, theta, omega0, sigma, tau0, npulse, period):
     return out
 
 
+def data_len(nt, dt, Q, H):
+    """Samples of the time mesh of the real-signal recursion: the nt
+    requested, and at least enough to cover [0, s_Q + H], the whole support
+    of the last window (Section 5 takes the time mesh on [0, s_Q + H]; a
+    window cut short would give its data a jump, and its spectrum a slowly
+    decaying tail that no band-limited transform reproduces)."""
+    return max(nt, int(math.ceil((1.5 * (Q - 1) * H + H) / dt - 1e-9)) + 1)
+
+
 def run_windowed(layout, omegas, weights, dt, nt, Q, H, inc):
     """Traces u_M(x_p, t_n), t_n = n dt (n < nt), of the windowed recursion;
-    inc = dict(theta, omega0, sigma, tau0, npulse, period)."""
+    inc = dict(theta, omega0, sigma, tau0, npulse, period).  The time mesh
+    is the nt samples asked for: the trapezoid transform on a uniform
+    frequency grid is periodic in time (period 2 pi / spacing), so the mesh
+    must stay inside one period and the caller sizes both."""
     p, J = layout.p, layout.J
     om = np.asarray(omegas, dtype=float)
     w = np.asarray(weights, dtype=float)
@@ -105,10 +117,13 @@ def run_windowed_real(layout, fs, dt, nt, Q, H, inc):
     the frequencies of fs (positive; real data have G(-w) = conj G(w)), and
     the way back is the real-signal transform of Section 4.1 (Filon-Clenshaw-
     Curtis near 0, Fourier continuation on [w_c, W]) at the shifted times
-    t - s_q of eq. TDsol."""
+    t - s_q of eq. TDsol.  The recursion runs on the time mesh of data_len
+    samples (these transforms are quadratures, with no period in time); the
+    first nt rows are returned."""
     from . import hftransform as hf
     p, J = layout.p, layout.J
     om = np.asarray(fs.omega, dtype=float)
+    nt_out, nt = nt, data_len(nt, dt, Q, H)
     t = dt * np.arange(nt)
     sq = 1.5 * H * np.arange(Q)
     nodes = layout.nodes
@@ -138,5 +153,5 @@ def run_windowed_real(layout, fs, dt, nt, Q, H, inc):
                 Vo = np.array([layout.field(j, om[l], p.obs, psi[l]) for l in range(om.size)])
                 u += np.real(back[q] @ Vo)
         g = [-layout.chi[k][None, :] * cross[k] for k in range(J)]
-    return u
+    return u[:nt_out]
 

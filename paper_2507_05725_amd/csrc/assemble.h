@@ -45,12 +45,16 @@ namespace fthms {
 // own table entry and weight).  With ylist / Glist (uneven batches) matrix b
 // takes its own arc's nodes and table; otherwise every matrix uses y0 / G0.
 // G0 / Glist[b]: the arc's tables G and Gl, n x n each, one after the other.
+// lower (symmetric matrices only, not WCOL): write the lower block triangle
+// only -- every 64 x 64 block on or below the diagonal, the diagonal blocks in
+// full -- which is all the symmetric form of the LU and the symmetric
+// residual of the refinement read (lu.h); the rest is left untouched.
 template <bool W32, bool WCOL>
 __global__ __launch_bounds__(256) void assemble_kernel(
     const double2 *__restrict__ y0, const double *__restrict__ G0, int N,
     const double *__restrict__ kvec, double2 *__restrict__ A64,
     float2 *__restrict__ A32, long long mstride, const double2 *const *ylist,
-    const double *const *Glist, const double *__restrict__ wcol) {
+    const double *const *Glist, const double *__restrict__ wcol, int lower = 0) {
   __shared__ double2 tile[32][33];
   __shared__ unsigned char large[32][33];
   const int b = blockIdx.y;
@@ -123,6 +127,9 @@ __global__ __launch_bounds__(256) void assemble_kernel(
     }
     return;
   }
+  // this tile lies above the diagonal (I < J); in the lower form it is
+  // written only inside a diagonal 64 x 64 block
+  const bool direct = !lower || (I >> 1) == (J >> 1);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int j = j0 + ty + 8 * q;
@@ -143,8 +150,10 @@ __global__ __launch_bounds__(256) void assemble_kernel(
         else bessel_series(z, j0v, yv);
         v = make_double2(j0v * (g - (big ? 0.0 : ck)) - hq * yv, hq * j0v);
       }
-      A[e] = v;
-      if (W32) Af[e] = make_float2((float)v.x, (float)v.y);
+      if (direct) {
+        A[e] = v;
+        if (W32) Af[e] = make_float2((float)v.x, (float)v.y);
+      }
     }
     tile[ty + 8 * q][tx] = v;
   }

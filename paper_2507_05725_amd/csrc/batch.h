@@ -106,10 +106,13 @@ static int batch_factor(fthms_batch *bt, const fthms_batch::Bucket &bk, const Bu
   const long long ms = (long long)n * n;
   const int T = (n + 31) / 32;
   dim3 g(T * (T + 1) / 2, c), blk(256);
+  // single-panel arc matrices are complex symmetric: the symmetric form
+  // (lower block triangle, symmetric LU and residual) wherever it applies
+  const bool sym = fp32 && lu_sym_fits(true, n);
   tbeg(ctx, "assemble");
   if (fp32)
     assemble_kernel<true, false><<<g, blk, 0, ctx->stream>>>(
-        nullptr, nullptr, n, bk.d_k, w.A64, w.A32, ms, bk.d_y, bk.d_G, nullptr);
+        nullptr, nullptr, n, bk.d_k, w.A64, w.A32, ms, bk.d_y, bk.d_G, nullptr, sym ? 1 : 0);
   else
     assemble_kernel<false, false><<<g, blk, 0, ctx->stream>>>(
         nullptr, nullptr, n, bk.d_k, w.A64, nullptr, ms, bk.d_y, bk.d_G, nullptr);
@@ -117,10 +120,8 @@ static int batch_factor(fthms_batch *bt, const fthms_batch::Bucket &bk, const Bu
   int rc = check_launch(ctx, "assemble_kernel (batch)");
   if (rc) return rc;
   tbeg(ctx, "lu");
-  // single-panel arc matrices are complex symmetric: the symmetric form
-  // wherever it applies (refined, n <= 512)
   LuOpts o = bk.opts;
-  o.sym = true;
+  o.sym = sym;
   rc = launch_lu(ctx, fp32, fp32 ? (void *)w.A32 : (void *)w.A64, n, ms, w.piv, w.scr, w.status, c,
                  0, o);
   tend(ctx);
@@ -141,10 +142,11 @@ static int batch_enqueue(fthms_batch *bt) {
     int rc = check_launch(ctx, "batch_rhs_kernel");
     if (rc) return rc;
     if ((rc = batch_factor(bt, bk, w))) return rc;
+    const bool sym = fp32 && lu_sym_fits(true, n);
     tbeg(ctx, "solve");
     if (fp32)
-      refine_kernel<<<c, kLuThreads, 2 * n * sizeof(double2), ctx->stream>>>(
-          w.A32, lu_perm(w.scr, c), w.A64, n, ms, w.rhs, w.x, n, bt->tol, 10, w.status, nullptr);
+      launch_refine(ctx->stream, sym, c, w.A32, lu_perm(w.scr, c), w.A64, n, ms, w.rhs, w.x, n,
+                    bt->tol, 10, w.status, nullptr, 0);
     else
       lu_solve64_kernel<<<c, kLuThreads, 0, ctx->stream>>>(w.A64, lu_perm(w.scr, c), n, ms, w.rhs,
                                                            w.x, n);
@@ -152,7 +154,8 @@ static int batch_enqueue(fthms_batch *bt) {
     if ((rc = check_launch(ctx, "batch solve"))) return rc;
     if (fp32) {
       tbeg(ctx, "fallback");
-      rc = launch_fallback(ctx, w.A64, n, ms, w.piv, w.scr, w.rhs, w.x, w.status, c);
+      rc = launch_fallback(ctx, w.A64, n, ms, w.piv, w.scr, w.rhs, w.x, w.status, c, kRedoFailed,
+                           sym);
       tend(ctx);
       if (rc) return rc;
     }
@@ -403,7 +406,7 @@ int fthms_batch_tune(fthms_batch *bt, int reps) {
         LuOpts o;
         o.split = s == 0;
         o.reg_panel = r == 0;
-        o.sym = true;
+        o.sym = fp32 && lu_sym_fits(true, bk.n);
         if (!o.split && bk.count < kLuSplitMin) continue;  // same launches as split
         if (!o.reg_panel && bk.n > (fp32 ? 512 : 256)) continue;
         // the symmetric form always takes the register panel

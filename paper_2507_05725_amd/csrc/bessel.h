@@ -89,12 +89,9 @@ FTHMS_HD void bessel_series(double z, double &j0, double &y0hat) {
   y0hat = b;
 }
 
-// J0 and Y0 for z >= 4 from the fitted modulus functions; the phase
-// z - pi/4 through sin/cos of z itself:
-// cos(z - pi/4) = (cos z + sin z)/sqrt2, sin(z - pi/4) = (sin z - cos z)/sqrt2.
-FTHMS_HD void bessel_modphase(double z, double &j0, double &y0) {
-  const double iz = 1.0 / z;
-  double P, Qz;
+// The modulus functions P(z) and Q(z) for z >= 4 (iz = 1/z).
+FTHMS_HD void bessel_pq(double z, double iz, double &P, double &Q) {
+  double Qz;
   if (z < kBesselMidTo) {
     const double x = (16.0 * iz * iz - kPQMidC) * (1.0 / kPQMidH);
     P = kPQMidP[14];
@@ -114,14 +111,29 @@ FTHMS_HD void bessel_modphase(double z, double &j0, double &y0) {
       Qz = Qz * w + kPQBigQ[k];
     }
   }
-  const double Q = Qz * iz;
-  double s, co;
-  sincos(z, &s, &co);
+  Q = Qz * iz;
+}
+
+// J0 = f (P cos chi - Q sin chi), Y0 = f (P sin chi + Q cos chi), chi =
+// z - pi/4, from cos z and sin z and the amplitude f = sqrt(2/(pi z)):
+// cos(z - pi/4) = (cos z + sin z)/sqrt2, sin(z - pi/4) = (sin z - cos z)/sqrt2.
+FTHMS_HD void bessel_combine(double P, double Q, double cz, double sz, double f, double &j0,
+                             double &y0) {
   const double r2 = 0.70710678118654752440084436210484904;
-  const double cm = (co + s) * r2, sm = (s - co) * r2;
-  const double f = sqrt((2.0 / kPi) * iz);
+  const double cm = (cz + sz) * r2, sm = (sz - cz) * r2;
   j0 = f * (P * cm - Q * sm);
   y0 = f * (P * sm + Q * cm);
+}
+
+// J0 and Y0 for z >= 4 from the fitted modulus functions, the phase from
+// sin/cos of z itself.
+FTHMS_HD void bessel_modphase(double z, double &j0, double &y0) {
+  const double iz = 1.0 / z;
+  double P, Q;
+  bessel_pq(z, iz, P, Q);
+  double s, co;
+  sincos(z, &s, &co);
+  bessel_combine(P, Q, co, s, sqrt((2.0 / kPi) * iz), j0, y0);
 }
 
 // J0(z) and Y0hat(z), z >= 0.

@@ -830,6 +830,14 @@ static bool lu_sym_fits(bool fp32, int N) {
 // composite-panel and closed-patch matrices are not.
 static bool arc_symmetric(const fthms_arc *arc) { return !arc->closed && !arc->d_w; }
 
+// Refined solves of a symmetric arc's matrices take the symmetric form
+// throughout: the lower block triangle assembled, the symmetric LU, the
+// symmetric residual in the refinement (and the upper part completed before
+// an FP64 redo).  One predicate for all of them.
+static bool use_sym_form(bool fp32, const fthms_arc *arc) {
+  return fp32 && arc_symmetric(arc) && lu_sym_fits(true, arc->n);
+}
+
 // Panel of the block at k0: register-resident kernel when the block fits
 // (m = N - k0 <= 512 in FP32, <= 320 in FP64), else the LDS/global kernel.
 // Symmetric form (FP32, m <= 512): the register panel without row interchanges.
@@ -1009,9 +1017,18 @@ static int launch_lu(fthms_ctx *ctx, bool fp32, void *A, int N, long long ms, in
 // refinement failed at a later solve) and solve every matrix whose status
 // is negative with its FP64 factors (those redone now and, at later solves,
 // those redone before).
+// lower: A holds its lower block triangle only (the symmetric form); the
+// upper part of the selected matrices is completed first.
 static int launch_fallback(fthms_ctx *ctx, double2 *A, int N, long long ms, int *piv, void *swp,
                            const double2 *b, double2 *x, int *status, int count,
-                           int mode = kRedoFailed) {
+                           int mode = kRedoFailed, bool lower = false) {
+  const int nbk = (N + 63) / 64;
+  if (lower && nbk > 1) {
+    symmetrize_kernel<<<dim3(nbk * (nbk - 1) / 2, count), 256, 0, ctx->stream>>>(A, N, ms, status,
+                                                                                mode);
+    int rc = check_launch(ctx, "symmetrize_kernel");
+    if (rc) return rc;
+  }
   int rc = launch_lu(ctx, false, A, N, ms, piv, swp, status, count, mode);
   if (rc) return rc;
   if (mode == kRedoLate) {
@@ -1077,8 +1094,9 @@ static int solve_ws(fthms_ctx *ctx, int N, bool fp32, int nk, SolveWs &w) {
   return FTHMS_OK;
 }
 
+// lower: the lower block triangle only (symmetric arcs, the symmetric form)
 static int assemble_launch(fthms_ctx *ctx, const fthms_arc *arc, const double *k_dev,
-                           int count, double2 *A64, float2 *A32) {
+                           int count, double2 *A64, float2 *A32, bool lower = false) {
   const int N = arc->n;
   const int T = (N + 31) / 32;
   dim3 g(T * (T + 1) / 2, count), b(256);
@@ -1103,11 +1121,11 @@ static int assemble_launch(fthms_ctx *ctx, const fthms_arc *arc, const double *k
       assemble_kernel<false, true><<<g, b, 0, ctx->stream>>>(
           arc->d_y, arc->d_G, N, k_dev, A64, nullptr, ms, nullptr, nullptr, arc->d_w);
   } else if (A32) {
-    assemble_kernel<true, false><<<g, b, 0, ctx->stream>>>(arc->d_y, arc->d_G, N, k_dev, A64,
-                                                           A32, ms, nullptr, nullptr, nullptr);
+    assemble_kernel<true, false><<<g, b, 0, ctx->stream>>>(
+        arc->d_y, arc->d_G, N, k_dev, A64, A32, ms, nullptr, nullptr, nullptr, lower ? 1 : 0);
   } else {
     assemble_kernel<false, false><<<g, b, 0, ctx->stream>>>(
-        arc->d_y, arc->d_G, N, k_dev, A64, nullptr, ms, nullptr, nullptr, nullptr);
+        arc->d_y, arc->d_G, N, k_dev, A64, nullptr, ms, nullptr, nullptr, nullptr, lower ? 1 : 0);
   }
   return check_launch(ctx, "assemble_kernel");
 }
@@ -1191,13 +1209,14 @@ static int solve_dev_impl(fthms_ctx *ctx, const fthms_arc *arc, int nk, const do
     const int c = std::min(w.chunk, nk - f0);
     const double2 *b = rhs + (long long)f0 * N;
     double2 *x = alpha + (long long)f0 * N;
+    const bool sym = use_sym_form(fp32, arc);
     tbeg(ctx, "assemble");
-    rc = assemble_launch(ctx, arc, k_dev + f0, c, w.A64, fp32 ? w.A32 : nullptr);
+    rc = assemble_launch(ctx, arc, k_dev + f0, c, w.A64, fp32 ? w.A32 : nullptr, sym);
     tend(ctx);
     if (rc) return rc;
     tbeg(ctx, "lu");
     LuOpts lo;
-    lo.sym = arc_symmetric(arc);
+    lo.sym = sym;
     rc = launch_lu(ctx, fp32, fp32 ? (void *)w.A32 : (void *)w.A64, N, ms, w.piv, w.swp, w.status,
                    c, 0, lo);
     tend(ctx);
@@ -1210,12 +1229,12 @@ static int solve_dev_impl(fthms_ctx *ctx, const fthms_arc *arc, int nk, const do
       if ((rc = check_launch(ctx, "lu_solve64_kernel"))) return rc;
     } else {
       tbeg(ctx, "solve");
-      refine_kernel<<<c, kLuThreads, 2 * N * sizeof(double2), ctx->stream>>>(
-          w.A32, lu_perm(w.swp, c), w.A64, N, ms, b, x, N, tol, 10, w.status, w.relres);
+      launch_refine(ctx->stream, sym, c, w.A32, lu_perm(w.swp, c), w.A64, N, ms, b, x, N, tol, 10,
+                    w.status, w.relres, 0);
       tend(ctx);
       if ((rc = check_launch(ctx, "refine_kernel"))) return rc;
       tbeg(ctx, "fallback");
-      rc = launch_fallback(ctx, w.A64, N, ms, w.piv, w.swp, b, x, w.status, c);
+      rc = launch_fallback(ctx, w.A64, N, ms, w.piv, w.swp, b, x, w.status, c, kRedoFailed, sym);
       tend(ctx);
       if (rc) return rc;
     }
@@ -1702,9 +1721,9 @@ int fthms_lu_refine_dev(fthms_ctx *ctx, int n, int nb, const fthms_c64 *A_dev,
   HIPCK(ctx, hipMemsetAsync(status, 0, sizeof(int) * (size_t)nb, ctx->stream));
   tbeg(ctx, "solve");
   launch_perm(ctx->stream, piv_dev, n, perm, nullptr, nb, 0);
-  refine_kernel<<<nb, kLuThreads, 2 * n * sizeof(double2), ctx->stream>>>(
-      (const float2 *)LU32_dev, perm, (const double2 *)A_dev, n, (long long)n * n,
-      (const double2 *)b_dev, (double2 *)x_dev, n, tol, max_iter, status, relres_dev);
+  launch_refine(ctx->stream, false, nb, (const float2 *)LU32_dev, perm, (const double2 *)A_dev, n,
+                (long long)n * n, (const double2 *)b_dev, (double2 *)x_dev, n, tol, max_iter,
+                status, relres_dev, 0);
   tend(ctx);
   if ((rc = check_launch(ctx, "refine_kernel"))) return rc;
   if (iters_dev)

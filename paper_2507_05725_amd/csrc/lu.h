@@ -968,18 +968,84 @@ __device__ double block_sum(double v, double *red) {
   return s;
 }
 
+// rs = bb - A xs for a complex symmetric A held as its lower block triangle
+// (64 x 64 blocks (I, J) with I >= J, the diagonal blocks in full, as the
+// symmetric form's assembly writes it; A_ij for j beyond i's diagonal block
+// is A_ji).  Each element is read once:
+//   * the stored part of row i (columns up to the end of its diagonal
+//     block) by the thread owning the row, a column sweep coalesced across
+//     the rows of a wave (which share one diagonal block, so the sweep
+//     length is uniform across the wave);
+//   * the rest of the row, column i below its diagonal block: each wave
+//     takes eight columns at a time (a group of 32 columns, all in one
+//     diagonal block, is shared by the four waves), lanes down the columns
+//     (coalesced), the eight columns' loads of a row chunk in flight
+//     together, then a wave sum per column.
+// xs, rs: N complex in LDS.  Ends with a barrier.  The sums run in a fixed
+// order (no atomics), so results are reproducible bit for bit.
+__device__ void sym_residual(const double2 *__restrict__ A, int N, const double2 *__restrict__ bb,
+                             const double2 *xs, double2 *rs) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int r = tid; r < N; r += kLuThreads) {
+    const int cend = min(N, ((r >> 6) + 1) * 64);
+    rs[r] = row_sweep(bb[r], A + r, N, xs, cend);
+  }
+  __syncthreads();
+  constexpr int W = kLuThreads / 64, U = 8;
+  for (int g0 = 0; g0 < N; g0 += W * U) {
+    const int j0 = ((g0 >> 6) + 1) * 64;  // the group's diagonal block ends here
+    if (j0 >= N) break;
+    const double2 *col[U];
+    double2 acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      col[u] = A + (long long)min(g0 + wave + W * u, N - 1) * N;
+      acc[u] = make_double2(0.0, 0.0);
+    }
+    for (int j = j0 + lane; j < N; j += 64) {
+      double2 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = col[u][j];
+      const double2 xj = xs[j];
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc[u] = cfma(acc[u], v[u], xj);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        acc[u].x += __shfl_xor(acc[u].x, off);
+        acc[u].y += __shfl_xor(acc[u].y, off);
+      }
+      const int c = g0 + wave + W * u;
+      if (lane == 0 && c < N) rs[c] = csub(rs[c], acc[u]);
+    }
+  }
+  __syncthreads();
+}
+
+// Bytes of the dynamic LDS of refine_kernel: x and r.
+constexpr size_t refine_lds_bytes(int N, bool lower) {
+  return (void)lower, sizeof(double2) * 2 * (size_t)N;
+}
+
 // Refined solve: x0 from the FP32 factors, then repeat
 //   r = b - A64 x (FP64), d = LU32^{-1} r, x += d
 // and stop once the predicted error of the updated x, |d_k| * rho with
 // rho = |d_k| / |d_{k-1}| (observed contraction; d_0 = x0), is below tol |x|.
 // status[b] = steps taken, or -1 when the cap was hit or the iteration did
 // not contract (the caller then redoes the solve in FP64).
+// LOWER: A64 holds only its lower block triangle (the symmetric form's
+// assembly); the residual then reads that part once (sym_residual).  A
+// template argument, so that the other form keeps its register budget.
+template <bool LOWER>
 __global__ __launch_bounds__(kLuThreads, 3) void refine_kernel(
     const float2 *LUbase, const int *permbase, const double2 *A64base, int N,
     long long mstride, const double2 *b, double2 *x, long long vstride, double tol,
-    int max_iter, int *status, double *relres, int later = 0) {
-  // dynamic LDS: x and r, N complex128 each (sized at launch; 16 KB at
-  // N = 512), the only LDS of the kernel, so registers set its occupancy
+    int max_iter, int *status, double *relres, int later) {
+  // dynamic LDS (refine_lds_bytes, sized at launch): x and r, N complex128
+  // each (16 KB at N = 512), the only LDS of the kernel, so registers set
+  // its occupancy
   extern __shared__ double2 refine_dyn[];
   double2 *xs = refine_dyn, *rs = refine_dyn + N;
   __shared__ double red[4];
@@ -1006,8 +1072,12 @@ __global__ __launch_bounds__(kLuThreads, 3) void refine_kernel(
   int it = 0, done = 0;
   for (; it < max_iter && !done; ++it) {
     // r = b - A x  (each thread owns rows; column sweep, coalesced)
-    for (int r = tid; r < N; r += kLuThreads) rs[r] = row_sweep(bb[r], A + r, N, xs, N);
-    __syncthreads();
+    if constexpr (LOWER) {
+      sym_residual(A, N, bb, xs, rs);
+    } else {
+      for (int r = tid; r < N; r += kLuThreads) rs[r] = row_sweep(bb[r], A + r, N, xs, N);
+      __syncthreads();
+    }
     lu_solve_lds<float>(LU, piv, rs, N);
     double dn = 0.0, xn = 0.0;
     for (int i = tid; i < N; i += kLuThreads) {
@@ -1034,6 +1104,60 @@ __global__ __launch_bounds__(kLuThreads, 3) void refine_kernel(
     if (status) status[mb] = done ? (it > 0 ? it : 1) : (later ? kStatusLateFail : -1);
     if (relres) relres[mb] = last;
   }
+}
+
+// Completes the upper block triangle of complex symmetric matrices held as
+// their lower block triangle (A_IJ = A_JI^T for 64 x 64 blocks I < J), for
+// the matrices the redo mode selects, before their FP64 redo with partial
+// pivoting.  Grid: (64 x 64 blocks above the diagonal, count); 32 x 32
+// quarters through LDS.
+__global__ __launch_bounds__(256) void symmetrize_kernel(double2 *Abase, int N, long long mstride,
+                                                          const int *status, int mode) {
+  __shared__ double2 t[32][33];
+  const long long mb = blockIdx.y;
+  if (redo_skips(mode, status, mb)) return;
+  const int nbk = (N + 63) / 64;
+  // upper block (I, J), I < J, from the block index
+  int I = 0, rem = blockIdx.x;
+  while (rem >= nbk - 1 - I) {
+    rem -= nbk - 1 - I;
+    ++I;
+  }
+  const int J = I + 1 + rem;
+  double2 *A = Abase + mb * mstride;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int qr = 0; qr < 2; ++qr)
+    for (int qc = 0; qc < 2; ++qc) {
+      // quarter of block (J, I) at rows 64J + 32qr, cols 64I + 32qc, read
+      // down its columns, written transposed into block (I, J)
+      const int r0 = 64 * J + 32 * qr, c0 = 64 * I + 32 * qc;
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = r0 + tx, c = c0 + ty + 8 * u;
+        if (r < N && c < N) t[ty + 8 * u][tx] = A[r + (long long)c * N];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = c0 + tx, c = r0 + ty + 8 * u;  // element (r, c) = (c, r) of the source
+        if (r < N && c < N) A[r + (long long)c * N] = t[tx][ty + 8 * u];
+      }
+    }
+}
+
+// refine_kernel for `count` matrices on stream st; lower: A64 holds its
+// lower block triangle only.
+inline void launch_refine(hipStream_t st, bool lower, int count, const float2 *LU,
+                          const int *perm, const double2 *A64, int N, long long ms,
+                          const double2 *b, double2 *x, long long vstride, double tol,
+                          int max_iter, int *status, double *relres, int later) {
+  if (lower)
+    refine_kernel<true><<<count, kLuThreads, refine_lds_bytes(N, true), st>>>(
+        LU, perm, A64, N, ms, b, x, vstride, tol, max_iter, status, relres, later);
+  else
+    refine_kernel<false><<<count, kLuThreads, refine_lds_bytes(N, false), st>>>(
+        LU, perm, A64, N, ms, b, x, vstride, tol, max_iter, status, relres, later);
 }
 
 // After a late redo: the matrices factored in FP64 (status

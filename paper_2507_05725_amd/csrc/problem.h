@@ -582,16 +582,17 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
       tend(ctx);
       return check_launch(ctx, "lu_solve64_kernel");
     }
+    const bool sym = use_sym_form(fp32, pb->arcs[j]);
     tbeg(ctx, "solve");
-    refine_kernel<<<c, kLuThreads, 2 * n * sizeof(double2), ctx->stream>>>(
-        w[j].A32, lu_perm(w[j].swp, c), w[j].A64, n, ms, w[j].b, w[j].al, n, pb->tol,
-        later ? late_maxit : 10, w[j].status, w[j].relres, later ? 1 : 0);
+    launch_refine(ctx->stream, sym, c, w[j].A32, lu_perm(w[j].swp, c), w[j].A64, n, ms, w[j].b,
+                  w[j].al, n, pb->tol, later ? late_maxit : 10, w[j].status, w[j].relres,
+                  later ? 1 : 0);
     tend(ctx);
     int r = check_launch(ctx, "refine_kernel");
     if (r) return r;
     tbeg(ctx, "fallback");
     r = launch_fallback(ctx, w[j].A64, n, ms, w[j].piv, w[j].swp, w[j].b, w[j].al, w[j].status,
-                        c, later ? kRedoLate : kRedoFailed);
+                        c, later ? kRedoLate : kRedoFailed, sym);
     tend(ctx);
     return r;
   };
@@ -653,13 +654,14 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
     for (int j = 0; j < J; ++j) {
       const fthms_arc *a = pb->arcs[j];
       const int n = a->n;
+      const bool sym = use_sym_form(fp32, a);
       tbeg(ctx, "assemble");
-      rc = assemble_launch(ctx, a, kc, c, w[j].A64, fp32 ? w[j].A32 : nullptr);
+      rc = assemble_launch(ctx, a, kc, c, w[j].A64, fp32 ? w[j].A32 : nullptr, sym);
       tend(ctx);
       if (rc) return rc;
       tbeg(ctx, "lu");
       LuOpts lo;
-      lo.sym = arc_symmetric(a);
+      lo.sym = sym;
       rc = launch_lu(ctx, fp32, fp32 ? (void *)w[j].A32 : (void *)w[j].A64, n, (long long)n * n,
                      w[j].piv, w[j].swp, w[j].status, c, 0, lo);
       tend(ctx);

@@ -183,13 +183,14 @@ static int problem_windowed_impl(fthms_problem *pb, int nk, const double *k_dev,
     const int n = a->n;
     double2 *A = (double2 *)at(o[j].A);
     float2 *A32 = fp32 ? (float2 *)at(o[j].A32) : nullptr;
+    const bool sym = use_sym_form(fp32, a);
     tbeg(ctx, "assemble");
-    rc = assemble_launch(ctx, a, k_dev, nk, A, A32);
+    rc = assemble_launch(ctx, a, k_dev, nk, A, A32, sym);
     tend(ctx);
     if (rc) return rc;
     tbeg(ctx, "lu");
     LuOpts lo;
-    lo.sym = arc_symmetric(a);
+    lo.sym = sym;
     rc = launch_lu(ctx, fp32, fp32 ? (void *)A32 : (void *)A, n, (long long)n * n,
                    (int *)at(o[j].piv), at(o[j].swp), (int *)at(o[j].st), nk, 0, lo);
     tend(ctx);
@@ -237,17 +238,18 @@ static int problem_windowed_impl(fthms_problem *pb, int nk, const double *k_dev,
           // the first solve of each matrix uses fresh factors; every later
           // one (other windows, later steps) reuses them
           const bool later = m > 0 || q > 0;
+          const bool sym = use_sym_form(fp32, pb->arcs[j]);
           tbeg(ctx, "solve");
-          refine_kernel<<<nk, kLuThreads, 2 * n * sizeof(double2), ctx->stream>>>(
-              (const float2 *)at(o[j].A32), lu_perm(at(o[j].swp), nk), (const double2 *)at(o[j].A),
-              n, (long long)n * n, Gq, pq, n, pb->tol, 10, (int *)at(o[j].st),
-              (double *)at(o[j].rr), later ? 1 : 0);
+          launch_refine(ctx->stream, sym, nk, (const float2 *)at(o[j].A32),
+                        lu_perm(at(o[j].swp), nk), (const double2 *)at(o[j].A), n,
+                        (long long)n * n, Gq, pq, n, pb->tol, 10, (int *)at(o[j].st),
+                        (double *)at(o[j].rr), later ? 1 : 0);
           tend(ctx);
           if ((rc = check_launch(ctx, "refine_kernel"))) return rc;
           tbeg(ctx, "fallback");
           rc = launch_fallback(ctx, (double2 *)at(o[j].A), n, (long long)n * n,
                                (int *)at(o[j].piv), at(o[j].swp), Gq, pq, (int *)at(o[j].st), nk,
-                               later ? kRedoLate : kRedoFailed);
+                               later ? kRedoLate : kRedoFailed, sym);
           tend(ctx);
           if (rc) return rc;
         }
@@ -359,6 +361,13 @@ int fthms_problem_traces_windowed_real(fthms_problem *pb, const fthms_hf_grid *g
                 "bad argument to fthms_problem_traces_windowed_real");
   fthms_ctx *ctx = pb->ctx;
   const int nk = (int)hs.omega.size();
+  const int nt_out = nt;
+  // the recursion's time mesh covers [0, s_Q + H], the whole support of the
+  // last window (the time mesh of Section 5): a window cut short would give
+  // its data a jump that no band-limited transform reproduces; these
+  // transforms have no period in time, so the mesh may extend past the
+  // traces asked for
+  nt = std::max(nt, (int)std::ceil((1.5 * (Q - 1) * H + H) / dt - 1e-9) + 1);
   HIPCK(ctx, hipSetDevice(ctx->device));
   // the transform's weights at the shifted times t_n - s_q, one row per
   // distinct time (the shifts are usually whole numbers of steps)
@@ -404,7 +413,7 @@ int fthms_problem_traces_windowed_real(fthms_problem *pb, const fthms_hf_grid *g
   if ((rc = problem_windowed_impl(pb, nk, dk, dw, hs.omega, hs.W, nt, dt, Q, H, d, du, dW)))
     return rc;
   if (pb->nobs) {
-    std::vector<double2> h((size_t)nt * pb->nobs);
+    std::vector<double2> h((size_t)nt_out * pb->nobs);  // the first rows
     HIPCK(ctx, hipMemcpyAsync(h.data(), du, sizeof(double2) * h.size(), hipMemcpyDeviceToHost,
                               ctx->stream));
     HIPCK(ctx, hipStreamSynchronize(ctx->stream));

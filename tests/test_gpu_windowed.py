@@ -108,3 +108,29 @@ def test_windowed_real_pulses_match_oracle(ctx, fth):
     ref = ow.run_windowed_real(oms.Layout(pb), fs, 0.1, 101, 2, 6.0,
                                dict(theta=0.3, npulse=2, period=6.0))
     assert rel(u, ref) < TOL, rel(u, ref)
+
+
+def test_geometry1_long_time_against_exact(ctx, fth):
+    """Geometry 1 of Section 5 at the paper's long-time setting: the unit disc
+    as three overlapping arcs, the five-pulse field u4 (eq. multi) at
+    theta = 0, M = 40, J = 872 frequencies up to W = 20, dt = 0.1, Q = 5
+    windows of H = 10, times up to 60.  Inside the disc the field is exactly
+    -u4; the paper reports errors uniformly below 1e-6 at (0.5, 0).
+    Composite-panel arcs of 3 x 96 nodes (2.3e-7 measured; 9e-6 at 3 x 48)."""
+    from oracle import hftransform as hf
+    grid = (1.0, 20.0, 10, 12.0, 15, 745)
+    om = fth.hf_frequencies(fth.hf_grid(*grid))
+    assert om.size == 872
+    pb = disc_interior_case(n=96, omegas=om, M=40)
+    obs = np.array([[0.5, 0.0]])
+    iv = np.array([a.curve.interval for a in pb.arcs])
+    brs = fth.tov_breaks(iv, None, pb.period)
+    arcs = [ctx.panel_arc_from_curve(a.curve, 96, b) for a, b in zip(pb.arcs, brs)]
+    prob = fth.Problem(ctx, arcs, pb.incident, obs, intervals=iv, M=40)
+    say("geometry 1 long time, J", om.size)
+    u = prob.traces_windowed_real(fth.hf_grid(*grid), 0.1, 601, 5, 10.0, theta=0.0, npulse=5,
+                                  period=10.0)
+    t = 0.1 * np.arange(601)
+    err = np.max(np.abs(u[:, 0] + hf.u4(obs, t, 0.0)[:, 0]))
+    say("geometry 1 max error %.2e" % err)
+    assert err < 1e-6, err
