@@ -70,7 +70,13 @@ enum {
   FTHMS_ECANCELLED = -8   /* served request was cancelled                */
 };
 
-enum { FTHMS_FP64 = 0, FTHMS_FP32_REFINED = 1, FTHMS_GMRES = 2, FTHMS_FP32_SYM = 3 };
+enum {
+  FTHMS_FP64 = 0,
+  FTHMS_FP32_REFINED = 1,
+  FTHMS_GMRES = 2,
+  FTHMS_FP32_SYM = 3,
+  FTHMS_FP16_GMRES_IR = 4
+};
 
 enum { FTHMS_INC_PLANE = 0, FTHMS_INC_GPLANE = 1, FTHMS_INC_POINT = 2 };
 
@@ -333,7 +339,16 @@ int fthms_arc_panel_table(const fthms_arc *arc, double *W, double *w);
  * Geometries 5) until the residual estimate is below tol |rhs| (tol <= 0:
  * 1e-12) or min(n, 256) iterations; iters receives the GMRES iterations,
  * relres the final relative residual estimate; the host entry point
- * returns FTHMS_ENOCONV (results written) if a system did not converge. */
+ * returns FTHMS_ENOCONV (results written) if a system did not converge.
+ * precision FTHMS_FP16_GMRES_IR (GMRES-IR, for well-conditioned arcs): the
+ * matrices are factored with the trailing-update products on the FP16
+ * matrix cores (FP32 storage and accumulation; the symmetric form for
+ * single-panel arcs of n <= 512), and FP64 GMRES right-preconditioned by
+ * those factors solves each system to tol (tol <= 0: 1e-12), at most
+ * min(n, 30) iterations; a system whose factors are unusable or whose GMRES
+ * misses tol is solved with FP64 LU instead.  iters receives the GMRES
+ * iterations (-1 for an FP64 solve), relres the final relative residual
+ * estimate. */
 int fthms_solve(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double *k,
                 const fthms_c64 *rhs, fthms_c64 *alpha, int precision,
                 double tol, int *iters, double *relres);

@@ -6,7 +6,7 @@ this package is its Python binding.  Build the library with
 use of any name below; it raises ImportError when the library is missing
 (there is no CPU fallback).
 """
-_NAMES = ("FP64", "FP32_REFINED", "GMRES", "FP32_SYM", "INC_PLANE", "INC_GPLANE", "INC_POINT",
+_NAMES = ("FP64", "FP32_REFINED", "GMRES", "FP32_SYM", "FP16_GMRES_IR", "INC_PLANE", "INC_GPLANE", "INC_POINT",
           "Arc", "Batch", "Context", "FthmsError", "Problem", "Server", "cheb_nodes",
           "JOB_QUEUED", "JOB_RUNNING", "JOB_DONE", "JOB_FAILED", "JOB_CANCELLED",
           "incident_struct", "lib", "EXPORTED", "request_from_workload", "panel_nodes", "tov_breaks",

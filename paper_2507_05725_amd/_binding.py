@@ -20,6 +20,7 @@ FP64 = 0
 FP32_REFINED = 1
 GMRES = 2
 FP32_SYM = 3  # fthms_lu_dev only: complex symmetric matrices, no row interchanges
+FP16_GMRES_IR = 4  # FP64 GMRES preconditioned by an FP16-MFMA LU
 # Context(stream=OWN_STREAM): the context creates a private stream
 OWN_STREAM = "own"
 _OWN_STREAM_HANDLE = (1 << 64) - 1  # FTHMS_OWN_STREAM, (void *)(intptr_t)-1

@@ -45,7 +45,18 @@ struct fthms_batch {
   hipStream_t cs = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   bool tuned = false;
+  // concurrent lanes: the buckets are dealt to up to kBatchLanes streams
+  // (balanced by LU work, count n^3), each with its own workspace, so that
+  // small buckets no longer wait for each other; the captured graph forks
+  // from cs to the lanes and joins back
+  int lanes = 1;
+  std::vector<int> lane_of;           // per bucket
+  std::vector<size_t> lane_off;       // workspace offset of each lane
+  hipStream_t ls[4] = {};
+  hipEvent_t lev[4] = {}, ev_fork = nullptr;
 };
+
+constexpr int kBatchLanes = 4;
 
 namespace {
 
@@ -122,6 +133,8 @@ static int batch_factor(fthms_batch *bt, const fthms_batch::Bucket &bk, const Bu
   tbeg(ctx, "lu");
   LuOpts o = bk.opts;
   o.sym = sym;
+  // the two-half split shares the context's second stream: not across lanes
+  if (bt->lanes > 1) o.split = false;
   rc = launch_lu(ctx, fp32, fp32 ? (void *)w.A32 : (void *)w.A64, n, ms, w.piv, w.scr, w.status, c,
                  0, o);
   tend(ctx);
@@ -131,17 +144,28 @@ static int batch_factor(fthms_batch *bt, const fthms_batch::Bucket &bk, const Bu
 static int batch_enqueue(fthms_batch *bt) {
   fthms_ctx *ctx = bt->ctx;
   const bool fp32 = bt->precision == FTHMS_FP32_REFINED;
-  for (const auto &bk : bt->buckets) {
+  const hipStream_t origin = ctx->stream;
+  if (bt->lanes > 1) {
+    HIPCK(ctx, hipEventRecord(bt->ev_fork, origin));
+    for (int l = 0; l < bt->lanes; ++l) HIPCK(ctx, hipStreamWaitEvent(bt->ls[l], bt->ev_fork, 0));
+  }
+  for (size_t bi = 0; bi < bt->buckets.size(); ++bi) {
+    const auto &bk = bt->buckets[bi];
+    const int lane = bt->lanes > 1 ? bt->lane_of[bi] : 0;
+    if (bt->lanes > 1) ctx->stream = bt->ls[lane];
     const int n = bk.n, c = bk.count;
     const long long ms = (long long)n * n;
-    BucketWs w = bucket_ws(bt->ws, n, c, fp32);
+    BucketWs w = bucket_ws((char *)bt->ws + bt->lane_off[lane], n, c, fp32);
     dim3 gv((n + 255) / 256, c);
     tbeg(ctx, "rhs");
     batch_rhs_kernel<<<gv, 256, 0, ctx->stream>>>(bk.d_inc, bk.d_y, bk.d_k, n, w.rhs, n);
     tend(ctx);
     int rc = check_launch(ctx, "batch_rhs_kernel");
-    if (rc) return rc;
-    if ((rc = batch_factor(bt, bk, w))) return rc;
+    if (!rc) rc = batch_factor(bt, bk, w);
+    if (rc) {
+      ctx->stream = origin;
+      return rc;
+    }
     const bool sym = fp32 && lu_sym_fits(true, n);
     tbeg(ctx, "solve");
     if (fp32)
@@ -151,18 +175,30 @@ static int batch_enqueue(fthms_batch *bt) {
       lu_solve64_kernel<<<c, kLuThreads, 0, ctx->stream>>>(w.A64, lu_perm(w.scr, c), n, ms, w.rhs,
                                                            w.x, n);
     tend(ctx);
-    if ((rc = check_launch(ctx, "batch solve"))) return rc;
-    if (fp32) {
+    rc = check_launch(ctx, "batch solve");
+    if (!rc && fp32) {
       tbeg(ctx, "fallback");
       rc = launch_fallback(ctx, w.A64, n, ms, w.piv, w.scr, w.rhs, w.x, w.status, c, kRedoFailed,
                            sym);
       tend(ctx);
-      if (rc) return rc;
+    }
+    if (rc) {
+      ctx->stream = origin;
+      return rc;
     }
     batch_scatter_kernel<<<gv, 256, 0, ctx->stream>>>(w.x, n, bk.d_off, w.status, bk.d_item,
                                                       bt->d_alpha, bt->d_iters);
-    if ((rc = check_launch(ctx, "batch_scatter_kernel"))) return rc;
+    if ((rc = check_launch(ctx, "batch_scatter_kernel"))) {
+      ctx->stream = origin;
+      return rc;
+    }
   }
+  ctx->stream = origin;
+  if (bt->lanes > 1)
+    for (int l = 0; l < bt->lanes; ++l) {
+      HIPCK(ctx, hipEventRecord(bt->lev[l], bt->ls[l]));
+      HIPCK(ctx, hipStreamWaitEvent(origin, bt->lev[l], 0));
+    }
   return FTHMS_OK;
 }
 
@@ -194,6 +230,14 @@ int fthms_batch_destroy(fthms_batch *bt) {
   }
   if (bt->ev_in) (void)hipEventDestroy(bt->ev_in);
   if (bt->ev_out) (void)hipEventDestroy(bt->ev_out);
+  for (int l = 0; l < kBatchLanes; ++l) {
+    if (bt->ls[l]) {
+      (void)hipStreamSynchronize(bt->ls[l]);
+      (void)hipStreamDestroy(bt->ls[l]);
+    }
+    if (bt->lev[l]) (void)hipEventDestroy(bt->lev[l]);
+  }
+  if (bt->ev_fork) (void)hipEventDestroy(bt->ev_fork);
   dev_free(ctx, bt->ws, bt->ws_bytes);
   dev_free(ctx, bt->d_alpha, sizeof(double2) * std::max<long long>(1, bt->total));
   dev_free(ctx, bt->d_iters, sizeof(int) * std::max(1, bt->nb));
@@ -297,6 +341,49 @@ int fthms_batch_create(fthms_ctx *ctx, int nb, const fthms_arc *const *arcs, con
       break;
     }
   }
+  // deal the buckets to lanes, largest LU work first to the least loaded
+  // lane; each lane's workspace holds its largest bucket.  One lane when the
+  // lanes' workspaces would not fit twice the single-lane cap.
+  if (rc == FTHMS_OK) {
+    const int nbk = (int)bt->buckets.size();
+    int L = std::min(kBatchLanes, nbk);
+    for (; L >= 1; --L) {
+      std::vector<double> work(L, 0.0);
+      std::vector<size_t> lneed(L, 0);
+      std::vector<int> order(nbk);
+      for (int i = 0; i < nbk; ++i) order[i] = i;
+      auto w_of = [&](int i) {
+        const double nn = bt->buckets[i].n;
+        return bt->buckets[i].count * nn * nn * nn;
+      };
+      std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return w_of(a) > w_of(b); });
+      bt->lane_of.assign(nbk, 0);
+      for (int i : order) {
+        const int l = (int)(std::min_element(work.begin(), work.end()) - work.begin());
+        bt->lane_of[i] = l;
+        work[l] += w_of(i);
+        lneed[l] = std::max(lneed[l], bucket_bytes(bt->buckets[i].n, bt->buckets[i].count, fp32));
+      }
+      size_t tot = 0;
+      bt->lane_off.assign(L, 0);
+      for (int l = 0; l < L; ++l) {
+        bt->lane_off[l] = tot;
+        tot += (lneed[l] + 255) & ~(size_t)255;
+      }
+      if (L == 1 || tot <= 2 * cap) {
+        bt->lanes = L;
+        need = tot;
+        break;
+      }
+    }
+    for (int l = 0; l < bt->lanes && bt->lanes > 1 && rc == FTHMS_OK; ++l)
+      if (hipStreamCreateWithFlags(&bt->ls[l], hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&bt->lev[l], hipEventDisableTiming) != hipSuccess)
+        rc = fail(ctx, FTHMS_EDEVICE, "stream/event creation failed");
+    if (rc == FTHMS_OK && bt->lanes > 1 &&
+        hipEventCreateWithFlags(&bt->ev_fork, hipEventDisableTiming) != hipSuccess)
+      rc = fail(ctx, FTHMS_EDEVICE, "event creation failed");
+  }
   if (rc == FTHMS_OK) rc = dev_alloc(ctx, &bt->ws, need);
   if (rc == FTHMS_OK) bt->ws_bytes = need;
   if (rc == FTHMS_OK)
@@ -398,8 +485,10 @@ int fthms_batch_tune(fthms_batch *bt, int reps) {
   const bool timing = ctx->timing;
   ctx->timing = false;
   int rc = FTHMS_OK;
-  for (auto &bk : bt->buckets) {
-    BucketWs w = bucket_ws(bt->ws, bk.n, bk.count, fp32);
+  for (size_t bi = 0; bi < bt->buckets.size(); ++bi) {
+    auto &bk = bt->buckets[bi];
+    BucketWs w = bucket_ws((char *)bt->ws + bt->lane_off[bt->lanes > 1 ? bt->lane_of[bi] : 0],
+                           bk.n, bk.count, fp32);
     std::vector<LuOpts> cand;
     for (int s = 0; s < 2; ++s)
       for (int r = 0; r < 2; ++r) {
@@ -408,6 +497,7 @@ int fthms_batch_tune(fthms_batch *bt, int reps) {
         o.reg_panel = r == 0;
         o.sym = fp32 && lu_sym_fits(true, bk.n);
         if (!o.split && bk.count < kLuSplitMin) continue;  // same launches as split
+        if (o.split && bt->lanes > 1) continue;  // lanes run their LUs on one stream each
         if (!o.reg_panel && bk.n > (fp32 ? 512 : 256)) continue;
         // the symmetric form always takes the register panel
         if (!o.reg_panel && lu_sym_fits(fp32, bk.n)) continue;

@@ -812,6 +812,9 @@ struct LuOpts {
   // checked against partial pivoting; lu.h), FP32 with N <= 512 only -- the
   // refined solve redoes a flagged matrix in FP64 from its FP64 copy
   bool sym = false;
+  // FP32 only: trailing-update products on the FP16 matrix cores (the
+  // low-precision factorisation of GMRES-IR)
+  bool h16 = false;
 };
 
 // The symmetric form applies: FP32 factors (an FP64 copy stays for the
@@ -925,11 +928,17 @@ static void lu_step(fthms_ctx *ctx, hipStream_t st, cplx_t<T> *A, int N, long lo
     if (tk) tbeg(ctx, "lu_strip", st);
     bool done = false;
     if constexpr (sizeof(T) == 4) {
-      if (sym) {
+      const bool h16 = o.h16 && !only_failed;
+      if (sym && h16)
+        lu_strip_kernel<T, true, true><<<(unsigned)blocks, kLuThreads, 0, st>>>(
+            A, N, ms, k0, swp, linv, count, nleft, nright, status, only_failed);
+      else if (sym)
         lu_strip_kernel<T, true><<<(unsigned)blocks, kLuThreads, 0, st>>>(
             A, N, ms, k0, swp, linv, count, nleft, nright, status, only_failed);
-        done = true;
-      }
+      else if (h16)
+        lu_strip_kernel<T, false, true><<<(unsigned)blocks, kLuThreads, 0, st>>>(
+            A, N, ms, k0, swp, linv, count, nleft, nright, status, only_failed);
+      done = sym || h16;
     }
     if (!done)
       lu_strip_kernel<T, false><<<(unsigned)blocks, kLuThreads, 0, st>>>(
@@ -1139,9 +1148,10 @@ static long long gmres_wstride(int N, int maxit) {
 static int gmres_launch(fthms_ctx *ctx, const double2 *A, long long mstride, int N, int nb,
                         const double2 *b, long long bstride, double2 *x, long long xstride,
                         int maxit, double tol, double2 *work, int *iters, double *relres) {
-  gmres_kernel<<<nb, kGmresThreads, 0, ctx->stream>>>(A, mstride, N, b, bstride, x, xstride,
-                                                       maxit, tol, work,
-                                                       gmres_wstride(N, maxit), iters, relres);
+  gmres_kernel<false><<<nb, kGmresThreads, 0, ctx->stream>>>(A, mstride, N, b, bstride, x,
+                                                              xstride, maxit, tol, work,
+                                                              gmres_wstride(N, maxit), iters,
+                                                              relres);
   return check_launch(ctx, "gmres_kernel");
 }
 
@@ -1192,6 +1202,87 @@ static int gmres_solve_impl(fthms_ctx *ctx, const fthms_arc *arc, int nk, const 
   return FTHMS_OK;
 }
 
+// GMRES-IR iterations per system at most (each applies the FP16-MFMA
+// factors once): well-conditioned arcs need a handful.
+constexpr int kGmresIrMaxIt = 30;
+
+// Assembly, FP16-MFMA LU (FP32 storage; symmetric form where it applies)
+// and FP64 GMRES right-preconditioned by it, for nk wavenumbers; systems whose
+// factors are unusable (status -2) or whose GMRES misses tol are solved by
+// the FP64 LU instead (iters -1).  iters: GMRES iterations.
+static int gmres_ir_impl(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double *k_dev,
+                         const double2 *rhs, double2 *alpha, double tol, int *iters_dev,
+                         double *relres_dev) {
+  const int N = arc->n;
+  const int maxit = std::min(N, kGmresIrMaxIt);
+  const long long ws = gmres_wstride(N, maxit);
+  const size_t nn = (size_t)N * N;
+  const size_t per = nn * (sizeof(double2) + sizeof(float2)) + sizeof(int) * N + kLuScratchBytes +
+                     sizeof(double2) * (size_t)ws + sizeof(int) + sizeof(double) + 2048;
+  size_t cap = kChunkBytes;
+  if (ctx->budget) {
+    const size_t avail = ctx->budget > ctx->held ? ctx->budget - ctx->held + ctx->ws_bytes : 0;
+    cap = std::min(cap, avail);
+  }
+  int chunk = (int)std::min<size_t>((size_t)nk, std::max<size_t>(1, cap / per));
+  chunk = std::min(chunk, 4096);
+  const int nchunks = (nk + chunk - 1) / chunk;
+  chunk = (nk + nchunks - 1) / nchunks;
+  if ((size_t)chunk * per > cap) return fail(ctx, FTHMS_ENOMEM, "no room for one matrix");
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return r;
+  };
+  const size_t oA = take(sizeof(double2) * nn * chunk), oA32 = take(sizeof(float2) * nn * chunk);
+  const size_t oP = take(sizeof(int) * (size_t)N * chunk), oS = take(kLuScratchBytes * chunk);
+  const size_t oW = take(sizeof(double2) * (size_t)ws * chunk);
+  const size_t oSt = take(sizeof(int) * chunk), oR = take(sizeof(double) * chunk);
+  int rc = ensure_ws(ctx, off);
+  if (rc) return rc;
+  char *base = (char *)ctx->ws;
+  double2 *A64 = (double2 *)(base + oA), *work = (double2 *)(base + oW);
+  float2 *A32 = (float2 *)(base + oA32);
+  int *piv = (int *)(base + oP), *status = (int *)(base + oSt);
+  void *swp = base + oS;
+  double *rr = (double *)(base + oR);
+  const long long ms = (long long)nn;
+  for (int f0 = 0; f0 < nk; f0 += chunk) {
+    const int c = std::min(chunk, nk - f0);
+    const double2 *b = rhs + (long long)f0 * N;
+    double2 *x = alpha + (long long)f0 * N;
+    tbeg(ctx, "assemble");
+    rc = assemble_launch(ctx, arc, k_dev + f0, c, A64, A32);
+    tend(ctx);
+    if (rc) return rc;
+    tbeg(ctx, "lu");
+    LuOpts lo;
+    lo.sym = arc_symmetric(arc) && lu_sym_fits(true, N);
+    lo.h16 = true;
+    rc = launch_lu(ctx, true, A32, N, ms, piv, swp, status, c, 0, lo);
+    tend(ctx);
+    if (rc) return rc;
+    tbeg(ctx, "gmres");
+    gmres_kernel<true><<<c, kGmresThreads, 0, ctx->stream>>>(
+        A64, ms, N, b, N, x, N, maxit, tol, work, ws, iters_dev ? iters_dev + f0 : status, rr,
+        A32, lu_perm(swp, c), status);
+    tend(ctx);
+    if ((rc = check_launch(ctx, "gmres_kernel (GMRES-IR)"))) return rc;
+    tbeg(ctx, "fallback");
+    rc = launch_fallback(ctx, A64, N, ms, piv, swp, b, x, status, c);
+    tend(ctx);
+    if (rc) return rc;
+    if (iters_dev)
+      HIPCK(ctx, hipMemcpyAsync(iters_dev + f0, status, sizeof(int) * c, hipMemcpyDeviceToDevice,
+                                ctx->stream));
+    if (relres_dev)
+      HIPCK(ctx, hipMemcpyAsync(relres_dev + f0, rr, sizeof(double) * c, hipMemcpyDeviceToDevice,
+                                ctx->stream));
+  }
+  return FTHMS_OK;
+}
+
 // Internal: solve for nk wavenumbers, device pointers, on ctx->stream.
 static int solve_dev_impl(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double *k_dev,
                           const double2 *rhs, double2 *alpha, int precision, double tol,
@@ -1201,6 +1292,8 @@ static int solve_dev_impl(fthms_ctx *ctx, const fthms_arc *arc, int nk, const do
   if (tol <= 0.0) tol = 1e-12;
   if (precision == FTHMS_GMRES)
     return gmres_solve_impl(ctx, arc, nk, k_dev, rhs, alpha, tol, iters_dev, relres_dev);
+  if (precision == FTHMS_FP16_GMRES_IR)
+    return gmres_ir_impl(ctx, arc, nk, k_dev, rhs, alpha, tol, iters_dev, relres_dev);
   SolveWs w;
   int rc = solve_ws(ctx, N, fp32, nk, w);
   if (rc) return rc;
@@ -1284,7 +1377,8 @@ int fthms_solve_dev(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double *
                     double tol, int *iters_dev, double *relres_dev) {
   if (!ctx || !arc || !k_dev || !rhs_dev || !alpha_dev || nk < 0)
     return fail(ctx, FTHMS_EINVAL, "bad argument to fthms_solve_dev");
-  if (precision != FTHMS_FP64 && precision != FTHMS_FP32_REFINED && precision != FTHMS_GMRES)
+  if (precision != FTHMS_FP64 && precision != FTHMS_FP32_REFINED && precision != FTHMS_GMRES &&
+      precision != FTHMS_FP16_GMRES_IR)
     return fail(ctx, FTHMS_EINVAL, "unknown precision");
   if (nk == 0) return FTHMS_OK;
   HIPCK(ctx, hipSetDevice(ctx->device));

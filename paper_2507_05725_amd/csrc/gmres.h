@@ -45,11 +45,22 @@ __device__ __forceinline__ double2 gm_block_sum(double2 v, double2 *red) {
 
 // work: per system (maxit + 1) N double2 for the basis, then maxit (maxit + 1)
 // double2 for the triangular factor (column j holds R[0..j][j]).
+//
+// PREC: GMRES-IR -- right preconditioning by low-precision LU factors
+// (LUbase / permbase, FP32 storage, as lu.h writes them): GMRES on
+// A M^{-1} u = b with M = L U, x = M^{-1} u; every iteration applies the
+// factors' triangular solves (FP64 accumulation) to the basis vector before
+// the FP64 product with A, and the residual estimate is that of the original
+// system.  status[sys] < 0 on entry (factors not usable) leaves the system
+// alone; on exit it holds the iterations taken, or -1 when tol was not
+// reached (the caller then solves that system in FP64).
+template <bool PREC>
 __global__ __launch_bounds__(kGmresThreads) void gmres_kernel(
     const double2 *__restrict__ Abase, long long mstride, int N, const double2 *__restrict__ bbase,
     long long bstride, double2 *__restrict__ xbase, long long xstride, int maxit, double tol,
     double2 *__restrict__ work, long long wstride, int *__restrict__ iters,
-    double *__restrict__ relres) {
+    double *__restrict__ relres, const float2 *__restrict__ LUbase = nullptr,
+    const int *__restrict__ permbase = nullptr, int *__restrict__ status = nullptr) {
   __shared__ double2 sv[1024];
   __shared__ double2 red[kGmresThreads / 64];
   __shared__ double2 col[kGmresMaxIt + 1];
@@ -58,6 +69,7 @@ __global__ __launch_bounds__(kGmresThreads) void gmres_kernel(
   __shared__ double cs[kGmresMaxIt];
   __shared__ int done;
   const int sys = blockIdx.x, tid = threadIdx.x;
+  if (PREC && status[sys] < 0) return;
   const double2 *A = Abase + (long long)sys * mstride;
   const double2 *b = bbase + (long long)sys * bstride;
   double2 *x = xbase + (long long)sys * xstride;
@@ -86,6 +98,7 @@ __global__ __launch_bounds__(kGmresThreads) void gmres_kernel(
     if (tid == 0) {
       iters[sys] = 0;
       relres[sys] = 0.0;
+      if (PREC) status[sys] = 0;
     }
     return;
   }
@@ -106,6 +119,10 @@ __global__ __launch_bounds__(kGmresThreads) void gmres_kernel(
     __syncthreads();
     for (int i = tid; i < N; i += kGmresThreads) sv[i] = V[(long long)j * N + i];
     __syncthreads();
+    // z_j = M^{-1} v_j in place (its own barriers)
+    if constexpr (PREC)
+      lu_solve_lds<float>(LUbase + (long long)sys * mstride, permbase + (long long)sys * kMaxN, sv,
+                          N);
     // w = A v_j, four columns per batch with all their loads in flight.
     // Rows are clamped into the matrix rather than tested (a load under a
     // divergent test is waited for before the next one is issued); the
@@ -244,7 +261,16 @@ __global__ __launch_bounds__(kGmresThreads) void gmres_kernel(
       acc.x += v.x * y.x - v.y * y.y;
       acc.y += v.x * y.y + v.y * y.x;
     }
-    x[i] = acc;
+    if (PREC) sv[i] = acc;
+    else x[i] = acc;
+  }
+  if constexpr (PREC) {
+    // x = M^{-1} V y
+    __syncthreads();
+    lu_solve_lds<float>(LUbase + (long long)sys * mstride, permbase + (long long)sys * kMaxN, sv,
+                        N);
+    for (int i = tid; i < N; i += kGmresThreads) x[i] = sv[i];
+    if (tid == 0) status[sys] = relres[sys] <= tol ? k : -1;
   }
 }
 

@@ -528,7 +528,12 @@ constexpr int kStripW = 64;
 // form (unit lower L, upper U, identity permutation) for the solves; the
 // part of the matrix strictly above the diagonal blocks is otherwise never
 // read again and is left stale.
-template <typename T, bool SYM = false>
+//
+// H16 (T = float): the trailing update's products on the FP16 matrix cores
+// (16x16x16 f16 MFMA, FP32 accumulation): L21 and U12 rounded to FP16 as
+// they enter the products, the factors kept in FP32 -- the low-precision
+// factorisation of GMRES-IR, whose FP64 GMRES recovers the accuracy.
+template <typename T, bool SYM = false, bool H16 = false>
 __global__ __launch_bounds__(kLuThreads, sizeof(T) == 8 ? 2 : 3)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3, sizeof(T) == 8 ? 2 : 3))) void lu_strip_kernel(
     cplx_t<T> *Abase, int N, long long mstride, int k0, const int *swapbase,
@@ -705,9 +710,14 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3, sizeof(T) == 8 ? 2 : 
     // own fragment only.  The scheduling barrier keeps the compiler from
     // sinking the loads towards their uses.
     const int arow = min(rw + li, N - 1) + k0 * N;
+    // fragment st: column 4 st + lk of the block (FP32/FP64 steps of k = 4);
+    // with H16, steps of k = 16: fa[4 s + e] is column 16 s + 4 lk + e
     T2 fa[kLuNB / 4];
 #pragma unroll
-    for (int st = 0; st < kLuNB / 4; ++st) fa[st] = A[arow + min(4 * st + lk, nb - 1) * N];
+    for (int st = 0; st < kLuNB / 4; ++st) {
+      const int kc = H16 ? 16 * (st >> 2) + 4 * lk + (st & 3) : 4 * st + lk;
+      fa[st] = A[arow + min(kc, nb - 1) * N];
+    }
     const int ccl = c0 + min(li, cw - 1);  // clamped column of cb = 0
     T cx[4][4], cy[4][4];
 #pragma unroll
@@ -730,6 +740,37 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3, sizeof(T) == 8 ? 2 : 
         cr[cb][r] = 0;
         ci[cb][r] = 0;
       }
+    if constexpr (H16) {
+      // four steps of k = 16: lane (li, lk) holds k = 16 s + 4 lk + e of
+      // row li (A) and of column li (B), e = 0..3
+      typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+      for (int s4 = 0; s4 < kLuNB / 16; ++s4) {
+        h4 ar, ai, pai;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const T2 f = fa[4 * s4 + e];
+          ar[e] = (_Float16)(-f.x);
+          ai[e] = (_Float16)(-f.y);
+          pai[e] = (_Float16)f.y;
+        }
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          h4 br, bi;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const T2 bv = sX[16 * s4 + 4 * lk + e][cb * 16 + li];
+            br[e] = (_Float16)bv.x;
+            bi[e] = (_Float16)bv.y;
+          }
+          // C - A B:  re += (-Ar) Br + Ai Bi ;  im += (-Ar) Bi + (-Ai) Br
+          cr[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(ar, br, cr[cb], 0, 0, 0);
+          ci[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(ar, bi, ci[cb], 0, 0, 0);
+          cr[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(pai, bi, cr[cb], 0, 0, 0);
+          ci[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(ai, br, ci[cb], 0, 0, 0);
+        }
+      }
+    } else {
 #pragma unroll
     // all 16 steps (zero fragments and rows beyond a partial block)
     for (int st = 0; st < kLuNB / 4; ++st) {
@@ -753,6 +794,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3, sizeof(T) == 8 ? 2 : 
         cr[cb] = Mma<T>::run(pai, bi[cb], cr[cb]);
         ci[cb] = Mma<T>::run(ai, br[cb], ci[cb]);
       }
+    }
     }
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) {
