@@ -116,6 +116,91 @@ def field(k, z, nd, psi, eta=None):
     return (math.pi / n) * (kern @ psi)
 
 
+def trig_interp(psi, tau):
+    """The trigonometric interpolant of the 2n node values psi at parameters
+    tau: sum_{|m| < n} c_m e^{i m tau} + c_n cos(n tau), c_m from the DFT of
+    the samples (the unique interpolant of that degree, Nyquist term split
+    evenly between +n and -n)."""
+    psi = np.asarray(psi, dtype=complex)
+    n2 = psi.size
+    n = n2 // 2
+    c = np.fft.fft(psi) / n2            # c[m] for m = 0..n2-1 (negative m wrapped)
+    tau = np.atleast_1d(np.asarray(tau, dtype=float))
+    m = np.arange(-n + 1, n)
+    cm = c[m % n2]
+    out = np.exp(1j * np.outer(tau, m)) @ cm
+    return out + c[n] * np.cos(n * tau)
+
+
+def closest_param(curve, z, tau0, h):
+    """Parameter of the point of the curve closest to z near tau0: the best
+    of 129 samples on [tau0 - h, tau0 + h], then golden-section search."""
+    dist = lambda t: float(np.hypot(*(curve.x(np.array([t]))[0] - z)))
+    ts = tau0 + h * np.linspace(-1.0, 1.0, 129)
+    xs = curve.x(ts)
+    i = int(np.argmin(np.hypot(xs[:, 0] - z[0], xs[:, 1] - z[1])))
+    a, b = ts[max(i - 1, 0)], ts[min(i + 1, ts.size - 1)]
+    g = 0.5 * (math.sqrt(5.0) - 1.0)
+    for _ in range(60):
+        c, d = b - g * (b - a), a + g * (b - a)
+        if dist(c) < dist(d):
+            b = d
+        else:
+            a = c
+    return 0.5 * (a + b)
+
+
+def field_near(k, z, curve, nd, psi, eta=None, order=24):
+    """(D - i eta S)[Psi] at targets z [P, 2] at any distance off the curve:
+    the integral over one period of the curve x(tau) itself of the kernel
+    against the trigonometric interpolant of the node densities, by
+    composite Gauss-Legendre quadrature (``order`` points a panel) on panels
+    graded geometrically toward the parameter t* of the curve's closest
+    point: [t* - delta, t* + delta], then [t* + 2^m delta, t* + 2^(m+1) delta]
+    and their mirrors, delta = d / (2 |x'(t*)|), d the distance -- every
+    panel as long as its distance to t*, so the kernel's near-singularity at
+    distance d stays outside each panel's region of analyticity -- and, once
+    they reach the node spacing h = 2 pi / N, panels of length h up to half a
+    period each side (delta itself at most h / 2)."""
+    if eta is None:
+        eta = eta_of(k)
+    z = np.atleast_2d(np.asarray(z, dtype=float))
+    psi = np.asarray(psi, dtype=complex)
+    n2 = psi.size
+    n = n2 // 2
+    c = np.fft.fft(psi) / n2
+    m = np.arange(-n + 1, n)
+    cm = c[m % n2]
+    gx, gw = np.polynomial.legendre.leggauss(order)
+    h = 2.0 * math.pi / n2
+    out = np.zeros(z.shape[0], dtype=complex)
+    for p in range(z.shape[0]):
+        zz = z[p]
+        j = int(np.argmin(np.hypot(nd["y"][:, 0] - zz[0], nd["y"][:, 1] - zz[1])))
+        ts = closest_param(curve, zz, nd["tau"][j], h)
+        d = float(np.hypot(*(curve.x(np.array([ts]))[0] - zz)))
+        delta = min(max(0.5 * d / float(np.hypot(*curve.dx(np.array([ts]))[0])), 1e-12), 0.5 * h)
+        edges = [delta]
+        while edges[-1] < math.pi:
+            # doubling, but no panel longer than the node spacing (the
+            # interpolant oscillates at up to n / 2 periods a period)
+            edges.append(min(2.0 * edges[-1], edges[-1] + h, math.pi))
+        brk = np.concatenate([-np.array(edges[::-1]), np.array(edges)])
+        lo, hi = brk[:-1], brk[1:]
+        t = ts + (0.5 * (hi - lo)[:, None] * gx[None, :] + 0.5 * (hi + lo)[:, None]).ravel()
+        w = (0.5 * (hi - lo)[:, None] * gw[None, :]).ravel()
+        x, dx = curve.x(t), curve.dx(t)
+        e1, e2 = zz[0] - x[:, 0], zz[1] - x[:, 1]
+        r = np.hypot(e1, e2)
+        q = dx[:, 1] * e1 - dx[:, 0] * e2
+        sp = np.hypot(dx[:, 0], dx[:, 1])
+        kern = (0.25j * k * special.hankel1(1, k * r) * q / r
+                + 0.25 * eta * sp * special.hankel1(0, k * r))
+        dens = np.exp(1j * np.outer(t, m)) @ cm + c[n] * np.cos(n * t)
+        out[p] = np.sum(w * kern * dens)
+    return out
+
+
 def near_limit(nd, factor=5.0):
     """Targets closer than this to a node are outside the trapezoid rule's
     accuracy (error ~ exp(-2 pi d / h))."""

@@ -27,6 +27,10 @@ Readings taken where the text is silent or loose:
   * A closed curve may also be one patch of its own (Section 3.3): its
     density solves the combined-field equation and its field is
     (D - i eta S) Psi (``oracle.closed``); chi = 1 and nothing is masked.
+    Targets of that field closer than five node spacings (another patch's
+    nodes) take the adaptive integral over the curve of the density's
+    trigonometric interpolant, the trapezoid rule's accuracy being lost
+    there.
   * Discretisation: ``problem.scheme`` "cheb" is the single-panel
     weighted-Chebyshev scheme (``oracle.nystrom``); "panels" cuts each arc
     at the ends of its truncated overlap into three panels, each with the
@@ -139,7 +143,17 @@ class Layout:
     def field(self, j, k, z, alpha):
         """Potential of arc j's density at targets z."""
         if self.closed[j]:
-            return cl.field(k, z, self.nodes[j], alpha)
+            # the trapezoid rule where it is accurate (five node spacings and
+            # more from every node), the adaptive integral over the curve nearer
+            nd = self.nodes[j]
+            z = np.atleast_2d(np.asarray(z, dtype=float))
+            out = cl.field(k, z, nd, alpha)
+            d = np.min(np.hypot(z[:, None, 0] - nd["y"][None, :, 0],
+                                z[:, None, 1] - nd["y"][None, :, 1]), axis=1)
+            near = d < cl.near_limit(nd)
+            if np.any(near):
+                out[near] = cl.field_near(k, z[near], self.arcs[j], nd, alpha)
+            return out
         if self.scheme == "panels":
             return pn.field(k, z, self.nodes[j], alpha)
         return ny.field(k, z, self.arcs[j], self.nodes[j], alpha)

@@ -87,3 +87,116 @@ def test_closed_patch_must_be_alone_on_its_curve():
                    obs=np.zeros((1, 2)), times=np.zeros(0))
     with pytest.raises(ValueError):
         ms.Layout(pb)
+
+
+def test_trig_interp_reproduces_trigonometric_polynomials():
+    """The interpolant of 2n samples of a trigonometric polynomial of degree
+    below n is that polynomial at every parameter, and equals the samples at
+    the nodes for any data (degree n included: cos(n tau) is its own
+    Nyquist term)."""
+    n2 = 20
+    tau = 2.0 * math.pi * np.arange(n2) / n2
+    t = np.array([0.1, 1.234, 3.0, 5.9, -2.2])
+    f = lambda s: (0.3 + 1.2j * np.cos(3 * s) - 0.7 * np.sin(9 * s) + (0.25 - 0.5j) * np.exp(4j * s))
+    assert np.max(np.abs(cl.trig_interp(f(tau), t) - f(t))) < 1e-13
+    rng = np.random.default_rng(5)
+    g = rng.standard_normal(n2) + 1j * rng.standard_normal(n2)
+    assert np.max(np.abs(cl.trig_interp(g, tau) - g)) < 1e-13
+    assert np.max(np.abs(cl.trig_interp(np.cos(10 * tau), t) - np.cos(10 * t))) < 1e-13
+
+
+def test_closest_param_on_an_ellipse():
+    """Axis-aligned ellipse at the origin: the closest point to a target on
+    the major axis beyond the tip is the tip (tau = 0), to one on the minor
+    axis the co-vertex (tau = pi / 2)."""
+    E = ClosedEllipse(1.0, 0.6)
+    h = 2.0 * math.pi / 32
+    assert abs(cl.closest_param(E, np.array([1.3, 0.0]), 0.05, h)) < 1e-8
+    assert abs(cl.closest_param(E, np.array([0.0, 0.9]), math.pi / 2 - 0.04, h) - math.pi / 2) < 1e-8
+
+
+def _exterior_points(curve, tt, dist):
+    """Points at distance `dist` along the outward normal (x2', -x1') of
+    the curve (counter-clockwise) at parameters tt."""
+    y, dy = curve.x(tt), curve.dx(tt)
+    nrm = np.stack([dy[:, 1], -dy[:, 0]], -1) / np.hypot(dy[:, 0], dy[:, 1])[:, None]
+    return y + dist * nrm
+
+
+@pytest.mark.parametrize("curve,n2", [(ClosedKite(1.0), 256),
+                                      (ClosedEllipse(1.0, 0.6, (0.2, -0.1), 0.3), 128)],
+                         ids=["kite256", "ellipse128"])
+@pytest.mark.parametrize("k", [2.0, 7.5])
+def test_field_near_exact_exterior(curve, n2, k):
+    """Point source inside, resolved density: the near-target integral
+    reaches the exact exterior field -Phi(x, z0) from 6 node spacings down
+    to a hundredth of one, where the trapezoid rule is wrong in the first
+    digit."""
+    z0 = (0.05, 0.1)
+
+    def ui(p):
+        return 0.25j * hankel1(0, k * np.hypot(p[:, 0] - z0[0], p[:, 1] - z0[1]))
+
+    nd = cl.nodes(curve, n2)
+    psi = np.linalg.solve(cl.assemble(nd, k), -ui(nd["y"]))
+    h = cl.near_limit(nd) / 5.0
+    tt = np.array([0.31, 1.7, 2.95, 4.4, 5.9])
+    for f in (0.01, 0.1, 0.5, 2.0, 6.0):
+        z = _exterior_points(curve, tt, f * h)
+        U = cl.field_near(k, z, curve, nd, psi)
+        assert np.max(np.abs(U + ui(z)) / np.abs(ui(z))) < 1e-12, f
+    z = _exterior_points(curve, tt, 0.01 * h)
+    assert np.max(np.abs(cl.field(k, z, nd, psi) + ui(z)) / np.abs(ui(z))) > 0.1
+
+
+def test_field_near_equals_fine_trapezoid():
+    """For a density of low degree (12), given at 96 nodes, the integral of
+    the interpolant is the same integral that the trapezoid rule on 384
+    nodes (the same trigonometric polynomial sampled there) takes, to
+    rounding at eight and sixteen node spacings off the curve; the 96-node
+    rule itself is 1e-10 away (the kite's speed |x'| is not a trigonometric
+    polynomial)."""
+    curve = ClosedKite(1.0)
+    nd, nf = cl.nodes(curve, 96), cl.nodes(curve, 384)
+    rng = np.random.default_rng(9)
+    m = np.arange(-12, 13)
+    cm = (rng.standard_normal(m.size) + 1j * rng.standard_normal(m.size)) / (1.0 + np.abs(m))
+    psi, psif = (np.exp(1j * np.outer(x["tau"], m)) @ cm for x in (nd, nf))
+    for f in (8.0, 16.0):
+        z = _exterior_points(curve, np.array([0.4, 2.0, 3.3, 5.0]), f * cl.near_limit(nd) / 5.0)
+        a, b = cl.field_near(4.0, z, curve, nd, psi), cl.field(4.0, z, nf, psif)
+        assert np.max(np.abs(a - b)) < 1e-14 * np.max(np.abs(b))
+
+
+def test_ms_near_closed_patches_exact():
+    """Two obstacles 0.24 apart (under five node spacings at 64 nodes each),
+    point source inside the first, k = 5 + 3i: the MS sum reaches -U^i at
+    far points and at points in the gap, whose fields (and the cross fields
+    at the nodes facing the other obstacle) need the near-target integral;
+    with the trapezoid rule alone the nearest gap point is off by more than
+    1e-5."""
+    E = ClosedEllipse(0.8, 0.5, (-1.0, 0.0))
+    K = ClosedKite(0.5, (0.62, 0.2))
+    t = np.linspace(0.0, 2.0 * math.pi, 2001)
+    xe, xk = E.x(t), K.x(t)
+    D = np.hypot(xe[:, None, 0] - xk[None, :, 0], xe[:, None, 1] - xk[None, :, 1])
+    i, j = np.unravel_index(np.argmin(D), D.shape)
+    gap = np.array([xe[i] + f * (xk[j] - xe[i]) for f in (0.3, 0.5, 0.7)])
+    far = np.stack([2.8 * np.cos(np.linspace(0, 6, 4)), 2.8 * np.sin(np.linspace(0, 6, 4))], -1)
+    obs = np.concatenate([far, gap])
+    k = 5.0 + 3.0j
+    arcs = [ArcSpec(E, 64, group=0), ArcSpec(K, 64, group=1)]
+    pb = MSProblem(arcs=arcs, incident=IncidentSpec("point", z0=(-1.1, 0.1), sigma=0.0),
+                   omegas=np.array([k]), M=20, obs=obs, times=np.zeros(0))
+    lay = ms.Layout(pb)
+    assert D.min() < cl.near_limit(lay.nodes[0])
+    ui = oinc.incident(pb.incident, k, obs)
+    err = np.abs(ms.run_frequency(lay, k)["U"] + ui) / np.max(np.abs(ui))
+    assert np.max(err[:4]) < 1e-12 and np.max(err[4:]) < 5e-9, err
+    orig = cl.near_limit
+    try:
+        cl.near_limit = lambda nd, factor=5.0: 0.0
+        err0 = np.abs(ms.run_frequency(ms.Layout(pb), k)["U"] + ui) / np.max(np.abs(ui))
+    finally:
+        cl.near_limit = orig
+    assert err0[4] > 1e-5
