@@ -294,8 +294,12 @@ int fthms_problem_traces_windowed_real(fthms_problem *pb, const fthms_hf_grid *g
  * xy, dxy, ddxy [n][2] = x, x', x''.  Densities are per unit length at the
  * nodes.  Such an arc works in fthms_solve, fthms_rhs, fthms_eval_field and
  * problems (where it must be alone in its group: chi = 1, nothing masked);
- * fields are the trapezoid rule and refuse targets closer than 5 node
- * spacings (FTHMS_EINVAL_DATA).  Not for batches. */
+ * fields are the trapezoid rule at targets 5 node spacings h (the largest)
+ * or more from the nodes; nearer targets take the same rule on a grid kappa
+ * = 2, 4, .., 128 times finer (the smallest with h / kappa <= d / 5.2, d
+ * the target's distance to the curve), with the density's and the
+ * geometry's trigonometric interpolants there; targets nearer than h / 25
+ * are refused (FTHMS_EINVAL_DATA).  Not for batches. */
 int fthms_closed_create(fthms_ctx *ctx, int n, const double *xy, const double *dxy,
                         const double *ddxy, fthms_arc **out);
 

@@ -338,6 +338,8 @@ __global__ __launch_bounds__(256) void freq_to_time_sum_kernel(int nsplit, long 
 // Device copy of a near-target quadrature plan (built on the host by
 // plan_near): per point class, near target list, quadrature offsets, points,
 // weights and cos(phi) values.
+constexpr int kClosedLevels = 7;  // upsampling factors 2, 4, ..., 128
+
 struct NearPlan {
   int np = 0, ntgt = 0, nq = 0;
   unsigned char *d_cls = nullptr;
@@ -347,6 +349,14 @@ struct NearPlan {
   double *d_wq = nullptr;
   double *d_cq = nullptr;
   int *d_pq = nullptr;  // panel of each point (composite-panel arcs)
+  // closed patches: near targets by the trapezoid rule on an upsampled grid,
+  // one level per factor kappa = 2^(l+1) in use; the level's targets are
+  // d_tgt[lev_first[l] .. lev_first[l + 1]); its fine geometry (kappa n
+  // points) and periodic interpolation kernel (kappa n values)
+  int np_nodes = 0;
+  int lev_kappa[kClosedLevels] = {}, lev_first[kClosedLevels + 1] = {};
+  double2 *d_yf[kClosedLevels] = {}, *d_dyf[kClosedLevels] = {};
+  double *d_Tf[kClosedLevels] = {};
 };
 
 }  // namespace fthms

@@ -1534,7 +1534,29 @@ int field_dev_impl(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double *k
     closed_field_kernel<<<gf, kFieldThreads, 0, ctx->stream>>>(
         arc->d_y, arc->d_dy, arc->n, k_dev, alpha, astride, pts_dev, np, plan.d_cls, U, ustride,
         accumulate, split);
-    return check_launch(ctx, "closed_field_kernel");
+    int rc = check_launch(ctx, "closed_field_kernel");
+    if (rc || plan.ntgt == 0) return rc;
+    // near targets, level by level: density upsampled into ws2 (wavenumbers
+    // in chunks that keep it within 64 MB), then the fine trapezoid rule
+    for (int l = 0; l < kClosedLevels; ++l) {
+      const int t0 = plan.lev_first[l], ntg = plan.lev_first[l + 1] - t0;
+      if (ntg == 0) continue;
+      const int M = plan.lev_kappa[l] * arc->n;
+      const int chunk = std::max(1, std::min(nk, (int)((64ll << 20) / (sizeof(double2) * M))));
+      if ((rc = ensure_ws2(ctx, sizeof(double2) * (size_t)chunk * M))) return rc;
+      double2 *psif = (double2 *)ctx->ws2;
+      for (int b0 = 0; b0 < nk; b0 += chunk) {
+        const int c = std::min(chunk, nk - b0);
+        closed_upsample_kernel<<<dim3((M + 255) / 256, c), 256, 0, ctx->stream>>>(
+            alpha + (long long)b0 * astride, astride, arc->n, plan.lev_kappa[l], plan.d_Tf[l], psif);
+        if ((rc = check_launch(ctx, "closed_upsample_kernel"))) return rc;
+        closed_near_kernel<<<dim3(ntg, c), 256, 0, ctx->stream>>>(
+            plan.d_yf[l], plan.d_dyf[l], M, k_dev + b0, psif, plan.d_tgt + t0, pts_dev,
+            U + (long long)b0 * ustride, ustride, accumulate);
+        if ((rc = check_launch(ctx, "closed_near_kernel"))) return rc;
+      }
+    }
+    return FTHMS_OK;
   }
   field_far_kernel<<<gf, kFieldThreads, 0, ctx->stream>>>(arc->d_y, arc->n, arc->d_w, k_dev,
                                                          alpha, astride, pts_dev, np, plan.d_cls,

@@ -110,26 +110,140 @@ void near_plan_free(fthms_ctx *ctx, NearPlan &p) {
   dev_free(ctx, p.d_wq, sizeof(double) * p.nq);
   dev_free(ctx, p.d_cq, sizeof(double) * p.nq);
   dev_free(ctx, p.d_pq, sizeof(int) * p.nq);
+  for (int l = 0; l < kClosedLevels; ++l) {
+    const size_t M = (size_t)p.lev_kappa[l] * p.np_nodes;
+    dev_free(ctx, p.d_yf[l], sizeof(double2) * M);
+    dev_free(ctx, p.d_dyf[l], sizeof(double2) * M);
+    dev_free(ctx, p.d_Tf[l], sizeof(double) * M);
+  }
   p = NearPlan();
+}
+
+// The periodic interpolation kernel of N (even) equispaced samples:
+// T(t) = (1/N) sin(N t / 2) cot(t / 2), T(0) = 1.
+static double closed_interp_kernel(double t, int N) {
+  const double s = std::sin(0.5 * t);
+  if (std::fabs(s) < 1e-15) return 1.0;
+  return std::sin(0.5 * N * t) * std::cos(0.5 * t) / (s * N);
+}
+
+// Near targets of a closed patch: the distance of each target to the
+// curve's trigonometric interpolant (sampled around the nearest node, then
+// a golden-section refinement), its upsampling level (the smallest
+// kappa = 2, 4, ..., 128 with h / kappa <= d / 5.2, h the largest node
+// spacing), and per level in use the fine geometry and interpolation kernel.
+static int closed_near_plan(fthms_ctx *ctx, const fthms_arc *arc, int np, const double *xy,
+                            const unsigned char *skip, NearPlanHost &h, NearPlan &plan) {
+  const int N = arc->n;
+  const double hs = arc->hmax, dtau = 2.0 * kPi / N;
+  auto point = [&](double t, double &x, double &y) {
+    x = y = 0.0;
+    for (int j = 0; j < N; ++j) {
+      const double w = closed_interp_kernel(t - dtau * j, N);
+      x += w * arc->xy[2 * j];
+      y += w * arc->xy[2 * j + 1];
+    }
+  };
+  h.cls.assign(np, 0);
+  h.qoff.assign(1, 0);
+  std::vector<std::vector<int>> lev(kClosedLevels);
+  for (int p = 0; p < np; ++p) {
+    if (skip && skip[p]) continue;
+    const double zx = xy[2 * p], zy = xy[2 * p + 1];
+    double dmin = 1e300;
+    int jn = 0;
+    for (int j = 0; j < N; ++j) {
+      const double d = std::hypot(zx - arc->xy[2 * j], zy - arc->xy[2 * j + 1]);
+      if (d < dmin) {
+        dmin = d;
+        jn = j;
+      }
+    }
+    if (dmin >= 5.0 * hs) {
+      h.cls[p] = 1;
+      continue;
+    }
+    auto dist = [&](double t) {
+      double x, y;
+      point(t, x, y);
+      return std::hypot(zx - x, zy - y);
+    };
+    // the curve's nearest point lies within a node spacing of the nearest
+    // node: sample, then golden-section search around the best sample
+    double best = dmin, tb = dtau * jn;
+    for (int i = -32; i <= 32; ++i) {
+      const double t = dtau * (jn + i / 16.0), d = dist(t);
+      if (d < best) {
+        best = d;
+        tb = t;
+      }
+    }
+    double a = tb - dtau / 16.0, b = tb + dtau / 16.0;
+    const double g = 0.5 * (std::sqrt(5.0) - 1.0);
+    for (int it = 0; it < 40; ++it) {
+      const double c = b - g * (b - a), d = a + g * (b - a);
+      if (dist(c) < dist(d)) b = d;
+      else a = c;
+    }
+    const double dc = std::min(best, dist(0.5 * (a + b)));
+    int l = 0;
+    while (l < kClosedLevels && hs / (double)(2 << l) > dc / 5.2) ++l;
+    if (l == kClosedLevels)
+      return fail(ctx, FTHMS_EINVAL_DATA,
+                  "target closer than h/25 to a closed patch (h its largest node spacing)");
+    h.cls[p] = 2;
+    lev[l].push_back(p);
+  }
+  for (int l = 0; l < kClosedLevels; ++l) {
+    plan.lev_first[l] = (int)h.tgt.size();
+    for (int p : lev[l]) h.tgt.push_back(p);
+  }
+  plan.lev_first[kClosedLevels] = (int)h.tgt.size();
+  plan.np_nodes = N;
+  for (int l = 0; l < kClosedLevels; ++l) {
+    if (lev[l].empty()) continue;
+    const int kappa = 2 << l, M = kappa * N;
+    std::vector<double2> yf(M), dyf(M);
+    std::vector<double> T(M);
+    for (int q = 0; q < M; ++q) T[q] = closed_interp_kernel(2.0 * kPi * q / M, N);
+    for (int q = 0; q < M; ++q) {
+      double x = 0.0, y = 0.0, dx = 0.0, dy = 0.0;
+      for (int j = 0; j < N; ++j) {
+        int d = q - kappa * j;
+        d %= M;
+        if (d < 0) d += M;
+        const double w = T[d];
+        x += w * arc->xy[2 * j];
+        y += w * arc->xy[2 * j + 1];
+        dx += w * arc->dxy[2 * j];
+        dy += w * arc->dxy[2 * j + 1];
+      }
+      yf[q] = make_double2(x, y);
+      dyf[q] = make_double2(dx, dy);
+    }
+    int rc;
+    plan.lev_kappa[l] = kappa;  // before the allocations: near_plan_free sizes by it
+    if ((rc = dev_alloc(ctx, (void **)&plan.d_yf[l], sizeof(double2) * M)) ||
+        (rc = dev_alloc(ctx, (void **)&plan.d_dyf[l], sizeof(double2) * M)) ||
+        (rc = dev_alloc(ctx, (void **)&plan.d_Tf[l], sizeof(double) * M)))
+      return rc;
+    HIPCK(ctx, hipMemcpy(plan.d_yf[l], yf.data(), sizeof(double2) * M, hipMemcpyHostToDevice));
+    HIPCK(ctx, hipMemcpy(plan.d_dyf[l], dyf.data(), sizeof(double2) * M, hipMemcpyHostToDevice));
+    HIPCK(ctx, hipMemcpy(plan.d_Tf[l], T.data(), sizeof(double) * M, hipMemcpyHostToDevice));
+  }
+  return FTHMS_OK;
 }
 
 int near_plan_build(fthms_ctx *ctx, const fthms_arc *arc, int np, const double *xy,
                     NearPlan &plan, const unsigned char *skip, double kmax) {
   NearPlanHost h;
   if (arc->closed) {
-    // trapezoid rule only: every target must lie a few node spacings away
-    h.cls.assign(np, 0);
-    h.qoff.assign(1, 0);
-    const double rad = 5.0 * arc->hmax;
-    for (int p = 0; p < np; ++p) {
-      if (skip && skip[p]) continue;
-      double dmin = 1e300;
-      for (int j = 0; j < arc->n; ++j)
-        dmin = std::min(dmin, std::hypot(xy[2 * p] - arc->xy[2 * j], xy[2 * p + 1] - arc->xy[2 * j + 1]));
-      if (!(dmin >= rad))
-        return fail(ctx, FTHMS_EINVAL_DATA,
-                    "target closer than 5 node spacings to a closed patch (trapezoid rule only)");
-      h.cls[p] = 1;
+    // far targets (five node spacings away and more): the trapezoid rule;
+    // nearer ones: the same rule on an upsampled grid
+    int rc = closed_near_plan(ctx, arc, np, xy, skip, h, plan);
+    if (rc) {
+      near_plan_free(ctx, plan);
+      return rc;
     }
   } else if (arc->d_w) {
     std::vector<double> smax(arc->npan, 0.0);
@@ -149,7 +263,10 @@ int near_plan_build(fthms_ctx *ctx, const fthms_arc *arc, int np, const double *
   int rc;
   if ((rc = dev_alloc(ctx, (void **)&plan.d_cls, (size_t)std::max(np, 1)))) return rc;
   HIPCK(ctx, hipMemcpy(plan.d_cls, h.cls.data(), (size_t)np, hipMemcpyHostToDevice));
-  if (plan.ntgt > 0) {
+  if (plan.ntgt > 0 && arc->closed) {
+    if ((rc = dev_alloc(ctx, (void **)&plan.d_tgt, sizeof(int) * plan.ntgt))) return rc;
+    HIPCK(ctx, hipMemcpy(plan.d_tgt, h.tgt.data(), sizeof(int) * plan.ntgt, hipMemcpyHostToDevice));
+  } else if (plan.ntgt > 0) {
     if ((rc = dev_alloc(ctx, (void **)&plan.d_tgt, sizeof(int) * plan.ntgt)) ||
         (rc = dev_alloc(ctx, (void **)&plan.d_qoff, sizeof(int) * (plan.ntgt + 1))) ||
         (rc = dev_alloc(ctx, (void **)&plan.d_xq, sizeof(double2) * plan.nq)) ||
@@ -444,6 +561,19 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
   // every step instead of evaluating the fields again.
   bool use_ops = J > 1 && nsum <= kCrossMaxS;
   for (int j = 0; j < J; ++j) use_ops = use_ops && pb->arcs[j]->closed;
+  // the stored operators take the plain trapezoid rule: every node must lie
+  // five node spacings or more from the other patches; nearer patches take
+  // the field kernels, whose near plans upsample
+  for (int j = 0; use_ops && j < J; ++j)
+    for (int k = 0; use_ops && k < J; ++k) {
+      if (k == j) continue;
+      const fthms_arc *ak = pb->arcs[k], *aj = pb->arcs[j];
+      for (int i = 0; use_ops && i < aj->n; ++i)
+        for (int l = 0; use_ops && l < ak->n; ++l)
+          if (!(std::hypot(aj->xy[2 * i] - ak->xy[2 * l], aj->xy[2 * i + 1] - ak->xy[2 * l + 1]) >=
+                5.0 * ak->hmax))
+            use_ops = false;
+    }
   const size_t op_per = (size_t)nsum * nsum * sizeof(double2) + 2 * (size_t)nsum * sizeof(double2);
   if (use_ops && (size_t)nk * (per + op_per) + (size_t)(4 * nsum + 64) * 16 > cap) use_ops = false;
   if (use_ops) per += op_per;
@@ -542,20 +672,6 @@ static int problem_run_impl(fthms_problem *pb, int nk, const double *k_dev, doub
                            hipMemcpyHostToDevice));
       HIPCK(ctx, hipMemcpy(base + ops_off[6], hh.data(), sizeof(double) * nsum,
                            hipMemcpyHostToDevice));
-      // every target must be a few node spacings from the other patches (the
-      // trapezoid rule of the stored operators, as for the field kernel)
-      for (int j = 0; j < J; ++j)
-        for (int k = 0; k < J; ++k) {
-          if (k == j) continue;
-          const fthms_arc *ak = pb->arcs[k], *aj = pb->arcs[j];
-          for (int i = 0; i < aj->n; ++i)
-            for (int l = 0; l < ak->n; ++l)
-              if (!(std::hypot(aj->xy[2 * i] - ak->xy[2 * l],
-                               aj->xy[2 * i + 1] - ak->xy[2 * l + 1]) >= 5.0 * ak->hmax))
-                return fail(ctx, FTHMS_EINVAL_DATA,
-                            "target closer than 5 node spacings to a closed patch "
-                            "(trapezoid rule only)");
-        }
     }
     if (tr) {
       Ustep = (double2 *)(base + o[(size_t)10 * J]);

@@ -112,7 +112,7 @@ def test_closed_error_paths(ctx, fth):
     curve = ClosedEllipse(1.0, 0.6)
     arc = ctx.closed_from_curve(curve, 32)
     psi = np.ones((1, 32), dtype=complex)
-    # a target on the curve: refused (trapezoid rule only)
+    # a target on the curve: refused (nearer than h / 25, h the node spacing)
     with pytest.raises(fth.FthmsError):
         ctx.eval_field(arc, np.array([3.0]), psi, np.array([[1.0, 0.0]]))
     # odd node count
@@ -149,3 +149,65 @@ def test_closed_field_target_counts(ctx, fth, npts):
     for i, k in enumerate(ks):
         Uref = ocl.field(k, z, nd, psi[i])
         assert rel(U[i], Uref) < 1e-12, (npts, k, rel(U[i], Uref))
+
+
+def _exterior_points(curve, tt, dist):
+    y, dy = curve.x(tt), curve.dx(tt)
+    nrm = np.stack([dy[:, 1], -dy[:, 0]], -1) / np.hypot(dy[:, 0], dy[:, 1])[:, None]
+    return y + dist * nrm
+
+
+@pytest.mark.parametrize("curve,n", [(ClosedKite(1.0), 256),
+                                     (ClosedEllipse(1.0, 0.6, (0.2, -0.1), 0.3), 128)],
+                         ids=["kite256", "ellipse128"])
+def test_closed_near_targets(ctx, fth, curve, n):
+    """Targets from 6 node spacings down to 0.05 of one (every upsampling
+    level, kappa = 2 .. 128, and the far rule) beside the oracle's
+    near-target integral and the exact exterior field of an interior point
+    source; a target at 0.03 of a node spacing is refused."""
+    spec = IncidentSpec("point", z0=(0.05, 0.1), sigma=0.0)
+    ks = np.array([2.0, 7.5])
+    arc = ctx.closed_from_curve(curve, n)
+    rhs = ctx.rhs(arc, ks, spec)
+    psi, _, _ = ctx.solve(arc, ks, rhs, 0)
+    nd = ocl.nodes(curve, n)
+    h = ocl.near_limit(nd) / 5.0
+    tt = np.array([0.31, 1.7, 2.95, 4.4, 5.9])
+    fr = (0.05, 0.09, 0.2, 0.35, 0.7, 1.4, 2.0, 4.5, 6.0)
+    z = np.concatenate([_exterior_points(curve, tt, f * h) for f in fr])
+    say("closed near targets", n, z.shape[0])
+    U = ctx.eval_field(arc, ks, psi, z)
+    for i, k in enumerate(ks):
+        ref = ocl.field_near(k, z, curve, nd, psi[i])
+        assert np.max(np.abs(U[i] - ref)) < 1e-11 * np.max(np.abs(ref)), k
+        ui = oinc.incident(spec, k, z)
+        assert np.max(np.abs(U[i] + ui) / np.abs(ui)) < 1e-11, k
+    with pytest.raises(fth.FthmsError):
+        ctx.eval_field(arc, ks, psi, _exterior_points(curve, tt[:1], 0.03 * h))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_closed_ms_near_obstacles(ctx, fth, prec):
+    """Two obstacles 0.24 apart at 64 nodes each (nodes of each within five
+    node spacings of the other: no stored operators, the near rule for the
+    cross fields) and observation points in the gap: the GPU recursion
+    against the oracle's."""
+    E = ClosedEllipse(0.8, 0.5, (-1.0, 0.0))
+    K = ClosedKite(0.5, (0.62, 0.2))
+    gap = np.array([[-0.18017388, -0.19891766], [-0.13765677, -0.22256675],
+                    [-0.09513967, -0.24621585]])
+    far = np.stack([2.8 * np.cos(np.linspace(0, 6, 4)), 2.8 * np.sin(np.linspace(0, 6, 4))], -1)
+    obs = np.concatenate([far, gap])
+    from workloads.configs import ArcSpec, MSProblem
+    pb = MSProblem(arcs=[ArcSpec(E, 64, group=0), ArcSpec(K, 64, group=1)],
+                   incident=IncidentSpec("plane", theta=0.4), omegas=np.array([5.5]), M=4,
+                   obs=obs, times=np.zeros(0))
+    say("closed ms near obstacles prec", prec)
+    arcs = [ctx.closed_from_curve(a.curve, a.n) for a in pb.arcs]
+    iv = np.array([a.curve.interval for a in pb.arcs])
+    prob = fth.Problem(ctx, arcs, pb.incident, pb.obs, intervals=iv, M=pb.M, groups=[0, 1],
+                       precision=prec)
+    U, A = prob.run(np.array([5.5]), want_alpha=True)
+    ref = oms.run_frequency(oms.Layout(pb), 5.5)
+    assert rel(U[0], ref["U"]) < TOL, rel(U[0], ref["U"])
+    assert rel(A[0], np.concatenate(ref["alpha_tot"])) < TOL
