@@ -844,8 +844,32 @@ static bool use_sym_form(bool fp32, const fthms_arc *arc) {
 // Panel of the block at k0: register-resident kernel when the block fits
 // (m = N - k0 <= 512 in FP32, <= 320 in FP64), else the LDS/global kernel.
 // Symmetric form (FP32, m <= 512): the register panel without row interchanges.
+// FTHMS_SYM_PANEL=reg in the environment selects the one-launch register
+// panel over the whole column block for the symmetric form (a comparison
+// switch); by default the diagonal block and the rows below it take a
+// launch each.
+static bool sym_panel_split() {
+  static const bool split = [] {
+    const char *e = getenv("FTHMS_SYM_PANEL");
+    return !(e && std::string(e) == "reg");
+  }();
+  return split;
+}
+
 static void launch_panel_sym(hipStream_t st, float2 *A, int N, long long ms, int k0, int *piv,
                              int *swp, float2 *linv, int *status, int count) {
+  if (sym_panel_split()) {
+    lu_panel_reg_kernel<float, 1, false><<<count, kPrThreads, 0, st>>>(
+        A, N, ms, k0, piv, swp, linv, status, 0, kLuNB);
+    const int rows = N - k0 - kLuNB;
+    const int nt = std::min(256, (rows + 63) / 64 * 64);
+    for (int b0 = 0; rows > 0 && b0 < count; b0 += 65535) {
+      const int c = std::min(65535, count - b0);
+      lu_rows_sym_kernel<float><<<dim3((rows + nt - 1) / nt, c), nt, 0, st>>>(
+          A + (long long)b0 * ms, N, ms, k0, status + b0, 0);
+    }
+    return;
+  }
   const int rl = (N - k0 + 63) / 64;
 #define FTHMS_PANEL_SYM(RL)                                                         \
   lu_panel_reg_kernel<float, RL, false><<<count, kPrThreads, 0, st>>>(A, N, ms, k0, piv, swp, \

@@ -276,7 +276,7 @@ __device__ __forceinline__ void panel_reg_column(cplx_t<T> (&a)[RL][4], int &use
 template <typename T, int RL, bool PIV = true>
 __global__ __launch_bounds__(kPrThreads) void lu_panel_reg_kernel(
     cplx_t<T> *Abase, int N, long long mstride, int k0, int *pivbase, int *swapbase,
-    cplx_t<T> *Linv, int *status, int only_failed) {
+    cplx_t<T> *Linv, int *status, int only_failed, int mrows = 1 << 30) {
   typedef cplx_t<T> T2;
   __shared__ PanelRegSmem<T, RL> sm;
   const long long mb = blockIdx.x;
@@ -288,7 +288,9 @@ __global__ __launch_bounds__(kPrThreads) void lu_panel_reg_kernel(
   const int tid = threadIdx.x, lane = tid & 63;
   // wave index as a scalar, so that owner/follower branches are uniform
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int m = N - k0, nb = min(kLuNB, m);
+  // mrows: factor only the top mrows rows of the column block (the
+  // diagonal block of the symmetric form's two-launch panel)
+  const int m = min(N - k0, mrows), nb = min(kLuNB, m);
   // this wave's first column, row k0 (a scalar base; lanes add row offsets)
   T2 *colp = A + k0 + (long long)(k0 + 4 * w) * N;
   // The block, loaded with row and column indices clamped into it: rows past
@@ -414,6 +416,81 @@ __global__ __launch_bounds__(kPrThreads) void lu_panel_reg_kernel(
     if (k0 == 0) status[mb] = panel_status(only_failed, zero);
     else if (zero) status[mb] = -2;
   }
+}
+
+// The symmetric form's panel in two launches (the default in place of
+// lu_panel_reg_kernel<T, RL, false> over the whole column block; same
+// outputs, and the same test of partial pivoting, taken on the same updated
+// entries): lu_panel_reg_kernel<T, 1, false> with mrows = 64 factors the
+// diagonal block, A11 = L11 U11, then lu_rows_sym_kernel the rows below it.
+// (A one-wave kernel for the diagonal block, its rows in registers and the
+// pivot rows broadcast lane to lane, measured twice as slow: 64 dependent
+// broadcast-update rounds per column block with two waves per SIMD.)
+//
+// lu_rows_sym_kernel: L21 = A21 U11^{-1} for the rows below the diagonal
+// block (once that block is factored), one row per thread (so that every
+// access to a column is coalesced), by forward substitution
+//   s_c = a_c - sum_{j < c} l_j U11(j, c),   l_c = s_c / U11(c, c),
+// in four passes of 16 columns; a pass reads the multipliers of the earlier
+// passes back from the row it has written.  U11 sits in LDS, column c
+// contiguous, read as broadcasts.  |s_c| > |U11(c, c)| (|re| + |im|) means
+// partial pivoting would have taken this row: status -2.
+// Grid: ((m - 64 + T - 1) / T, count) of T = 64, 128, 192 or 256 threads,
+// m = N - k0 > 64.
+template <typename T>
+__global__ __launch_bounds__(256) void lu_rows_sym_kernel(cplx_t<T> *Abase, int N,
+                                                          long long mstride, int k0,
+                                                          int *status, int only_failed) {
+  typedef cplx_t<T> T2;
+  __shared__ T2 us[kLuNB][kLuNB];  // us[c][j] = U11(j, c) for j <= c, 0 below
+  __shared__ T2 rinv[kLuNB];
+  __shared__ double umag[kLuNB];
+  const long long mb = blockIdx.y;
+  if (redo_skips(only_failed, status, mb)) return;
+  T2 *A = Abase + mb * mstride + k0 + (long long)k0 * N;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int e = tid; e < kLuNB * kLuNB; e += nt) {
+    const int j = e & 63, c = e >> 6;
+    const T2 v = A[j + (long long)c * N];
+    us[c][j] = j <= c ? v : mk<T>(T(0), T(0));
+  }
+  if (tid < kLuNB) {
+    const T2 d = A[tid + (long long)tid * N];
+    const double dm = fabs((double)d.x) + fabs((double)d.y);
+    umag[tid] = dm;
+    rinv[tid] = dm > 0.0 ? from_d2<T>(trcp<double>(to_d2(d))) : mk<T>(T(0), T(0));
+  }
+  __syncthreads();
+  const int r = kLuNB + blockIdx.x * nt + tid;
+  if (r >= N - k0) return;
+  T2 *row = A + r;
+  int bad = 0;
+  for (int g = 0; g < kLuNB / 16; ++g) {
+    T2 s[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) s[c] = row[(long long)(16 * g + c) * N];
+    for (int h = 0; h < g; ++h) {
+      T2 l[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) l[j] = row[(long long)(16 * h + j) * N];
+      const T2 *ub = &us[16 * g][16 * h];
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) s[c] = tfms<T>(s[c], l[j], ub[c * kLuNB + j]);
+    }
+    const T2 *ud = &us[16 * g][16 * g];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+#pragma unroll
+      for (int j = 0; j < c; ++j) s[c] = tfms<T>(s[c], s[j], ud[c * kLuNB + j]);
+      if (fabs((double)s[c].x) + fabs((double)s[c].y) > umag[16 * g + c]) bad = 1;
+      s[c] = tmul<T>(s[c], rinv[16 * g + c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 16; ++c) row[(long long)(16 * g + c) * N] = s[c];
+  }
+  if (bad) status[mb] = -2;
 }
 
 }  // namespace fthms
