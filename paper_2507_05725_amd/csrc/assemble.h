@@ -141,13 +141,22 @@ __global__ __launch_bounds__(256) void assemble_kernel(
       } else {
         const double2 yj = y[j];
         const double dx = yi.x - yj.x, dy = yi.y - yj.y;
-        const double z = k * sqrt(dx * dx + dy * dy);
+        const double r = sqrt(dx * dx + dy * dy), z = k * r;
         const bool big = z >= kBesselSeriesTo;
         const double *tab = big ? Gl : G;  // one load from either table
         const double g = tab[e];
         double j0v, yv;
-        if (big) bessel_modphase(z, j0v, yv);
-        else bessel_series(z, j0v, yv);
+        if (big) {
+          // the arithmetic of assemble_mf_kernel at its first wavenumber, so
+          // that both kernels give the same entries bit for bit there
+          const double ir = 1.0 / r, ik = 1.0 / k;
+          double P, Q, sz, cz;
+          bessel_pq(z, ik * ir, P, Q);
+          sincos(k * r, &sz, &cz);
+          bessel_combine(P, Q, cz, sz, sqrt((2.0 / kPi) * ir) * sqrt(ik), j0v, yv);
+        } else {
+          bessel_series(z, j0v, yv);
+        }
         v = make_double2(j0v * (g - (big ? 0.0 : ck)) - hq * yv, hq * j0v);
       }
       if (direct) {
@@ -166,6 +175,127 @@ __global__ __launch_bounds__(256) void assemble_kernel(
         const double2 v = tile[tx][ty + 8 * q];
         A[row + (long long)col * N] = v;
         if (W32) Af[row + (long long)col * N] = make_float2((float)v.x, (float)v.y);
+      }
+    }
+  }
+}
+
+constexpr int kAsmF = 8;  // wavenumbers per block of assemble_mf_kernel
+
+// assemble_kernel<W32, false> (Chebyshev arcs, one table pair G / Gl) for
+// kAsmF consecutive wavenumbers per block: the geometry of a node pair
+// (r, 1/r, sqrt(2/(pi r))) and its two table entries are formed once, the
+// per-wavenumber constants (c_k, 1/k, sqrt(1/k)) once per block, and for
+// z = k r >= 4 the modulus-phase form takes 1/z = (1/k)(1/r) and the
+// amplitude sqrt(2/(pi r)) sqrt(1/k): a sine and cosine of z per entry, no
+// division or square root.  The Bessel coefficients are read from LDS.
+// assemble_kernel evaluates a single wavenumber with the same operations,
+// so an entry does not depend on the wavenumbers launched with it.  Grid
+// (tiles, ceil(count / kAsmF)).
+template <bool W32>
+__global__ __launch_bounds__(256) void assemble_mf_kernel(
+    const double2 *__restrict__ y, const double *__restrict__ G, int N,
+    const double *__restrict__ kvec, int count, double2 *__restrict__ A64,
+    float2 *__restrict__ A32, long long mstride, int lower) {
+  __shared__ double2 tile[32][33];
+  __shared__ double2 btab[kBesselTabLen];
+  __shared__ double wk[kAsmF][4];  // per wavenumber: k, c_k, 1/k, sqrt(1/k)
+  const double *__restrict__ Gl = G + (long long)N * N;
+  const int b0 = blockIdx.y * kAsmF, nf = min(kAsmF, count - b0);
+  if (threadIdx.x < kBesselTabLen) bessel_tab_fill(btab, threadIdx.x);
+  if (threadIdx.x >= 64 && threadIdx.x < 64 + nf) {
+    const int f = threadIdx.x - 64;
+    const double k = kvec[b0 + f], ik = 1.0 / k;
+    wk[f][0] = k;
+    wk[f][1] = (kEulerGamma + log(0.5 * k)) / (2.0 * N);
+    wk[f][2] = ik;
+    wk[f][3] = sqrt(ik);
+  }
+  const int t = blockIdx.x;
+  int J = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((J + 1) * (J + 2) / 2 <= t) ++J;
+  while (J * (J + 1) / 2 > t) --J;
+  const int I = t - J * (J + 1) / 2;
+  const int i0 = I * 32, j0 = J * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const double hq = kPi / (4.0 * N);
+  const int i = i0 + tx;
+  double2 yi = make_double2(0.0, 0.0);
+  if (i < N) yi = y[i];
+  // per entry: distance, 1/r, sqrt(2/(pi r)), both table entries
+  double r[4], ir[4], amp[4], g[4], gl[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int j = j0 + ty + 8 * q;
+    r[q] = 0.0;
+    ir[q] = amp[q] = g[q] = gl[q] = 0.0;
+    if (i < N && j < N) {
+      const long long e = i + (long long)j * N;
+      g[q] = G[e];
+      gl[q] = Gl[e];
+      if (i != j) {
+        const double2 yj = y[j];
+        const double dx = yi.x - yj.x, dy = yi.y - yj.y;
+        r[q] = sqrt(dx * dx + dy * dy);
+        ir[q] = 1.0 / r[q];
+        amp[q] = sqrt((2.0 / kPi) * ir[q]);
+      }
+    }
+  }
+  // this tile lies above the diagonal (I < J); in the lower form it is
+  // written only inside a diagonal 64 x 64 block
+  const bool direct = !lower || (I >> 1) == (J >> 1);
+  for (int f = 0; f < nf; ++f) {
+    const int b = b0 + f;
+    double2 *A = A64 + (long long)b * mstride;
+    float2 *Af = W32 ? A32 + (long long)b * mstride : nullptr;
+    __syncthreads();  // the tables and the previous wavenumber's mirror reads are done
+    const double k = wk[f][0], ck = wk[f][1], ik = wk[f][2], sk = wk[f][3];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      // the table's address is made opaque per entry so that its reads stay
+      // with the entry rather than 90 constants held in registers
+      int toff = 0;
+      asm volatile("" : "+v"(toff));
+      const double2 *tab = btab + toff;
+      __builtin_amdgcn_sched_barrier(0);
+      const int j = j0 + ty + 8 * q;
+      double2 v = make_double2(0.0, 0.0);
+      if (i < N && j < N) {
+        if (i == j) {
+          v = make_double2(g[q] - ck, hq);
+        } else {
+          const double z = k * r[q];
+          double j0v, yv;
+          if (z >= kBesselSeriesTo) {
+            double P, Q, sz, cz;
+            bessel_pq_tab(z, ik * ir[q], tab, P, Q);
+            sincos(k * r[q], &sz, &cz);
+            bessel_combine(P, Q, cz, sz, amp[q] * sk, j0v, yv);
+            v = make_double2(j0v * (gl[q] - 0.0) - hq * yv, hq * j0v);
+          } else {
+            bessel_series_tab(z, tab, j0v, yv);
+            v = make_double2(j0v * (g[q] - ck) - hq * yv, hq * j0v);
+          }
+        }
+        if (direct) {
+          const long long e = i + (long long)j * N;
+          A[e] = v;
+          if (W32) Af[e] = make_float2((float)v.x, (float)v.y);
+        }
+      }
+      tile[ty + 8 * q][tx] = v;
+    }
+    if (I != J) {
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = j0 + tx, col = i0 + ty + 8 * q;
+        if (row < N && col < N) {
+          const double2 v = tile[tx][ty + 8 * q];
+          A[row + (long long)col * N] = v;
+          if (W32) Af[row + (long long)col * N] = make_float2((float)v.x, (float)v.y);
+        }
       }
     }
   }

@@ -125,6 +125,63 @@ FTHMS_HD void bessel_combine(double P, double Q, double cz, double sz, double f,
   y0 = f * (P * sm + Q * cm);
 }
 
+// The same polynomials with their coefficients read from a table (pairs
+// (J, Y) / (P, zQ) in one double2 each, in the order of bessel_fit.h):
+// kernels that loop over wavenumbers keep the 45 pairs in LDS instead of in
+// registers.  Same operations in the same order as bessel_series and
+// bessel_pq, so the results are identical.
+constexpr int kBesselTabSeries = 0, kBesselTabMid = 17, kBesselTabBig = 32, kBesselTabLen = 45;
+
+FTHMS_HD void bessel_tab_fill(double2 *tab, int i) {
+  if (i < 17) tab[kBesselTabSeries + i] = make_double2(kSeriesJ[i], kSeriesY[i]);
+  else if (i < 32) tab[i] = make_double2(kPQMidP[i - 17], kPQMidQ[i - 17]);
+  else if (i < 45) tab[i] = make_double2(kPQBigP[i - 32], kPQBigQ[i - 32]);
+}
+
+__device__ __forceinline__ void bessel_series_tab(double z, const double2 *tab, double &j0,
+                                                  double &y0hat) {
+  const double u = 0.25 * z * z;
+  const double2 *c = tab + kBesselTabSeries;
+  double a = c[16].x, b = c[16].y;
+#pragma unroll
+  for (int k = 15; k >= 0; --k) {
+    const double2 ck = c[k];
+    a = a * u + ck.x;
+    b = b * u + ck.y;
+  }
+  j0 = a;
+  y0hat = b;
+}
+
+__device__ __forceinline__ void bessel_pq_tab(double z, double iz, const double2 *tab, double &P,
+                                              double &Q) {
+  double Qz;
+  if (z < kBesselMidTo) {
+    const double x = (16.0 * iz * iz - kPQMidC) * (1.0 / kPQMidH);
+    const double2 *c = tab + kBesselTabMid;
+    P = c[14].x;
+    Qz = c[14].y;
+#pragma unroll
+    for (int k = 13; k >= 0; --k) {
+      const double2 ck = c[k];
+      P = P * x + ck.x;
+      Qz = Qz * x + ck.y;
+    }
+  } else {
+    const double w = 64.0 * iz * iz;
+    const double2 *c = tab + kBesselTabBig;
+    P = c[12].x;
+    Qz = c[12].y;
+#pragma unroll
+    for (int k = 11; k >= 0; --k) {
+      const double2 ck = c[k];
+      P = P * w + ck.x;
+      Qz = Qz * w + ck.y;
+    }
+  }
+  Q = Qz * iz;
+}
+
 // J0 and Y0 for z >= 4 from the fitted modulus functions, the phase from
 // sin/cos of z itself.
 FTHMS_HD void bessel_modphase(double z, double &j0, double &y0) {

@@ -23,73 +23,130 @@ namespace fthms {
 
 constexpr int kFieldThreads = 256;
 
-// One block: up to 256 targets for one wavenumber; nodes and density in LDS.
-// Composite-panel arcs pass their Fejer weights: U(z) = sum_j w_j Phi_k(z,
-// y_j) mu_j; otherwise the weight is pi/N.  With fewer targets than threads
-// (split = 2, 4 or 8) each target's node sum is shared by `split` threads
-// (nodes j = s, s + split, ...), whose partial sums are added in LDS in a
-// fixed order; split = 1 is one thread per target.
-__global__ __launch_bounds__(kFieldThreads) void field_far_kernel(
+constexpr int kFieldF = 4;  // wavenumbers per block of field_far_mf_kernel
+
+// Bytes of the dynamic LDS of field_far_mf_kernel: the nodes and kFieldF
+// densities.
+inline size_t field_mf_lds_bytes(int N) { return sizeof(double2) * (size_t)(1 + kFieldF) * N; }
+
+// Far targets: up to 256 targets for kFieldF consecutive wavenumbers per
+// block, nodes and weighted densities in LDS.  Composite-panel arcs pass
+// their Fejer weights: U(z) = sum_j w_j Phi_k(z, y_j) mu_j; otherwise the
+// weight is pi/N.  With fewer targets than threads (split = 2, 4 or 8) each
+// target's node sum is shared by `split` threads (nodes j = s, s + split,
+// ...), whose partial sums are added in LDS in a fixed order; split = 1 is
+// one thread per target.  A node's distance r to the target, 1/r and
+// sqrt(2/(pi r)) are formed once for the block's wavenumbers; z = k r >= 4
+// takes 1/z = (1/k)(1/r) and the amplitude sqrt(2/(pi r)) sqrt(1/k) (no
+// division or square root per pair and wavenumber), and the Bessel
+// coefficients are read from LDS.  A wavenumber's result does not depend on
+// the others launched with it.
+// Grid (target blocks, ceil(nk / kFieldF)); dynamic LDS field_mf_lds_bytes.
+__global__ __launch_bounds__(kFieldThreads) void field_far_mf_kernel(
     const double2 *__restrict__ ynodes, int N, const double *__restrict__ wnode,
-    const double *__restrict__ kvec, const double2 *__restrict__ alpha, long long astride,
-    const double2 *__restrict__ pts, int np, const unsigned char *__restrict__ cls,
-    double2 *__restrict__ U, long long ustride, int accumulate, int split) {
-  __shared__ double2 sy[1024];
-  __shared__ double2 sa[1024];
+    const double *__restrict__ kvec, int nk, const double2 *__restrict__ alpha,
+    long long astride, const double2 *__restrict__ pts, int np,
+    const unsigned char *__restrict__ cls, double2 *__restrict__ U, long long ustride,
+    int accumulate, int split) {
+  extern __shared__ double2 fdyn[];
+  double2 *sy = fdyn, *sa = fdyn + N;  // sa[f N + j]: weighted density f at node j
   __shared__ double2 red[kFieldThreads];
-  const int b = blockIdx.y;
+  __shared__ double2 btab[kBesselTabLen];
+  __shared__ double wk[kFieldF][3];  // k, 1/k, sqrt(1/k)
+  const int b0 = blockIdx.y * kFieldF, nf = min(kFieldF, nk - b0);
   for (int j = threadIdx.x; j < N; j += kFieldThreads) {
     sy[j] = ynodes[j];
-    double2 a = alpha[(long long)b * astride + j];
-    if (wnode) a = make_double2(wnode[j] * a.x, wnode[j] * a.y);
-    sa[j] = a;
+#pragma unroll
+    for (int f = 0; f < kFieldF; ++f) {
+      double2 a = make_double2(0.0, 0.0);
+      if (f < nf) a = alpha[(long long)(b0 + f) * astride + j];
+      if (wnode) a = make_double2(wnode[j] * a.x, wnode[j] * a.y);
+      sa[f * N + j] = a;
+    }
+  }
+  if (threadIdx.x < kBesselTabLen) bessel_tab_fill(btab, threadIdx.x);
+  if (threadIdx.x >= 64 && threadIdx.x < 64 + nf) {
+    const int f = threadIdx.x - 64;
+    const double k = kvec[b0 + f], ik = 1.0 / k;
+    wk[f][0] = k;
+    wk[f][1] = ik;
+    wk[f][2] = sqrt(ik);
   }
   __syncthreads();
   const int tpb = kFieldThreads / split;  // targets per block
   const int pl = threadIdx.x % tpb, sl = threadIdx.x / tpb;
   const int p = blockIdx.x * tpb + pl;
   const bool active = p < np && (!cls || cls[p] == 1);
-  const double k = kvec[b];
-  double accr = 0.0, acci = 0.0;
+  double ar[kFieldF], ai[kFieldF];
+#pragma unroll
+  for (int f = 0; f < kFieldF; ++f) ar[f] = ai[f] = 0.0;
   if (active) {
-    const double2 z = pts[p];
-    // node j + split is read from LDS (index clamped) before node j's Hankel
-    // evaluation, which hides the read
-    double2 yn = sy[min(sl, N - 1)], an = sa[min(sl, N - 1)];
+    const double2 zt = pts[p];
     for (int j = sl; j < N; j += split) {
-      const double2 yj = yn, a = an;
-      const int jn = min(j + split, N - 1);
-      yn = sy[jn];
-      an = sa[jn];
-      const double dx = z.x - yj.x, dy = z.y - yj.y;
-      double j0v, y0v;
-      bessel_j0_y0(k * sqrt(dx * dx + dy * dy), j0v, y0v);
-      // (i J0 - Y0) * a
-      accr += -y0v * a.x - j0v * a.y;
-      acci += j0v * a.x - y0v * a.y;
+      const double2 yj = sy[j];
+      const double dx = zt.x - yj.x, dy = zt.y - yj.y;
+      const double r = sqrt(dx * dx + dy * dy), ir = 1.0 / r;
+      const double amp = sqrt((2.0 / kPi) * ir);
+      // the table's address is opaque per node so that its reads stay in
+      // the loop rather than 90 constants held in registers
+      int toff = 0;
+      asm volatile("" : "+v"(toff));
+      const double2 *tab = btab + toff;
+#pragma unroll
+      for (int f = 0; f < kFieldF; ++f) {
+        if (f < nf) {
+          const double k = wk[f][0], z = k * r;
+          double j0v, y0v;
+          if (z >= kBesselSeriesTo) {
+            double P, Q, sz, cz;
+            bessel_pq_tab(z, wk[f][1] * ir, tab, P, Q);
+            sincos(z, &sz, &cz);
+            bessel_combine(P, Q, cz, sz, amp * wk[f][2], j0v, y0v);
+          } else {
+            double yh;
+            bessel_series_tab(z, tab, j0v, yh);
+            y0v = yh + bessel_logpart(z) * j0v;
+          }
+          // (i J0 - Y0) * a
+          const double2 a = sa[f * N + j];
+          ar[f] += -y0v * a.x - j0v * a.y;
+          ai[f] += j0v * a.x - y0v * a.y;
+        }
+      }
     }
   }
   if (split > 1) {
-    red[threadIdx.x] = make_double2(accr, acci);
-    __syncthreads();
-    if (sl != 0) return;
-    for (int q = 1; q < split; ++q) {
-      accr += red[pl + q * tpb].x;
-      acci += red[pl + q * tpb].y;
+#pragma unroll
+    for (int f = 0; f < kFieldF; ++f) {
+      red[threadIdx.x] = make_double2(ar[f], ai[f]);
+      __syncthreads();
+      if (sl == 0) {
+        for (int q = 1; q < split; ++q) {
+          ar[f] += red[pl + q * tpb].x;
+          ai[f] += red[pl + q * tpb].y;
+        }
+      }
+      __syncthreads();
     }
+    if (sl != 0) return;
   }
   if (!active) return;
   const double s = wnode ? 0.25 : kPi / (4.0 * N);
-  double2 *u = U + (long long)b * ustride + p;
-  if (accumulate) {
-    const double2 o = *u;
-    *u = make_double2(o.x + s * accr, o.y + s * acci);
-  } else {
-    *u = make_double2(s * accr, s * acci);
+#pragma unroll
+  for (int f = 0; f < kFieldF; ++f) {
+    if (f < nf) {
+      double2 *u = U + (long long)(b0 + f) * ustride + p;
+      if (accumulate) {
+        const double2 o = *u;
+        *u = make_double2(o.x + s * ar[f], o.y + s * ai[f]);
+      } else {
+        *u = make_double2(s * ar[f], s * ai[f]);
+      }
+    }
   }
 }
 
-// Threads per target for field_far_kernel and closed_field_kernel: 1 for
+// Threads per target for field_far_mf_kernel and closed_field_kernel: 1 for
 // 256 targets or more, else up to 8 so that a block's threads all have work.
 inline int field_target_split(int np) {
   int split = 1;

@@ -1153,12 +1153,16 @@ static int assemble_launch(fthms_ctx *ctx, const fthms_arc *arc, const double *k
     else
       assemble_kernel<false, true><<<g, b, 0, ctx->stream>>>(
           arc->d_y, arc->d_G, N, k_dev, A64, nullptr, ms, nullptr, nullptr, arc->d_w);
-  } else if (A32) {
-    assemble_kernel<true, false><<<g, b, 0, ctx->stream>>>(
-        arc->d_y, arc->d_G, N, k_dev, A64, A32, ms, nullptr, nullptr, nullptr, lower ? 1 : 0);
   } else {
-    assemble_kernel<false, false><<<g, b, 0, ctx->stream>>>(
-        arc->d_y, arc->d_G, N, k_dev, A64, nullptr, ms, nullptr, nullptr, nullptr, lower ? 1 : 0);
+    // Chebyshev arcs: kAsmF wavenumbers per block
+    dim3 gm(T * (T + 1) / 2, (count + kAsmF - 1) / kAsmF);
+    if (A32)
+      assemble_mf_kernel<true><<<gm, b, 0, ctx->stream>>>(arc->d_y, arc->d_G, N, k_dev, count,
+                                                          A64, A32, ms, lower ? 1 : 0);
+    else
+      assemble_mf_kernel<false><<<gm, b, 0, ctx->stream>>>(arc->d_y, arc->d_G, N, k_dev, count,
+                                                           A64, nullptr, ms, lower ? 1 : 0);
+    return check_launch(ctx, "assemble_mf_kernel");
   }
   return check_launch(ctx, "assemble_kernel");
 }
@@ -1582,10 +1586,13 @@ int field_dev_impl(fthms_ctx *ctx, const fthms_arc *arc, int nk, const double *k
     }
     return FTHMS_OK;
   }
-  field_far_kernel<<<gf, kFieldThreads, 0, ctx->stream>>>(arc->d_y, arc->n, arc->d_w, k_dev,
-                                                         alpha, astride, pts_dev, np, plan.d_cls,
-                                                         U, ustride, accumulate, split);
-  int rc = check_launch(ctx, "field_far_kernel");
+  {
+    dim3 gm(gf.x, (nk + kFieldF - 1) / kFieldF);
+    field_far_mf_kernel<<<gm, kFieldThreads, field_mf_lds_bytes(arc->n), ctx->stream>>>(
+        arc->d_y, arc->n, arc->d_w, k_dev, nk, alpha, astride, pts_dev, np, plan.d_cls, U,
+        ustride, accumulate, split);
+  }
+  int rc = check_launch(ctx, "field_far_mf_kernel");
   if (rc) return rc;
   if (plan.ntgt > 0) {
     if ((rc = ensure_ws2(ctx, sizeof(double2) * (size_t)nk * arc->n))) return rc;

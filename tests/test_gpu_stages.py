@@ -66,6 +66,30 @@ def test_assembly_matches_oracle(env, curve, n):
         assert err < 1e-13, (n, kk, err, np.unravel_index(np.argmax(np.abs(Ag[b] - ref)), ref.shape))
 
 
+@pytest.mark.parametrize("kgrid", ["low", "high"])
+def test_assembly_dense_wavenumber_grid(env, kgrid):
+    """Dense, evenly spaced wavenumbers (the assembly takes eight
+    wavenumbers per workgroup): ragged group counts (21 and 20), arguments
+    k r crossing the series / modulus-phase boundaries at 4 and 8 (low) and
+    large arguments (high), against the oracle entry by entry."""
+    fth, ctx, torch = env
+    curve = CircularArc(1.0, 0.3, 2.8)
+    n = 97
+    k = np.linspace(1.0, 5.0, 21) if kgrid == "low" else 40.0 + 0.05 * np.arange(20)
+    say("assembly dense grid", kgrid)
+    arc = ctx.arc_from_curve(curve, n)
+    kt = torch.tensor(k, device="cuda", dtype=torch.float64)
+    A = torch.empty((k.size, n, n), device="cuda", dtype=torch.complex128)
+    ctx.assemble_dev(arc, kt, A)
+    torch.cuda.synchronize()
+    Ag = A.cpu().numpy().transpose(0, 2, 1)
+    nd = ony.arc_nodes(curve, n)
+    for b, kk in enumerate(k):
+        ref = ony.assemble(nd, kk)
+        err = np.max(np.abs(Ag[b] - ref)) / np.max(np.abs(ref))
+        assert err < 1e-13, (kgrid, b, kk, err)
+
+
 def _lu_reconstruct(LU, piv):
     n = LU.shape[0]
     L = np.tril(LU, -1) + np.eye(n)
