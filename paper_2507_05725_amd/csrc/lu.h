@@ -1013,62 +1013,97 @@ __device__ double block_sum(double v, double *red) {
 // rs = bb - A xs for a complex symmetric A held as its lower block triangle
 // (64 x 64 blocks (I, J) with I >= J, the diagonal blocks in full, as the
 // symmetric form's assembly writes it; A_ij for j beyond i's diagonal block
-// is A_ji).  Each element is read once:
-//   * the stored part of row i (columns up to the end of its diagonal
-//     block) by the thread owning the row, a column sweep coalesced across
-//     the rows of a wave (which share one diagonal block, so the sweep
-//     length is uniform across the wave);
-//   * the rest of the row, column i below its diagonal block: each wave
-//     takes eight columns at a time (a group of 32 columns, all in one
-//     diagonal block, is shared by the four waves), lanes down the columns
-//     (coalesced), the eight columns' loads of a row chunk in flight
-//     together, then a wave sum per column.
-// xs, rs: N complex in LDS.  Ends with a barrier.  The sums run in a fixed
-// order (no atomics), so results are reproducible bit for bit.
-__device__ void sym_residual(const double2 *__restrict__ A, int N, const double2 *__restrict__ bb,
-                             const double2 *xs, double2 *rs) {
+// is A_ji), every stored element read once: each wave takes the blocks,
+// J <= I, numbered row by row, t = wave, wave + 4, ...; lane i is row
+// 64 I + i of the block, eight columns' loads in flight at a time (coalesced
+// across the lanes).  Every element gives its row's term A_ij x_j (a
+// per-lane sum) and, off the diagonal blocks, its column's term A_ij x_i
+// (the transposed block's use): the eight columns' terms are summed over the
+// 64 lanes in one transposing butterfly (lane pairs 32, 16 and 8 apart each
+// halve the values held, then 4, 2, 1 apart add the last one), which leaves
+// column u's sum in lane 8u.  The row and column sums go to the wave's own
+// partial vector part[wave][N] in LDS, and rs = bb - the four partials
+// added in a fixed order: no atomics, reproducible bit for bit.  (Reading
+// the strictly lower blocks a second time, down their columns, for the
+// transposed terms cost the refinement stage 20% more time.)
+// xs, rs: N complex in LDS; part: 4N complex in LDS.  Ends with a barrier.
+__device__ void sym_residual_fused(const double2 *__restrict__ A, int N,
+                                   const double2 *__restrict__ bb, const double2 *xs,
+                                   double2 *rs, double2 *part) {
+  static_assert(kLuThreads == 256, "four waves, four partial vectors");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int r = tid; r < N; r += kLuThreads) {
-    const int cend = min(N, ((r >> 6) + 1) * 64);
-    rs[r] = row_sweep(bb[r], A + r, N, xs, cend);
+  for (int e = tid; e < 4 * N; e += kLuThreads) part[e] = make_double2(0.0, 0.0);
+  __syncthreads();
+  double2 *pw = part + (long long)wave * N;
+  const int nbk = (N + 63) >> 6, nblk = nbk * (nbk + 1) / 2;
+  const int b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1;
+  for (int t = wave; t < nblk; t += 4) {
+    int I = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    while (I * (I + 1) / 2 > t) --I;
+    const int J = t - I * (I + 1) / 2;
+    const int i = 64 * I + lane, jb = 64 * J;
+    const int ncol = min(64, N - jb);
+    const double m = i < N ? 1.0 : 0.0;  // rows past N contribute nothing
+    const double2 xi = xs[min(i, N - 1)];
+    const double2 *arow = A + min(i, N - 1);
+    double2 racc = make_double2(0.0, 0.0);
+    for (int c0 = 0; c0 < 64; c0 += 8) {
+      double2 a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = arow[(long long)(jb + min(c0 + u, ncol - 1)) * N];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        // columns past N (clamped loads) and rows past N: zero terms
+        const double mu = c0 + u < ncol ? m : 0.0;
+        a[u] = make_double2(a[u].x * mu, a[u].y * mu);
+        racc = cfma(racc, a[u], xs[jb + min(c0 + u, ncol - 1)]);
+      }
+      if (I != J) {
+        double2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = cmul(a[u], xi);
+        // lanes 32 apart: keep half of the eight, add the partner's half
+        double2 w4[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double2 snd = b5 ? v[k] : v[k + 4], kep = b5 ? v[k + 4] : v[k];
+          w4[k] = make_double2(kep.x + __shfl_xor(snd.x, 32), kep.y + __shfl_xor(snd.y, 32));
+        }
+        double2 w2[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const double2 snd = b4 ? w4[k] : w4[k + 2], kep = b4 ? w4[k + 2] : w4[k];
+          w2[k] = make_double2(kep.x + __shfl_xor(snd.x, 16), kep.y + __shfl_xor(snd.y, 16));
+        }
+        const double2 snd = b3 ? w2[0] : w2[1], kep = b3 ? w2[1] : w2[0];
+        double2 w1 = make_double2(kep.x + __shfl_xor(snd.x, 8), kep.y + __shfl_xor(snd.y, 8));
+#pragma unroll
+        for (int off = 4; off >= 1; off >>= 1) {
+          w1.x += __shfl_xor(w1.x, off);
+          w1.y += __shfl_xor(w1.y, off);
+        }
+        // lane 8u holds the sum of column c0 + u (u = 4 b5 + 2 b4 + b3)
+        if ((lane & 7) == 0) {
+          const int c = c0 + (lane >> 3);
+          if (c < ncol) pw[jb + c] = cadd(pw[jb + c], w1);
+        }
+      }
+    }
+    if (i < N) pw[i] = cadd(pw[i], racc);
   }
   __syncthreads();
-  constexpr int W = kLuThreads / 64, U = 8;
-  for (int g0 = 0; g0 < N; g0 += W * U) {
-    const int j0 = ((g0 >> 6) + 1) * 64;  // the group's diagonal block ends here
-    if (j0 >= N) break;
-    const double2 *col[U];
-    double2 acc[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      col[u] = A + (long long)min(g0 + wave + W * u, N - 1) * N;
-      acc[u] = make_double2(0.0, 0.0);
-    }
-    for (int j = j0 + lane; j < N; j += 64) {
-      double2 v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) v[u] = col[u][j];
-      const double2 xj = xs[j];
-#pragma unroll
-      for (int u = 0; u < U; ++u) acc[u] = cfma(acc[u], v[u], xj);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        acc[u].x += __shfl_xor(acc[u].x, off);
-        acc[u].y += __shfl_xor(acc[u].y, off);
-      }
-      const int c = g0 + wave + W * u;
-      if (lane == 0 && c < N) rs[c] = csub(rs[c], acc[u]);
-    }
+  for (int r = tid; r < N; r += kLuThreads) {
+    const double2 s = cadd(cadd(part[r], part[N + r]), cadd(part[2 * N + r], part[3 * N + r]));
+    rs[r] = csub(bb[r], s);
   }
   __syncthreads();
 }
 
-// Bytes of the dynamic LDS of refine_kernel: x and r.
+// Bytes of the dynamic LDS of refine_kernel: x and r, and for the fused
+// symmetric residual four partial vectors.
 constexpr size_t refine_lds_bytes(int N, bool lower) {
-  return (void)lower, sizeof(double2) * 2 * (size_t)N;
+  return sizeof(double2) * (size_t)(lower ? 6 : 2) * N;
 }
 
 // Refined solve: x0 from the FP32 factors, then repeat
@@ -1078,16 +1113,16 @@ constexpr size_t refine_lds_bytes(int N, bool lower) {
 // status[b] = steps taken, or -1 when the cap was hit or the iteration did
 // not contract (the caller then redoes the solve in FP64).
 // LOWER: A64 holds only its lower block triangle (the symmetric form's
-// assembly); the residual then reads that part once (sym_residual).  A
-// template argument, so that the other form keeps its register budget.
+// assembly), the residual by sym_residual_fused.  A template argument, so
+// that the other form keeps its register budget.
 template <bool LOWER>
 __global__ __launch_bounds__(kLuThreads, 3) void refine_kernel(
     const float2 *LUbase, const int *permbase, const double2 *A64base, int N,
     long long mstride, const double2 *b, double2 *x, long long vstride, double tol,
     int max_iter, int *status, double *relres, int later) {
   // dynamic LDS (refine_lds_bytes, sized at launch): x and r, N complex128
-  // each (16 KB at N = 512), the only LDS of the kernel, so registers set
-  // its occupancy
+  // each (16 KB at N = 512), and with the fused symmetric residual its four
+  // partial vectors (48 KB in all at N = 512)
   extern __shared__ double2 refine_dyn[];
   double2 *xs = refine_dyn, *rs = refine_dyn + N;
   __shared__ double red[4];
@@ -1115,7 +1150,7 @@ __global__ __launch_bounds__(kLuThreads, 3) void refine_kernel(
   for (; it < max_iter && !done; ++it) {
     // r = b - A x  (each thread owns rows; column sweep, coalesced)
     if constexpr (LOWER) {
-      sym_residual(A, N, bb, xs, rs);
+      sym_residual_fused(A, N, bb, xs, rs, refine_dyn + 2 * N);
     } else {
       for (int r = tid; r < N; r += kLuThreads) rs[r] = row_sweep(bb[r], A + r, N, xs, N);
       __syncthreads();
