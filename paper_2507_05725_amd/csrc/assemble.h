@@ -254,7 +254,7 @@ __global__ __launch_bounds__(256) void assemble_mf_kernel(
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       // the table's address is made opaque per entry so that its reads stay
-      // with the entry rather than 90 constants held in registers
+      // with the entry rather than 104 constants held in registers
       int toff = 0;
       asm volatile("" : "+v"(toff));
       const double2 *tab = btab + toff;

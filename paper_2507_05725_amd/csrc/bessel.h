@@ -7,8 +7,9 @@
 //   z >= 4       the modulus-phase form of Hankel's expansion (DLMF 10.17.3,
 //                10.17.4) with the exact modulus functions P(z), Q(z) in
 //                place of their divergent series: polynomial fits in
-//                (4/z)^2 on [4, 8) and in (8/z)^2 beyond (bessel_fit.h,
-//                written by bessel_fit.py), phase by sin/cos of z.
+//                (4/z)^2 on [4, 8), in (8/z)^2 on [8, 24) and in (24/z)^2
+//                beyond (bessel_fit.h, written by bessel_fit.py), phase by
+//                sin/cos of z.
 //
 // Besides J0 and Y0 the routines expose the regular part
 //   Y0hat(z) = Y0(z) - (2/pi)(log(z/2) + gamma) J0(z),
@@ -101,7 +102,7 @@ FTHMS_HD void bessel_pq(double z, double iz, double &P, double &Q) {
       P = P * x + kPQMidP[k];
       Qz = Qz * x + kPQMidQ[k];
     }
-  } else {
+  } else if (z < kPQFarZ) {
     const double w = 64.0 * iz * iz;
     P = kPQBigP[12];
     Qz = kPQBigQ[12];
@@ -109,6 +110,15 @@ FTHMS_HD void bessel_pq(double z, double iz, double &P, double &Q) {
     for (int k = 11; k >= 0; --k) {
       P = P * w + kPQBigP[k];
       Qz = Qz * w + kPQBigQ[k];
+    }
+  } else {
+    const double v = (kPQFarZ * kPQFarZ) * iz * iz;
+    P = kPQFarP[6];
+    Qz = kPQFarQ[6];
+#pragma unroll
+    for (int k = 5; k >= 0; --k) {
+      P = P * v + kPQFarP[k];
+      Qz = Qz * v + kPQFarQ[k];
     }
   }
   Q = Qz * iz;
@@ -127,15 +137,17 @@ FTHMS_HD void bessel_combine(double P, double Q, double cz, double sz, double f,
 
 // The same polynomials with their coefficients read from a table (pairs
 // (J, Y) / (P, zQ) in one double2 each, in the order of bessel_fit.h):
-// kernels that loop over wavenumbers keep the 45 pairs in LDS instead of in
+// kernels that loop over wavenumbers keep the 52 pairs in LDS instead of in
 // registers.  Same operations in the same order as bessel_series and
 // bessel_pq, so the results are identical.
-constexpr int kBesselTabSeries = 0, kBesselTabMid = 17, kBesselTabBig = 32, kBesselTabLen = 45;
+constexpr int kBesselTabSeries = 0, kBesselTabMid = 17, kBesselTabBig = 32, kBesselTabFar = 45,
+              kBesselTabLen = 52;
 
 FTHMS_HD void bessel_tab_fill(double2 *tab, int i) {
   if (i < 17) tab[kBesselTabSeries + i] = make_double2(kSeriesJ[i], kSeriesY[i]);
   else if (i < 32) tab[i] = make_double2(kPQMidP[i - 17], kPQMidQ[i - 17]);
   else if (i < 45) tab[i] = make_double2(kPQBigP[i - 32], kPQBigQ[i - 32]);
+  else if (i < 52) tab[i] = make_double2(kPQFarP[i - 45], kPQFarQ[i - 45]);
 }
 
 __device__ __forceinline__ void bessel_series_tab(double z, const double2 *tab, double &j0,
@@ -167,7 +179,7 @@ __device__ __forceinline__ void bessel_pq_tab(double z, double iz, const double2
       P = P * x + ck.x;
       Qz = Qz * x + ck.y;
     }
-  } else {
+  } else if (z < kPQFarZ) {
     const double w = 64.0 * iz * iz;
     const double2 *c = tab + kBesselTabBig;
     P = c[12].x;
@@ -177,6 +189,17 @@ __device__ __forceinline__ void bessel_pq_tab(double z, double iz, const double2
       const double2 ck = c[k];
       P = P * w + ck.x;
       Qz = Qz * w + ck.y;
+    }
+  } else {
+    const double v = (kPQFarZ * kPQFarZ) * iz * iz;
+    const double2 *c = tab + kBesselTabFar;
+    P = c[6].x;
+    Qz = c[6].y;
+#pragma unroll
+    for (int k = 5; k >= 0; --k) {
+      const double2 ck = c[k];
+      P = P * v + ck.x;
+      Qz = Qz * v + ck.y;
     }
   }
   Q = Qz * iz;

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kFieldThreads) void field_far_mf_kernel(
       const double r = sqrt(dx * dx + dy * dy), ir = 1.0 / r;
       const double amp = sqrt((2.0 / kPi) * ir);
       // the table's address is opaque per node so that its reads stay in
-      // the loop rather than 90 constants held in registers
+      // the loop rather than 104 constants held in registers
       int toff = 0;
       asm volatile("" : "+v"(toff));
       const double2 *tab = btab + toff;

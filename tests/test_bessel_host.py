@@ -4,7 +4,7 @@ The same header the HIP kernels include is built into a small CPU probe
 (tests/native/bessel_probe.cpp) with hipcc; nothing runs on a GPU.  The
 absolute error bound 1.5e-15 holds uniformly over [0, 1500], covering every
 regime boundary of the order-zero routines (series below 4, fitted modulus
-functions on [4, 8) and beyond) and of the order-one routine (1e-6, 8,
+functions on [4, 8), [8, 24) and beyond) and of the order-one routine (1e-6, 8,
 16.5); the order-zero values also satisfy the Wronskian with the order-one
 values of the independent order-one routine."""
 import os
@@ -44,8 +44,8 @@ def test_device_bessel_against_mpmath(probe):
     rng = np.random.default_rng(7)
     z = np.concatenate([
         np.geomspace(1e-9, 1e-5, 20),
-        np.array([1e-6, 4.0 - 1e-12, 4.0, 8.0 - 1e-12, 8.0, 16.5]),
-        rng.uniform(0.0, 20.0, 600) + 1e-3,
+        np.array([1e-6, 4.0 - 1e-12, 4.0, 8.0 - 1e-12, 8.0, 16.5, 24.0 - 1e-12, 24.0]),
+        rng.uniform(0.0, 20.0, 600) + 1e-3, rng.uniform(20.0, 30.0, 200),
         rng.uniform(20.0, 1500.0, 300)])
     res = _run(probe, z)
     g = mp.euler
@@ -89,7 +89,8 @@ def test_device_bessel_wronskian(probe):
     every regime), relative to the size of the two products."""
     rng = np.random.default_rng(9)
     z = np.concatenate([np.geomspace(1e-4, 4.0, 200), rng.uniform(3.9, 8.1, 300),
-                        rng.uniform(8.0, 20.0, 300), rng.uniform(20.0, 1500.0, 300)])
+                        rng.uniform(8.0, 20.0, 300), rng.uniform(20.0, 28.0, 200),
+                        rng.uniform(20.0, 1500.0, 300)])
     res = _run(probe, z)
     zz, j0, y0, j1, y1 = res[:, 0], res[:, 1], res[:, 2], res[:, 7], res[:, 8]
     w = j1 * y0 - j0 * y1
