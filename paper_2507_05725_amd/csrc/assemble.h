@@ -152,7 +152,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(
           const double ir = 1.0 / r, ik = 1.0 / k;
           double P, Q, sz, cz;
           bessel_pq(z, ik * ir, P, Q);
-          sincos(k * r, &sz, &cz);
+          phase_sincos(k * r, sz, cz);
           bessel_combine(P, Q, cz, sz, sqrt((2.0 / kPi) * ir) * sqrt(ik), j0v, yv);
         } else {
           bessel_series(z, j0v, yv);
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(256) void assemble_mf_kernel(
           if (z >= kBesselSeriesTo) {
             double P, Q, sz, cz;
             bessel_pq_tab(z, ik * ir[q], tab, P, Q);
-            sincos(k * r[q], &sz, &cz);
+            phase_sincos(k * r[q], sz, cz);
             bessel_combine(P, Q, cz, sz, amp[q] * sk, j0v, yv);
             v = make_double2(j0v * (gl[q] - 0.0) - hq * yv, hq * j0v);
           } else {

@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kFieldThreads) void field_far_mf_kernel(
           if (z >= kBesselSeriesTo) {
             double P, Q, sz, cz;
             bessel_pq_tab(z, wk[f][1] * ir, tab, P, Q);
-            sincos(z, &sz, &cz);
+            phase_sincos(z, sz, cz);
             bessel_combine(P, Q, cz, sz, amp * wk[f][2], j0v, y0v);
           } else {
             double yh;

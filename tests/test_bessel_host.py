@@ -39,6 +39,24 @@ def _run(exe, z):
     return np.array([[float(x) for x in l.split()] for l in out.strip().splitlines()])
 
 
+def test_phase_sincos_against_mpmath(probe):
+    """The phase sine and cosine of the modulus-phase form (Cody-Waite
+    reduction, Taylor polynomials) within 2e-16 of mpmath on [0, 1e5],
+    next to multiples of pi/2 included, and the library's beyond 1e6."""
+    mp.mp.dps = 40
+    rng = np.random.default_rng(11)
+    k = rng.integers(1, 60000, 200)
+    z = np.concatenate([rng.uniform(0.0, 100.0, 300), rng.uniform(100.0, 1e5, 300),
+                        k * (np.pi / 2) + rng.uniform(-1e-9, 1e-9, 200),
+                        np.array([0.0, 1e-300, np.pi / 4, 3 * np.pi / 4, 2e6])])
+    res = _run(probe, z)
+    worst = 0.0
+    for row in res:
+        zz = mp.mpf(row[0])
+        worst = max(worst, float(abs(row[9] - mp.sin(zz))), float(abs(row[10] - mp.cos(zz))))
+    assert worst < 2e-16, worst
+
+
 def test_device_bessel_against_mpmath(probe):
     mp.mp.dps = 30
     rng = np.random.default_rng(7)
