@@ -770,6 +770,44 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3, sizeof(T) == 8 ? 2 : 
           ci[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(ai, br, ci[cb], 0, 0, 0);
         }
       }
+    } else if constexpr (sizeof(T) == 4) {
+      // three real products per complex one (the FP32 factors, which the
+      // refinement corrects): T1 = Ar Br, T2 = Ai Bi, T3 = (Ar + Ai)(Br + Bi), so that
+      // Re AB = T1 - T2 and Im AB = T3 - T1 - T2; every step's three chains
+      // accumulate from zero and are combined at the end
+      acc_t c3[4];
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) c3[cb][r] = 0;
+#pragma unroll
+      for (int st = 0; st < kLuNB / 4; ++st) {
+        const T ar = fa[st].x, ai = fa[st].y, as = fa[st].x + fa[st].y;
+        T br[4], bi[4], bs[4];
+        const int krow = 4 * st + lk;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          const T2 bv = sX[krow][cb * 16 + li];
+          br[cb] = bv.x;
+          bi[cb] = bv.y;
+          bs[cb] = bv.x + bv.y;
+        }
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          cr[cb] = Mma<T>::run(ar, br[cb], cr[cb]);
+          ci[cb] = Mma<T>::run(ai, bi[cb], ci[cb]);
+          c3[cb] = Mma<T>::run(as, bs[cb], c3[cb]);
+        }
+      }
+      // C - A B: cr = T1, ci = T2 -> (T2 - T1, T1 + T2 - T3)
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const T t1 = cr[cb][r], t2 = ci[cb][r];
+          cr[cb][r] = t2 - t1;
+          ci[cb][r] = (t1 + t2) - c3[cb][r];
+        }
     } else {
 #pragma unroll
     // all 16 steps (zero fragments and rows beyond a partial block)
