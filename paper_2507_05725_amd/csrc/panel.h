@@ -222,8 +222,14 @@ __device__ __forceinline__ void panel_reg_column(cplx_t<T> (&a)[RL][4], int &use
       }
     }
     const bool nz = best > 0.0;
-    // pivot reciprocal in FP64, rounded once to the storage precision
-    const T2 inv = nz ? from_d2<T>(trcp<double>(to_d2(u[J]))) : mk<T>(T(0), T(0));
+    // pivot reciprocal: FP64 factors in FP64; FP32 factors (which the
+    // refinement corrects) from the FP32 hardware reciprocal, which keeps
+    // the owner's step per column short
+    T2 inv = mk<T>(T(0), T(0));
+    if (nz) {
+      if constexpr (sizeof(T) == 4) inv = trcp<T>(u[J]);
+      else inv = trcp<double>(to_d2(u[J]));
+    }
 #pragma unroll
     for (int i = 0; i < RL; ++i) {
       const bool below = ((used >> i) & 1) == 0;
