@@ -32,7 +32,7 @@ inline size_t field_mf_lds_bytes(int N) { return sizeof(double2) * (size_t)(1 + 
 // Far targets: up to 256 targets for kFieldF consecutive wavenumbers per
 // block, nodes and weighted densities in LDS.  Composite-panel arcs pass
 // their Fejer weights: U(z) = sum_j w_j Phi_k(z, y_j) mu_j; otherwise the
-// weight is pi/N.  With fewer targets than threads (split = 2, 4 or 8) each
+// weight is pi/N.  With up to 256 targets (split = 2, 4 or 8) each
 // target's node sum is shared by `split` threads (nodes j = s, s + split,
 // ...), whose partial sums are added in LDS in a fixed order; split = 1 is
 // one thread per target.  A node's distance r to the target, 1/r and
@@ -146,11 +146,15 @@ __global__ __launch_bounds__(kFieldThreads) void field_far_mf_kernel(
   }
 }
 
-// Threads per target for field_far_mf_kernel and closed_field_kernel: 1 for
-// 256 targets or more, else up to 8 so that a block's threads all have work.
+// Threads per target for field_far_mf_kernel and closed_field_kernel: 8 up
+// to 64 targets, 4 up to 128, 2 up to 256, 1 above.  Every launch has
+// about twice as many threads as targets (at 256 targets one per target
+// left four waves per SIMD in all, too few to cover the latency of the
+// Bessel evaluations' dependent chains).  A function of the target count
+// only, so a field does not depend on what else is launched.
 inline int field_target_split(int np) {
   int split = 1;
-  while (split < 8 && np * split * 2 <= kFieldThreads) split *= 2;
+  while (split < 8 && np * split <= kFieldThreads) split *= 2;
   return split;
 }
 

@@ -318,8 +318,9 @@ def test_error_paths(ctx, fth):
 @pytest.mark.parametrize("npts", [1, 33, 100, 200, 256, 300])
 def test_far_field_target_counts(ctx, fth, npts):
     """Far-field sums at target counts that take every thread-per-target
-    split (8, 4, 2 threads below 256 targets, one from 256 up, a ragged
-    second block at 300) against the oracle's Gauss-Chebyshev sum."""
+    split (8 threads up to 64 targets, 4 up to 128, 2 up to 256, one
+    above with a ragged second block at 300) against the oracle's
+    Gauss-Chebyshev sum."""
     curve = CircularArc(1.0, -1.0, 1.0)
     n = 96
     arc = ctx.arc_from_curve(curve, n)
