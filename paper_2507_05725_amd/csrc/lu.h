@@ -595,6 +595,9 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3, sizeof(T) == 8 ? 2 : 
     }
   }
   if (!right) return;
+  // a block with columns to its right is a full one (nb < 64 only for the
+  // last block of a matrix); the update below relies on it
+  if (nb < kLuNB) return;
   // ---- U12 for this strip: X = L11^{-1} A12 on the matrix cores, with
   // the inverse from the panel kernel; A12 in LDS as the B operand, the
   // product kept in registers, then written over it (and to memory)
@@ -694,15 +697,22 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3, sizeof(T) == 8 ? 2 : 
     __syncthreads();
   }
   // ---- A22 -= L21 U12 down the strip: each wave owns 16 rows x 64 columns
-  // (the symmetric form: from the strip's diagonal tile down)
+  // (the symmetric form: from the strip's diagonal tile down).  FP32 (and
+  // H16): the matrix cores form the transposed tile, U12^T L21^T (U12 the
+  // A operand, L21 the B operand), so that an accumulator's 16 columns are
+  // 16 consecutive rows of the column-major matrix: lane (li, g) register
+  // r holds the entry at row rw + li, column 16 cb + crow(g, r), and a C
+  // load or store instruction touches four whole cache lines rather than a
+  // quarter of sixteen.  FP64 keeps the direct form (its register budget).
+  constexpr bool TR = sizeof(T) == 4;
   for (int r0 = SYM ? c0 : k0 + nb; r0 < N; r0 += 64) {
     const int rw = r0 + 16 * wave;  // first row of this wave
     if (rw >= N) continue;
     // C tile and L21 fragments in one round trip, indices clamped (no
     // selects either: the compiler turns a select of a load back into a
     // branch).  Clamped C entries (rows >= N, columns >= cw) only feed
-    // outputs that are never stored; clamped L21 columns (kc >= nb, in a
-    // partial last block) meet the zero rows >= nb of U12.  The products
+    // outputs that are never stored; the L21 columns need no clamp (the
+    // block is a full one).  The products
     // accumulate from zero and C is added at the end, so that the C loads
     // have the whole product chain to arrive.
     // Issue order: the L21 fragments (needed first, in step order), then C;
@@ -716,19 +726,39 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3, sizeof(T) == 8 ? 2 : 
 #pragma unroll
     for (int st = 0; st < kLuNB / 4; ++st) {
       const int kc = H16 ? 16 * (st >> 2) + 4 * lk + (st & 3) : 4 * st + lk;
-      fa[st] = A[arow + min(kc, nb - 1) * N];
+      fa[st] = A[arow + kc * N];
     }
-    const int ccl = c0 + min(li, cw - 1);  // clamped column of cb = 0
     T cx[4][4], cy[4][4];
+    if constexpr (TR) {
+      // 32-bit byte offsets from the matrix's (uniform) base: one register
+      // per address instead of a 64-bit pointer
+      const int rowc = min(rw + li, N - 1);  // clamped row of this lane
+      // the strip's width, opaque per tile: its clamps are recomputed here
+      // rather than sixteen column offsets held through the loop
+      int cwt = cw;
+      asm volatile("" : "+v"(cwt));
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-      const int colc = min(ccl + cb * 16, c0 + cw - 1);
+      for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = min(rw + Mma<T>::crow(lk, r), N - 1);
-        const T2 v = A[row + colc * N];
-        cx[cb][r] = v.x;
-        cy[cb][r] = v.y;
+        for (int r = 0; r < 4; ++r) {
+          const int colc = c0 + min(cb * 16 + Mma<T>::crow(lk, r), cwt - 1);
+          const unsigned off = (unsigned)(rowc + colc * N) * (unsigned)sizeof(T2);
+          const T2 v = *(const T2 *)((const char *)A + off);
+          cx[cb][r] = v.x;
+          cy[cb][r] = v.y;
+        }
+    } else {
+      const int ccl = c0 + min(li, cw - 1);  // clamped column of cb = 0
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        const int colc = min(ccl + cb * 16, c0 + cw - 1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = min(rw + Mma<T>::crow(lk, r), N - 1);
+          const T2 v = A[row + colc * N];
+          cx[cb][r] = v.x;
+          cy[cb][r] = v.y;
+        }
       }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -764,10 +794,10 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3, sizeof(T) == 8 ? 2 : 
             bi[e] = (_Float16)bv.y;
           }
           // C - A B:  re += (-Ar) Br + Ai Bi ;  im += (-Ar) Bi + (-Ai) Br
-          cr[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(ar, br, cr[cb], 0, 0, 0);
-          ci[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(ar, bi, ci[cb], 0, 0, 0);
-          cr[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(pai, bi, cr[cb], 0, 0, 0);
-          ci[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(ai, br, ci[cb], 0, 0, 0);
+          cr[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(br, ar, cr[cb], 0, 0, 0);
+          ci[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(bi, ar, ci[cb], 0, 0, 0);
+          cr[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(bi, pai, cr[cb], 0, 0, 0);
+          ci[cb] = __builtin_amdgcn_mfma_f32_16x16x16f16(br, ai, ci[cb], 0, 0, 0);
         }
       }
     } else if constexpr (sizeof(T) == 4) {
@@ -783,20 +813,13 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3, sizeof(T) == 8 ? 2 : 
 #pragma unroll
       for (int st = 0; st < kLuNB / 4; ++st) {
         const T ar = fa[st].x, ai = fa[st].y, as = fa[st].x + fa[st].y;
-        T br[4], bi[4], bs[4];
         const int krow = 4 * st + lk;
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
           const T2 bv = sX[krow][cb * 16 + li];
-          br[cb] = bv.x;
-          bi[cb] = bv.y;
-          bs[cb] = bv.x + bv.y;
-        }
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-          cr[cb] = Mma<T>::run(ar, br[cb], cr[cb]);
-          ci[cb] = Mma<T>::run(ai, bi[cb], ci[cb]);
-          c3[cb] = Mma<T>::run(as, bs[cb], c3[cb]);
+          cr[cb] = Mma<T>::run(bv.x, ar, cr[cb]);
+          ci[cb] = Mma<T>::run(bv.y, ai, ci[cb]);
+          c3[cb] = Mma<T>::run(bv.x + bv.y, as, c3[cb]);
         }
       }
       // C - A B: cr = T1, ci = T2 -> (T2 - T1, T1 + T2 - T3)
@@ -836,12 +859,17 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3, sizeof(T) == 8 ? 2 : 
     }
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) {
-      const int col = cb * 16 + li;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = rw + Mma<T>::crow(lk, r);
-        if (row < N && col < cw)
-          A[row + (c0 + col) * N] = mk<T>(cx[cb][r] + cr[cb][r], cy[cb][r] + ci[cb][r]);
+        const int row = TR ? rw + li : rw + Mma<T>::crow(lk, r);
+        const int col = TR ? cb * 16 + Mma<T>::crow(lk, r) : cb * 16 + li;
+        const T vx = cx[cb][r] + cr[cb][r], vy = cy[cb][r] + ci[cb][r];
+        if (row < N && col < cw) {
+          if constexpr (TR)
+            *(T2 *)((char *)A + (unsigned)(row + (c0 + col) * N) * (unsigned)sizeof(T2)) = mk<T>(vx, vy);
+          else
+            A[row + (c0 + col) * N] = mk<T>(vx, vy);
+        }
       }
     }
   }
