@@ -697,14 +697,14 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3, sizeof(T) == 8 ? 2 : 
     __syncthreads();
   }
   // ---- A22 -= L21 U12 down the strip: each wave owns 16 rows x 64 columns
-  // (the symmetric form: from the strip's diagonal tile down).  FP32 (and
-  // H16): the matrix cores form the transposed tile, U12^T L21^T (U12 the
-  // A operand, L21 the B operand), so that an accumulator's 16 columns are
-  // 16 consecutive rows of the column-major matrix: lane (li, g) register
-  // r holds the entry at row rw + li, column 16 cb + crow(g, r), and a C
-  // load or store instruction touches four whole cache lines rather than a
-  // quarter of sixteen.  FP64 keeps the direct form (its register budget).
-  constexpr bool TR = sizeof(T) == 4;
+  // (the symmetric form: from the strip's diagonal tile down).  The matrix
+  // cores form the transposed tile, U12^T L21^T (U12 the A operand, L21 the
+  // B operand), so that an accumulator's 16 columns are 16 consecutive rows
+  // of the column-major matrix: lane (li, g) register r holds the entry at
+  // row rw + li, column 16 cb + crow(g, r), and a C load or store
+  // instruction touches whole cache lines (four in FP32, eight in FP64)
+  // rather than a part of sixteen.  TR = false is the direct form.
+  constexpr bool TR = true;
   for (int r0 = SYM ? c0 : k0 + nb; r0 < N; r0 += 64) {
     const int rw = r0 + 16 * wave;  // first row of this wave
     if (rw >= N) continue;
@@ -847,13 +847,13 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3, sizeof(T) == 8 ? 2 : 
       // C - A B:  re += (-Ar) Br + Ai Bi ;  im += (-Ar) Bi + (-Ai) Br
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) {
-        cr[cb] = Mma<T>::run(ar, br[cb], cr[cb]);
-        ci[cb] = Mma<T>::run(ar, bi[cb], ci[cb]);
+        cr[cb] = Mma<T>::run(br[cb], ar, cr[cb]);
+        ci[cb] = Mma<T>::run(bi[cb], ar, ci[cb]);
       }
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) {
-        cr[cb] = Mma<T>::run(pai, bi[cb], cr[cb]);
-        ci[cb] = Mma<T>::run(ai, br[cb], ci[cb]);
+        cr[cb] = Mma<T>::run(bi[cb], pai, cr[cb]);
+        ci[cb] = Mma<T>::run(br[cb], ai, ci[cb]);
       }
     }
     }
