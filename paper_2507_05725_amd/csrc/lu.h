@@ -512,6 +512,19 @@ __global__ __launch_bounds__(kLuThreads) void lu_panel_kernel(cplx_t<T> *Abase, 
 
 constexpr int kStripW = 64;
 
+// A strip's U12 block (nb x cw, staged in LDS) to rows k0.., columns c0..
+// of the matrix, consecutive lanes down each column (whole cache lines).
+template <typename T2>
+__device__ __forceinline__ void u12_store(T2 *A, int N, int k0, int c0, int nb, int cw,
+                                          const T2 (*sX)[kStripW + 1]) {
+  constexpr int kSi = kLuNB * kStripW / kLuThreads;
+#pragma unroll
+  for (int it = 0; it < kSi; ++it) {
+    const int e = threadIdx.x + it * kLuThreads, r = e % kLuNB, c = e / kLuNB;
+    if (r < nb && c < cw) A[(k0 + r) + (c0 + c) * N] = sX[r][c];
+  }
+}
+
 // One workgroup per (matrix, 64-column strip).  Strips left of the block
 // only receive the block's row permutation; strips right of it also get
 // U12 = L11^{-1} A12 and the update A22 -= L21 U12 down the whole strip.
@@ -604,8 +617,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3, sizeof(T) == 8 ? 2 : 
   const int lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
   if constexpr (SYM) {
     // U12[r][c] = d_r L(c0 + c, k0 + r): the panel's rows c0.. of its
-    // columns, contiguous in c for each r; stored (the U part of the
-    // factors) and kept in LDS as the update's B operand
+    // columns, contiguous in c for each r; kept in LDS as the update's B
+    // operand and stored from there (the U part of the factors)
     constexpr int kSi = kLuNB * kStripW / kLuThreads;
     T2 lv[kSi], dv[kSi];
 #pragma unroll
@@ -621,22 +634,23 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3, sizeof(T) == 8 ? 2 : 
       const T2 d = dv[it], l = lv[it];
       const T2 v = ok ? mk<T>(d.x * l.x - d.y * l.y, d.x * l.y + d.y * l.x) : mk<T>(T(0), T(0));
       sX[r][c] = v;
-      if (ok) A[(k0 + r) + (long long)(c0 + c) * N] = v;
     }
     __syncthreads();
+    u12_store(A, N, k0, c0, nb, cw, sX);
   } else {
     constexpr int kSi = kLuNB * kStripW / kLuThreads;
     T gx[kSi], gy[kSi];
 #pragma unroll
     for (int it = 0; it < kSi; ++it) {
-      const int e = tid + it * kLuThreads, r = e / kStripW, c = e % kStripW;
+      // consecutive lanes down a column of A12
+      const int e = tid + it * kLuThreads, r = e % kLuNB, c = e / kLuNB;
       const T2 v = A[(k0 + min(r, nb - 1)) + (c0 + min(c, cw - 1)) * N];
       gx[it] = v.x;
       gy[it] = v.y;
     }
 #pragma unroll
     for (int it = 0; it < kSi; ++it) {
-      const int e = tid + it * kLuThreads, r = e / kStripW, c = e % kStripW;
+      const int e = tid + it * kLuThreads, r = e % kLuNB, c = e / kLuNB;
       const bool ok = r < nb && c < cw;
       sX[r][c] = mk<T>(ok ? gx[it] : T(0), ok ? gy[it] : T(0));
     }
@@ -690,11 +704,10 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3, sizeof(T) == 8 ? 2 : 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * wave + Mma<T>::crow(lk, r), col = cb * 16 + li;
-        const T2 v = mk<T>(xr[cb][r], xi[cb][r]);
-        sX[row][col] = v;
-        if (row < nb && col < cw) A[(k0 + row) + (c0 + col) * N] = v;
+        sX[row][col] = mk<T>(xr[cb][r], xi[cb][r]);
       }
     __syncthreads();
+    u12_store(A, N, k0, c0, nb, cw, sX);
   }
   // ---- A22 -= L21 U12 down the strip: each wave owns 16 rows x 64 columns
   // (the symmetric form: from the strip's diagonal tile down).  The matrix
