@@ -926,7 +926,7 @@ static void launch_panel(hipStream_t st, cplx_t<T> *A, int N, long long ms, int 
 template <typename T, int R>
 static void lu_step(fthms_ctx *ctx, hipStream_t st, cplx_t<T> *A, int N, long long ms, int k0,
                     int *piv, int *swp, cplx_t<T> *linv, int *status, int count,
-                    int only_failed, const LuOpts &o) {
+                    int only_failed, const LuOpts &o, hipEvent_t after_panel = nullptr) {
   // per-kernel timing ranges, except in the redo pass (timed as a whole)
   const bool tk = !only_failed;
   const int nb = std::min(kLuNB, N - k0);
@@ -943,6 +943,7 @@ static void lu_step(fthms_ctx *ctx, hipStream_t st, cplx_t<T> *A, int N, long lo
                        o.reg_panel);
   }
   if (tk) tend(ctx);
+  if (after_panel) (void)hipEventRecord(after_panel, st);
   // the symmetric form has no row interchanges: strips left of the block
   // have nothing to do
   const int nleft = sym ? 0 : (k0 + kStripW - 1) / kStripW;
@@ -1006,12 +1007,11 @@ static void lu_blocks(fthms_ctx *ctx, cplx_t<T> *A, int N, long long ms, int *pi
   (void)hipEventRecord(ctx->ev_fork, ctx->stream);
   (void)hipStreamWaitEvent(ctx->aux, ctx->ev_fork, 0);
   for (int k0 = 0; k0 < N; k0 += kLuNB) {
-    lu_step<T, R>(ctx, ctx->stream, A, N, ms, k0, piv, swp, linv, status, h, 0, o);
-    if (k0 == 0) {
-      // start the second half once the first half's first panel is done
-      (void)hipEventRecord(ctx->ev_lead, ctx->stream);
-      (void)hipStreamWaitEvent(ctx->aux, ctx->ev_lead, 0);
-    }
+    // the second half starts once the first half's first panel is done, so
+    // that its panel runs beside the first half's first strip launch
+    lu_step<T, R>(ctx, ctx->stream, A, N, ms, k0, piv, swp, linv, status, h, 0, o,
+                  k0 == 0 ? ctx->ev_lead : nullptr);
+    if (k0 == 0) (void)hipStreamWaitEvent(ctx->aux, ctx->ev_lead, 0);
   }
   for (int k0 = 0; k0 < N; k0 += kLuNB)
     lu_step<T, R>(ctx, ctx->aux, A2, N, ms, k0, piv2, swp2, linv2, status2, c2, 0, o);
