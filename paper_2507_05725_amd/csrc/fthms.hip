@@ -856,11 +856,26 @@ static bool sym_panel_split() {
   return split;
 }
 
+// The diagonal blocks of the two-launch form: one wave per matrix
+// (lu_diag_sym_kernel) by default; FTHMS_SYM_DIAG=reg in the environment
+// takes the 1024-thread register panel instead (a comparison switch).
+static bool sym_diag_wave() {
+  static const bool wave = [] {
+    const char *e = getenv("FTHMS_SYM_DIAG");
+    return !(e && std::string(e) == "reg");
+  }();
+  return wave;
+}
+
 static void launch_panel_sym(hipStream_t st, float2 *A, int N, long long ms, int k0, int *piv,
                              int *swp, float2 *linv, int *status, int count) {
   if (sym_panel_split()) {
-    lu_panel_reg_kernel<float, 1, false><<<count, kPrThreads, 0, st>>>(
-        A, N, ms, k0, piv, swp, linv, status, 0, kLuNB);
+    if (sym_diag_wave())
+      lu_diag_sym_kernel<<<(count + kDiagWaves - 1) / kDiagWaves, 64 * kDiagWaves, 0, st>>>(
+          A, N, ms, k0, piv, swp, status, count);
+    else
+      lu_panel_reg_kernel<float, 1, false><<<count, kPrThreads, 0, st>>>(
+          A, N, ms, k0, piv, swp, linv, status, 0, kLuNB);
     const int rows = N - k0 - kLuNB;
     const int nt = std::min(256, (rows + 63) / 64 * 64);
     for (int b0 = 0; rows > 0 && b0 < count; b0 += 65535) {

@@ -499,4 +499,72 @@ __global__ __launch_bounds__(256) void lu_rows_sym_kernel(cplx_t<T> *Abase, int 
   if (bad) status[mb] = -2;
 }
 
+// The symmetric form's 64 x 64 diagonal block with one wave per matrix (in
+// place of lu_panel_reg_kernel<float, 1, false> with mrows = 64; the same
+// operations in the same order, so the same factors): lane r holds row r of
+// the block in registers, the column steps unrolled so that every entry
+// keeps its register.  Step c: lane c publishes its reduced row (from the
+// diagonal on) in LDS, every lane reads it back as broadcasts, and lane
+// r > c forms L(r, c) = A(r, c) / A(c, c) and updates A(r, j) -= L(r, c) A(c, j)
+// for j > c -- one wave, so no workgroup barrier per column.  The tests are
+// the register panel's: a row below the diagonal with a strictly larger
+// |re| + |im| in column c (FP64 magnitudes), or a zero pivot, gives status
+// -2.  (Publishing column c instead, one store per lane, the reduced matrix
+// being symmetric in exact arithmetic: 0.4 ms less LU per step, but factors
+// whose refinement needed 1.21 instead of 1.07 steps.)
+// Grid: ceil(count / kDiagWaves) workgroups of kDiagWaves waves.
+constexpr int kDiagWaves = 4;
+__global__ __launch_bounds__(64 * kDiagWaves) void lu_diag_sym_kernel(
+    float2 *Abase, int N, long long mstride, int k0, int *pivbase, int *swapbase, int *status,
+    int count) {
+  __shared__ float2 rowv[kDiagWaves][2][kLuNB];  // the published pivot rows
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long long mb = (long long)blockIdx.x * kDiagWaves + wave;
+  if (mb >= count) return;
+  float2 *A = Abase + mb * mstride + k0 + (long long)k0 * N;
+  const int nb = min(kLuNB, N - k0);
+  // rows and columns past a partial block are clamped copies: they never
+  // reach a stored entry or a test
+  const int rl = min(lane, nb - 1);
+  float2 a[kLuNB];
+#pragma unroll
+  for (int j = 0; j < kLuNB; ++j) a[j] = A[rl + (long long)min(j, nb - 1) * N];
+  int bad = 0;
+#pragma unroll
+  for (int c = 0; c < kLuNB; ++c) {
+    if (c < nb) {
+      float2 *row = rowv[wave][c & 1];
+      if (lane == c) {
+#pragma unroll
+        for (int j = c; j < kLuNB; ++j) row[j] = a[j];
+      }
+      __builtin_amdgcn_wave_barrier();
+      const float2 p = row[c];
+      const double pm = fabs((double)p.x) + fabs((double)p.y);
+      const double mag = fabs((double)a[c].x) + fabs((double)a[c].y);
+      if (lane > c && lane < nb && mag > pm) bad = 1;
+      if (!(pm > 0.0)) bad = 1;
+      float2 inv = make_float2(0.f, 0.f);
+      if (pm > 0.0) inv = trcp<float>(p);
+      const float2 l = lane > c ? tmul<float>(a[c], inv) : make_float2(0.f, 0.f);
+      if (lane > c) a[c] = l;
+#pragma unroll
+      for (int j = c + 1; j < kLuNB; ++j) a[j] = tfms<float>(a[j], l, row[j]);
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  if (lane < nb) {
+#pragma unroll
+    for (int j = 0; j < kLuNB; ++j)
+      if (j < nb) A[lane + (long long)j * N] = a[j];
+    pivbase[mb * N + k0 + lane] = k0 + lane;
+  }
+  const bool flag = __builtin_amdgcn_ballot_w64(bad != 0) != 0;
+  if (lane == 0) {
+    swapbase[mb * kSwapStride] = 0;
+    if (k0 == 0) status[mb] = panel_status(0, flag);
+    else if (flag) status[mb] = -2;
+  }
+}
+
 }  // namespace fthms
