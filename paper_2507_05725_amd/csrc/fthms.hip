@@ -857,8 +857,12 @@ static bool sym_panel_split() {
 }
 
 // The diagonal blocks of the two-launch form: one wave per matrix
-// (lu_diag_sym_kernel) by default; FTHMS_SYM_DIAG=reg in the environment
-// takes the 1024-thread register panel instead (a comparison switch).
+// (lu_diag_sym_kernel) for launches of kDiagWaveMin matrices or more, the
+// 1024-thread register panel below that (one matrix: 22 against 57 us, the
+// 64 column steps shared by 16 waves; 4096 matrices: 237 against 198 us).
+// The two take the same operations in the same order.  FTHMS_SYM_DIAG=reg
+// in the environment takes the register panel always (a comparison switch).
+constexpr int kDiagWaveMin = 1024;
 static bool sym_diag_wave() {
   static const bool wave = [] {
     const char *e = getenv("FTHMS_SYM_DIAG");
@@ -870,7 +874,7 @@ static bool sym_diag_wave() {
 static void launch_panel_sym(hipStream_t st, float2 *A, int N, long long ms, int k0, int *piv,
                              int *swp, float2 *linv, int *status, int count) {
   if (sym_panel_split()) {
-    if (sym_diag_wave())
+    if (sym_diag_wave() && count >= kDiagWaveMin)
       lu_diag_sym_kernel<<<(count + kDiagWaves - 1) / kDiagWaves, 64 * kDiagWaves, 0, st>>>(
           A, N, ms, k0, piv, swp, status, count);
     else

@@ -155,6 +155,25 @@ def test_batch_invariance(ctx, fth):
             assert np.array_equal(one[0], batch[i])
 
 
+def test_batch_invariance_large_refined(ctx, fth):
+    """The refined form's solves are the same alone and inside a batch whose
+    LU halves are large enough (over 1024 matrices each) to factor their
+    diagonal blocks one wave per matrix, while a single solve takes the
+    1024-thread panel: the two kernels must give the same bits.  N = 96 also
+    has a partial last block."""
+    curve = CircularArc(1.0, -1.0, 1.3)
+    k = np.linspace(2.0, 40.0, 2100)
+    inc = IncidentSpec("plane", theta=0.5)
+    say("batch invariance, 2100 refined solves")
+    arc = ctx.arc_from_curve(curve, 96)
+    rhs = ctx.rhs(arc, k, inc)
+    batch, iters, _ = ctx.solve(arc, k, rhs, 1)
+    assert np.all(iters >= 1), iters.min()
+    for i in (0, 1049, 1050, 2099):
+        one, _, _ = ctx.solve(arc, k[i:i + 1], rhs[i:i + 1], 1)
+        assert np.array_equal(one[0], batch[i]), (i, np.max(np.abs(one[0] - batch[i])))
+
+
 @pytest.mark.parametrize("kind", ["gplane", "point"])
 def test_incident_kinds(ctx, fth, kind):
     curve = SineArc((0.0, 0.0), 2.0, 0.2, 1, 0.3)
