@@ -157,3 +157,36 @@ def test_traces_sum_of_steps_and_stop_rule():
     assert np.linalg.norm(u_all - ref) <= 1e-13 * np.linalg.norm(ref)
     u_part, s2 = ms.run_traces(lay, om, w, pb.times, stop_tol=0.9)
     assert 1 <= s2 < pb.M
+
+
+def test_stop_rule_against_partial_sums():
+    """The stop rule of run_traces pinned by brute force: the traces of the
+    same problem cut at M' = 1 .. 6 steps without a stop (each the whole
+    sum, pinned above) give every step's increment; with a tolerance the run
+    must end at the first step whose increment is at most tol times the sum
+    so far, returning that step's partial sum.  The increments here are not
+    monotone, so a tolerance is chosen that an earlier step misses by less
+    than a later one meets it."""
+    from oracle import transform as tr
+
+    def traces(M, tol):
+        pb = small_kite_case(n=12, omegas=(2.0, 2.5, 3.0), M=M, nobs=3, nt=10, dt=0.3)
+        lay = ms.Layout(pb)
+        om = np.asarray(pb.omegas, dtype=float)
+        return ms.run_traces(lay, om, tr.trapezoid_weights(om), pb.times, stop_tol=tol)
+
+    M = 6
+    parts = [traces(m, 0.0)[0] for m in range(1, M + 1)]
+    ratio = [1.0] + [np.linalg.norm(parts[m] - parts[m - 1]) / np.linalg.norm(parts[m])
+                     for m in range(1, M)]
+    tested = 0
+    for tol in (0.5, 0.4):
+        first = next((m + 1 for m in range(M) if ratio[m] <= tol), M)
+        if not (2 < first < M and min(ratio[1:first - 1]) > tol):
+            continue
+        u, steps = traces(M, tol)
+        assert steps == first, (tol, steps, first, ratio)
+        assert np.linalg.norm(u - parts[first - 1]) <= 1e-13 * np.linalg.norm(u)
+        tested += 1
+    assert tested >= 1, ratio
+
