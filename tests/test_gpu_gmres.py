@@ -43,7 +43,15 @@ CAVITY = (0.02 * math.pi, 1.98 * math.pi)
 @pytest.mark.parametrize("case", ["arc", "cavity", "patch"])
 def test_gmres_open_arcs(ctx, fth, case):
     """Open arcs: a circular arc (N = 128), the nearly closed circular cavity
-    of Geometries 5 (N = 256, trapping) and one of its six patches (N = 64)."""
+    of Geometries 5 (N = 256, trapping) and one of its six patches (N = 64).
+    Iteration counts within one of the oracle's GMRES; the true relative
+    residual |A x - b| / |b| at most 2e-12; and the iterate element by
+    element against both the direct solve and the oracle's GMRES iterate
+    within 1e-10.  Two iterates whose relative residuals are at most 1e-12
+    differ by at most 2e-12 |A^-1| |b|, 1.5e-11 to 3.6e-10 of |x| on these
+    matrices (the cavity's trapped modes make |A^-1| large); the iterates
+    themselves agree with the oracle's to 1e-14 (arc, patch) and 3e-12
+    (cavity), and with the direct solve to 1e-11."""
     if case == "arc":
         curve, n = CircularArc(1.0, -1.0, 1.4), 128
     elif case == "cavity":
@@ -64,8 +72,11 @@ def test_gmres_open_arcs(ctx, fth, case):
         xo, ito, hist = ogm.gmres(A, b, tol=1e-12, maxit=min(n, 256))
         assert abs(int(it[i]) - ito) <= 1, (k, it[i], ito)
         assert rr[i] <= 1e-12
+        assert np.linalg.norm(A @ x[i] - b) <= 2e-12 * np.linalg.norm(b), k
         ref = np.linalg.solve(A, b)
-        assert rel(x[i], ref) < 1e-9, (k, rel(x[i], ref))
+        say("k", k, "vs direct %.2e, vs oracle GMRES %.2e" % (rel(x[i], ref), rel(x[i], xo)))
+        assert rel(x[i], ref) < 1e-10, (k, rel(x[i], ref))
+        assert rel(x[i], xo) < 1e-10, (k, rel(x[i], xo))
 
 
 def test_gmres_closed_patch(ctx, fth):
@@ -81,9 +92,10 @@ def test_gmres_closed_patch(ctx, fth):
     for i, k in enumerate(ks):
         A = ocl.assemble(nd, k)
         b = -oinc.incident(spec, k, nd["y"])
-        _, ito, _ = ogm.gmres(A, b, tol=1e-12, maxit=n)
+        xo, ito, _ = ogm.gmres(A, b, tol=1e-12, maxit=n)
         assert abs(int(it[i]) - ito) <= 1 and it[i] < 60
         assert rel(x[i], np.linalg.solve(A, b)) < 1e-10
+        assert rel(x[i], xo) < 1e-10
 
 
 def test_gmres_dev_raw_matrices(ctx, fth):
