@@ -25,12 +25,18 @@ constexpr int kFieldThreads = 256;
 
 constexpr int kFieldF = 4;  // wavenumbers per block of field_far_mf_kernel
 
-// Bytes of the dynamic LDS of field_far_mf_kernel: the nodes and kFieldF
-// densities.
-inline size_t field_mf_lds_bytes(int N) { return sizeof(double2) * (size_t)(1 + kFieldF) * N; }
+// Nodes per LDS chunk of field_far_mf_kernel (a multiple of every split).
+constexpr int kFieldChunk = 256;
+
+// Bytes of the dynamic LDS of field_far_mf_kernel: one chunk of nodes and
+// their kFieldF weighted densities.
+inline size_t field_mf_lds_bytes(int N) {
+  return sizeof(double2) * (size_t)(1 + kFieldF) * (size_t)(N < kFieldChunk ? N : kFieldChunk);
+}
 
 // Far targets: up to 256 targets for kFieldF consecutive wavenumbers per
-// block, nodes and weighted densities in LDS.  Composite-panel arcs pass
+// block, nodes and weighted densities in LDS, kFieldChunk nodes at a time
+// (about 26 KB of LDS per block: four blocks per CU, four waves per SIMD).  Composite-panel arcs pass
 // their Fejer weights: U(z) = sum_j w_j Phi_k(z, y_j) mu_j; otherwise the
 // weight is pi/N.  With up to 256 targets (split = 2, 4 or 8) each
 // target's node sum is shared by `split` threads (nodes j = s, s + split,
@@ -42,28 +48,19 @@ inline size_t field_mf_lds_bytes(int N) { return sizeof(double2) * (size_t)(1 + 
 // coefficients are read from LDS.  A wavenumber's result does not depend on
 // the others launched with it.
 // Grid (target blocks, ceil(nk / kFieldF)); dynamic LDS field_mf_lds_bytes.
-__global__ __launch_bounds__(kFieldThreads) void field_far_mf_kernel(
+__global__ __launch_bounds__(kFieldThreads) __attribute__((amdgpu_waves_per_eu(4))) void field_far_mf_kernel(
     const double2 *__restrict__ ynodes, int N, const double *__restrict__ wnode,
     const double *__restrict__ kvec, int nk, const double2 *__restrict__ alpha,
     long long astride, const double2 *__restrict__ pts, int np,
     const unsigned char *__restrict__ cls, double2 *__restrict__ U, long long ustride,
     int accumulate, int split) {
   extern __shared__ double2 fdyn[];
-  double2 *sy = fdyn, *sa = fdyn + N;  // sa[f N + j]: weighted density f at node j
+  const int C = min(N, kFieldChunk);
+  double2 *sy = fdyn, *sa = fdyn + C;  // sa[f C + j]: weighted density f at chunk node j
   __shared__ double2 red[kFieldThreads];
   __shared__ double2 btab[kBesselTabLen];
   __shared__ double wk[kFieldF][3];  // k, 1/k, sqrt(1/k)
   const int b0 = blockIdx.y * kFieldF, nf = min(kFieldF, nk - b0);
-  for (int j = threadIdx.x; j < N; j += kFieldThreads) {
-    sy[j] = ynodes[j];
-#pragma unroll
-    for (int f = 0; f < kFieldF; ++f) {
-      double2 a = make_double2(0.0, 0.0);
-      if (f < nf) a = alpha[(long long)(b0 + f) * astride + j];
-      if (wnode) a = make_double2(wnode[j] * a.x, wnode[j] * a.y);
-      sa[f * N + j] = a;
-    }
-  }
   if (threadIdx.x < kBesselTabLen) bessel_tab_fill(btab, threadIdx.x);
   if (threadIdx.x >= 64 && threadIdx.x < 64 + nf) {
     const int f = threadIdx.x - 64;
@@ -72,7 +69,6 @@ __global__ __launch_bounds__(kFieldThreads) void field_far_mf_kernel(
     wk[f][1] = ik;
     wk[f][2] = sqrt(ik);
   }
-  __syncthreads();
   const int tpb = kFieldThreads / split;  // targets per block
   const int pl = threadIdx.x % tpb, sl = threadIdx.x / tpb;
   const int p = blockIdx.x * tpb + pl;
@@ -80,37 +76,56 @@ __global__ __launch_bounds__(kFieldThreads) void field_far_mf_kernel(
   double ar[kFieldF], ai[kFieldF];
 #pragma unroll
   for (int f = 0; f < kFieldF; ++f) ar[f] = ai[f] = 0.0;
-  if (active) {
-    const double2 zt = pts[p];
-    for (int j = sl; j < N; j += split) {
-      const double2 yj = sy[j];
-      const double dx = zt.x - yj.x, dy = zt.y - yj.y;
-      const double r = sqrt(dx * dx + dy * dy), ir = 1.0 / r;
-      const double amp = sqrt((2.0 / kPi) * ir);
-      // the table's address is opaque per node so that its reads stay in
-      // the loop rather than 104 constants held in registers
-      int toff = 0;
-      asm volatile("" : "+v"(toff));
-      const double2 *tab = btab + toff;
+  const double2 zt = active ? pts[p] : make_double2(0.0, 0.0);
+  // the chunks in order, and in each a thread's nodes j0 + sl, j0 + sl +
+  // split, ... (chunks are a multiple of split): every node in the order of
+  // one pass over all of them
+  for (int j0 = 0; j0 < N; j0 += C) {
+    const int nc = min(C, N - j0);
+    __syncthreads();  // the previous chunk is no longer read
+    for (int j = threadIdx.x; j < nc; j += kFieldThreads) {
+      sy[j] = ynodes[j0 + j];
+      const double wj = wnode ? wnode[j0 + j] : 1.0;
 #pragma unroll
       for (int f = 0; f < kFieldF; ++f) {
-        if (f < nf) {
-          const double k = wk[f][0], z = k * r;
-          double j0v, y0v;
-          if (z >= kBesselSeriesTo) {
-            double P, Q, sz, cz;
-            bessel_pq_tab(z, wk[f][1] * ir, tab, P, Q);
-            phase_sincos(z, sz, cz);
-            bessel_combine(P, Q, cz, sz, amp * wk[f][2], j0v, y0v);
-          } else {
-            double yh;
-            bessel_series_tab(z, tab, j0v, yh);
-            y0v = yh + bessel_logpart(z) * j0v;
+        double2 a = make_double2(0.0, 0.0);
+        if (f < nf) a = alpha[(long long)(b0 + f) * astride + j0 + j];
+        if (wnode) a = make_double2(wj * a.x, wj * a.y);
+        sa[f * C + j] = a;
+      }
+    }
+    __syncthreads();
+    if (active) {
+      for (int j = sl; j < nc; j += split) {
+        const double2 yj = sy[j];
+        const double dx = zt.x - yj.x, dy = zt.y - yj.y;
+        const double r = sqrt(dx * dx + dy * dy), ir = 1.0 / r;
+        const double amp = sqrt((2.0 / kPi) * ir);
+        // the table's address is opaque per node so that its reads stay in
+        // the loop rather than 104 constants held in registers
+        int toff = 0;
+        asm volatile("" : "+v"(toff));
+        const double2 *tab = btab + toff;
+#pragma unroll
+        for (int f = 0; f < kFieldF; ++f) {
+          if (f < nf) {
+            const double k = wk[f][0], z = k * r;
+            double j0v, y0v;
+            if (z >= kBesselSeriesTo) {
+              double P, Q, sz, cz;
+              bessel_pq_tab(z, wk[f][1] * ir, tab, P, Q);
+              phase_sincos(z, sz, cz);
+              bessel_combine(P, Q, cz, sz, amp * wk[f][2], j0v, y0v);
+            } else {
+              double yh;
+              bessel_series_tab(z, tab, j0v, yh);
+              y0v = yh + bessel_logpart(z) * j0v;
+            }
+            // (i J0 - Y0) * a
+            const double2 a = sa[f * C + j];
+            ar[f] += -y0v * a.x - j0v * a.y;
+            ai[f] += j0v * a.x - y0v * a.y;
           }
-          // (i J0 - Y0) * a
-          const double2 a = sa[f * N + j];
-          ar[f] += -y0v * a.x - j0v * a.y;
-          ai[f] += j0v * a.x - y0v * a.y;
         }
       }
     }
