@@ -161,15 +161,17 @@ __global__ __launch_bounds__(kFieldThreads) __attribute__((amdgpu_waves_per_eu(4
   }
 }
 
-// Threads per target for field_far_mf_kernel and closed_field_kernel: 8 up
-// to 64 targets, 4 up to 128, 2 up to 256, 1 above.  Every launch has
-// about twice as many threads as targets (at 256 targets one per target
-// left four waves per SIMD in all, too few to cover the latency of the
-// Bessel evaluations' dependent chains).  A function of the target count
-// only, so a field does not depend on what else is launched.
+// Threads per target for field_far_mf_kernel and closed_field_kernel: the
+// smallest power of two (at most 8) that gives at least four blocks' worth
+// of threads, np x split >= 1024: 8 below 256 targets, 4 below 512, 2 below
+// 1024, 1 from 1024 up.  At the headline's 256
+// targets one thread per target left four waves per SIMD in all, too few to
+// cover the latency of the Bessel evaluations' dependent chains (2.75 ms per
+// step; 2.17 with two threads, 1.98 with four).  A function of the target
+// count only, so a field does not depend on what else is launched.
 inline int field_target_split(int np) {
   int split = 1;
-  while (split < 8 && np * split <= kFieldThreads) split *= 2;
+  while (split < 8 && np * split < 4 * kFieldThreads) split *= 2;
   return split;
 }
 

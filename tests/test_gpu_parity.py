@@ -334,12 +334,12 @@ def test_error_paths(ctx, fth):
     assert e.value.code == -3
 
 
-@pytest.mark.parametrize("npts", [1, 33, 100, 200, 256, 300])
+@pytest.mark.parametrize("npts", [1, 33, 200, 256, 300, 600, 1100])
 def test_far_field_target_counts(ctx, fth, npts):
     """Far-field sums at target counts that take every thread-per-target
-    split (8 threads up to 64 targets, 4 up to 128, 2 up to 256, one
-    above with a ragged second block at 300) against the oracle's
-    Gauss-Chebyshev sum."""
+    split (8 threads below 256 targets, 4 below 512, 2 below 1024, one
+    from 1024 up; ragged last blocks at 300, 600 and 1100) against the
+    oracle's Gauss-Chebyshev sum."""
     curve = CircularArc(1.0, -1.0, 1.0)
     n = 96
     arc = ctx.arc_from_curve(curve, n)
