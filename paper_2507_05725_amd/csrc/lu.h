@@ -1111,9 +1111,13 @@ __device__ void sym_residual_fused(const double2 *__restrict__ A, int N,
                                    double2 *rs, double2 *part) {
   static_assert(kLuThreads == 256, "four waves, four partial vectors");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int e = tid; e < 4 * N; e += kLuThreads) part[e] = make_double2(0.0, 0.0);
+  // waves 0..2 accumulate in part[0, 3N), wave 3 in rs itself (free until
+  // the residual is formed): 40 KB of LDS in all at N = 512, four
+  // workgroups per CU
+  for (int e = tid; e < 3 * N; e += kLuThreads) part[e] = make_double2(0.0, 0.0);
+  for (int e = tid; e < N; e += kLuThreads) rs[e] = make_double2(0.0, 0.0);
   __syncthreads();
-  double2 *pw = part + (long long)wave * N;
+  double2 *pw = wave < 3 ? part + (long long)wave * N : rs;
   const int nbk = (N + 63) >> 6, nblk = nbk * (nbk + 1) / 2;
   const int b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1;
   for (int t = wave; t < nblk; t += 4) {
@@ -1173,16 +1177,18 @@ __device__ void sym_residual_fused(const double2 *__restrict__ A, int N,
   }
   __syncthreads();
   for (int r = tid; r < N; r += kLuThreads) {
-    const double2 s = cadd(cadd(part[r], part[N + r]), cadd(part[2 * N + r], part[3 * N + r]));
+    const double2 s = cadd(cadd(part[r], part[N + r]), cadd(part[2 * N + r], rs[r]));
     rs[r] = csub(bb[r], s);
   }
   __syncthreads();
 }
 
 // Bytes of the dynamic LDS of refine_kernel: x and r, and for the fused
-// symmetric residual four partial vectors.
+// symmetric residual three more partial vectors (whose first doubles also
+// hold the block sums' four wave totals, outside the residual); without it
+// room for those four totals.
 constexpr size_t refine_lds_bytes(int N, bool lower) {
-  return sizeof(double2) * (size_t)(lower ? 6 : 2) * N;
+  return lower ? sizeof(double2) * 5 * (size_t)N : sizeof(double2) * (2 * (size_t)N + 2);
 }
 
 // Refined solve: x0 from the FP32 factors, then repeat
@@ -1195,16 +1201,18 @@ constexpr size_t refine_lds_bytes(int N, bool lower) {
 // assembly), the residual by sym_residual_fused.  A template argument, so
 // that the other form keeps its register budget.
 template <bool LOWER>
-__global__ __launch_bounds__(kLuThreads, 3) void refine_kernel(
+__global__ __launch_bounds__(kLuThreads, 4) void refine_kernel(
     const float2 *LUbase, const int *permbase, const double2 *A64base, int N,
     long long mstride, const double2 *b, double2 *x, long long vstride, double tol,
     int max_iter, int *status, double *relres, int later) {
   // dynamic LDS (refine_lds_bytes, sized at launch): x and r, N complex128
-  // each (16 KB at N = 512), and with the fused symmetric residual its four
-  // partial vectors (48 KB in all at N = 512)
+  // each (16 KB at N = 512), then with the fused symmetric residual its
+  // three partial vectors (40 KB in all at N = 512), else two double2; the
+  // block sums' wave totals at refine_dyn + 2N (the partial vectors are
+  // only in use inside the residual, between barriers)
   extern __shared__ double2 refine_dyn[];
   double2 *xs = refine_dyn, *rs = refine_dyn + N;
-  __shared__ double red[4];
+  double *red = (double *)(refine_dyn + 2 * N);
   const long long mb = (long long)blockIdx.x;
   const float2 *LU = LUbase + mb * mstride;
   const int *piv = permbase + mb * kMaxN;
