@@ -372,6 +372,50 @@ def test_symmetric_lu_flags_pivoting(env, n):
         ctx.lu_dev(big, p2, precision=fth.FP32_SYM)
 
 
+def test_symmetric_lu_large_batch_flags(env):
+    """A batch large enough (2100 matrices, halves of 1050) that the
+    diagonal blocks are factored one wave per matrix: matrices with a small
+    diagonal entry in the first 64 x 64 block, in the partial last block
+    (N = 96) or an exactly zero pivot get info -2, all others 0 with
+    identity pivots, and every factor equals the factor of the same matrix
+    alone (the 1024-thread register panel) bit for bit."""
+    fth, ctx, torch = env
+    rng = np.random.default_rng(4242)
+    n, nb = 96, 2100
+    M = _symmetric_dominant(rng, nb, n)
+    planted = {5: 20, 1500: 70, 2000: 40}
+    M[5][20, 20] = 1e-3
+    M[1500][70, 70] = 1e-3
+    M[2000][40, 40] = 0.0
+    for b in planted:
+        assert _pp_swaps(M[b]) > 0
+    for b in (0, 1049, 1050, 2099):
+        assert _pp_swaps(M[b]) == 0
+    say("symmetric lu, batch of", nb)
+    Acm = np.ascontiguousarray(M.transpose(0, 2, 1))
+    LU32 = torch.tensor(Acm, dtype=torch.complex64, device="cuda")
+    piv = torch.empty((nb, n), dtype=torch.int32, device="cuda")
+    info = torch.empty(nb, dtype=torch.int32, device="cuda")
+    ctx.lu_dev(LU32, piv, info, precision=fth.FP32_SYM)
+    torch.cuda.synchronize()
+    inf = info.cpu().numpy()
+    expect = np.zeros(nb, dtype=inf.dtype)
+    for b in planted:
+        expect[b] = -2
+    assert np.array_equal(inf, expect), np.nonzero(inf != expect)
+    ok = inf == 0
+    assert np.array_equal(piv.cpu().numpy()[ok], np.tile(np.arange(n), (int(ok.sum()), 1)))
+    LUb = LU32.cpu().numpy()
+    for b in (0, 17, 1049, 1050, 2099):
+        one = torch.tensor(Acm[b:b + 1], dtype=torch.complex64, device="cuda")
+        p1 = torch.empty((1, n), dtype=torch.int32, device="cuda")
+        i1 = torch.empty(1, dtype=torch.int32, device="cuda")
+        ctx.lu_dev(one, p1, i1, precision=fth.FP32_SYM)
+        torch.cuda.synchronize()
+        assert int(i1.cpu().numpy()[0]) == 0
+        assert np.array_equal(one.cpu().numpy()[0], LUb[b]), b
+
+
 def test_refined_solve_reports_cap(env):
     """With a cap of one step and an unreachable tolerance the refinement
     reports -1 (not converged) and still returns its last iterate."""
